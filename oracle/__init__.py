@@ -1,0 +1,37 @@
+"""CPU oracle for the hierarchical-grid correlator.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library (no kernels, headers, tables or helpers) and imports nothing from it.
+
+Everything here is a plain, slow, float64 transcription of what the paper
+defines, written so it can be checked against the paper by eye:
+
+* ``visibilities``      -- the visibility hypercube G, i.e. the correlation of
+  every antenna pair summed over pairs sharing the same index difference
+  (Sec. II.A; Sec. II.C Eq. ConvolutionDefEq; Sec. II.D Eq. ProofEq2).
+* ``visibility_cells``  -- the same quantity for a list of individual index
+  differences, one overlap sum per cell (for spot checks at full size).
+* ``fourier_power``     -- the time-summed square modulus of the padded
+  Fourier transform at chosen frequency cells (Sec. II.A: FFT, square
+  modulus, inverse FFT); by Wiener-Khinchin it equals the DFT of G.
+* ``baselines``         -- the physical separation of each index-difference
+  cell, sum_k Delta_k a_k (Sec. II.D Eq. GridEq).
+* ``decode_*``          -- the voltage sample formats (independent decoders).
+
+Every function is pinned by tests in ``tests/test_oracle_pins.py`` against
+values printed in the paper, closed forms, library routines and brute force.
+"""
+
+from .correlator import (  # noqa: F401
+    baselines,
+    decode,
+    decode_cf32,
+    decode_ci4,
+    decode_ci8,
+    fourier_power,
+    lag_shape,
+    visibilities,
+    visibility_cells,
+)
