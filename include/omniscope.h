@@ -1,0 +1,193 @@
+/*
+ * omniscope.h -- C ABI of the MI355X (gfx950) hierarchical-grid correlator.
+ *
+ * What it computes (Tegmark & Zaldarriaga, "Omniscopes", Sec. II):
+ *   Antennas sit on an L-level hierarchy of rectangular grids,
+ *   r = sum_l A_l (i_lx, i_ly)  (Sec. II.D, Eq. GridEq).  One channel's voltages
+ *   at one time form the 2L-dimensional hypercube F_{i_1 ... i_2L}.  The
+ *   visibility hypercube, i.e. every antenna pair's correlation summed over all
+ *   pairs sharing the same index difference Delta, is
+ *
+ *       V_f[Delta] = sum_t sum_j x_{t,f,j} conj(x_{t,f,j-Delta}),
+ *       Delta_k in [-(n_k-1), n_k-1]          (Sec. II.D, Eq. ProofEq2)
+ *
+ *   and is computed the fast way (Sec. II.A, II.C): zero-pad every axis to
+ *   m_k = 2 n_k, 2L-dimensional DFT, square modulus, sum over the time samples,
+ *   one inverse DFT per channel.  The lattice matrices A_l never enter the
+ *   arithmetic (Sec. II.D); they only label each output cell with its physical
+ *   baseline (omni_baselines).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns OMNI_OK (0) or a negative omni_status.  No C++
+ *     exception crosses this boundary.  omni_last_error() gives a message for
+ *     the most recent failure on the calling thread.
+ *   - Axis order: axis 2l is level l's x index, axis 2l+1 its y index, levels
+ *     in the caller's order (outermost first is the natural choice).  The
+ *     antenna index a of a voltage sample is row-major over these axes.
+ *   - Voltages: device memory [T][F][N] samples, 256-byte aligned, in one of
+ *       OMNI_CF32 interleaved float32 (re, im)                 8 bytes/sample
+ *       OMNI_CI8  interleaved int8 (re, im)                    2 bytes/sample
+ *       OMNI_CI4  one byte, re = high nibble, im = low nibble,
+ *                 two's complement, values in [-7, 7]         1 byte/sample
+ *   - Visibilities: device memory, complex64 (float re, float im),
+ *     [F][2n_1-1]...[2n_d-1] row-major, Delta_k stored at index Delta_k+n_k-1
+ *     (centred).  V is Hermitian: V[-Delta] = conj V[Delta]; V[0] is the total
+ *     power.  Plain sums: no 1/T and no per-pair normalisation.
+ *   - The caller owns voltage and visibility buffers; the plan owns its
+ *     twiddle tables, accumulators and workspace.  A plan is not re-entrant:
+ *     calls on one plan must not overlap; distinct plans are independent.
+ *   - omni_correlate* are asynchronous on the caller's HIP stream; results are
+ *     valid once that stream has been synchronised.
+ */
+#ifndef OMNISCOPE_H
+#define OMNISCOPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OMNI_OK = 0,
+  OMNI_E_INVAL = -1,  /* null pointer, bad enum, bad size or flag            */
+  OMNI_E_SHAPE = -2,  /* grid dimensions outside what a plan supports        */
+  OMNI_E_GEOM = -3,   /* non-finite lattice matrix, or two antennas collide  */
+  OMNI_E_NODEV = -4,  /* no usable gfx950 device                             */
+  OMNI_E_NOMEM = -5,  /* device allocation failed or plan exceeds memory     */
+  OMNI_E_HIP = -6,    /* a HIP runtime call failed (message has the detail)  */
+  OMNI_E_STATE = -7   /* call not valid for this plan (e.g. host-only plan)  */
+} omni_status;
+
+typedef enum { OMNI_CF32 = 0, OMNI_CI8 = 1, OMNI_CI4 = 2 } omni_dtype;
+
+/* Arithmetic form of the forward transforms.
+ *   OMNI_FORM_FP32 : float32 DFT stages on the vector ALUs, float32 twiddles.
+ *                    Error <= 1e-5 of the zero-lag power.
+ *   OMNI_FORM_MIXED: float16 MFMA DFT stages with float32 accumulation,
+ *                    twiddles split into float16 hi + lo parts, per-stage
+ *                    power-of-two scaling.  Error <= 2e-3 of zero-lag power.
+ * Both forms integrate |X|^2 in float32 over short blocks of time samples and
+ * then in float64, and run the inverse transform in float64. */
+typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
+
+/* omni_opts.flags */
+#define OMNI_PLAN_HOST_ONLY 0x1u /* geometry only: no device resources; correlate -> OMNI_E_STATE */
+#define OMNI_PLAN_TIMING 0x2u    /* record HIP events around each stage of every correlate call  */
+
+/* flags argument of omni_correlate* */
+#define OMNI_NO_RESET 0x1u    /* add this call's samples to the running accumulator            */
+#define OMNI_NO_FINALIZE 0x2u /* skip the inverse transform (vis is not touched, may be NULL)  */
+
+typedef struct {
+  omni_dtype dtype;   /* sample format of the voltages                        */
+  omni_form form;     /* arithmetic form of the forward transform             */
+  int32_t time_block; /* samples per float32 block before the float64 add; 0 = default */
+  uint32_t flags;     /* OMNI_PLAN_* flags                                    */
+} omni_opts;
+
+typedef struct omni_plan_s* omni_plan_t;
+
+/* Plan one array.
+ *   levels : L >= 1 levels of the hierarchy (d = 2L axes, d <= 8).
+ *   dims   : [L][2] int32 (n_x, n_y) per level; each >= 1; N = prod n <= 2^22.
+ *   A      : [L][2][2] float64 row-major; column c is the level's lattice vector
+ *            of index c, in wavelengths at the reference frequency.  Used only
+ *            for omni_baselines and the position-collision check; may be NULL
+ *            (then no check and omni_baselines returns OMNI_E_STATE).
+ *   nchan  : F >= 1 frequency channels.
+ *   opts   : may be NULL (CF32, FP32 form, defaults).
+ * On success *out holds a new plan (free with omni_destroy).  Device resources
+ * (twiddles from a float64 generator kernel, accumulators, workspace) are
+ * allocated on the current HIP device.  Errors: OMNI_E_INVAL, OMNI_E_SHAPE,
+ * OMNI_E_GEOM, OMNI_E_NODEV, OMNI_E_NOMEM, OMNI_E_HIP. */
+int omni_plan(omni_plan_t* out, int32_t levels, const int32_t* dims, const double* A, int32_t nchan,
+              const omni_opts* opts);
+
+/* One array of a batched plan. */
+typedef struct {
+  int32_t levels;
+  const int32_t* dims; /* [levels][2] */
+  const double* A;     /* [levels][2][2] or NULL */
+  int32_t nchan;
+} omni_array_desc;
+
+/* Plan several arrays (possibly of different shapes) that are always
+ * correlated together, in one launch sequence, with a common T.  Sample format
+ * and form are shared.  Errors as for omni_plan. */
+int omni_plan_batch(omni_plan_t* out, int32_t n_arrays, const omni_array_desc* arrays, const omni_opts* opts);
+
+/* Correlate T time samples (T >= 0) of every channel.
+ *   volt   : device [T][F][N] samples in the plan's format (may be NULL iff T == 0).
+ *   vis    : device complex64 [F][2n_1-1]...[2n_d-1]; may be NULL with OMNI_NO_FINALIZE.
+ *   stream : hipStream_t, or NULL for the default stream.
+ *   flags  : OMNI_NO_RESET, OMNI_NO_FINALIZE.
+ * Without OMNI_NO_RESET the plan's float64 accumulator restarts at zero; with
+ * it, this call's samples are added (a long integration split over calls, or
+ * resumed from omni_accumulator_set, equals the single call up to rounding).
+ * T == 0 with no flags yields all-zero visibilities.
+ * Errors: OMNI_E_INVAL (bad pointer/T/flags), OMNI_E_STATE (host-only plan),
+ * OMNI_E_HIP. */
+int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream, uint32_t flags);
+
+/* Batched form: volt[i] / vis[i] belong to array i of the batch plan. */
+int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, void* const* vis, void* stream,
+                         uint32_t flags);
+
+/* Number of arrays in the plan (1 for omni_plan). */
+int omni_n_arrays(omni_plan_t plan, int32_t* n);
+
+/* Visibility shape of array `array`: *ndim = 1 + d, shape = [F, 2n_1-1, ...].
+ * shape must hold 9 entries. */
+int omni_vis_shape(omni_plan_t plan, int32_t array, int32_t* ndim, int64_t* shape);
+
+/* Physical baseline of every visibility cell of array `array`:
+ * uv[cell][2] = sum_l A_l (Delta_lx, Delta_ly) in wavelengths at the reference
+ * frequency (Sec. II.D, Eq. GridEq), cells in the visibility layout.  uv is
+ * host memory of prod(2n_k-1)*2 doubles.  OMNI_E_STATE if planned without A. */
+int omni_baselines(omni_plan_t plan, int32_t array, double* uv);
+
+/* Size in bytes of the plan's float64 accumulator (the integration state):
+ * sum over arrays of F * prod(2 n_k) doubles, natural frequency order. */
+int omni_accumulator_bytes(omni_plan_t plan, size_t* bytes);
+
+/* Copy the accumulator to / from `buf` (host or device memory, `bytes` must
+ * equal omni_accumulator_bytes).  Synchronous with respect to `stream`.
+ * Together with OMNI_NO_RESET this checkpoints and resumes an integration. */
+int omni_accumulator_get(omni_plan_t plan, void* buf, size_t bytes, void* stream);
+int omni_accumulator_set(omni_plan_t plan, const void* buf, size_t bytes, void* stream);
+
+/* A JSON description of the schedule the planner chose (axis order, fold
+ * moduli, work-group split, kernel variants).  Writes at most len bytes
+ * including the terminating NUL; *needed receives the full length. */
+int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed);
+
+/* Stages timed by a plan made with OMNI_PLAN_TIMING. */
+typedef enum {
+  OMNI_STAGE_FORWARD = 0, /* forward transform + |X|^2 + time integration kernel(s)  */
+  OMNI_STAGE_REDUCE = 1,  /* partial-sum reduction into the float64 accumulator      */
+  OMNI_STAGE_INVERSE = 2  /* inverse transform to visibilities                       */
+} omni_stage;
+
+/* Durations in milliseconds of `stage` over the most recent correlate calls
+ * (oldest first; at most 256 calls are remembered; for a batch plan the
+ * stage spans all arrays).  Waits for the recorded events.  Writes at most
+ * `max` values to ms and the count to *n.  OMNI_E_STATE without
+ * OMNI_PLAN_TIMING. */
+int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n);
+
+/* Release the plan (waits for its last stream first).  NULL is a no-op. */
+int omni_destroy(omni_plan_t plan);
+
+/* Static text for a status code. */
+const char* omni_strerror(int code);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* omni_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMNISCOPE_H */

@@ -1,0 +1,276 @@
+"""Python binding of libomniscope (the MI355X hierarchical-grid correlator).
+
+Thin ctypes marshalling over the C ABI in include/omniscope.h: every step of
+the correlation runs in the library's HIP kernels.  torch is used only to own
+device memory and to name the current HIP stream.  Importing this package
+fails loudly if the library has not been built (``python
+paper_0909_0001_amd/build.py``); there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libomniscope.so")
+
+OMNI_OK = 0
+STATUS = {
+    0: "OMNI_OK",
+    -1: "OMNI_E_INVAL",
+    -2: "OMNI_E_SHAPE",
+    -3: "OMNI_E_GEOM",
+    -4: "OMNI_E_NODEV",
+    -5: "OMNI_E_NOMEM",
+    -6: "OMNI_E_HIP",
+    -7: "OMNI_E_STATE",
+}
+DTYPES = {"cf32": 0, "ci8": 1, "ci4": 2}
+FORMS = {"fp32": 0, "mixed": 1}
+PLAN_HOST_ONLY = 0x1
+PLAN_TIMING = 0x2
+STAGES = {"forward": 0, "reduce": 1, "inverse": 2}
+NO_RESET = 0x1
+NO_FINALIZE = 0x2
+
+#: Every symbol include/omniscope.h declares.
+EXPORTS = [
+    "omni_plan",
+    "omni_plan_batch",
+    "omni_correlate",
+    "omni_correlate_batch",
+    "omni_n_arrays",
+    "omni_vis_shape",
+    "omni_baselines",
+    "omni_accumulator_bytes",
+    "omni_accumulator_get",
+    "omni_accumulator_set",
+    "omni_plan_describe",
+    "omni_stage_times",
+    "omni_destroy",
+    "omni_strerror",
+    "omni_last_error",
+]
+
+
+class OmniError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int),
+        ("form", ctypes.c_int),
+        ("time_block", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class _ArrayDesc(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("dims", ctypes.POINTER(ctypes.c_int32)),
+        ("A", ctypes.POINTER(ctypes.c_double)),
+        ("nchan", ctypes.c_int32),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python paper_0909_0001_amd/build.py` (no CPU fallback exists)"
+        )
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "omni_plan": (ctypes.c_int, [ctypes.POINTER(P), i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), i32,
+                                     ctypes.POINTER(_Opts)]),
+        "omni_plan_batch": (ctypes.c_int, [ctypes.POINTER(P), i32, ctypes.POINTER(_ArrayDesc), ctypes.POINTER(_Opts)]),
+        "omni_correlate": (ctypes.c_int, [P, P, i64, P, P, u32]),
+        "omni_correlate_batch": (ctypes.c_int, [P, ctypes.POINTER(P), i64, ctypes.POINTER(P), P, u32]),
+        "omni_n_arrays": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
+        "omni_vis_shape": (ctypes.c_int, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+        "omni_baselines": (ctypes.c_int, [P, i32, ctypes.POINTER(ctypes.c_double)]),
+        "omni_accumulator_bytes": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "omni_accumulator_get": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
+        "omni_accumulator_set": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
+        "omni_plan_describe": (ctypes.c_int, [P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+        "omni_stage_times": (ctypes.c_int, [P, i32, i32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]),
+        "omni_destroy": (ctypes.c_int, [P]),
+        "omni_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "omni_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(code: int) -> None:
+    if code != OMNI_OK:
+        raise OmniError(code, lib.omni_last_error().decode())
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Plan:
+    """A correlation plan for one array (or a batch of arrays) of a hierarchical grid.
+
+    ``level_dims``: [[n_x, n_y], ...] per level (outer first);  ``A``: [levels, 2, 2]
+    lattice matrices (columns = lattice vectors), or None.
+    """
+
+    def __init__(
+        self,
+        level_dims=None,
+        A=None,
+        nchan: int = 1,
+        dtype: str = "cf32",
+        form: str = "fp32",
+        time_block: int = 0,
+        host_only: bool = False,
+        batch: Sequence[tuple] | None = None,
+        timing: bool = False,
+    ):
+        self._h = ctypes.c_void_p()
+        flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_TIMING if timing else 0)
+        opts = _Opts(DTYPES[dtype], FORMS[form], time_block, flags)
+        self.dtype, self.form = dtype, form
+        self._keep = []
+        if batch is None:
+            dims = np.ascontiguousarray(np.asarray(level_dims, dtype=np.int32).reshape(-1, 2))
+            levels = dims.shape[0]
+            Ap = None
+            if A is not None:
+                Aa = np.ascontiguousarray(np.asarray(A, dtype=np.float64).reshape(levels, 2, 2))
+                self._keep.append(Aa)
+                Ap = Aa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            _check(lib.omni_plan(ctypes.byref(self._h), levels, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 Ap, nchan, ctypes.byref(opts)))
+        else:
+            descs = (_ArrayDesc * len(batch))()
+            for i, (ld, Ab, nc) in enumerate(batch):
+                dims = np.ascontiguousarray(np.asarray(ld, dtype=np.int32).reshape(-1, 2))
+                self._keep.append(dims)
+                descs[i].levels = dims.shape[0]
+                descs[i].dims = dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+                if Ab is not None:
+                    Aa = np.ascontiguousarray(np.asarray(Ab, dtype=np.float64).reshape(dims.shape[0], 2, 2))
+                    self._keep.append(Aa)
+                    descs[i].A = Aa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                descs[i].nchan = nc
+            _check(lib.omni_plan_batch(ctypes.byref(self._h), len(batch), descs, ctypes.byref(opts)))
+        n = ctypes.c_int32()
+        _check(lib.omni_n_arrays(self._h, ctypes.byref(n)))
+        self.n_arrays = n.value
+
+    # -- metadata ---------------------------------------------------------
+    def vis_shape(self, array: int = 0) -> tuple:
+        nd = ctypes.c_int32()
+        shape = (ctypes.c_int64 * 9)()
+        _check(lib.omni_vis_shape(self._h, array, ctypes.byref(nd), shape))
+        return tuple(shape[i] for i in range(nd.value))
+
+    def baselines(self, array: int = 0) -> np.ndarray:
+        shp = self.vis_shape(array)[1:]
+        uv = np.zeros(int(np.prod(shp)) * 2, dtype=np.float64)
+        _check(lib.omni_baselines(self._h, array, uv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return uv.reshape(tuple(shp) + (2,))
+
+    def describe(self) -> str:
+        need = ctypes.c_size_t()
+        _check(lib.omni_plan_describe(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.omni_plan_describe(self._h, buf, need.value, ctypes.byref(need)))
+        return buf.value.decode()
+
+    def stage_times(self, stage: str = "forward", max_calls: int = 256) -> list:
+        """Per-call durations (ms) of a stage over the most recent calls (plans made with timing=True)."""
+        buf = (ctypes.c_float * max_calls)()
+        n = ctypes.c_int32()
+        _check(lib.omni_stage_times(self._h, STAGES[stage], max_calls, buf, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def accumulator_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib.omni_accumulator_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    # -- device calls -----------------------------------------------------
+    def correlate_into(self, volt, T: int, vis, stream=None, flags: int = 0) -> None:
+        """Raw call: ``volt`` / ``vis`` are device pointers (int) or tensors."""
+        vp = volt.data_ptr() if hasattr(volt, "data_ptr") else volt
+        op = vis.data_ptr() if hasattr(vis, "data_ptr") else vis
+        _check(lib.omni_correlate(self._h, vp, T, op, _stream_handle(stream), flags))
+
+    def correlate(self, volt, flags: int = 0, out=None, stream=None):
+        """Correlate device voltages [T, F, N(, 2)] -> complex64 visibilities [F, 2n_1-1, ...]."""
+        import torch
+
+        T = int(volt.shape[0]) if volt is not None else 0
+        if volt is not None:
+            if not volt.is_cuda or not volt.is_contiguous():
+                raise ValueError("voltages must be a contiguous device tensor")
+        if out is None and not (flags & NO_FINALIZE):
+            dev = volt.device if volt is not None else torch.device("cuda")
+            out = torch.empty(self.vis_shape(0), dtype=torch.complex64, device=dev)
+        self.correlate_into(volt if volt is not None else 0, T, out if out is not None else 0, stream, flags)
+        return out
+
+    def correlate_batch(self, volts, flags: int = 0, outs=None, stream=None):
+        import torch
+
+        T = int(volts[0].shape[0])
+        if outs is None and not (flags & NO_FINALIZE):
+            outs = [torch.empty(self.vis_shape(i), dtype=torch.complex64, device=volts[0].device)
+                    for i in range(self.n_arrays)]
+        vp = (ctypes.c_void_p * self.n_arrays)(*[v.data_ptr() for v in volts])
+        op = (ctypes.c_void_p * self.n_arrays)(*([o.data_ptr() for o in outs] if outs else [0] * self.n_arrays))
+        _check(lib.omni_correlate_batch(self._h, vp, T, op, _stream_handle(stream), flags))
+        return outs
+
+    def accumulator_get(self, buf, stream=None) -> None:
+        ptr = buf.data_ptr() if hasattr(buf, "data_ptr") else buf.ctypes.data
+        _check(lib.omni_accumulator_get(self._h, ptr, self.accumulator_bytes(), _stream_handle(stream)))
+
+    def accumulator_set(self, buf, stream=None) -> None:
+        ptr = buf.data_ptr() if hasattr(buf, "data_ptr") else buf.ctypes.data
+        _check(lib.omni_accumulator_set(self._h, ptr, self.accumulator_bytes(), _stream_handle(stream)))
+
+    def close(self) -> None:
+        if self._h:
+            lib.omni_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def strerror(code: int) -> str:
+    return lib.omni_strerror(code).decode()

@@ -1,0 +1,741 @@
+// C ABI of the hierarchical-grid correlator: validation, planning, device
+// resources and launch sequencing.  See include/omniscope.h for the contract.
+#include "omniscope.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace omni {
+hipError_t launch_fused_fp32(int fmt, int cpt, const void* src, int64_t T, int64_t tps, const float2* tw,
+                             double* partial, const FusedP& P, int grid, size_t lds, hipStream_t st);
+hipError_t launch_reduce_scatter(const double* partial, const int32_t* kmap, double* A, int n_slices, int F,
+                                 int n_split, int cells_wg, int64_t M, int accumulate, hipStream_t st);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* dst, const double2* twi,
+                               int64_t outer, int m, int n, int64_t inner, double scale, hipStream_t st);
+hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, double2* tw64, hipStream_t st);
+}  // namespace omni
+
+using omni::AxisP;
+using omni::FusedP;
+using omni::PassP;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+constexpr int kNT = 256;              // threads per fused work-group
+constexpr int kMaxCPT = 32;           // Fourier cells per thread
+constexpr int kCellsMax = kNT * kMaxCPT;
+constexpr size_t kLdsMax = 160 * 1024;
+constexpr int64_t kMaxN = int64_t(1) << 22;
+constexpr size_t kPartialBudget = size_t(512) << 20;
+
+struct ArrayPlan {
+  int levels = 0;
+  std::vector<int> dims;    // original axes, 2 per level
+  std::vector<double> A;    // [levels][2][2] or empty
+  int F = 0;
+  std::vector<int> n;       // axes with n > 1 (or a single axis when N == 1), in order
+  int64_t N = 0, M = 0, n_out = 0;
+  FusedP fp{};
+  int cpt = 0;
+  size_t lds = 0;
+  std::vector<int32_t> kmap;
+  std::vector<int32_t> tw_desc_fwd, tw_desc_inv;
+  std::vector<int> inv_off;  // per axis offset into the float64 inverse table
+  int n_tw_inv = 0;
+  int max_slices = 1;
+  int last_slices = 1;
+  // device resources
+  float2* d_tw32 = nullptr;
+  double2* d_tw64 = nullptr;
+  int32_t* d_kmap = nullptr;
+  double* d_A = nullptr;
+  double* d_partial = nullptr;
+  double2* d_ws[2] = {nullptr, nullptr};
+};
+
+}  // namespace
+
+constexpr int kTimingRing = 256;
+
+struct omni_plan_s {
+  std::vector<ArrayPlan> arrays;
+  bool timing = false;
+  // [call % ring][stage][begin/end]
+  std::vector<hipEvent_t> ev;
+  int64_t n_calls = 0;
+  omni_dtype dtype = OMNI_CF32;
+  omni_form form = OMNI_FORM_FP32;
+  int time_block = 64;
+  bool host_only = false;
+  int device = -1;
+};
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int64_t prod(const std::vector<int>& v) {
+  int64_t p = 1;
+  for (int x : v) p *= x;
+  return p;
+}
+
+// Antenna positions r = sum_l A_l (i_lx, i_ly) must be distinct (Sec. II.D: every grid
+// point has a unique index tuple).  Positions are compared after rounding to a
+// relative grain of 1e-9 of the layout's extent.
+int check_geometry(const ArrayPlan& ap) {
+  if (ap.A.empty()) return OMNI_OK;
+  for (double v : ap.A)
+    if (!std::isfinite(v)) return fail(OMNI_E_GEOM, "lattice matrix has a non-finite entry");
+  const int64_t N = ap.N;
+  if (N > (int64_t(1) << 22)) return OMNI_OK;
+  std::vector<std::pair<double, double>> pos((size_t)N);
+  const int d = (int)ap.dims.size();
+  double ext = 0.0;
+  for (int64_t a = 0; a < N; ++a) {
+    int64_t rem = a;
+    std::vector<int> idx(d);
+    for (int k = d - 1; k >= 0; --k) {
+      idx[k] = (int)(rem % ap.dims[k]);
+      rem /= ap.dims[k];
+    }
+    double x = 0, y = 0;
+    for (int l = 0; l < ap.levels; ++l) {
+      const double* Al = &ap.A[4 * l];
+      x += Al[0] * idx[2 * l] + Al[1] * idx[2 * l + 1];
+      y += Al[2] * idx[2 * l] + Al[3] * idx[2 * l + 1];
+    }
+    pos[(size_t)a] = {x, y};
+    ext = std::max(ext, std::max(std::fabs(x), std::fabs(y)));
+  }
+  const double grain = std::max(ext, 1.0) * 1e-9;
+  std::vector<std::pair<long long, long long>> q(pos.size());
+  for (size_t i = 0; i < pos.size(); ++i)
+    q[i] = {std::llround(pos[i].first / grain), std::llround(pos[i].second / grain)};
+  std::sort(q.begin(), q.end());
+  for (size_t i = 1; i < q.size(); ++i)
+    if (q[i] == q[i - 1]) return fail(OMNI_E_GEOM, "two antennas share a position (index tuples must be unique)");
+  return OMNI_OK;
+}
+
+// Choose the fused schedule.  See plan.hpp for the fold + short-DFT form.
+int plan_fused(ArrayPlan& ap, std::string* why) {
+  const int d = (int)ap.n.size();
+  FusedP& P = ap.fp;
+  std::memset(&P, 0, sizeof(P));
+  P.d = d;
+  P.F = ap.F;
+  P.N = (int32_t)ap.N;
+  std::vector<int> m(d), r(d), L(d), R(d), step(d), E(d);
+  std::vector<int64_t> in_str(d);
+  in_str[d - 1] = 1;
+  for (int k = d - 2; k >= 0; --k) in_str[k] = in_str[k + 1] * ap.n[k + 1];
+  for (int k = 0; k < d; ++k) {
+    m[k] = 2 * ap.n[k];
+    int rr = 1;
+    while (m[k] / rr > omni::kMaxL && (m[k] % (2 * rr)) == 0) rr *= 2;
+    if (m[k] / rr > omni::kMaxL) {
+      *why = "axis length " + std::to_string(ap.n[k]) + " has an odd factor above 16";
+      return OMNI_E_SHAPE;
+    }
+    r[k] = rr;
+  }
+  // Processing order: the outermost axis is loaded and folded first, then the
+  // others from the innermost outwards; the last one is squared.
+  std::vector<int> order;
+  order.push_back(0);
+  for (int k = d - 1; k >= 1; --k) order.push_back(k);
+  // Divide the Fourier cells among work-groups by residue classes, earliest
+  // processed axes first (a split on a later axis repeats the earlier passes in
+  // every work-group of the split).
+  std::vector<int> split(d, 1), split_div(d, 1);
+  int64_t n_split = 1;
+  for (int p = 0; p < d && ap.M / n_split > kCellsMax; ++p) {
+    const int k = order[p];
+    while (ap.M / n_split > kCellsMax && m[k] % (2 * split[k]) == 0) {
+      split[k] *= 2;
+      n_split *= 2;
+    }
+  }
+  if (ap.M / n_split > kCellsMax) {
+    *why = "per-channel Fourier grid cannot be divided into work-group shares of <= 8192 cells";
+    return OMNI_E_SHAPE;
+  }
+  {
+    int64_t div = 1;
+    for (int k = d - 1; k >= 0; --k) {
+      split_div[k] = (int)div;
+      div *= split[k];
+    }
+  }
+  for (int k = 0; k < d; ++k) {
+    r[k] = std::max(r[k], split[k]);
+    L[k] = m[k] / r[k];
+    R[k] = r[k] / split[k];
+    step[k] = split[k];
+    E[k] = R[k] * L[k];
+  }
+  const int last = order[d - 1];
+  // LDS layouts: W holds every axis but the last at its transformed extent; Pw holds all cells.
+  std::vector<int64_t> w_str(d), p_str(d);
+  int64_t ws = 1, pst = 1;
+  for (int k = d - 1; k >= 0; --k) {
+    w_str[k] = ws;
+    ws *= (k == last && d > 1) ? ap.n[k] : E[k];
+    p_str[k] = pst;
+    pst *= E[k];
+  }
+  const int64_t cells = pst;
+  int cpt = 1;
+  while ((int64_t)cpt * kNT < cells) cpt *= 2;
+  if (cpt > kMaxCPT) {
+    *why = "work-group cell share too large";
+    return OMNI_E_SHAPE;
+  }
+  ap.cpt = cpt;
+  P.n_split = (int32_t)n_split;
+  P.cells_wg = (int32_t)cells;
+  P.w_elems = (int32_t)(d > 1 ? ws : 1);
+  // forward twiddle tables w_m^q, one per axis
+  ap.tw_desc_fwd.clear();
+  int off = 0;
+  for (int k = 0; k < d; ++k) {
+    AxisP& a = P.ax[k];
+    a.n = ap.n[k];
+    a.m = m[k];
+    a.r = r[k];
+    a.L = L[k];
+    a.R = R[k];
+    a.rho_step = step[k];
+    a.split = split[k];
+    a.split_div = split_div[k];
+    a.E = E[k];
+    a.w_stride = (int32_t)w_str[k];
+    a.p_stride = (int32_t)p_str[k];
+    a.in_stride = (int32_t)in_str[k];
+    a.tw_off = off;
+    ap.tw_desc_fwd.insert(ap.tw_desc_fwd.end(), {m[k], -1, off});
+    off += m[k];
+  }
+  P.n_tw = off;
+  for (int p = 0; p < d; ++p) {
+    PassP& ps = P.pass[p];
+    const int ax = order[p];
+    ps.axis = ax;
+    int no = 0;
+    int64_t lines = 1;
+    for (int k = d - 1; k >= 0; --k) {
+      if (k == ax) continue;
+      bool done = false;
+      for (int q = 0; q < p; ++q) done = done || order[q] == k;
+      const int ext = done ? E[k] : ap.n[k];
+      ps.ext[no] = ext;
+      ps.w_str[no] = (int32_t)w_str[k];
+      ps.src_str[no] = (int32_t)(p == 0 ? in_str[k] : w_str[k]);
+      ps.p_str[no] = (int32_t)p_str[k];
+      lines *= ext;
+      ++no;
+    }
+    ps.n_other = no;
+    ps.lines = (int32_t)lines;
+    ps.jobs = (int32_t)(lines * R[ax]);
+  }
+  ap.lds = (size_t)P.w_elems * 8 + (size_t)cpt * kNT * 4 + (size_t)P.n_tw * 8;
+  if (ap.lds > kLdsMax) {
+    *why = "LDS working set exceeds 160 KiB";
+    return OMNI_E_SHAPE;
+  }
+  // Cell -> natural frequency index, for every split residue.
+  ap.kmap.assign((size_t)ap.M, 0);
+  std::vector<int64_t> nat_str(d);
+  int64_t s = 1;
+  for (int k = d - 1; k >= 0; --k) {
+    nat_str[k] = s;
+    s *= m[k];
+  }
+  for (int c = 0; c < n_split; ++c) {
+    for (int64_t cell = 0; cell < cells; ++cell) {
+      int64_t rem = cell, nat = 0;
+      for (int k = d - 1; k >= 0; --k) {
+        const int pos = (int)(rem % E[k]);
+        rem /= E[k];
+        const int i = pos / L[k], q = pos % L[k];
+        const int rho = (int)((c / split_div[k]) % split[k]) + i * step[k];
+        const int kappa = r[k] * q + rho;
+        nat += kappa * nat_str[k];
+      }
+      ap.kmap[(size_t)(c * cells + cell)] = (int32_t)nat;
+    }
+  }
+  // inverse twiddles exp(+2 pi i q / m)
+  ap.tw_desc_inv.clear();
+  ap.inv_off.assign(d, 0);
+  int ioff = 0;
+  for (int k = 0; k < d; ++k) {
+    ap.inv_off[k] = ioff;
+    ap.tw_desc_inv.insert(ap.tw_desc_inv.end(), {m[k], +1, ioff});
+    ioff += m[k];
+  }
+  ap.n_tw_inv = ioff;
+  const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
+  ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
+  return OMNI_OK;
+}
+
+int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan) {
+  if (levels < 1 || levels > omni::kMaxD / 2) return fail(OMNI_E_SHAPE, "levels must be in [1, 4]");
+  if (!dims) return fail(OMNI_E_INVAL, "dims is NULL");
+  if (nchan < 1) return fail(OMNI_E_INVAL, "nchan must be >= 1");
+  ap.levels = levels;
+  ap.dims.assign(dims, dims + 2 * levels);
+  ap.F = nchan;
+  int64_t N = 1;
+  for (int v : ap.dims) {
+    if (v < 1) return fail(OMNI_E_SHAPE, "every grid dimension must be >= 1");
+    if (v > 4096) return fail(OMNI_E_SHAPE, "grid dimension above 4096");
+    N *= v;
+    if (N > kMaxN) return fail(OMNI_E_SHAPE, "more than 2^22 antennas");
+  }
+  ap.N = N;
+  if (A) ap.A.assign(A, A + 4 * levels);
+  ap.n.clear();
+  for (int v : ap.dims)
+    if (v > 1) ap.n.push_back(v);
+  if (ap.n.empty()) ap.n.push_back(1);
+  ap.M = 1;
+  ap.n_out = 1;
+  for (int v : ap.n) {
+    ap.M *= 2 * v;
+    ap.n_out *= 2 * v - 1;
+  }
+  int rc = check_geometry(ap);
+  if (rc) return rc;
+  std::string why;
+  rc = plan_fused(ap, &why);
+  if (rc) return fail(rc, why);
+  return OMNI_OK;
+}
+
+void free_array(ArrayPlan& ap) {
+  hipFree(ap.d_tw32);
+  hipFree(ap.d_tw64);
+  hipFree(ap.d_kmap);
+  hipFree(ap.d_A);
+  hipFree(ap.d_partial);
+  hipFree(ap.d_ws[0]);
+  hipFree(ap.d_ws[1]);
+  ap.d_tw32 = nullptr;
+  ap.d_tw64 = nullptr;
+  ap.d_kmap = nullptr;
+  ap.d_A = nullptr;
+  ap.d_partial = nullptr;
+  ap.d_ws[0] = ap.d_ws[1] = nullptr;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? OMNI_E_NOMEM : OMNI_E_HIP,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+int alloc_array(ArrayPlan& ap) {
+  const size_t accA = (size_t)ap.F * ap.M * sizeof(double);
+  HIP_TRY(hipMalloc(&ap.d_tw32, (size_t)ap.fp.n_tw * sizeof(float2)));
+  HIP_TRY(hipMalloc(&ap.d_tw64, (size_t)ap.n_tw_inv * sizeof(double2)));
+  HIP_TRY(hipMalloc(&ap.d_kmap, ap.kmap.size() * sizeof(int32_t)));
+  HIP_TRY(hipMalloc(&ap.d_A, accA));
+  HIP_TRY(hipMalloc(&ap.d_partial, accA * (size_t)ap.max_slices));
+  const size_t ws = (size_t)ap.F * ap.M * sizeof(double2);
+  HIP_TRY(hipMalloc(&ap.d_ws[0], ws));
+  HIP_TRY(hipMalloc(&ap.d_ws[1], ws));
+  HIP_TRY(hipMemcpy(ap.d_kmap, ap.kmap.data(), ap.kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  int32_t* d_desc = nullptr;
+  const size_t nd = std::max(ap.tw_desc_fwd.size(), ap.tw_desc_inv.size());
+  HIP_TRY(hipMalloc(&d_desc, nd * sizeof(int32_t)));
+  hipError_t e = hipMemcpy(d_desc, ap.tw_desc_fwd.data(), ap.tw_desc_fwd.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = omni::launch_twiddles(d_desc, (int)ap.tw_desc_fwd.size() / 3, ap.d_tw32, nullptr, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(d_desc, ap.tw_desc_inv.data(), ap.tw_desc_inv.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = omni::launch_twiddles(d_desc, (int)ap.tw_desc_inv.size() / 3, nullptr, ap.d_tw64, 0);
+  if (e == hipSuccess) e = omni::launch_fill_f64(ap.d_A, (int64_t)ap.F * ap.M, 0.0, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipFree(d_desc);
+  if (e != hipSuccess) return fail(OMNI_E_HIP, std::string("twiddle setup: ") + hipGetErrorString(e));
+  return OMNI_OK;
+}
+
+int check_device(int* dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(OMNI_E_NODEV, "no HIP device");
+  HIP_TRY(hipGetDevice(dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, *dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(OMNI_E_NODEV, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+  return OMNI_OK;
+}
+
+int fmt_of(omni_dtype t) { return (int)t; }
+
+hipEvent_t stage_event(omni_plan_s* p, int stage, int end) {
+  return p->ev[(size_t)(((p->n_calls % kTimingRing) * 3 + stage) * 2 + end)];
+}
+
+// Records the stage's begin event before the first array and its end event after the last.
+void mark(omni_plan_s* p, int stage, int end, bool edge, hipStream_t st) {
+  if (p->timing && edge) hipEventRecord(stage_event(p, stage, end), st);
+}
+
+int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, void* vis, hipStream_t st,
+                    uint32_t flags, int stage) {
+  const bool accumulate = (flags & OMNI_NO_RESET) != 0;
+  if (stage == 0 && T > 0) {
+    FusedP P = ap.fp;
+    const int64_t per_slice_groups = (int64_t)ap.F * P.n_split;
+    int64_t ns = std::max<int64_t>(1, (1024 + per_slice_groups - 1) / per_slice_groups);
+    ns = std::min<int64_t>(ns, ap.max_slices);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 4));
+    const int64_t tps = (T + ns - 1) / ns;
+    ns = (T + tps - 1) / tps;
+    P.n_slices = (int32_t)ns;
+    P.time_block = p->time_block;
+    const int64_t groups = ns * ap.F;
+    P.xcd_groups = (groups % 8 == 0) ? 1 : 0;
+    const int64_t grid = groups * P.n_split;
+    if (grid > INT32_MAX) return fail(OMNI_E_SHAPE, "grid too large");
+    ap.last_slices = (int)ns;
+    HIP_TRY(omni::launch_fused_fp32(fmt_of(p->dtype), ap.cpt, volt, T, tps, ap.d_tw32, ap.d_partial, P, (int)grid,
+                                    ap.lds, st));
+  }
+  if (stage == 1) {
+    if (T > 0) {
+      HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, ap.last_slices, ap.F, ap.fp.n_split,
+                                          ap.fp.cells_wg, ap.M, accumulate ? 1 : 0, st));
+    } else if (!accumulate) {
+      HIP_TRY(omni::launch_fill_f64(ap.d_A, (int64_t)ap.F * ap.M, 0.0, st));
+    }
+  }
+  if (stage == 2 && !(flags & OMNI_NO_FINALIZE)) {
+    const int d = (int)ap.n.size();
+    const void* src = ap.d_A;
+    int64_t outer = ap.F;
+    for (int k = 0; k < d; ++k) {
+      int64_t inner = 1;
+      for (int j = k + 1; j < d; ++j) inner *= 2 * ap.n[j];
+      const bool last = (k == d - 1);
+      void* dst = last ? vis : (void*)ap.d_ws[k & 1];
+      HIP_TRY(omni::launch_inverse_axis(k == 0, last, src, dst, ap.d_tw64 + ap.inv_off[k], outer, 2 * ap.n[k],
+                                        ap.n[k], inner, 1.0 / (double)ap.M, st));
+      src = dst;
+      outer *= 2 * ap.n[k] - 1;
+    }
+  }
+  return OMNI_OK;
+}
+
+int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, const omni_opts* opts) {
+  if (!out) return fail(OMNI_E_INVAL, "out is NULL");
+  *out = nullptr;
+  omni_opts o{OMNI_CF32, OMNI_FORM_FP32, 0, 0};
+  if (opts) o = *opts;
+  if (o.dtype < OMNI_CF32 || o.dtype > OMNI_CI4) return fail(OMNI_E_INVAL, "unknown dtype");
+  if (o.form != OMNI_FORM_FP32 && o.form != OMNI_FORM_MIXED) return fail(OMNI_E_INVAL, "unknown form");
+  if (o.time_block < 0) return fail(OMNI_E_INVAL, "time_block < 0");
+  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING)) return fail(OMNI_E_INVAL, "unknown plan flag");
+  omni_plan_s* p = new (std::nothrow) omni_plan_s;
+  if (!p) return fail(OMNI_E_NOMEM, "host allocation failed");
+  p->dtype = o.dtype;
+  p->form = o.form;
+  p->time_block = o.time_block > 0 ? o.time_block : 64;
+  p->host_only = (o.flags & OMNI_PLAN_HOST_ONLY) != 0;
+  p->timing = (o.flags & OMNI_PLAN_TIMING) != 0 && !p->host_only;
+  p->arrays.resize(arrays.size());
+  for (size_t i = 0; i < arrays.size(); ++i) {
+    int rc = build_array(p->arrays[i], arrays[i].levels, arrays[i].dims, arrays[i].A, arrays[i].nchan);
+    if (rc) {
+      delete p;
+      return rc;
+    }
+  }
+  if (!p->host_only) {
+    int rc = check_device(&p->device);
+    if (rc) {
+      delete p;
+      return rc;
+    }
+    if (p->timing) {
+      p->ev.assign((size_t)kTimingRing * 3 * 2, nullptr);
+      for (auto& e : p->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+          for (auto& e2 : p->ev)
+            if (e2) hipEventDestroy(e2);
+          delete p;
+          return fail(OMNI_E_HIP, "hipEventCreate failed");
+        }
+      }
+    }
+    for (auto& ap : p->arrays) {
+      rc = alloc_array(ap);
+      if (rc) {
+        for (auto& a2 : p->arrays) free_array(a2);
+        delete p;
+        return rc;
+      }
+    }
+  }
+  *out = p;
+  return OMNI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int omni_plan(omni_plan_t* out, int32_t levels, const int32_t* dims, const double* A, int32_t nchan,
+              const omni_opts* opts) {
+  try {
+    omni_array_desc a{levels, dims, A, nchan};
+    return make_plan(out, {a}, opts);
+  } catch (...) {
+    return fail(OMNI_E_NOMEM, "unexpected host exception");
+  }
+}
+
+int omni_plan_batch(omni_plan_t* out, int32_t n_arrays, const omni_array_desc* arrays, const omni_opts* opts) {
+  try {
+    if (n_arrays < 1 || !arrays) return fail(OMNI_E_INVAL, "need at least one array");
+    return make_plan(out, std::vector<omni_array_desc>(arrays, arrays + n_arrays), opts);
+  } catch (...) {
+    return fail(OMNI_E_NOMEM, "unexpected host exception");
+  }
+}
+
+int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, void* const* vis, void* stream,
+                         uint32_t flags) {
+  try {
+    if (!plan) return fail(OMNI_E_INVAL, "plan is NULL");
+    if (plan->host_only) return fail(OMNI_E_STATE, "plan was made with OMNI_PLAN_HOST_ONLY");
+    if (T < 0) return fail(OMNI_E_INVAL, "T < 0");
+    if (flags & ~(OMNI_NO_RESET | OMNI_NO_FINALIZE)) return fail(OMNI_E_INVAL, "unknown correlate flag");
+    const size_t na = plan->arrays.size();
+    if (T > 0 && !volt) return fail(OMNI_E_INVAL, "volt is NULL");
+    if (!(flags & OMNI_NO_FINALIZE) && !vis) return fail(OMNI_E_INVAL, "vis is NULL");
+    for (size_t i = 0; i < na; ++i) {
+      if (T > 0 && !volt[i]) return fail(OMNI_E_INVAL, "a voltage pointer is NULL");
+      if (T > 0 && (reinterpret_cast<uintptr_t>(volt[i]) & 3u))
+        return fail(OMNI_E_INVAL, "voltage pointer not 4-byte aligned");
+      if (!(flags & OMNI_NO_FINALIZE) && !vis[i]) return fail(OMNI_E_INVAL, "a visibility pointer is NULL");
+    }
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (cur != plan->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (int stage = 0; stage < 3; ++stage) {
+      for (size_t i = 0; i < na; ++i) {
+        mark(plan, stage, 0, i == 0, st);
+        int rc = correlate_array(plan, plan->arrays[i], T > 0 ? volt[i] : nullptr, T,
+                                 (flags & OMNI_NO_FINALIZE) ? nullptr : vis[i], st, flags, stage);
+        if (rc) return rc;
+        mark(plan, stage, 1, i + 1 == na, st);
+      }
+    }
+    if (plan->timing) ++plan->n_calls;
+    return OMNI_OK;
+  } catch (...) {
+    return fail(OMNI_E_NOMEM, "unexpected host exception");
+  }
+}
+
+int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream, uint32_t flags) {
+  if (plan && plan->arrays.size() != 1) return fail(OMNI_E_STATE, "batch plan: use omni_correlate_batch");
+  const void* v[1] = {volt};
+  void* o[1] = {vis};
+  return omni_correlate_batch(plan, v, T, o, stream, flags);
+}
+
+int omni_n_arrays(omni_plan_t plan, int32_t* n) {
+  if (!plan || !n) return fail(OMNI_E_INVAL, "NULL argument");
+  *n = (int32_t)plan->arrays.size();
+  return OMNI_OK;
+}
+
+int omni_vis_shape(omni_plan_t plan, int32_t array, int32_t* ndim, int64_t* shape) {
+  if (!plan || !ndim || !shape) return fail(OMNI_E_INVAL, "NULL argument");
+  if (array < 0 || (size_t)array >= plan->arrays.size()) return fail(OMNI_E_INVAL, "array index out of range");
+  const ArrayPlan& ap = plan->arrays[(size_t)array];
+  *ndim = 1 + (int32_t)ap.dims.size();
+  shape[0] = ap.F;
+  for (size_t k = 0; k < ap.dims.size(); ++k) shape[k + 1] = 2 * ap.dims[k] - 1;
+  return OMNI_OK;
+}
+
+int omni_baselines(omni_plan_t plan, int32_t array, double* uv) {
+  if (!plan || !uv) return fail(OMNI_E_INVAL, "NULL argument");
+  if (array < 0 || (size_t)array >= plan->arrays.size()) return fail(OMNI_E_INVAL, "array index out of range");
+  const ArrayPlan& ap = plan->arrays[(size_t)array];
+  if (ap.A.empty()) return fail(OMNI_E_STATE, "plan has no lattice matrices");
+  const int d = (int)ap.dims.size();
+  std::vector<int> out(d);
+  int64_t cells = 1;
+  for (int k = 0; k < d; ++k) {
+    out[k] = 2 * ap.dims[k] - 1;
+    cells *= out[k];
+  }
+  for (int64_t c = 0; c < cells; ++c) {
+    int64_t rem = c;
+    double x = 0, y = 0;
+    std::vector<int> delta(d);
+    for (int k = d - 1; k >= 0; --k) {
+      delta[k] = (int)(rem % out[k]) - (ap.dims[k] - 1);
+      rem /= out[k];
+    }
+    for (int l = 0; l < ap.levels; ++l) {
+      const double* Al = &ap.A[4 * l];
+      x += Al[0] * delta[2 * l] + Al[1] * delta[2 * l + 1];
+      y += Al[2] * delta[2 * l] + Al[3] * delta[2 * l + 1];
+    }
+    uv[2 * c] = x;
+    uv[2 * c + 1] = y;
+  }
+  return OMNI_OK;
+}
+
+int omni_accumulator_bytes(omni_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(OMNI_E_INVAL, "NULL argument");
+  size_t b = 0;
+  for (const auto& ap : plan->arrays) b += (size_t)ap.F * ap.M * sizeof(double);
+  *bytes = b;
+  return OMNI_OK;
+}
+
+static int acc_copy(omni_plan_t plan, void* buf, size_t bytes, void* stream, bool get) {
+  if (!plan || !buf) return fail(OMNI_E_INVAL, "NULL argument");
+  if (plan->host_only) return fail(OMNI_E_STATE, "host-only plan has no accumulator");
+  size_t need = 0;
+  omni_accumulator_bytes(plan, &need);
+  if (bytes != need) return fail(OMNI_E_INVAL, "buffer size must equal omni_accumulator_bytes");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  size_t off = 0;
+  for (auto& ap : plan->arrays) {
+    const size_t b = (size_t)ap.F * ap.M * sizeof(double);
+    char* hb = static_cast<char*>(buf) + off;
+    if (get)
+      HIP_TRY(hipMemcpyAsync(hb, ap.d_A, b, hipMemcpyDefault, st));
+    else
+      HIP_TRY(hipMemcpyAsync(ap.d_A, hb, b, hipMemcpyDefault, st));
+    off += b;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return OMNI_OK;
+}
+
+int omni_accumulator_get(omni_plan_t plan, void* buf, size_t bytes, void* stream) {
+  return acc_copy(plan, buf, bytes, stream, true);
+}
+
+int omni_accumulator_set(omni_plan_t plan, const void* buf, size_t bytes, void* stream) {
+  return acc_copy(plan, const_cast<void*>(buf), bytes, stream, false);
+}
+
+int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) {
+  if (!plan) return fail(OMNI_E_INVAL, "plan is NULL");
+  std::string s = "{\"form\":\"";
+  s += plan->form == OMNI_FORM_FP32 ? "fp32" : "mixed";
+  s += "\",\"dtype\":" + std::to_string((int)plan->dtype) + ",\"time_block\":" + std::to_string(plan->time_block);
+  s += ",\"arrays\":[";
+  for (size_t i = 0; i < plan->arrays.size(); ++i) {
+    const ArrayPlan& ap = plan->arrays[i];
+    const FusedP& P = ap.fp;
+    if (i) s += ",";
+    s += "{\"kernel\":\"fused_fp32\",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) +
+         ",\"F\":" + std::to_string(ap.F) + ",\"n_split\":" + std::to_string(P.n_split) +
+         ",\"cells_wg\":" + std::to_string(P.cells_wg) +
+         ",\"cells_per_thread\":" + std::to_string(ap.cpt) + ",\"lds_bytes\":" + std::to_string(ap.lds) +
+         ",\"max_slices\":" + std::to_string(ap.max_slices) + ",\"axes\":[";
+    for (int k = 0; k < P.d; ++k) {
+      const AxisP& a = P.ax[k];
+      if (k) s += ",";
+      s += "{\"n\":" + std::to_string(a.n) + ",\"m\":" + std::to_string(a.m) + ",\"r\":" + std::to_string(a.r) +
+           ",\"L\":" + std::to_string(a.L) + ",\"R\":" + std::to_string(a.R) +
+           ",\"split\":" + std::to_string(a.split) + "}";
+    }
+    s += "],\"order\":[";
+    for (int p = 0; p < P.d; ++p) s += (p ? "," : "") + std::to_string(P.pass[p].axis);
+    s += "]}";
+  }
+  s += "]}";
+  if (needed) *needed = s.size() + 1;
+  if (buf && len) {
+    const size_t n = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return OMNI_OK;
+}
+
+int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n) {
+  if (!plan || !n || (max > 0 && !ms)) return fail(OMNI_E_INVAL, "NULL argument");
+  if (!plan->timing) return fail(OMNI_E_STATE, "plan was not made with OMNI_PLAN_TIMING");
+  if (stage < 0 || stage > 2) return fail(OMNI_E_INVAL, "unknown stage");
+  const int64_t avail = std::min<int64_t>(plan->n_calls, kTimingRing);
+  const int64_t cnt = std::min<int64_t>(avail, max);
+  for (int64_t j = 0; j < cnt; ++j) {
+    const int64_t call = plan->n_calls - cnt + j;
+    hipEvent_t b = plan->ev[(size_t)(((call % kTimingRing) * 3 + stage) * 2 + 0)];
+    hipEvent_t e = plan->ev[(size_t)(((call % kTimingRing) * 3 + stage) * 2 + 1)];
+    HIP_TRY(hipEventSynchronize(e));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, b, e));
+    ms[j] = t;
+  }
+  *n = (int32_t)cnt;
+  return OMNI_OK;
+}
+
+int omni_destroy(omni_plan_t plan) {
+  if (!plan) return OMNI_OK;
+  if (!plan->host_only) hipDeviceSynchronize();
+  for (auto& e : plan->ev)
+    if (e) hipEventDestroy(e);
+  for (auto& ap : plan->arrays) free_array(ap);
+  delete plan;
+  return OMNI_OK;
+}
+
+const char* omni_strerror(int code) {
+  switch (code) {
+    case OMNI_OK: return "success";
+    case OMNI_E_INVAL: return "invalid argument";
+    case OMNI_E_SHAPE: return "unsupported grid shape";
+    case OMNI_E_GEOM: return "invalid array geometry";
+    case OMNI_E_NODEV: return "no usable gfx950 device";
+    case OMNI_E_NOMEM: return "out of memory";
+    case OMNI_E_HIP: return "HIP runtime error";
+    case OMNI_E_STATE: return "invalid call for this plan";
+    default: return "unknown status";
+  }
+}
+
+const char* omni_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Integration state, inverse transform and twiddle tables (gfx950).
+//
+// After the forward kernels have produced per-slice float64 partial sums of
+// |X_t[kappa]|^2, the accumulator A_f[kappa] = sum_t |X_t[kappa]|^2 (time
+// integration, Sec. II.A) is formed in natural frequency order, and once per
+// integration the visibilities follow from one pruned inverse DFT per axis
+// (Sec. II.A "inverse FFT"; Sec. II.C "inverse transforming"):
+//
+//   V_f[Delta] = (1/M) sum_kappa A_f[kappa] exp(+2 pi i sum_k kappa_k Delta_k / m_k),
+//   Delta_k in [-(n_k-1), n_k-1]  (Sec. II.D, index range after Eq. ProofEq2).
+//
+// Only the 2n_k-1 valid lags of each axis are produced; since every pair
+// separation along axis k lies in that range and m_k = 2 n_k, no lag wraps.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace omni {
+
+// A[f][kmap[c][cell]] (+)= sum_s partial[s][f][c][cell], float64, fixed summation order.
+__global__ void reduce_scatter_kernel(const double* __restrict__ partial, const int32_t* __restrict__ kmap,
+                                      double* __restrict__ A, int n_slices, int F, int n_split, int cells_wg,
+                                      int64_t M, int accumulate) {
+  const int64_t per_f = (int64_t)n_split * cells_wg;  // == M
+  const int64_t total = (int64_t)F * per_f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = i / per_f;
+    const int64_t cc = i - f * per_f;  // c * cells_wg + cell
+    double s = 0.0;
+    for (int sl = 0; sl < n_slices; ++sl) s += partial[((int64_t)sl * F + f) * per_f + cc];
+    double* dst = A + f * M + kmap[cc];
+    *dst = accumulate ? *dst + s : s;
+  }
+}
+
+__global__ void fill_f64_kernel(double* __restrict__ p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// One axis of the inverse transform.  Source [outer][m][inner] (real if REAL_IN,
+// else complex float64), destination [outer][2n-1][inner].  twi[q] =
+// exp(+2 pi i q / m).  Output lag index o corresponds to Delta = o - (n-1).
+// If LAST, the destination is complex64 scaled by `scale`.
+template <bool REAL_IN, bool LAST>
+__global__ void inverse_axis_kernel(const void* __restrict__ src, void* __restrict__ dst,
+                                    const double2* __restrict__ twi, int64_t outer, int m, int n, int64_t inner,
+                                    double scale) {
+  const int nout = 2 * n - 1;
+  const int64_t total = outer * nout * inner;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t in_i = i % inner;
+    const int64_t rest = i / inner;
+    const int o = (int)(rest % nout);
+    const int64_t ou = rest / nout;
+    const int delta = o - (n - 1);
+    const int dm = ((delta % m) + m) % m;  // Delta mod m
+    double re = 0.0, im = 0.0;
+    const int64_t base = ou * m * inner + in_i;
+    int e = 0;  // kappa * Delta mod m, stepped incrementally
+    for (int k = 0; k < m; ++k) {
+      const double2 w = twi[e];
+      if (REAL_IN) {
+        const double a = reinterpret_cast<const double*>(src)[base + (int64_t)k * inner];
+        re = fma(a, w.x, re);
+        im = fma(a, w.y, im);
+      } else {
+        const double2 a = reinterpret_cast<const double2*>(src)[base + (int64_t)k * inner];
+        re = fma(a.x, w.x, fma(-a.y, w.y, re));
+        im = fma(a.x, w.y, fma(a.y, w.x, im));
+      }
+      e += dm;
+      if (e >= m) e -= m;
+    }
+    if (LAST) {
+      reinterpret_cast<float2*>(dst)[i] = make_float2((float)(re * scale), (float)(im * scale));
+    } else {
+      reinterpret_cast<double2*>(dst)[i] = make_double2(re, im);
+    }
+  }
+}
+
+// Twiddle generator, float64 on the device: for each table entry (m, q, sign)
+// w = exp(sign * 2 pi i q / m), evaluated with sincospi on the exact reduced
+// ratio 2q/m.  Writes float32 copies for the forward kernels and float64
+// copies for the inverse.
+__global__ void twiddle_kernel(const int32_t* __restrict__ desc, int n_tables, float2* __restrict__ tw32,
+                               double2* __restrict__ tw64) {
+  // desc: per table {m, sign, offset}
+  for (int t = 0; t < n_tables; ++t) {
+    const int m = desc[3 * t], sign = desc[3 * t + 1], off = desc[3 * t + 2];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
+      double s, c;
+      sincospi(2.0 * (double)q / (double)m, &s, &c);
+      const double im = sign * s;
+      if (tw32) tw32[off + q] = make_float2((float)c, (float)im);
+      if (tw64) tw64[off + q] = make_double2(c, im);
+    }
+  }
+}
+
+static inline int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_reduce_scatter(const double* partial, const int32_t* kmap, double* A, int n_slices, int F,
+                                 int n_split, int cells_wg, int64_t M, int accumulate, hipStream_t st) {
+  const int64_t total = (int64_t)F * M;
+  hipLaunchKernelGGL(reduce_scatter_kernel, dim3(grid_for(total, 256)), dim3(256), 0, st, partial, kmap, A, n_slices,
+                     F, n_split, cells_wg, M, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* dst, const double2* twi,
+                               int64_t outer, int m, int n, int64_t inner, double scale, hipStream_t st) {
+  const int64_t total = outer * (2 * n - 1) * inner;
+  const dim3 g(grid_for(total, 256)), b(256);
+  if (real_in && last)
+    hipLaunchKernelGGL((inverse_axis_kernel<true, true>), g, b, 0, st, src, dst, twi, outer, m, n, inner, scale);
+  else if (real_in)
+    hipLaunchKernelGGL((inverse_axis_kernel<true, false>), g, b, 0, st, src, dst, twi, outer, m, n, inner, scale);
+  else if (last)
+    hipLaunchKernelGGL((inverse_axis_kernel<false, true>), g, b, 0, st, src, dst, twi, outer, m, n, inner, scale);
+  else
+    hipLaunchKernelGGL((inverse_axis_kernel<false, false>), g, b, 0, st, src, dst, twi, outer, m, n, inner, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, double2* tw64, hipStream_t st) {
+  hipLaunchKernelGGL(twiddle_kernel, dim3(4), dim3(256), 0, st, desc_dev, n_tables, tw32, tw64);
+  return hipGetLastError();
+}
+
+}  // namespace omni

@@ -1,0 +1,228 @@
+"""Parity of the HIP correlator with the CPU oracle, through the C ABI.
+
+Tolerances: the float32 form must agree with the exact (float64) oracle to
+1e-5 of the channel's zero-lag power, the mixed form to 2e-3 (per channel,
+max over all lags):  err_f = max_Delta |V_gpu - V_oracle| / V_oracle_f[0].
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0909_0001_amd as omni
+import skysim
+from tests.conftest import load_golden
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "mixed": 2e-3}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dims_of(level_dims):
+    return [int(n) for ld in level_dims for n in ld]
+
+
+def random_raw(dtype, T, F, N, gen, scale=1.0):
+    if dtype == "cf32":
+        return (torch.randn((T, F, N, 2), generator=gen) * scale).float()
+    if dtype == "ci8":
+        return torch.randint(-127, 128, (T, F, N, 2), generator=gen, dtype=torch.int16).to(torch.int8)
+    re = torch.randint(-7, 8, (T, F, N), generator=gen, dtype=torch.int16)
+    im = torch.randint(-7, 8, (T, F, N), generator=gen, dtype=torch.int16)
+    return skysim.pack_ci4(re, im)
+
+
+def oracle_vis(raw_cpu, dtype, level_dims):
+    dims = dims_of(level_dims)
+    T, F = raw_cpu.shape[0], raw_cpu.shape[1]
+    x = oracle.decode(raw_cpu.numpy(), dtype, T, F, math.prod(dims))
+    return oracle.visibilities(x, dims).reshape((F,) + tuple(2 * n - 1 for n in dims))
+
+
+def rel_err(got, ref):
+    F = ref.shape[0]
+    g = got.reshape(F, -1)
+    r = ref.reshape(F, -1)
+    c = r.shape[1] // 2  # centre cell (Delta = 0) of an odd-sized row-major grid
+    z = np.abs(r[:, c])
+    z[z == 0] = 1.0
+    return float(np.max(np.abs(g - r).max(axis=1) / z))
+
+
+def gpu_vis(level_dims, raw_cpu, dtype, form="fp32", F=None, **kw):
+    F = raw_cpu.shape[1] if F is None else F
+    plan = omni.Plan(level_dims, None, F, dtype, form, **kw)
+    vis = plan.correlate(raw_cpu.cuda())
+    torch.cuda.synchronize()
+    return vis.cpu().numpy(), plan
+
+
+# ---------------------------------------------------------------------------
+
+
+def test_paper_example():
+    """Sec. II.C worked example, run as a 1-level 2x3 plan and as a 9x1 plan with real voltages."""
+    g = load_golden("paper_toy_example.txt")
+    h = np.array(g["hypercube"], dtype=np.float32)
+    raw = torch.zeros((1, 1, 6, 2), dtype=torch.float32)
+    raw[0, 0, :, 0] = torch.from_numpy(h.ravel())
+    say("paper example 2x3")
+    vis, _ = gpu_vis([[2, 3]], raw, "cf32")
+    want = np.array(g["vis_2d"])
+    assert np.max(np.abs(vis[0] - want)) <= 1e-5 * 91
+    v1 = np.array(g["voltages_1d"][0], dtype=np.float32)
+    raw = torch.zeros((1, 1, 9, 2), dtype=torch.float32)
+    raw[0, 0, :, 0] = torch.from_numpy(v1)
+    say("paper example 9x1")
+    vis, _ = gpu_vis([[9, 1]], raw, "cf32")
+    assert np.max(np.abs(vis[0, :, 0] - np.array(g["vis_1d"][0]))) <= 1e-5 * 91
+
+
+SHAPES = [
+    [[4, 4]],
+    [[3, 5]],
+    [[7, 1]],
+    [[1, 1]],
+    [[2, 3], [4, 2]],
+    [[8, 8]],
+    [[6, 10]],
+    [[16, 16]],
+    [[32, 32]],
+    [[5, 3], [3, 3]],
+    [[2, 2], [2, 2], [2, 2]],
+    [[4, 4], [4, 4]],
+    [[8, 8], [8, 8]],
+    [[3, 3], [3, 3], [5, 3]],
+]
+
+
+@pytest.mark.parametrize("dtype", ["cf32", "ci8", "ci4"])
+@pytest.mark.parametrize("level_dims", SHAPES, ids=lambda s: "x".join(str(v) for ld in s for v in ld))
+def test_random_shapes(level_dims, dtype):
+    dims = dims_of(level_dims)
+    N = math.prod(dims)
+    gen = torch.Generator().manual_seed(N * 7 + len(dtype))
+    T, F = 37, 3
+    raw = random_raw(dtype, T, F, N, gen)
+    say("shape", level_dims, dtype, "T", T, "F", F)
+    vis, _ = gpu_vis(level_dims, raw, dtype)
+    ref = oracle_vis(raw, dtype, level_dims)
+    assert rel_err(vis, ref) <= TOL["fp32"]
+
+
+def test_grid16_workload():
+    """16x16 unit grid, 1 channel, T=1024 float voltages from 8 point sources + noise."""
+    w = skysim.WORKLOADS["grid16"]
+    raw = skysim.make_voltages(w)
+    say("grid16 workload")
+    vis, _ = gpu_vis(w.level_dims, raw, w.dtype)
+    ref = oracle_vis(raw, w.dtype, w.level_dims)
+    assert rel_err(vis, ref) <= TOL["fp32"]
+
+
+def test_hier8x8_small_many_tiles():
+    """The 8x8-of-8x8 geometry at full N with few samples and a ragged channel count."""
+    w = skysim.WORKLOADS["hier8x8"]
+    raw = skysim.make_voltages(w, T=75, nchan=5)
+    say("hier8x8 T=75 F=5")
+    vis, _ = gpu_vis(w.level_dims, raw, w.dtype)
+    ref = oracle_vis(raw, w.dtype, w.level_dims)
+    assert rel_err(vis, ref) <= TOL["fp32"]
+
+
+def test_hier8x8_full_size():
+    """Full 8x8-of-8x8 workload (F=64, T=4096, ci8): oracle on two channels, invariants on all 64."""
+    w = skysim.WORKLOADS["hier8x8"]
+    say("hier8x8 full size: generating")
+    raw = skysim.make_voltages(w, device="cuda")
+    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, "fp32")
+    say("hier8x8 full size: correlating")
+    vis = plan.correlate(raw)
+    torch.cuda.synchronize()
+    vis_h = vis.cpu().numpy().reshape(w.nchan, -1)
+    xf = raw.double()
+    power = (xf**2).sum(dim=(0, 2, 3)).cpu().numpy()  # sum |x|^2 per channel
+    s = xf.sum(dim=2)  # [T, F, 2] sum over antennas
+    lagsum = (s**2).sum(dim=(0, 2)).cpu().numpy()  # sum_t |sum_a x|^2
+    c = vis_h.shape[1] // 2
+    assert np.max(np.abs(vis_h[:, c] - power) / power) <= TOL["fp32"]
+    assert np.max(np.abs(vis_h.sum(axis=1) - lagsum) / power) <= TOL["fp32"] * 100
+    for f in (0, 37):
+        say("hier8x8 full size: oracle channel", f)
+        sub = raw[:, f : f + 1].cpu()
+        ref = oracle_vis(sub, w.dtype, w.level_dims)
+        assert rel_err(vis_h[f : f + 1], ref) <= TOL["fp32"]
+
+
+def test_empty_time_gives_zero():
+    plan = omni.Plan([[4, 4]], None, 2, "ci8")
+    out = torch.full(plan.vis_shape(), 7.0 + 1j, dtype=torch.complex64, device="cuda")
+    plan.correlate_into(0, 0, out)
+    torch.cuda.synchronize()
+    assert not out.abs().max().item()
+
+
+def test_split_integration_and_resume():
+    """T = T1 + T2 with OMNI_NO_RESET, and a checkpoint/resume of the accumulator, equal one call."""
+    level_dims = [[4, 4], [2, 4]]
+    N = 128
+    gen = torch.Generator().manual_seed(5)
+    raw = random_raw("ci8", 50, 2, N, gen).cuda()
+    plan = omni.Plan(level_dims, None, 2, "ci8")
+    full = plan.correlate(raw).clone()
+    plan.correlate(raw[:20].contiguous(), flags=omni.NO_FINALIZE)
+    part = plan.correlate(raw[20:].contiguous(), flags=omni.NO_RESET)
+    torch.cuda.synchronize()
+    assert torch.allclose(full, part, rtol=0, atol=1e-6 * full.abs().max().item())
+    # checkpoint after 20 samples, resume in a fresh plan
+    plan.correlate(raw[:20].contiguous(), flags=omni.NO_FINALIZE)
+    ck = np.zeros(plan.accumulator_bytes() // 8)
+    plan.accumulator_get(ck)
+    plan2 = omni.Plan(level_dims, None, 2, "ci8")
+    plan2.accumulator_set(ck)
+    resumed = plan2.correlate(raw[20:].contiguous(), flags=omni.NO_RESET)
+    torch.cuda.synchronize()
+    assert torch.allclose(full, resumed, rtol=0, atol=1e-6 * full.abs().max().item())
+
+
+def test_bitwise_deterministic():
+    w = skysim.WORKLOADS["hier8x8"]
+    raw = skysim.make_voltages(w, T=64, nchan=8).cuda()
+    plan = omni.Plan(w.level_dims, None, 8, "ci8")
+    a = plan.correlate(raw).clone()
+    b = plan.correlate(raw).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_side_stream():
+    gen = torch.Generator().manual_seed(9)
+    raw = random_raw("cf32", 16, 2, 64, gen)
+    ref = oracle_vis(raw, "cf32", [[8, 8]])
+    plan = omni.Plan([[8, 8]], None, 2, "cf32")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d = raw.cuda()
+        out = plan.correlate(d, stream=s)
+    s.synchronize()
+    assert rel_err(out.cpu().numpy(), ref) <= TOL["fp32"]
+
+
+def test_ci4_extremes():
+    """All-extreme 4-bit samples (+-7, and -8 which the format can also hold)."""
+    vals = torch.tensor([-8, -7, 7], dtype=torch.int16)
+    gen = torch.Generator().manual_seed(11)
+    T, F, N = 9, 2, 64
+    re = vals[torch.randint(0, 3, (T, F, N), generator=gen)]
+    im = vals[torch.randint(0, 3, (T, F, N), generator=gen)]
+    raw = skysim.pack_ci4(re, im)
+    vis, _ = gpu_vis([[8, 8]], raw, "ci4")
+    assert rel_err(vis, oracle_vis(raw, "ci4", [[8, 8]])) <= TOL["fp32"]
