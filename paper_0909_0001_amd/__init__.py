@@ -82,6 +82,12 @@ class _ArrayDesc(ctypes.Structure):
 
 
 def _load():
+    # torch owns the device memory and streams this library works on, so its HIP
+    # runtime must be the one in the process: import it before the library pulls
+    # in libamdhip64.so.7 by soname (the system copy would otherwise be loaded
+    # first and torch would start a second, device-less runtime).
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python paper_0909_0001_amd/build.py` (no CPU fallback exists)"
