@@ -23,6 +23,8 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* dst, const double2* twi,
                                int64_t outer, int m, int n, int64_t inner, double scale, hipStream_t st);
 hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, double2* tw64, hipStream_t st);
+hipError_t launch_fused8x4_fp32(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16, double* partial,
+                                int F, int n_slices, int time_block, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -53,6 +55,7 @@ struct ArrayPlan {
   std::vector<int> n;       // axes with n > 1 (or a single axis when N == 1), in order
   int64_t N = 0, M = 0, n_out = 0;
   FusedP fp{};
+  int kernel = 0;  // 0: general fused kernel; 1: 8x8x8x8 float32 kernel
   int cpt = 0;
   size_t lds = 0;
   std::vector<int32_t> kmap;
@@ -299,7 +302,30 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
   return OMNI_OK;
 }
 
-int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan) {
+// The 8x8x8x8 float32 kernel: work-group = (slice, channel, residue c of axis 0 mod 8);
+// its cell i (of 32) in thread tid is written at i * 256 + tid and holds
+// line l = tid + 256 (i / 16), output o = i % 16 of the last (axis 1) transform.
+// Positions p in [0,16) along axes 1..3 hold kappa = 2 (p % 8) + p / 8.
+void plan_fused8x4(ArrayPlan& ap) {
+  ap.kernel = 1;
+  FusedP& P = ap.fp;
+  P.n_split = 8;
+  P.cells_wg = 8192;
+  ap.cpt = 32;
+  auto kap = [](int p) { return 2 * (p & 7) + (p >> 3); };
+  for (int c = 0; c < 8; ++c) {
+    for (int i = 0; i < 32; ++i) {
+      for (int tid = 0; tid < 256; ++tid) {
+        const int l = tid + 256 * (i >> 4), o = i & 15;
+        const int k0 = c + 8 * (l >> 8);
+        const int k1 = kap(o), k2 = kap((l >> 4) & 15), k3 = kap(l & 15);
+        ap.kmap[(size_t)(c * 8192 + i * 256 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
+      }
+    }
+  }
+}
+
+int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form) {
   if (levels < 1 || levels > omni::kMaxD / 2) return fail(OMNI_E_SHAPE, "levels must be in [1, 4]");
   if (!dims) return fail(OMNI_E_INVAL, "dims is NULL");
   if (nchan < 1) return fail(OMNI_E_INVAL, "nchan must be >= 1");
@@ -330,6 +356,7 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   std::string why;
   rc = plan_fused(ap, &why);
   if (rc) return fail(rc, why);
+  if (form == OMNI_FORM_FP32 && ap.n == std::vector<int>{8, 8, 8, 8}) plan_fused8x4(ap);
   return OMNI_OK;
 }
 
@@ -409,7 +436,18 @@ void mark(omni_plan_s* p, int stage, int end, bool edge, hipStream_t st) {
 int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, void* vis, hipStream_t st,
                     uint32_t flags, int stage) {
   const bool accumulate = (flags & OMNI_NO_RESET) != 0;
-  if (stage == 0 && T > 0) {
+  if (stage == 0 && T > 0 && ap.kernel == 1) {
+    // three 48 KiB work-groups fit one CU: aim for two full rounds over 256 CUs
+    const int64_t per_slice_groups = (int64_t)ap.F * 8;
+    int64_t ns = std::max<int64_t>(1, (1536 + per_slice_groups / 2) / per_slice_groups);
+    ns = std::min<int64_t>(ns, ap.max_slices);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
+    const int64_t tps = (T + ns - 1) / ns;
+    ns = (T + tps - 1) / tps;
+    ap.last_slices = (int)ns;
+    HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
+                                       p->time_block, st));
+  } else if (stage == 0 && T > 0) {
     FusedP P = ap.fp;
     const int64_t per_slice_groups = (int64_t)ap.F * P.n_split;
     int64_t ns = std::max<int64_t>(1, (1024 + per_slice_groups - 1) / per_slice_groups);
@@ -471,7 +509,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   p->timing = (o.flags & OMNI_PLAN_TIMING) != 0 && !p->host_only;
   p->arrays.resize(arrays.size());
   for (size_t i = 0; i < arrays.size(); ++i) {
-    int rc = build_array(p->arrays[i], arrays[i].levels, arrays[i].dims, arrays[i].A, arrays[i].nchan);
+    int rc = build_array(p->arrays[i], arrays[i].levels, arrays[i].dims, arrays[i].A, arrays[i].nchan, p->form);
     if (rc) {
       delete p;
       return rc;
@@ -667,7 +705,7 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
     const ArrayPlan& ap = plan->arrays[i];
     const FusedP& P = ap.fp;
     if (i) s += ",";
-    s += "{\"kernel\":\"fused_fp32\",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) +
+    s += std::string("{\"kernel\":\"") + (ap.kernel == 1 ? "fused8x4_fp32" : "fused_fp32") + "\",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) +
          ",\"F\":" + std::to_string(ap.F) + ",\"n_split\":" + std::to_string(P.n_split) +
          ",\"cells_wg\":" + std::to_string(P.cells_wg) +
          ",\"cells_per_thread\":" + std::to_string(ap.cpt) + ",\"lds_bytes\":" + std::to_string(ap.lds) +
