@@ -25,6 +25,8 @@ hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* d
 hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, double2* tw64, hipStream_t st);
 hipError_t launch_fused8x4_fp32(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16, double* partial,
                                 int F, int n_slices, int time_block, hipStream_t st);
+hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16,
+                                 double* partial, int F, int n_slices, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -55,7 +57,7 @@ struct ArrayPlan {
   std::vector<int> n;       // axes with n > 1 (or a single axis when N == 1), in order
   int64_t N = 0, M = 0, n_out = 0;
   FusedP fp{};
-  int kernel = 0;  // 0: general fused kernel; 1: 8x8x8x8 float32 kernel
+  int kernel = 0;  // 0: general fused kernel; 1: 8x8x8x8 float32 kernel; 2: 8x8x8x8 mixed (MFMA) kernel
   int cpt = 0;
   size_t lds = 0;
   std::vector<int32_t> kmap;
@@ -325,7 +327,32 @@ void plan_fused8x4(ArrayPlan& ap) {
   }
 }
 
-int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form) {
+// The 8x8x8x8 mixed-precision kernel: work-group = (slice, channel, residue h of
+// kappa_3 mod 2), 512 threads; cell idx (of 64) of thread tid is written at
+// idx * 512 + tid.  With wave = tid / 64, lane = tid % 64, col = lane % 32,
+// hh = lane / 32 and idx = ((cc * 2 + tt) * 2 + i') * 4 + j it holds
+// kappa_0 = 8 i' + 4 hh + j, kappa_1 = 2 wave + tt, kappa_2 = 4 cc + col % 4,
+// kappa_3 = 2 (col / 4) + h.
+void plan_fused8x4_mixed(ArrayPlan& ap) {
+  ap.kernel = 2;
+  FusedP& P = ap.fp;
+  P.n_split = 2;
+  P.cells_wg = 32768;
+  ap.cpt = 64;
+  for (int h = 0; h < 2; ++h) {
+    for (int idx = 0; idx < 64; ++idx) {
+      for (int tid = 0; tid < 512; ++tid) {
+        const int wave = tid >> 6, lane = tid & 63, col = lane & 31, hh = lane >> 5;
+        const int cc = idx >> 4, tt = (idx >> 3) & 1, ip = (idx >> 2) & 1, j = idx & 3;
+        const int k0 = 8 * ip + 4 * hh + j, k1 = 2 * wave + tt, k2 = 4 * cc + (col & 3), k3 = 2 * (col >> 2) + h;
+        ap.kmap[(size_t)(h * 32768 + idx * 512 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
+      }
+    }
+  }
+}
+
+int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form,
+                omni_dtype dtype) {
   if (levels < 1 || levels > omni::kMaxD / 2) return fail(OMNI_E_SHAPE, "levels must be in [1, 4]");
   if (!dims) return fail(OMNI_E_INVAL, "dims is NULL");
   if (nchan < 1) return fail(OMNI_E_INVAL, "nchan must be >= 1");
@@ -356,7 +383,9 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   std::string why;
   rc = plan_fused(ap, &why);
   if (rc) return fail(rc, why);
-  if (form == OMNI_FORM_FP32 && ap.n == std::vector<int>{8, 8, 8, 8}) plan_fused8x4(ap);
+  const bool eight4 = ap.n == std::vector<int>{8, 8, 8, 8};
+  if (form == OMNI_FORM_FP32 && eight4) plan_fused8x4(ap);
+  if (form == OMNI_FORM_MIXED && eight4 && dtype != OMNI_CF32) plan_fused8x4_mixed(ap);
   return OMNI_OK;
 }
 
@@ -447,6 +476,16 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     ap.last_slices = (int)ns;
     HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
                                        p->time_block, st));
+  } else if (stage == 0 && T > 0 && ap.kernel == 2) {
+    // two 64 KiB work-groups per CU: one round of 512 work-groups
+    const int64_t per_slice_groups = (int64_t)ap.F * 2;
+    int64_t ns = std::max<int64_t>(1, (512 + per_slice_groups / 2) / per_slice_groups);
+    ns = std::min<int64_t>(ns, ap.max_slices);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
+    const int64_t tps = (T + ns - 1) / ns;
+    ns = (T + tps - 1) / tps;
+    ap.last_slices = (int)ns;
+    HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, st));
   } else if (stage == 0 && T > 0) {
     FusedP P = ap.fp;
     const int64_t per_slice_groups = (int64_t)ap.F * P.n_split;
@@ -509,7 +548,8 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   p->timing = (o.flags & OMNI_PLAN_TIMING) != 0 && !p->host_only;
   p->arrays.resize(arrays.size());
   for (size_t i = 0; i < arrays.size(); ++i) {
-    int rc = build_array(p->arrays[i], arrays[i].levels, arrays[i].dims, arrays[i].A, arrays[i].nchan, p->form);
+    int rc = build_array(p->arrays[i], arrays[i].levels, arrays[i].dims, arrays[i].A, arrays[i].nchan, p->form,
+                         p->dtype);
     if (rc) {
       delete p;
       return rc;
@@ -705,7 +745,7 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
     const ArrayPlan& ap = plan->arrays[i];
     const FusedP& P = ap.fp;
     if (i) s += ",";
-    s += std::string("{\"kernel\":\"") + (ap.kernel == 1 ? "fused8x4_fp32" : "fused_fp32") + "\",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) +
+    s += std::string("{\"kernel\":\"") + (ap.kernel == 1 ? "fused8x4_fp32" : ap.kernel == 2 ? "fused8x4_mixed" : "fused_fp32") + "\",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) +
          ",\"F\":" + std::to_string(ap.F) + ",\"n_split\":" + std::to_string(P.n_split) +
          ",\"cells_wg\":" + std::to_string(P.cells_wg) +
          ",\"cells_per_thread\":" + std::to_string(ap.cpt) + ",\"lds_bytes\":" + std::to_string(ap.lds) +

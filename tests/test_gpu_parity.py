@@ -226,3 +226,52 @@ def test_ci4_extremes():
     raw = skysim.pack_ci4(re, im)
     vis, _ = gpu_vis([[8, 8]], raw, "ci4")
     assert rel_err(vis, oracle_vis(raw, "ci4", [[8, 8]])) <= TOL["fp32"]
+
+
+# ---------------------------------------------------------------------------
+# Mixed form (float16 MFMA stages with float32 accumulation).
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("dtype", ["ci8", "ci4"])
+def test_mixed_hier8x8_small(dtype):
+    """8x8-of-8x8 geometry, few samples, ragged channel count, both integer formats."""
+    w = skysim.WORKLOADS["hier8x8-mixed"]
+    gen = torch.Generator().manual_seed(17)
+    raw = random_raw(dtype, 75, 5, w.N, gen)
+    say("mixed hier8x8 T=75 F=5", dtype)
+    vis, plan = gpu_vis(w.level_dims, raw, dtype, "mixed")
+    assert '"fused8x4_mixed"' in plan.describe()
+    ref = oracle_vis(raw, dtype, w.level_dims)
+    err = rel_err(vis, ref)
+    say("mixed error", err)
+    assert err <= TOL["mixed"]
+
+
+def test_mixed_sky_workload_full_size():
+    """The full mixed-form workload (F=64, T=4096, ci8 sky + noise): oracle on two channels, zero lag on all."""
+    w = skysim.WORKLOADS["hier8x8-mixed"]
+    say("mixed full size: generating")
+    raw = skysim.make_voltages(w, device="cuda")
+    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, "mixed")
+    assert '"fused8x4_mixed"' in plan.describe()
+    vis = plan.correlate(raw)
+    torch.cuda.synchronize()
+    vis_h = vis.cpu().numpy().reshape(w.nchan, -1)
+    power = (raw.double() ** 2).sum(dim=(0, 2, 3)).cpu().numpy()
+    c = vis_h.shape[1] // 2
+    assert np.max(np.abs(vis_h[:, c] - power) / power) <= TOL["mixed"]
+    for f in (3, 60):
+        say("mixed full size: oracle channel", f)
+        ref = oracle_vis(raw[:, f : f + 1].cpu(), w.dtype, w.level_dims)
+        err = rel_err(vis_h[f : f + 1], ref)
+        say("mixed full size error", f, err)
+        assert err <= TOL["mixed"]
+
+
+def test_mixed_other_shapes_fall_back_to_fp32_kernel():
+    gen = torch.Generator().manual_seed(23)
+    raw = random_raw("ci8", 12, 2, 36, gen)
+    vis, plan = gpu_vis([[6, 6]], raw, "ci8", "mixed")
+    assert '"fused_fp32"' in plan.describe()
+    assert rel_err(vis, oracle_vis(raw, "ci8", [[6, 6]])) <= TOL["fp32"]
