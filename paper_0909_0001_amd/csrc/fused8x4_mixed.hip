@@ -23,6 +23,9 @@
 // In every pass the 32 lines of a tile are ordered with the next pass'
 // contracted axis fastest, so each lane stores 4 consecutive values of it with
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte read.
+// The next sample's input is prefetched during the current one, and P3/P4 are
+// software-pipelined over a double-buffered chunk buffer (six barriers per
+// sample).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -49,38 +52,6 @@ __device__ __forceinline__ float embed(float2 w, bool im_out, bool im_in) {
   return !im_out ? (!im_in ? w.x : -w.y) : (!im_in ? w.y : w.x);
 }
 
-// 8 samples of one component (0 = re, 1 = im) along i3, from the sample format.
-template <int FMT>
-__device__ __forceinline__ half8 load_line(const void* __restrict__ base, int64_t sample, int comp);
-
-template <>
-__device__ __forceinline__ half8 load_line<1>(const void* __restrict__ base, int64_t sample, int comp) {
-  const uint4 v = *reinterpret_cast<const uint4*>(reinterpret_cast<const int8_t*>(base) + 2 * sample);
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-  half8 r;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint32_t word = w[i >> 1];
-    const int sh = 16 * (i & 1) + 8 * comp;
-    r[i] = (_Float16)(float)(int8_t)(word >> sh);
-  }
-  return r;
-}
-
-template <>
-__device__ __forceinline__ half8 load_line<2>(const void* __restrict__ base, int64_t sample, int comp) {
-  const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const int8_t*>(base) + sample);
-  const uint32_t w[2] = {v.x, v.y};
-  half8 r;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int8_t byte = (int8_t)(w[i >> 2] >> (8 * (i & 3)));
-    const int val = comp == 0 ? (byte >> 4) : ((int8_t)(byte << 4) >> 4);
-    r[i] = (_Float16)(float)val;
-  }
-  return r;
-}
-
 __device__ __forceinline__ void store4(_Float16* p, float a, float b, float c, float d) {
   half4 v;
   v[0] = (_Float16)a;
@@ -90,18 +61,71 @@ __device__ __forceinline__ void store4(_Float16* p, float a, float b, float c, f
   *reinterpret_cast<half4*>(p) = v;
 }
 
+// Raw input of one P1 operand: 8 samples along i3 (16 bytes of ci8, 8 of ci4).
+template <int FMT>
+struct Raw;
+template <>
+struct Raw<1> {
+  uint4 v;
+  __device__ __forceinline__ void load(const void* __restrict__ base, int64_t sample) {
+    v = *reinterpret_cast<const uint4*>(reinterpret_cast<const int8_t*>(base) + 2 * sample);
+  }
+  __device__ __forceinline__ half8 to_half(int comp) const {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    half8 r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = (_Float16)(float)(int8_t)(w[i >> 1] >> (16 * (i & 1) + 8 * comp));
+    return r;
+  }
+};
+template <>
+struct Raw<2> {
+  uint2 v;
+  __device__ __forceinline__ void load(const void* __restrict__ base, int64_t sample) {
+    v = *reinterpret_cast<const uint2*>(reinterpret_cast<const int8_t*>(base) + sample);
+  }
+  __device__ __forceinline__ half8 to_half(int comp) const {
+    const uint32_t w[2] = {v.x, v.y};
+    half8 r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int8_t byte = (int8_t)(w[i >> 2] >> (8 * (i & 3)));
+      r[i] = (_Float16)(float)(comp == 0 ? (byte >> 4) : ((int8_t)(byte << 4) >> 4));
+    }
+    return r;
+  }
+};
+
+// LDS layouts (float16).  A 16-byte operand row holds the 8 values of one
+// component along the axis the next pass contracts.  Rows are XOR-swizzled
+// within their block so that the 8-byte stores of a pass and the 16-byte
+// operand loads of the next one both spread over the 64 LDS banks (chosen
+// with a bank model of the six access patterns: at most 2-way conflicts).
+//   L2 [comp][i0][q][i1 ^ (q/2) ^ 4 comp][i2]   (P1 -> P2)
+//   L3 [comp][q][k2][i0 ^ (k2/2 % 8)][i1]       (P2 -> P3)
+//   L4 [buf][comp][k1][(4 q + k2c) ^ k1][i0]    (P3 -> P4)
+__device__ __forceinline__ int l2_row(int comp, int i0, int q, int i1) {
+  return ((comp * 8 + i0) * 8 + q) * 8 + (i1 ^ (q >> 1) ^ (4 * comp));
+}
+__device__ __forceinline__ int l3_row(int comp, int q, int k2, int i0) {
+  return ((comp * 8 + q) * 16 + k2) * 8 + (i0 ^ ((k2 >> 1) & 7));
+}
+__device__ __forceinline__ int l4_row(int comp, int k1, int q, int k2c) {
+  return (comp * 16 + k1) * 32 + ((4 * q + k2c) ^ k1);
+}
+
 }  // namespace f8m
 
 template <int FMT>
 __global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* __restrict__ src, int64_t T,
-                                                                 int64_t t_per_slice,
-                                                                 const float2* __restrict__ tw16,
-                                                                 double* __restrict__ partial, int F,
-                                                                 int xcd_groups) {
+                                                                    int64_t t_per_slice,
+                                                                    const float2* __restrict__ tw16,
+                                                                    double* __restrict__ partial, int F,
+                                                                    int xcd_groups) {
   using namespace f8m;
-  __shared__ _Float16 L2[2 * 8 * 8 * 8 * 8];   // [comp][i0][i1][q][i2]
-  __shared__ _Float16 L3[2 * 8 * 8 * 16 * 8];  // [comp][i0][q][k2][i1]
-  __shared__ _Float16 L4[2 * 16 * 8 * 4 * 8];  // [comp][k1][q][k2c][i0]
+  __shared__ _Float16 L2[2 * 8 * 8 * 8 * 8];
+  __shared__ _Float16 L3[2 * 8 * 16 * 8 * 8];
+  __shared__ _Float16 L4[2][2 * 16 * 32 * 8];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -119,14 +143,13 @@ __global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* 
   const int f = grp % F;
   const int s = grp / F;
 
-  // DFT operands (identical register contents serve as the B operand of
-  // Y^T = X^T W^T and as the A operand of Y = W X).
+  // DFT operand registers: the same contents serve as the B operand of
+  // Y^T = X^T W^T (passes 1-3) and as the A operand of Y = W X (pass 4).
   half8 Wf_hi, Wf_lo;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int k = 8 * hh + i, j = k & 7;
-    const int o = col & 15;
-    const float2 w = tw16[(o * j) & 15];
+    const float2 w = tw16[((col & 15) * j) & 15];
     const float v = 0.125f * embed(w, col >= 16, k >= 8);
     const _Float16 hi = (_Float16)v;
     Wf_hi[i] = hi;
@@ -138,86 +161,96 @@ __global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* 
   for (int i = 0; i < CPL; ++i) acc[i] = 0.f;
   const floatx16 zero = {};
 
+  // P1 tiles of this wave: T1 = 2 wave + tt; line r = col -> (i0, i1, i2) = (wave, 4 tt + r/8, r%8)
+  const int p1_off = ((wave * 8 + (col >> 3)) * 8 + (col & 7)) * 8;  // + 4*8*8 samples for tt = 1
   const int64_t t0 = (int64_t)s * t_per_slice;
   const int64_t t1 = min(T, t0 + t_per_slice);
+  Raw<FMT> raw0, raw1;
+  if (t0 < t1) {
+    const int64_t tile = (t0 * F + f) * 4096;
+    raw0.load(src, tile + p1_off);
+    raw1.load(src, tile + p1_off + 256);
+  }
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t tile = (t * F + f) * 4096;
-    // ---- P1: axis 3, tiles 2 wave + tt (of 16): line r -> (i0, i1, i2) = (T1/2, 4(T1%2) + r/8, r%8)
+    // ---- P1: axis 3 from the prefetched samples; prefetch the next sample
+    {
+      const half8 a0 = raw0.to_half(hh), a1 = raw1.to_half(hh);
+      if (t + 1 < t1) {
+        const int64_t tile = ((t + 1) * F + f) * 4096;
+        raw0.load(src, tile + p1_off);
+        raw1.load(src, tile + p1_off + 256);
+      }
+      // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
+      const bool keep = (col & 1) == h;
+      const int comp = col >> 4, q = (col & 15) >> 1;
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int T1 = 2 * wave + tt;
-      const int i0 = T1 >> 1, i1 = 4 * (T1 & 1) + (col >> 3), i2 = col & 7;
-      const half8 a = load_line<FMT>(src, tile + ((i0 * 8 + i1) * 8 + i2) * 8, hh);
-      floatx16 d = mfma(a, Wf_hi, zero);
-      d = mfma(a, Wf_lo, d);
-      // column col: kappa_3 = col % 16 (re for col < 16, im otherwise); only kappa_3 = 2q + h is kept.
-      // rows -> i1 = 4(T1%2) + i, i2 = 4hh + j
-      if (((col & 15) & 1) == h) {
-        const int comp = col >> 4, q = (col & 15) >> 1;
+      for (int tt = 0; tt < 2; ++tt) {
+        floatx16 d = mfma(tt ? a1 : a0, Wf_hi, zero);
+        d = mfma(tt ? a1 : a0, Wf_lo, d);
+        if (keep) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int ii1 = 4 * (T1 & 1) + i;
-          store4(&L2[(((comp * 8 + i0) * 8 + ii1) * 8 + q) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-                 d[4 * i + 3]);
+          for (int i = 0; i < 4; ++i)
+            store4(&L2[l2_row(comp, wave, q, 4 * tt + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+                   d[4 * i + 3]);
         }
       }
     }
     __syncthreads();
-    // ---- P2: axis 2, lines (i0, q, i1), i1 fastest; tiles 2 wave + tt: i0 = T2/2, q = 4(T2%2) + r/8, i1 = r%8
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int T2 = 2 * wave + tt;
-      const int i0 = T2 >> 1, q = 4 * (T2 & 1) + (col >> 3), i1 = col & 7;
-      const half8 a = *reinterpret_cast<const half8*>(&L2[(((hh * 8 + i0) * 8 + i1) * 8 + q) * 8]);
-      floatx16 d = mfma(a, Wf_hi, zero);
-      d = mfma(a, Wf_lo, d);
-      // column col -> (comp, k2); rows -> q = 4(T2%2) + i, i1 = 4hh + j
+    // ---- P2: axis 2; tile T2 = 2 wave + tt: lines (i0, q, i1) = (wave, 4 tt + r/8, r%8)
+    {
+      const int i1 = col & 7, qa = col >> 3;
       const int comp = col >> 4, k2 = col & 15;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int qq = 4 * (T2 & 1) + i;
-        store4(&L3[(((comp * 8 + i0) * 8 + qq) * 16 + k2) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-               d[4 * i + 3]);
+      for (int tt = 0; tt < 2; ++tt) {
+        const half8 a = *reinterpret_cast<const half8*>(&L2[l2_row(hh, wave, 4 * tt + qa, i1) * 8]);
+        floatx16 d = mfma(a, Wf_hi, zero);
+        d = mfma(a, Wf_lo, d);
+        // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          store4(&L3[l3_row(comp, 4 * tt + i, k2, wave) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+                 d[4 * i + 3]);
       }
     }
+    __syncthreads();
+    // ---- P3 (axis 1) for kappa_2 chunk cc into L4[cc & 1]: tile = wave, lines (q, k2c, i0) with
+    //      (q, k2c) index = 4 wave + r/8, i0 = r%8
+    auto pass3 = [&](int cc) {
+      const int idx = 4 * wave + (col >> 3);
+      const int q = idx >> 2, k2c = idx & 3, i0 = col & 7;
+      const half8 a = *reinterpret_cast<const half8*>(&L3[l3_row(hh, q, 4 * cc + k2c, i0) * 8]);
+      floatx16 d = mfma(a, Wf_hi, zero);
+      d = mfma(a, Wf_lo, d);
+      const int comp = col >> 4, k1 = col & 15;
+      _Float16* L = L4[cc & 1];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int id2 = 4 * wave + i;
+        store4(&L[l4_row(comp, k1, id2 >> 2, id2 & 3) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+               d[4 * i + 3]);
+      }
+    };
+    pass3(0);
     __syncthreads();
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
-      // ---- P3: axis 1 for kappa_2 in [4cc, 4cc+4): lines (i0, q, k2c), i0 fastest; tile = wave:
-      //      (q, k2c) index = 4 wave + r/8, i0 = r%8
-      {
-        const int idx = 4 * wave + (col >> 3);
-        const int q = idx >> 2, k2c = idx & 3, i0 = col & 7;
-        const half8 a =
-            *reinterpret_cast<const half8*>(&L3[(((hh * 8 + i0) * 8 + q) * 16 + 4 * cc + k2c) * 8]);
-        floatx16 d = mfma(a, Wf_hi, zero);
-        d = mfma(a, Wf_lo, d);
-        // column -> (comp, k1); rows -> (q, k2c) index = 4 wave + i, i0 = 4hh + j
-        const int comp = col >> 4, k1 = col & 15;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int id2 = 4 * wave + i;
-          store4(&L4[(((comp * 16 + k1) * 8 + (id2 >> 2)) * 4 + (id2 & 3)) * 8 + 4 * hh], d[4 * i], d[4 * i + 1],
-                 d[4 * i + 2], d[4 * i + 3]);
-        }
-      }
-      __syncthreads();
-      // ---- P4: axis 0 on lines (k1, q, k2c); tile T4 = 2 wave + tt: k1 = T4, q = r/4, k2c = r%4
+      // ---- P4: axis 0 on lines (k1, q, k2c) = (2 wave + tt, r/4, r%4); square and accumulate
+      const _Float16* L = L4[cc & 1];
 #pragma unroll
       for (int tt = 0; tt < 2; ++tt) {
-        const int k1 = 2 * wave + tt, q = col >> 2, k2c = col & 3;
-        const half8 bop = *reinterpret_cast<const half8*>(&L4[(((hh * 16 + k1) * 8 + q) * 4 + k2c) * 8]);
+        const half8 bop = *reinterpret_cast<const half8*>(&L[l4_row(hh, 2 * wave + tt, col >> 2, col & 3) * 8]);
         floatx16 d = mfma(Wf_hi, bop, zero);
         d = mfma(Wf_lo, bop, d);
         // rows: 4hh + j (re), 8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im)
-        const int base = (cc * 2 + tt) * 8;
+        const int base = cc * 16 + tt * 8;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
           acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
         }
       }
-      __syncthreads();
+      if (cc < 3) pass3(cc + 1);
+      if (cc < 3) __syncthreads();
     }
   }
   // |X|^2 carried 8^-8 = 2^-24 from the four scaled stages
