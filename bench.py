@@ -38,107 +38,86 @@ def fp32_form_flops_per_as(dims) -> float:
     return sum((2**p) * 10 * math.log2(mp) for p, mp in enumerate(m)) + 4 * 2**d
 
 
-def cpu_oracle_baseline(raw_cpu, w, budget_s=10.0, max_channels=8):
-    """Time the oracle (as it stands) on whole channels until ~budget_s of work."""
-    import numpy as np
+def mixed_form_flops_per_as(dims) -> float:
+    """Fixed mixed-form MFMA work per antenna-sample: 2 (hi + lo twiddles) x 8 (real-embedded complex
+    MAC = 8 flops) x sum_p 2^p c(m_(p)), axes by decreasing padded length; c(m) = m for m <= 32 (dense
+    pruned DFT), else min over r1 r2 = m of r1 + 2 r2 + 2."""
+    m = sorted((2 * n for n in dims if n > 1), reverse=True)
 
-    import oracle
+    def c(mm):
+        if mm <= 32:
+            return mm
+        return min(r1 + 2 * (mm // r1) + 2 for r1 in range(2, mm) if mm % r1 == 0)
 
-    T = raw_cpu.shape[0]
-    done, t_used, results = 0, 0.0, {}
-    while done < max_channels and (t_used < budget_s or done == 0):
-        f = done
-        sub = raw_cpu[:, f : f + 1].contiguous().numpy()
-        t0 = time.perf_counter()
-        x = oracle.decode(sub, w.dtype, T, 1, w.N)
-        v = oracle.visibilities(x, w.dims)
-        t_used += time.perf_counter() - t0
-        results[f] = v.reshape(-1)
-        done += 1
-        log(f"cpu oracle: channel {f} done, {t_used:.1f} s so far")
-    rate = w.N * T * done / t_used
-    return rate, done, t_used, results
+    return 16 * sum((2**p) * c(mp) for p, mp in enumerate(m))
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hier8x8")
-    ap.add_argument("--form", default=None, help="fp32 | mixed (default: the workload's)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
-    args = ap.parse_args()
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is unchanged."""
+    import hashlib
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(
-            "bench.py: the correlator runs on one GPU; a multi-GPU run (channels or time blocks sharded one per "
-            f"GPU) is not part of this build (asked for --gpus {args.gpus}, WORLD_SIZE {world})",
-            file=sys.stderr,
-        )
-        return 2
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_0909_0001_amd", "csrc", rec.get("source", ""))
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
+        return None
+    return float(rec["traffic_bytes"])
 
-    import numpy as np
+
+def copy_calibration() -> int:
+    """A plain 1 GiB device copy (x3) for calibrating FETCH_SIZE / WRITE_SIZE against known bytes."""
     import torch
 
-    import paper_0909_0001_amd as omni
-    import skysim
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x 1 GiB device copies done")
+    return 0
 
-    w = skysim.WORKLOADS[args.workload]
-    form = args.form or w.form
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    log(f"bench: workload {w.name} N={w.N} F={w.nchan} T={w.T} {w.dtype} form={form}; generating voltages")
-    raw = skysim.make_voltages(w, device=dev)
-    torch.cuda.synchronize()
-    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form, timing=True)
-    desc = json.loads(plan.describe())
-    kernel_fwd = desc["arrays"][0]["kernel"] + "_kernel"
-    log("bench: plan " + plan.describe())
-    vis = torch.empty(plan.vis_shape(), dtype=torch.complex64, device=dev)
-    stream = torch.cuda.current_stream()
 
-    for i in range(args.warmup):
-        plan.correlate(raw, out=vis, stream=stream)
-    torch.cuda.synchronize()
-    log(f"bench: {args.warmup} warm-up steps done; timing {args.steps} steps")
+def run_form(omni, w, raw, form, steps, warmup):
+    """Plan, warm up and time `steps` correlate calls; returns timings and the last visibilities."""
+    import torch
 
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        plan.correlate(raw, out=vis, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    fwd = plan.stage_times("forward", args.steps)
-    red = plan.stage_times("reduce", args.steps)
-    inv = plan.stage_times("inverse", args.steps)
-    fwd_ms = sum(fwd) / len(fwd)
+    other = "mixed" if form == "fp32" else "fp32"
+    main = run_form(omni, w, raw, form, args.steps, args.warmup)
+    alt = None if args.no_other_form or (other == "mixed" and w.dtype == "cf32") else run_form(
+        omni, w, raw, other, args.steps, args.warmup)
     work = w.antenna_samples()
+    ms_per_step = main["ms"]
     value = work / (ms_per_step / 1e3)
-    log(
-        f"bench: {ms_per_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}); forward kernel {fwd_ms:.3f} ms, "
-        f"reduce {sum(red) / len(red):.3f} ms, inverse {sum(inv) / len(inv):.3f} ms"
-    )
+    vis = main["vis"]
 
-    flops_as = fp32_form_flops_per_as(w.dims)
-    achieved = flops_as * work / (fwd_ms / 1e3) / 1e12
-    roofline = {
-        "bound": "alu",
-        "achieved": round(achieved, 3),
-        "peak": PEAK_FP32_VECTOR_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": None,
-        "kernel": kernel_fwd,
-        "kernel_ms": round(fwd_ms, 4),
-        "algorithmic_flops_per_antenna_sample": flops_as,
-    }
+    def roofline_of(res, frm):
+        fwd_ms = res["stages"]["forward"]
+        if frm == "fp32":
+            per_as, peak, bound = fp32_form_flops_per_as(w.dims), PEAK_FP32_VECTOR_TFLOPS, "alu"
+        else:
+            per_as, peak, bound = mixed_form_flops_per_as(w.dims), PEAK_FP16_MFMA_TFLOPS, "mfma"
+        achieved = per_as * work / (fwd_ms / 1e3) / 1e12
+        return {
+            "bound": bound,
+            "achieved": round(achieved, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": recorded_traffic(res["kernel"], w.name),
+            "kernel": res["kernel"],
+            "kernel_ms": round(fwd_ms, 4),
+            "algorithmic_flops_per_antenna_sample": per_as,
+        }
+
+    roofline = roofline_of(main, form)
 
     # Accuracy: the zero lag of every channel against the exact total power.
     vh = vis.reshape(w.nchan, -1)
@@ -152,13 +131,21 @@ def main() -> int:
         err["zero_lag_all_channels"] = float(((vh[:, c].real.double() - power).abs() / power).max())
         del xf
 
+    if alt is not None and w.dtype != "ci4":
+        power = (raw.to(torch.float64) ** 2).sum(dim=(0, 2, 3))
+        va = alt["vis"].reshape(w.nchan, -1)
+        err[f"{other}_zero_lag_all_channels"] = float(((va[:, c].real.double() - power).abs() / power).max())
+
     cpu = None
     if not args.no_cpu_baseline:
         raw_cpu = raw.cpu()
         rate, nch, secs, ref = cpu_oracle_baseline(raw_cpu, w, budget_s=args.cpu_budget)
-        got = vis.cpu().numpy().reshape(w.nchan, -1)
-        e = max(float(np.max(np.abs(got[f] - ref[f])) / abs(ref[f][c])) for f in ref)
-        err[f"max_abs_over_zero_lag_oracle_{nch}ch"] = e
+        for tag, v in ((form, vis), (other, alt["vis"] if alt else None)):
+            if v is None:
+                continue
+            got = v.cpu().numpy().reshape(w.nchan, -1)
+            e = max(float(np.max(np.abs(got[f] - ref[f])) / abs(ref[f][c])) for f in ref)
+            err[f"{tag}_max_abs_over_zero_lag_oracle_{nch}ch"] = e
         cpu = {
             "value": rate,
             "unit": "antenna-samples/s",
@@ -192,8 +179,18 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
-        "stage_ms": {"forward": fwd_ms, "reduce": sum(red) / len(red), "inverse": sum(inv) / len(inv)},
+        "stage_ms": main["stages"],
     }
+    if alt is not None:
+        out["other_form"] = {
+            "form": other,
+            "config": f"{w.name} same input bytes, {other} form",
+            "value": work / (alt["ms"] / 1e3),
+            "ms_per_step": alt["ms"],
+            "stage_ms": alt["stages"],
+            "roofline": roofline_of(alt, other),
+            "speedup_vs_this_line": main["ms"] / alt["ms"],
+        }
     print(json.dumps(out), flush=True)
     return 0
 
