@@ -27,6 +27,8 @@ hipError_t launch_fused8x4_fp32(int fmt, const void* src, int64_t T, int64_t tps
                                 int F, int n_slices, int time_block, hipStream_t st);
 hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16,
                                  double* partial, int F, int n_slices, hipStream_t st);
+hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2* twm, int64_t tiles, int64_t outer,
+                             int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -49,6 +51,16 @@ constexpr size_t kLdsMax = 160 * 1024;
 constexpr int64_t kMaxN = int64_t(1) << 22;
 constexpr size_t kPartialBudget = size_t(512) << 20;
 
+// A fused-kernel schedule for a set of axes and channels.
+struct FusedSetup {
+  FusedP fp{};
+  int cpt = 0;               // cells per thread (general kernel)
+  size_t lds = 0;            // dynamic LDS bytes (general kernel)
+  std::vector<int32_t> kmap; // cell of (split residue, work-group cell) -> natural frequency index
+  int F = 0;                 // channels seen by the kernel
+  int64_t N = 0, M = 0;      // samples and Fourier cells per channel tile
+};
+
 struct ArrayPlan {
   int levels = 0;
   std::vector<int> dims;    // original axes, 2 per level
@@ -56,16 +68,20 @@ struct ArrayPlan {
   int F = 0;
   std::vector<int> n;       // axes with n > 1 (or a single axis when N == 1), in order
   int64_t N = 0, M = 0, n_out = 0;
-  FusedP fp{};
+  FusedSetup fs;            // schedule of the fused kernel (all axes, or the axes after the front)
   int kernel = 0;  // 0: general fused kernel; 1: 8x8x8x8 float32 kernel; 2: 8x8x8x8 mixed (MFMA) kernel
-  int cpt = 0;
-  size_t lds = 0;
-  std::vector<int32_t> kmap;
+  // front mode: the first n_front axes are transformed by front passes over HBM
+  int n_front = 0;
+  std::vector<int> front_r;   // fold modulus of each front axis
+  int front_tw_base = 0;      // offset of the remaining axes' twiddles
+  int64_t chunk_T = 0;        // time samples per front chunk
+  int64_t front_elems = 0;    // complex elements of each front workspace
   std::vector<int32_t> tw_desc_fwd, tw_desc_inv;
-  std::vector<int> inv_off;  // per axis offset into the float64 inverse table
-  int n_tw_inv = 0;
+  std::vector<int> inv_off;  // per axis offset into the twiddle tables
+  int n_tw = 0;
   int max_slices = 1;
   int last_slices = 1;
+  int inv_group = 1;         // channels per inverse-transform group
   // device resources
   float2* d_tw32 = nullptr;
   double2* d_tw64 = nullptr;
@@ -73,6 +89,7 @@ struct ArrayPlan {
   double* d_A = nullptr;
   double* d_partial = nullptr;
   double2* d_ws[2] = {nullptr, nullptr};
+  float2* d_y[2] = {nullptr, nullptr};
 };
 
 }  // namespace
@@ -140,24 +157,33 @@ int check_geometry(const ArrayPlan& ap) {
   return OMNI_OK;
 }
 
-// Choose the fused schedule.  See plan.hpp for the fold + short-DFT form.
-int plan_fused(ArrayPlan& ap, std::string* why) {
-  const int d = (int)ap.n.size();
-  FusedP& P = ap.fp;
+// Choose the fused schedule for axes n (F channels; the axes' forward twiddle
+// tables start at tw_base in the plan's table).  See plan.hpp for the fold +
+// short-DFT form.  With single_split the cells may only be divided along the
+// first-processed axis (a split on a later axis repeats the earlier passes in
+// every work-group of the split).
+int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_split, FusedSetup& fs,
+                    std::string* why) {
+  const int d = (int)n.size();
+  FusedP& P = fs.fp;
   std::memset(&P, 0, sizeof(P));
+  fs.F = F;
+  fs.N = prod(n);
+  fs.M = 1;
+  for (int v : n) fs.M *= 2 * v;
   P.d = d;
-  P.F = ap.F;
-  P.N = (int32_t)ap.N;
+  P.F = F;
+  P.N = (int32_t)fs.N;
   std::vector<int> m(d), r(d), L(d), R(d), step(d), E(d);
   std::vector<int64_t> in_str(d);
   in_str[d - 1] = 1;
-  for (int k = d - 2; k >= 0; --k) in_str[k] = in_str[k + 1] * ap.n[k + 1];
+  for (int k = d - 2; k >= 0; --k) in_str[k] = in_str[k + 1] * n[k + 1];
   for (int k = 0; k < d; ++k) {
-    m[k] = 2 * ap.n[k];
+    m[k] = 2 * n[k];
     int rr = 1;
     while (m[k] / rr > omni::kMaxL && (m[k] % (2 * rr)) == 0) rr *= 2;
     if (m[k] / rr > omni::kMaxL) {
-      *why = "axis length " + std::to_string(ap.n[k]) + " has an odd factor above 16";
+      *why = "axis length " + std::to_string(n[k]) + " has an odd factor above 16";
       return OMNI_E_SHAPE;
     }
     r[k] = rr;
@@ -167,19 +193,16 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
   std::vector<int> order;
   order.push_back(0);
   for (int k = d - 1; k >= 1; --k) order.push_back(k);
-  // Divide the Fourier cells among work-groups by residue classes, earliest
-  // processed axes first (a split on a later axis repeats the earlier passes in
-  // every work-group of the split).
   std::vector<int> split(d, 1), split_div(d, 1);
   int64_t n_split = 1;
-  for (int p = 0; p < d && ap.M / n_split > kCellsMax; ++p) {
+  for (int p = 0; p < (single_split ? 1 : d) && fs.M / n_split > kCellsMax; ++p) {
     const int k = order[p];
-    while (ap.M / n_split > kCellsMax && m[k] % (2 * split[k]) == 0) {
+    while (fs.M / n_split > kCellsMax && m[k] % (2 * split[k]) == 0) {
       split[k] *= 2;
       n_split *= 2;
     }
   }
-  if (ap.M / n_split > kCellsMax) {
+  if (fs.M / n_split > kCellsMax) {
     *why = "per-channel Fourier grid cannot be divided into work-group shares of <= 8192 cells";
     return OMNI_E_SHAPE;
   }
@@ -203,7 +226,7 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
   int64_t ws = 1, pst = 1;
   for (int k = d - 1; k >= 0; --k) {
     w_str[k] = ws;
-    ws *= (k == last && d > 1) ? ap.n[k] : E[k];
+    ws *= (k == last && d > 1) ? n[k] : E[k];
     p_str[k] = pst;
     pst *= E[k];
   }
@@ -214,16 +237,14 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
     *why = "work-group cell share too large";
     return OMNI_E_SHAPE;
   }
-  ap.cpt = cpt;
+  fs.cpt = cpt;
   P.n_split = (int32_t)n_split;
   P.cells_wg = (int32_t)cells;
   P.w_elems = (int32_t)(d > 1 ? ws : 1);
-  // forward twiddle tables w_m^q, one per axis
-  ap.tw_desc_fwd.clear();
   int off = 0;
   for (int k = 0; k < d; ++k) {
     AxisP& a = P.ax[k];
-    a.n = ap.n[k];
+    a.n = n[k];
     a.m = m[k];
     a.r = r[k];
     a.L = L[k];
@@ -235,10 +256,10 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
     a.w_stride = (int32_t)w_str[k];
     a.p_stride = (int32_t)p_str[k];
     a.in_stride = (int32_t)in_str[k];
-    a.tw_off = off;
-    ap.tw_desc_fwd.insert(ap.tw_desc_fwd.end(), {m[k], -1, off});
+    a.tw_off = off;  // relative to tw_base: the kernel gets the table from tw_base on
     off += m[k];
   }
+  (void)tw_base;
   P.n_tw = off;
   for (int p = 0; p < d; ++p) {
     PassP& ps = P.pass[p];
@@ -250,7 +271,7 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
       if (k == ax) continue;
       bool done = false;
       for (int q = 0; q < p; ++q) done = done || order[q] == k;
-      const int ext = done ? E[k] : ap.n[k];
+      const int ext = done ? E[k] : n[k];
       ps.ext[no] = ext;
       ps.w_str[no] = (int32_t)w_str[k];
       ps.src_str[no] = (int32_t)(p == 0 ? in_str[k] : w_str[k]);
@@ -262,18 +283,18 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
     ps.lines = (int32_t)lines;
     ps.jobs = (int32_t)(lines * R[ax]);
   }
-  ap.lds = (size_t)P.w_elems * 8 + (size_t)cpt * kNT * 4 + (size_t)P.n_tw * 8;
-  if (ap.lds > kLdsMax) {
+  fs.lds = (size_t)P.w_elems * 8 + (size_t)cpt * kNT * 4 + (size_t)P.n_tw * 8;
+  if (fs.lds > kLdsMax) {
     *why = "LDS working set exceeds 160 KiB";
     return OMNI_E_SHAPE;
   }
-  // Cell -> natural frequency index, for every split residue.
-  ap.kmap.assign((size_t)ap.M, 0);
+  // Cell -> natural frequency index (row-major over these axes), for every split residue.
+  fs.kmap.assign((size_t)fs.M, 0);
   std::vector<int64_t> nat_str(d);
-  int64_t s = 1;
+  int64_t sst = 1;
   for (int k = d - 1; k >= 0; --k) {
-    nat_str[k] = s;
-    s *= m[k];
+    nat_str[k] = sst;
+    sst *= m[k];
   }
   for (int c = 0; c < n_split; ++c) {
     for (int64_t cell = 0; cell < cells; ++cell) {
@@ -286,21 +307,9 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
         const int kappa = r[k] * q + rho;
         nat += kappa * nat_str[k];
       }
-      ap.kmap[(size_t)(c * cells + cell)] = (int32_t)nat;
+      fs.kmap[(size_t)(c * cells + cell)] = (int32_t)nat;
     }
   }
-  // inverse twiddles exp(+2 pi i q / m)
-  ap.tw_desc_inv.clear();
-  ap.inv_off.assign(d, 0);
-  int ioff = 0;
-  for (int k = 0; k < d; ++k) {
-    ap.inv_off[k] = ioff;
-    ap.tw_desc_inv.insert(ap.tw_desc_inv.end(), {m[k], +1, ioff});
-    ioff += m[k];
-  }
-  ap.n_tw_inv = ioff;
-  const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
-  ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
   return OMNI_OK;
 }
 
@@ -310,10 +319,10 @@ int plan_fused(ArrayPlan& ap, std::string* why) {
 // Positions p in [0,16) along axes 1..3 hold kappa = 2 (p % 8) + p / 8.
 void plan_fused8x4(ArrayPlan& ap) {
   ap.kernel = 1;
-  FusedP& P = ap.fp;
+  FusedP& P = ap.fs.fp;
   P.n_split = 8;
   P.cells_wg = 8192;
-  ap.cpt = 32;
+  ap.fs.cpt = 32;
   auto kap = [](int p) { return 2 * (p & 7) + (p >> 3); };
   for (int c = 0; c < 8; ++c) {
     for (int i = 0; i < 32; ++i) {
@@ -321,7 +330,7 @@ void plan_fused8x4(ArrayPlan& ap) {
         const int l = tid + 256 * (i >> 4), o = i & 15;
         const int k0 = c + 8 * (l >> 8);
         const int k1 = kap(o), k2 = kap((l >> 4) & 15), k3 = kap(l & 15);
-        ap.kmap[(size_t)(c * 8192 + i * 256 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
+        ap.fs.kmap[(size_t)(c * 8192 + i * 256 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
       }
     }
   }
@@ -335,20 +344,61 @@ void plan_fused8x4(ArrayPlan& ap) {
 // kappa_3 = 2 (col / 4) + h.
 void plan_fused8x4_mixed(ArrayPlan& ap) {
   ap.kernel = 2;
-  FusedP& P = ap.fp;
+  FusedP& P = ap.fs.fp;
   P.n_split = 2;
   P.cells_wg = 32768;
-  ap.cpt = 64;
+  ap.fs.cpt = 64;
   for (int h = 0; h < 2; ++h) {
     for (int idx = 0; idx < 64; ++idx) {
       for (int tid = 0; tid < 512; ++tid) {
         const int wave = tid >> 6, lane = tid & 63, col = lane & 31, hh = lane >> 5;
         const int cc = idx >> 4, tt = (idx >> 3) & 1, ip = (idx >> 2) & 1, j = idx & 3;
         const int k0 = 8 * ip + 4 * hh + j, k1 = 2 * wave + tt, k2 = 4 * cc + (col & 3), k3 = 2 * (col >> 2) + h;
-        ap.kmap[(size_t)(h * 32768 + idx * 512 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
+        ap.fs.kmap[(size_t)(h * 32768 + idx * 512 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
       }
     }
   }
+}
+
+// Front mode: the first s axes are transformed by front passes over HBM, after
+// which every outer Fourier index is a channel of the remaining axes.  A front
+// axis needs a power-of-two padded length of at most 64 (short DFTs of <= 32).
+bool front_axis_ok(int n) { return is_pow2(2 * n) && 2 * n <= 64; }
+
+int plan_front(ArrayPlan& ap, std::string* why) {
+  const int d = (int)ap.n.size();
+  int64_t MS = 1, NS = 1;
+  for (int s = 1; s < d; ++s) {
+    if (!front_axis_ok(ap.n[s - 1])) break;
+    MS *= 2 * ap.n[s - 1];
+    NS *= ap.n[s - 1];
+    std::vector<int> rest(ap.n.begin() + s, ap.n.end());
+    std::string w2;
+    if ((int64_t)ap.F * MS > INT32_MAX / 64) break;
+    int tw_base = 0;
+    for (int k = 0; k < s; ++k) tw_base += 2 * ap.n[k];
+    FusedSetup fs;
+    if (plan_fused_axes(rest, (int)(ap.F * MS), tw_base, true, fs, &w2) == OMNI_OK) {
+      ap.fs = std::move(fs);
+      ap.n_front = s;
+      ap.front_tw_base = tw_base;
+      ap.front_r.assign(s, 1);
+      for (int k = 0; k < s; ++k) ap.front_r[k] = std::max(1, 2 * ap.n[k] / 16);
+      // time chunk: the largest front output (after the last front pass) <= 2 GiB
+      const int64_t per_t = (int64_t)ap.F * MS * (ap.N / NS) * (int64_t)sizeof(float2);
+      ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t(2) << 30) / per_t));
+      ap.front_elems = 0;
+      int64_t mm = 1, nn = ap.N;
+      for (int k = 0; k < s; ++k) {
+        mm *= 2 * ap.n[k];
+        nn /= ap.n[k];
+        ap.front_elems = std::max(ap.front_elems, ap.chunk_T * ap.F * mm * nn);
+      }
+      return OMNI_OK;
+    }
+  }
+  *why = "per-channel Fourier grid too large and no front split applies";
+  return OMNI_E_SHAPE;
 }
 
 int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form,
@@ -380,12 +430,35 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   }
   int rc = check_geometry(ap);
   if (rc) return rc;
-  std::string why;
-  rc = plan_fused(ap, &why);
-  if (rc) return fail(rc, why);
+  const int d = (int)ap.n.size();
+  // forward (float32) and inverse (float64) twiddle tables, one per axis
+  ap.tw_desc_fwd.clear();
+  ap.tw_desc_inv.clear();
+  ap.inv_off.assign(d, 0);
+  int off = 0;
+  for (int k = 0; k < d; ++k) {
+    ap.tw_desc_fwd.insert(ap.tw_desc_fwd.end(), {2 * ap.n[k], -1, off});
+    ap.tw_desc_inv.insert(ap.tw_desc_inv.end(), {2 * ap.n[k], +1, off});
+    ap.inv_off[k] = off;
+    off += 2 * ap.n[k];
+  }
+  ap.n_tw = off;
+  std::string why, why2;
+  ap.n_front = 0;
+  rc = plan_fused_axes(ap.n, ap.F, 0, true, ap.fs, &why);
+  if (rc) rc = plan_front(ap, &why2);
+  if (rc) {
+    // last resort: residue splits along several axes (correct, repeats early passes)
+    rc = plan_fused_axes(ap.n, ap.F, 0, false, ap.fs, &why);
+    if (rc) return fail(rc, why + "; " + why2);
+  }
   const bool eight4 = ap.n == std::vector<int>{8, 8, 8, 8};
   if (form == OMNI_FORM_FP32 && eight4) plan_fused8x4(ap);
   if (form == OMNI_FORM_MIXED && eight4 && dtype != OMNI_CF32) plan_fused8x4_mixed(ap);
+  const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
+  ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
+  // inverse in groups of channels whose float64 workspace fits 512 MiB
+  ap.inv_group = (int)std::max<int64_t>(1, std::min<int64_t>(ap.F, (int64_t(512) << 20) / (ap.M * 16)));
   return OMNI_OK;
 }
 
@@ -397,12 +470,15 @@ void free_array(ArrayPlan& ap) {
   hipFree(ap.d_partial);
   hipFree(ap.d_ws[0]);
   hipFree(ap.d_ws[1]);
+  hipFree(ap.d_y[0]);
+  hipFree(ap.d_y[1]);
   ap.d_tw32 = nullptr;
   ap.d_tw64 = nullptr;
   ap.d_kmap = nullptr;
   ap.d_A = nullptr;
   ap.d_partial = nullptr;
   ap.d_ws[0] = ap.d_ws[1] = nullptr;
+  ap.d_y[0] = ap.d_y[1] = nullptr;
 }
 
 #define HIP_TRY(expr)                                                                      \
@@ -415,15 +491,19 @@ void free_array(ArrayPlan& ap) {
 
 int alloc_array(ArrayPlan& ap) {
   const size_t accA = (size_t)ap.F * ap.M * sizeof(double);
-  HIP_TRY(hipMalloc(&ap.d_tw32, (size_t)ap.fp.n_tw * sizeof(float2)));
-  HIP_TRY(hipMalloc(&ap.d_tw64, (size_t)ap.n_tw_inv * sizeof(double2)));
-  HIP_TRY(hipMalloc(&ap.d_kmap, ap.kmap.size() * sizeof(int32_t)));
+  HIP_TRY(hipMalloc(&ap.d_tw32, (size_t)ap.n_tw * sizeof(float2)));
+  HIP_TRY(hipMalloc(&ap.d_tw64, (size_t)ap.n_tw * sizeof(double2)));
+  HIP_TRY(hipMalloc(&ap.d_kmap, ap.fs.kmap.size() * sizeof(int32_t)));
   HIP_TRY(hipMalloc(&ap.d_A, accA));
   HIP_TRY(hipMalloc(&ap.d_partial, accA * (size_t)ap.max_slices));
-  const size_t ws = (size_t)ap.F * ap.M * sizeof(double2);
+  const size_t ws = (size_t)ap.inv_group * ap.M * sizeof(double2);
   HIP_TRY(hipMalloc(&ap.d_ws[0], ws));
   HIP_TRY(hipMalloc(&ap.d_ws[1], ws));
-  HIP_TRY(hipMemcpy(ap.d_kmap, ap.kmap.data(), ap.kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (ap.n_front > 0) {
+    HIP_TRY(hipMalloc(&ap.d_y[0], (size_t)ap.front_elems * sizeof(float2)));
+    HIP_TRY(hipMalloc(&ap.d_y[1], (size_t)ap.front_elems * sizeof(float2)));
+  }
+  HIP_TRY(hipMemcpy(ap.d_kmap, ap.fs.kmap.data(), ap.fs.kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   int32_t* d_desc = nullptr;
   const size_t nd = std::max(ap.tw_desc_fwd.size(), ap.tw_desc_inv.size());
   HIP_TRY(hipMalloc(&d_desc, nd * sizeof(int32_t)));
@@ -453,6 +533,8 @@ int check_device(int* dev) {
 
 int fmt_of(omni_dtype t) { return (int)t; }
 
+size_t sample_bytes(omni_dtype t) { return t == OMNI_CF32 ? 8 : t == OMNI_CI8 ? 2 : 1; }
+
 hipEvent_t stage_event(omni_plan_s* p, int stage, int end) {
   return p->ev[(size_t)(((p->n_calls % kTimingRing) * 3 + stage) * 2 + end)];
 }
@@ -462,10 +544,58 @@ void mark(omni_plan_s* p, int stage, int end, bool edge, hipStream_t st) {
   if (p->timing && edge) hipEventRecord(stage_event(p, stage, end), st);
 }
 
+// General fused kernel over T samples of `src` (format fmt) with setup fs; float64
+// partial sums into ap.d_partial; returns the number of time slices used.
+int launch_general(ArrayPlan& ap, const FusedSetup& fs, int fmt, const void* src, int64_t T, int time_block,
+                   const float2* tw, hipStream_t st, int* slices) {
+  FusedP P = fs.fp;
+  const int64_t per_slice_groups = (int64_t)fs.F * P.n_split;
+  int64_t ns = std::max<int64_t>(1, (1024 + per_slice_groups - 1) / per_slice_groups);
+  ns = std::min<int64_t>(ns, ap.max_slices);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 4));
+  const int64_t tps = (T + ns - 1) / ns;
+  ns = (T + tps - 1) / tps;
+  P.n_slices = (int32_t)ns;
+  P.time_block = time_block;
+  const int64_t groups = ns * fs.F;
+  P.xcd_groups = (groups % 8 == 0) ? 1 : 0;
+  const int64_t grid = groups * P.n_split;
+  if (grid > INT32_MAX) return fail(OMNI_E_SHAPE, "grid too large");
+  *slices = (int)ns;
+  HIP_TRY(omni::launch_fused_fp32(fmt, fs.cpt, src, T, tps, tw, ap.d_partial, P, (int)grid, fs.lds, st));
+  return OMNI_OK;
+}
+
 int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, void* vis, hipStream_t st,
                     uint32_t flags, int stage) {
   const bool accumulate = (flags & OMNI_NO_RESET) != 0;
-  if (stage == 0 && T > 0 && ap.kernel == 1) {
+  if (stage == 0 && T > 0 && ap.n_front > 0) {
+    // Front mode: per chunk of samples, front passes to HBM, then the fused
+    // kernel on the remaining axes, then the reduction into the accumulator.
+    const int s = ap.n_front;
+    for (int64_t c0 = 0; c0 < T; c0 += ap.chunk_T) {
+      const int64_t tc = std::min<int64_t>(ap.chunk_T, T - c0);
+      const void* cur = static_cast<const char*>(volt) + (size_t)(c0 * ap.F * ap.N) * sample_bytes(p->dtype);
+      int fmt = fmt_of(p->dtype);
+      int64_t outer = 1, inner = ap.N, tw_off = 0;
+      for (int k = 0; k < s; ++k) {
+        const int nk = ap.n[k], mk = 2 * nk;
+        inner /= nk;
+        float2* dst = ap.d_y[k & 1];
+        HIP_TRY(omni::launch_front_axis(fmt, cur, dst, ap.d_tw32 + tw_off, tc * ap.F, outer, nk, mk, ap.front_r[k],
+                                        inner, outer * nk * inner, outer * mk * inner, st));
+        outer *= mk;
+        tw_off += mk;
+        cur = dst;
+        fmt = 0;
+      }
+      int slices = 1;
+      int rc = launch_general(ap, ap.fs, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices);
+      if (rc) return rc;
+      HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, slices, ap.fs.F, ap.fs.fp.n_split,
+                                          ap.fs.fp.cells_wg, ap.fs.M, (accumulate || c0 > 0) ? 1 : 0, st));
+    }
+  } else if (stage == 0 && T > 0 && ap.kernel == 1) {
     // three 48 KiB work-groups fit one CU: aim for two full rounds over 256 CUs
     const int64_t per_slice_groups = (int64_t)ap.F * 8;
     int64_t ns = std::max<int64_t>(1, (1536 + per_slice_groups / 2) / per_slice_groups);
@@ -477,7 +607,7 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
                                        p->time_block, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 2) {
-    // two 64 KiB work-groups per CU: one round of 512 work-groups
+    // two 80 KiB work-groups per CU: one round of 512 work-groups
     const int64_t per_slice_groups = (int64_t)ap.F * 2;
     int64_t ns = std::max<int64_t>(1, (512 + per_slice_groups / 2) / per_slice_groups);
     ns = std::min<int64_t>(ns, ap.max_slices);
@@ -487,44 +617,33 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     ap.last_slices = (int)ns;
     HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, st));
   } else if (stage == 0 && T > 0) {
-    FusedP P = ap.fp;
-    const int64_t per_slice_groups = (int64_t)ap.F * P.n_split;
-    int64_t ns = std::max<int64_t>(1, (1024 + per_slice_groups - 1) / per_slice_groups);
-    ns = std::min<int64_t>(ns, ap.max_slices);
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 4));
-    const int64_t tps = (T + ns - 1) / ns;
-    ns = (T + tps - 1) / tps;
-    P.n_slices = (int32_t)ns;
-    P.time_block = p->time_block;
-    const int64_t groups = ns * ap.F;
-    P.xcd_groups = (groups % 8 == 0) ? 1 : 0;
-    const int64_t grid = groups * P.n_split;
-    if (grid > INT32_MAX) return fail(OMNI_E_SHAPE, "grid too large");
-    ap.last_slices = (int)ns;
-    HIP_TRY(omni::launch_fused_fp32(fmt_of(p->dtype), ap.cpt, volt, T, tps, ap.d_tw32, ap.d_partial, P, (int)grid,
-                                    ap.lds, st));
+    int rc = launch_general(ap, ap.fs, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
+    if (rc) return rc;
   }
   if (stage == 1) {
-    if (T > 0) {
-      HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, ap.last_slices, ap.F, ap.fp.n_split,
-                                          ap.fp.cells_wg, ap.M, accumulate ? 1 : 0, st));
-    } else if (!accumulate) {
+    if (T > 0 && ap.n_front == 0) {
+      HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, ap.last_slices, ap.F, ap.fs.fp.n_split,
+                                          ap.fs.fp.cells_wg, ap.M, accumulate ? 1 : 0, st));
+    } else if (T == 0 && !accumulate) {
       HIP_TRY(omni::launch_fill_f64(ap.d_A, (int64_t)ap.F * ap.M, 0.0, st));
     }
   }
   if (stage == 2 && !(flags & OMNI_NO_FINALIZE)) {
     const int d = (int)ap.n.size();
-    const void* src = ap.d_A;
-    int64_t outer = ap.F;
-    for (int k = 0; k < d; ++k) {
-      int64_t inner = 1;
-      for (int j = k + 1; j < d; ++j) inner *= 2 * ap.n[j];
-      const bool last = (k == d - 1);
-      void* dst = last ? vis : (void*)ap.d_ws[k & 1];
-      HIP_TRY(omni::launch_inverse_axis(k == 0, last, src, dst, ap.d_tw64 + ap.inv_off[k], outer, 2 * ap.n[k],
-                                        ap.n[k], inner, 1.0 / (double)ap.M, st));
-      src = dst;
-      outer *= 2 * ap.n[k] - 1;
+    for (int f0 = 0; f0 < ap.F; f0 += ap.inv_group) {
+      const int g = std::min(ap.inv_group, ap.F - f0);
+      const void* src = ap.d_A + (size_t)f0 * ap.M;
+      int64_t outer = g;
+      for (int k = 0; k < d; ++k) {
+        int64_t inner = 1;
+        for (int j = k + 1; j < d; ++j) inner *= 2 * ap.n[j];
+        const bool last = (k == d - 1);
+        void* dst = last ? (void*)(static_cast<float2*>(vis) + (size_t)f0 * ap.n_out) : (void*)ap.d_ws[k & 1];
+        HIP_TRY(omni::launch_inverse_axis(k == 0, last, src, dst, ap.d_tw64 + ap.inv_off[k], outer, 2 * ap.n[k],
+                                          ap.n[k], inner, 1.0 / (double)ap.M, st));
+        src = dst;
+        outer *= 2 * ap.n[k] - 1;
+      }
     }
   }
   return OMNI_OK;
@@ -743,13 +862,16 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
   s += ",\"arrays\":[";
   for (size_t i = 0; i < plan->arrays.size(); ++i) {
     const ArrayPlan& ap = plan->arrays[i];
-    const FusedP& P = ap.fp;
+    const FusedP& P = ap.fs.fp;
     if (i) s += ",";
-    s += std::string("{\"kernel\":\"") + (ap.kernel == 1 ? "fused8x4_fp32" : ap.kernel == 2 ? "fused8x4_mixed" : "fused_fp32") + "\",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) +
-         ",\"F\":" + std::to_string(ap.F) + ",\"n_split\":" + std::to_string(P.n_split) +
-         ",\"cells_wg\":" + std::to_string(P.cells_wg) +
-         ",\"cells_per_thread\":" + std::to_string(ap.cpt) + ",\"lds_bytes\":" + std::to_string(ap.lds) +
-         ",\"max_slices\":" + std::to_string(ap.max_slices) + ",\"axes\":[";
+    const char* kname = ap.kernel == 1 ? "fused8x4_fp32" : ap.kernel == 2 ? "fused8x4_mixed" : "fused_fp32";
+    s += std::string("{\"kernel\":\"") + kname + "\",\"mode\":\"" + (ap.n_front ? "front" : "direct") +
+         "\",\"n_front\":" + std::to_string(ap.n_front) + ",\"chunk_T\":" + std::to_string(ap.chunk_T) +
+         ",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) + ",\"F\":" + std::to_string(ap.F) +
+         ",\"kernel_channels\":" + std::to_string(ap.fs.F) + ",\"n_split\":" + std::to_string(P.n_split) +
+         ",\"cells_wg\":" + std::to_string(P.cells_wg) + ",\"cells_per_thread\":" + std::to_string(ap.fs.cpt) +
+         ",\"lds_bytes\":" + std::to_string(ap.fs.lds) + ",\"max_slices\":" + std::to_string(ap.max_slices) +
+         ",\"inverse_group\":" + std::to_string(ap.inv_group) + ",\"axes\":[";
     for (int k = 0; k < P.d; ++k) {
       const AxisP& a = P.ax[k];
       if (k) s += ",";

@@ -1,0 +1,137 @@
+// Front passes for arrays whose per-channel Fourier grid is too large for one
+// fused kernel (gfx950, float32).
+//
+// One pass transforms a single axis k of every (time, channel) tile, reading
+// [outer][n_k][inner] and writing [outer][m_k][inner] to HBM: the zero-padded
+// DFT of Sec. II.A/II.C along that axis, X[kappa] = sum_{j<n} x_j w_m^{kappa j},
+// kappa in [0, m), in natural frequency order.  It is done as the fold + short
+// DFT of the residue classes rho (mod r): for each rho the thread forms
+// z_j = sum_l x[j + l L] w_m^{rho (j + l L)} and a length-L DFT gives
+// X[r q + rho].  Consecutive threads take consecutive inner indices, so every
+// global load and store is coalesced.  After the front passes over the
+// outermost axes, each outer Fourier index is an independent "channel" of the
+// remaining axes for the fused kernel.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace omni {
+
+namespace fr {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+template <int FMT>
+__device__ __forceinline__ float2 load(const void* __restrict__ base, int64_t i) {
+  if (FMT == 0) return reinterpret_cast<const float2*>(base)[i];
+  if (FMT == 1) {
+    const char2 v = reinterpret_cast<const char2*>(base)[i];
+    return make_float2((float)v.x, (float)v.y);
+  }
+  const int8_t v = reinterpret_cast<const int8_t*>(base)[i];
+  return make_float2((float)(v >> 4), (float)((int8_t)(v << 4) >> 4));
+}
+
+// Radix-2 DIT DFT of length L (power of two), natural order; w_L^q = tw[q * (m / L)].
+template <int L>
+__device__ __forceinline__ void dft(float2 (&z)[L], const float2* __restrict__ tw, int stride) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    int j = 0;
+#pragma unroll
+    for (int b = 1, rb = L >> 1; b < L; b <<= 1, rb >>= 1)
+      if (i & b) j |= rb;
+    if (j > i) {
+      const float2 t = z[i];
+      z[i] = z[j];
+      z[j] = t;
+    }
+  }
+#pragma unroll
+  for (int s = 1; s < L; s <<= 1) {
+#pragma unroll
+    for (int k = 0; k < L; k += 2 * s) {
+#pragma unroll
+      for (int j = 0; j < s; ++j) {
+        float2 v = z[k + j + s];
+        if (j != 0) v = cmul(v, tw[j * (L / (2 * s)) * stride]);
+        const float2 u = z[k + j];
+        z[k + j] = cadd(u, v);
+        z[k + j + s] = csub(u, v);
+      }
+    }
+  }
+}
+
+}  // namespace fr
+
+// Grid: x over (tile, outer, inner) flattened with inner fastest, y over residues.
+// tiles = time samples x channels of this call; tile stride in the source is
+// src_tile (elements), in the destination dst_tile.
+template <int FMT, int L>
+__global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict__ src, float2* __restrict__ dst,
+                                                          const float2* __restrict__ twm, int64_t tiles,
+                                                          int64_t outer, int n, int m, int r, int64_t inner,
+                                                          int64_t src_tile, int64_t dst_tile) {
+  using namespace fr;
+  const int64_t per_tile = outer * inner;
+  const int64_t total = tiles * per_tile;
+  const int rho = blockIdx.y;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tile = idx / per_tile;
+    const int64_t rem = idx - tile * per_tile;
+    const int64_t o = rem / inner, in = rem - o * inner;
+    const int64_t sbase = tile * src_tile + o * n * inner + in;
+    float2 z[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int p = j; p < n; p += L) {
+        const float2 v = load<FMT>(src, sbase + (int64_t)p * inner);
+        acc = rho ? cadd(acc, cmul(v, twm[(rho * p) & (m - 1)])) : cadd(acc, v);
+      }
+      z[j] = acc;
+    }
+    dft<L>(z, twm, r);
+    const int64_t dbase = tile * dst_tile + o * m * inner + in;
+#pragma unroll
+    for (int q = 0; q < L; ++q) dst[dbase + (int64_t)(r * q + rho) * inner] = z[q];
+  }
+}
+
+hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2* twm, int64_t tiles, int64_t outer,
+                             int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st) {
+  const int L = m / r;
+  const int64_t total = tiles * outer * inner;
+  int64_t g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  const dim3 grid((unsigned)g, (unsigned)r), block(256);
+#define OMNI_FRONT(F_, L_)                                                                                     \
+  hipLaunchKernelGGL((front_axis_kernel<F_, L_>), grid, block, 0, st, src, dst, twm, tiles, outer, n, m, r, inner, \
+                     src_tile, dst_tile)
+#define OMNI_FRONT_L(F_)         \
+  switch (L) {                   \
+    case 2: OMNI_FRONT(F_, 2); break;   \
+    case 4: OMNI_FRONT(F_, 4); break;   \
+    case 8: OMNI_FRONT(F_, 8); break;   \
+    case 16: OMNI_FRONT(F_, 16); break; \
+    case 32: OMNI_FRONT(F_, 32); break; \
+    default: return hipErrorInvalidValue; \
+  }
+  switch (fmt) {
+    case 0: OMNI_FRONT_L(0); break;
+    case 1: OMNI_FRONT_L(1); break;
+    case 2: OMNI_FRONT_L(2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef OMNI_FRONT_L
+#undef OMNI_FRONT
+  return hipGetLastError();
+}
+
+}  // namespace omni

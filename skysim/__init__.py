@@ -210,13 +210,19 @@ def make_voltages(
     else:
         out = torch.empty((T, F, N), dtype=torch.uint8, device=dev)
     sqrt_flux = torch.tensor(np.sqrt(flux), dtype=torch.float32, device=dev)
-    proj = torch.tensor(np.outer(l, r[:, 0]) + np.outer(m, r[:, 1]), dtype=torch.float64, device=dev)  # [S, N]
+    lm = torch.tensor(np.stack([l, m], axis=1), dtype=torch.float64, device=dev)  # [S, 2]
+    rr = torch.tensor(r, dtype=torch.float64, device=dev)  # [N, 2]
+    # antennas are processed in chunks so that the [S, chunk] steering matrix stays small
+    chunk = N if S * N <= (1 << 24) else max(256, (1 << 24) // S)
     for f in range(F):
-        steer = torch.exp(-2j * math.pi * float(nu[f]) * proj).to(torch.complex64)  # [S, N]
         psi = torch.rand((T, S), generator=gen, device=dev) * (2 * math.pi)
         amp = torch.polar(sqrt_flux.expand(T, S).contiguous(), psi)  # [T, S] complex64
-        v = amp @ steer  # [T, N]
-        noise = torch.randn((T, N, 2), generator=gen, device=dev) * (noise_sigma / math.sqrt(2.0))
-        v = v + torch.view_as_complex(noise)
-        out[:, f] = quantise(v, w.dtype, gain)
+        for a0 in range(0, N, chunk):
+            a1 = min(N, a0 + chunk)
+            proj = lm @ rr[a0:a1].T  # [S, chunk]: l r_x + m r_y
+            steer = torch.exp(-2j * math.pi * float(nu[f]) * proj).to(torch.complex64)
+            v = amp @ steer  # [T, chunk]
+            noise = torch.randn((T, a1 - a0, 2), generator=gen, device=dev) * (noise_sigma / math.sqrt(2.0))
+            v = v + torch.view_as_complex(noise)
+            out[:, f, a0:a1] = quantise(v, w.dtype, gain)
     return out

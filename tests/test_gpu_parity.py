@@ -275,3 +275,77 @@ def test_mixed_other_shapes_fall_back_to_fp32_kernel():
     vis, plan = gpu_vis([[6, 6]], raw, "ci8", "mixed")
     assert '"fused_fp32"' in plan.describe()
     assert rel_err(vis, oracle_vis(raw, "ci8", [[6, 6]])) <= TOL["fp32"]
+
+
+# ---------------------------------------------------------------------------
+# Front mode (large per-channel grids) and the batched workload's shapes.
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize(
+    "level_dims, dtype, T",
+    [([[4, 4], [4, 4], [4, 4]], "ci8", 150), ([[8, 8], [4, 4], [2, 2]], "cf32", 9), ([[4, 4], [4, 4], [4, 4]], "ci4", 7)],
+)
+def test_front_mode_full_oracle(level_dims, dtype, T):
+    """Shapes whose grid needs front passes; T=150 spans several time chunks of the front workspace."""
+    N = math.prod(dims_of(level_dims))
+    gen = torch.Generator().manual_seed(N + T)
+    raw = random_raw(dtype, T, 3, N, gen)
+    say("front mode", level_dims, dtype, T)
+    vis, plan = gpu_vis(level_dims, raw, dtype)
+    assert '"mode":"front"' in plan.describe()
+    assert rel_err(vis, oracle_vis(raw, dtype, level_dims)) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("shape", [[[64, 64]], [[128, 128]]])
+def test_large_single_level_grids(shape):
+    N = math.prod(dims_of(shape))
+    gen = torch.Generator().manual_seed(N)
+    raw = random_raw("ci4", 6, 2, N, gen)
+    say("single level", shape)
+    vis, _ = gpu_vis(shape, raw, "ci4")
+    assert rel_err(vis, oracle_vis(raw, "ci4", shape)) <= TOL["fp32"]
+
+
+def sampled_cells_check(w, T, F, n_random=96, seed=0):
+    """Full-size geometry, few samples: the oracle one cell at a time (all |Delta_k| <= 1 plus random
+    cells), zero lag of every channel, and a few Fourier cells of the visibility grid against the
+    oracle's time-summed power (Wiener-Khinchin)."""
+    dims = w.dims
+    raw = skysim.make_voltages(w, T=T, nchan=F, device="cuda")
+    plan = omni.Plan(w.level_dims, w.A, F, w.dtype, "fp32")
+    desc = plan.describe()
+    say(w.name, desc[:200])
+    vis = plan.correlate(raw)
+    torch.cuda.synchronize()
+    V = vis.cpu().numpy()
+    x = oracle.decode(raw.cpu().numpy(), w.dtype, T, F, w.N)
+    rng = np.random.default_rng(seed)
+    near = np.array(np.meshgrid(*[[-1, 0, 1]] * len(dims), indexing="ij")).reshape(len(dims), -1).T
+    far = np.stack([rng.integers(-(n - 1), n, n_random) for n in dims], axis=1)
+    deltas = np.concatenate([near, far])
+    ref = oracle.visibility_cells(x, dims, deltas)
+    got = np.stack([V[(slice(None),) + tuple(dl + np.array(dims) - 1)] for dl in deltas], axis=1)
+    z = np.abs(ref[:, len(near) // 2])  # Delta = 0 is the centre of the near block
+    err = float(np.max(np.abs(got - ref) / z[:, None]))
+    say(w.name, "sampled-cell error", err)
+    assert err <= TOL["fp32"]
+    kap = rng.integers(0, 2 * np.array(dims), (3, len(dims)))
+    P = oracle.fourier_power(x, dims, kap)
+    G = np.meshgrid(*[np.arange(-(n - 1), n) for n in dims], indexing="ij", sparse=True)
+    for q, k in enumerate(kap):
+        ph = sum(kk * g / (2 * n) for kk, g, n in zip(k, G, dims))
+        wk = np.exp(-2j * np.pi * ph)
+        for f in range(F):
+            val = np.sum(V[f].astype(np.complex128) * wk)
+            assert abs(val - P[f, q]) <= 1e-4 * np.sum(np.abs(x[:, f]) ** 2), (f, k)
+
+
+def test_hier3_sampled_cells():
+    """The three-level 16x16 / 8x8 / 4x4 hierarchy (N = 262144, M = 16.8M cells) at full N."""
+    sampled_cells_check(skysim.WORKLOADS["hier3"], T=12, F=2)
+
+
+def test_hier16x16_sampled_cells():
+    """The two-level 16x16-of-16x16 array of the batched workload (N = 65536, M = 1M cells)."""
+    sampled_cells_check(skysim.WORKLOADS["hier16x16"], T=10, F=3)
