@@ -75,6 +75,8 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 /* omni_opts.flags */
 #define OMNI_PLAN_HOST_ONLY 0x1u /* geometry only: no device resources; correlate -> OMNI_E_STATE */
 #define OMNI_PLAN_TIMING 0x2u    /* record HIP events around each stage of every correlate call  */
+#define OMNI_PLAN_TUNE 0x4u      /* autotune the general kernel's schedule at plan time (timed on  \
+                                    an all-zero input; choice cached in the file OMNI_TUNE_CACHE) */
 
 /* flags argument of omni_correlate* */
 #define OMNI_NO_RESET 0x1u    /* add this call's samples to the running accumulator            */

@@ -33,6 +33,7 @@ DTYPES = {"cf32": 0, "ci8": 1, "ci4": 2}
 FORMS = {"fp32": 0, "mixed": 1}
 PLAN_HOST_ONLY = 0x1
 PLAN_TIMING = 0x2
+PLAN_TUNE = 0x4
 STAGES = {"forward": 0, "reduce": 1, "inverse": 2}
 NO_RESET = 0x1
 NO_FINALIZE = 0x2
@@ -154,9 +155,10 @@ class Plan:
         host_only: bool = False,
         batch: Sequence[tuple] | None = None,
         timing: bool = False,
+        tune: bool = False,
     ):
         self._h = ctypes.c_void_p()
-        flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_TIMING if timing else 0)
+        flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_TIMING if timing else 0) | (PLAN_TUNE if tune else 0)
         opts = _Opts(DTYPES[dtype], FORMS[form], time_block, flags)
         self.dtype, self.form = dtype, form
         self._keep = []

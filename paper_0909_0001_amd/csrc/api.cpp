@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -70,8 +71,12 @@ struct ArrayPlan {
   int64_t N = 0, M = 0, n_out = 0;
   FusedSetup fs;            // schedule of the fused kernel (all axes, or the axes after the front)
   int kernel = 0;  // 0: general fused kernel; 1: 8x8x8x8 float32 kernel; 2: 8x8x8x8 mixed (MFMA) kernel
+  int lcap = 32;             // longest short DFT the general kernel may use (autotuned)
+  int wg_target = 1024;      // work-groups the general kernel's time slicing aims for (autotuned)
+  double tuned_ms = 0.0;     // best candidate's time in the autotuner (0: not tuned)
   // front mode: the first n_front axes are transformed by front passes over HBM
   int n_front = 0;
+  bool single_split = true;   // the cells are divided along the first-processed axis only
   std::vector<int> front_r;   // fold modulus of each front axis
   int front_tw_base = 0;      // offset of the remaining axes' twiddles
   int64_t chunk_T = 0;        // time samples per front chunk
@@ -162,7 +167,7 @@ int check_geometry(const ArrayPlan& ap) {
 // short-DFT form.  With single_split the cells may only be divided along the
 // first-processed axis (a split on a later axis repeats the earlier passes in
 // every work-group of the split).
-int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_split, FusedSetup& fs,
+int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_split, int lcap, FusedSetup& fs,
                     std::string* why) {
   const int d = (int)n.size();
   FusedP& P = fs.fp;
@@ -181,7 +186,7 @@ int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_s
   for (int k = 0; k < d; ++k) {
     m[k] = 2 * n[k];
     int rr = 1;
-    while (m[k] / rr > omni::kMaxL && (m[k] % (2 * rr)) == 0) rr *= 2;
+    while (m[k] / rr > lcap && (m[k] % (2 * rr)) == 0) rr *= 2;
     if (m[k] / rr > omni::kMaxL) {
       *why = "axis length " + std::to_string(n[k]) + " has an odd factor above 16";
       return OMNI_E_SHAPE;
@@ -378,7 +383,7 @@ int plan_front(ArrayPlan& ap, std::string* why) {
     int tw_base = 0;
     for (int k = 0; k < s; ++k) tw_base += 2 * ap.n[k];
     FusedSetup fs;
-    if (plan_fused_axes(rest, (int)(ap.F * MS), tw_base, true, fs, &w2) == OMNI_OK) {
+    if (plan_fused_axes(rest, (int)(ap.F * MS), tw_base, true, ap.lcap, fs, &w2) == OMNI_OK) {
       ap.fs = std::move(fs);
       ap.n_front = s;
       ap.front_tw_base = tw_base;
@@ -445,12 +450,13 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   ap.n_tw = off;
   std::string why, why2;
   ap.n_front = 0;
-  rc = plan_fused_axes(ap.n, ap.F, 0, true, ap.fs, &why);
+  rc = plan_fused_axes(ap.n, ap.F, 0, true, ap.lcap, ap.fs, &why);
   if (rc) rc = plan_front(ap, &why2);
   if (rc) {
     // last resort: residue splits along several axes (correct, repeats early passes)
-    rc = plan_fused_axes(ap.n, ap.F, 0, false, ap.fs, &why);
+    rc = plan_fused_axes(ap.n, ap.F, 0, false, ap.lcap, ap.fs, &why);
     if (rc) return fail(rc, why + "; " + why2);
+    ap.single_split = false;
   }
   const bool eight4 = ap.n == std::vector<int>{8, 8, 8, 8};
   if (form == OMNI_FORM_FP32 && eight4) plan_fused8x4(ap);
@@ -550,7 +556,7 @@ int launch_general(ArrayPlan& ap, const FusedSetup& fs, int fmt, const void* src
                    const float2* tw, hipStream_t st, int* slices) {
   FusedP P = fs.fp;
   const int64_t per_slice_groups = (int64_t)fs.F * P.n_split;
-  int64_t ns = std::max<int64_t>(1, (1024 + per_slice_groups - 1) / per_slice_groups);
+  int64_t ns = std::max<int64_t>(1, (ap.wg_target + per_slice_groups - 1) / per_slice_groups);
   ns = std::min<int64_t>(ns, ap.max_slices);
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 4));
   const int64_t tps = (T + ns - 1) / ns;
@@ -649,6 +655,110 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
   return OMNI_OK;
 }
 
+// Autotuner for the general fused kernel: times every candidate schedule
+// (longest short DFT lcap x work-group target of the time slicing) on an
+// all-zero input of a few samples with HIP events, keeps the fastest, and
+// remembers the choice in the file named by OMNI_TUNE_CACHE (one line per
+// array: key lcap wg_target ms), if set.
+std::string tune_key(const ArrayPlan& ap, omni_dtype dtype) {
+  std::string k = "gfx950:";
+  for (int v : ap.n) k += std::to_string(v) + "x";
+  k += ":F" + std::to_string(ap.F) + ":t" + std::to_string((int)dtype);
+  return k;
+}
+
+bool tune_cache_lookup(const std::string& key, int* lcap, int* wgt) {
+  const char* path = std::getenv("OMNI_TUNE_CACHE");
+  if (!path) return false;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return false;
+  char k[256];
+  int a, b;
+  double ms;
+  bool found = false;
+  while (std::fscanf(fp, "%255s %d %d %lf", k, &a, &b, &ms) == 4)
+    if (key == k) {
+      *lcap = a;
+      *wgt = b;
+      found = true;
+    }
+  std::fclose(fp);
+  return found;
+}
+
+void tune_cache_store(const std::string& key, int lcap, int wgt, double ms) {
+  const char* path = std::getenv("OMNI_TUNE_CACHE");
+  if (!path) return;
+  FILE* fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fprintf(fp, "%s %d %d %.4f\n", key.c_str(), lcap, wgt, ms);
+  std::fclose(fp);
+}
+
+int tune_array(omni_plan_s* p, ArrayPlan& ap) {
+  if (ap.kernel != 0) return OMNI_OK;  // the specialised kernels have a fixed schedule
+  const std::string key = tune_key(ap, p->dtype);
+  int lc = 0, wg = 0;
+  const bool cached = tune_cache_lookup(key, &lc, &wg);
+  const bool front = ap.n_front > 0;
+  const std::vector<int> axes = front ? std::vector<int>(ap.n.begin() + ap.n_front, ap.n.end()) : ap.n;
+  const int Fk = ap.fs.F;
+  const int fmt = front ? 0 : fmt_of(p->dtype);
+  const size_t bytes_t = (size_t)Fk * (size_t)ap.fs.N * (front ? sizeof(float2) : sample_bytes(p->dtype));
+  const int64_t Tt = std::max<int64_t>(4, std::min<int64_t>(256, (int64_t(256) << 20) / (int64_t)bytes_t));
+  void* zero = nullptr;
+  HIP_TRY(hipMalloc(&zero, bytes_t * (size_t)Tt));
+  HIP_TRY(hipMemset(zero, 0, bytes_t * (size_t)Tt));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const float2* tw = ap.d_tw32 + (front ? ap.front_tw_base : 0);
+  double best = 1e30;
+  FusedSetup best_fs;
+  int best_lc = ap.lcap, best_wg = ap.wg_target;
+  const int lcaps[3] = {8, 16, 32};
+  const int wgts[3] = {512, 1024, 2048};
+  for (int li = 0; li < 3; ++li) {
+    for (int wi = 0; wi < 3; ++wi) {
+      if (cached && (lcaps[li] != lc || wgts[wi] != wg)) continue;
+      FusedSetup fs;
+      std::string why;
+      if (plan_fused_axes(axes, Fk, 0, front ? true : ap.single_split, lcaps[li], fs, &why)) continue;
+      const int keep_wg = ap.wg_target;
+      ap.wg_target = wgts[wi];
+      float ms = 0.f;
+      int slices = 1;
+      int rc = OMNI_OK;
+      for (int rep = 0; rep < 2 && rc == OMNI_OK; ++rep) {
+        HIP_TRY(hipEventRecord(e0, 0));
+        rc = launch_general(ap, fs, fmt, zero, Tt, p->time_block, tw, 0, &slices);
+        HIP_TRY(hipEventRecord(e1, 0));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      }
+      ap.wg_target = keep_wg;
+      if (rc == OMNI_OK && ms < best) {
+        best = ms;
+        best_fs = std::move(fs);
+        best_lc = lcaps[li];
+        best_wg = wgts[wi];
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(zero);
+  if (best < 1e30) {
+    ap.fs = std::move(best_fs);
+    ap.lcap = best_lc;
+    ap.wg_target = best_wg;
+    ap.tuned_ms = best;
+    HIP_TRY(hipMemcpy(ap.d_kmap, ap.fs.kmap.data(), ap.fs.kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!cached) tune_cache_store(key, best_lc, best_wg, best);
+  }
+  return OMNI_OK;
+}
+
 int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, const omni_opts* opts) {
   if (!out) return fail(OMNI_E_INVAL, "out is NULL");
   *out = nullptr;
@@ -657,7 +767,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   if (o.dtype < OMNI_CF32 || o.dtype > OMNI_CI4) return fail(OMNI_E_INVAL, "unknown dtype");
   if (o.form != OMNI_FORM_FP32 && o.form != OMNI_FORM_MIXED) return fail(OMNI_E_INVAL, "unknown form");
   if (o.time_block < 0) return fail(OMNI_E_INVAL, "time_block < 0");
-  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING)) return fail(OMNI_E_INVAL, "unknown plan flag");
+  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING | OMNI_PLAN_TUNE)) return fail(OMNI_E_INVAL, "unknown plan flag");
   omni_plan_s* p = new (std::nothrow) omni_plan_s;
   if (!p) return fail(OMNI_E_NOMEM, "host allocation failed");
   p->dtype = o.dtype;
@@ -693,6 +803,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
     }
     for (auto& ap : p->arrays) {
       rc = alloc_array(ap);
+      if (rc == OMNI_OK && (o.flags & OMNI_PLAN_TUNE)) rc = tune_array(p, ap);
       if (rc) {
         for (auto& a2 : p->arrays) free_array(a2);
         delete p;
@@ -871,7 +982,9 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
          ",\"kernel_channels\":" + std::to_string(ap.fs.F) + ",\"n_split\":" + std::to_string(P.n_split) +
          ",\"cells_wg\":" + std::to_string(P.cells_wg) + ",\"cells_per_thread\":" + std::to_string(ap.fs.cpt) +
          ",\"lds_bytes\":" + std::to_string(ap.fs.lds) + ",\"max_slices\":" + std::to_string(ap.max_slices) +
-         ",\"inverse_group\":" + std::to_string(ap.inv_group) + ",\"axes\":[";
+         ",\"inverse_group\":" + std::to_string(ap.inv_group) + ",\"lcap\":" + std::to_string(ap.lcap) +
+         ",\"wg_target\":" + std::to_string(ap.wg_target) + ",\"tuned_ms\":" + std::to_string(ap.tuned_ms) +
+         ",\"axes\":[";
     for (int k = 0; k < P.d; ++k) {
       const AxisP& a = P.ax[k];
       if (k) s += ",";

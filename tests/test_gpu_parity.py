@@ -349,3 +349,16 @@ def test_hier3_sampled_cells():
 def test_hier16x16_sampled_cells():
     """The two-level 16x16-of-16x16 array of the batched workload (N = 65536, M = 1M cells)."""
     sampled_cells_check(skysim.WORKLOADS["hier16x16"], T=10, F=3)
+
+
+def test_autotuned_plan_matches_oracle():
+    """A plan made with the autotuner still agrees with the oracle (schedule only changes speed)."""
+    gen = torch.Generator().manual_seed(31)
+    raw = random_raw("ci4", 21, 2, 1024, gen)
+    plan = omni.Plan([[32, 32]], None, 2, "ci4", "fp32", tune=True)
+    d = plan.describe()
+    say("tuned", d)
+    assert '"tuned_ms":0.000000' not in d
+    vis = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    assert rel_err(vis.cpu().numpy(), oracle_vis(raw, "ci4", [[32, 32]])) <= TOL["fp32"]
