@@ -26,10 +26,14 @@ hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* d
 hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, double2* tw64, hipStream_t st);
 hipError_t launch_fused8x4_fp32(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16, double* partial,
                                 int F, int n_slices, int time_block, hipStream_t st);
-hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16,
-                                 double* partial, int F, int n_slices, hipStream_t st);
+hipError_t launch_fused8x4_mixed(int fmt, int ns_per_iter, const void* src, int64_t T, int64_t tps,
+                                 const float2* tw16, double* partial, int F, int n_slices, hipStream_t st);
 hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2* twm, int64_t tiles, int64_t outer,
                              int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st);
+int fused_ct_lookup(int d, const int* n);
+void fused_ct_params(int idx, int* r, int* s0);
+hipError_t launch_fused_ct(int idx, int fmt, const void* src, int64_t T, int64_t tps, const float2* tw,
+                           double* partial, int F, int n_slices, int time_block, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -70,7 +74,8 @@ struct ArrayPlan {
   std::vector<int> n;       // axes with n > 1 (or a single axis when N == 1), in order
   int64_t N = 0, M = 0, n_out = 0;
   FusedSetup fs;            // schedule of the fused kernel (all axes, or the axes after the front)
-  int kernel = 0;  // 0: general fused kernel; 1: 8x8x8x8 float32 kernel; 2: 8x8x8x8 mixed (MFMA) kernel
+  int kernel = 0;  // 0: general; 1: 8x8x8x8 float32; 2: 8x8x8x8 mixed (MFMA); 3: compile-time shape (float32)
+  int ct_index = -1;         // entry of the compile-time shape table (kernel 3)
   int lcap = 32;             // longest short DFT the general kernel may use (autotuned)
   int wg_target = 1024;      // work-groups the general kernel's time slicing aims for (autotuned)
   double tuned_ms = 0.0;     // best candidate's time in the autotuner (0: not tuned)
@@ -168,7 +173,7 @@ int check_geometry(const ArrayPlan& ap) {
 // first-processed axis (a split on a later axis repeats the earlier passes in
 // every work-group of the split).
 int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_split, int lcap, FusedSetup& fs,
-                    std::string* why) {
+                    std::string* why, const int* r_force = nullptr, int s0_force = 0) {
   const int d = (int)n.size();
   FusedP& P = fs.fp;
   std::memset(&P, 0, sizeof(P));
@@ -200,7 +205,11 @@ int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_s
   for (int k = d - 1; k >= 1; --k) order.push_back(k);
   std::vector<int> split(d, 1), split_div(d, 1);
   int64_t n_split = 1;
-  for (int p = 0; p < (single_split ? 1 : d) && fs.M / n_split > kCellsMax; ++p) {
+  if (s0_force > 0) {
+    split[0] = s0_force;
+    n_split = s0_force;
+  }
+  for (int p = 0; p < (single_split ? 1 : d) && fs.M / n_split > kCellsMax && s0_force == 0; ++p) {
     const int k = order[p];
     while (fs.M / n_split > kCellsMax && m[k] % (2 * split[k]) == 0) {
       split[k] *= 2;
@@ -219,7 +228,7 @@ int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_s
     }
   }
   for (int k = 0; k < d; ++k) {
-    r[k] = std::max(r[k], split[k]);
+    r[k] = r_force ? r_force[k] : std::max(r[k], split[k]);
     L[k] = m[k] / r[k];
     R[k] = r[k] / split[k];
     step[k] = split[k];
@@ -459,6 +468,22 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
     ap.single_split = false;
   }
   const bool eight4 = ap.n == std::vector<int>{8, 8, 8, 8};
+  if (!eight4 && ap.single_split) {
+    // a compile-time-shape kernel for the axes the fused kernel sees (all, or those after the front)
+    const std::vector<int> axes = ap.n_front ? std::vector<int>(ap.n.begin() + ap.n_front, ap.n.end()) : ap.n;
+    const int idx = omni::fused_ct_lookup((int)axes.size(), axes.data());
+    if (idx >= 0) {
+      int rr[4] = {1, 1, 1, 1}, s0 = 1;
+      omni::fused_ct_params(idx, rr, &s0);
+      FusedSetup fs;
+      std::string w3;
+      if (plan_fused_axes(axes, ap.fs.F, 0, true, ap.lcap, fs, &w3, rr, s0) == OMNI_OK) {
+        ap.fs = std::move(fs);
+        ap.kernel = 3;
+        ap.ct_index = idx;
+      }
+    }
+  }
   if (form == OMNI_FORM_FP32 && eight4) plan_fused8x4(ap);
   if (form == OMNI_FORM_MIXED && eight4 && dtype != OMNI_CF32) plan_fused8x4_mixed(ap);
   const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
@@ -539,6 +564,13 @@ int check_device(int* dev) {
 
 int fmt_of(omni_dtype t) { return (int)t; }
 
+// Samples per iteration of the 8x8x8x8 mixed kernel: one (two 80 KiB work-groups per CU) by default;
+// OMNI_MIXED_SAMPLES=2 selects two samples per iteration in one 160 KiB work-group per CU.
+int mixed_samples_per_iter() {
+  const char* e = std::getenv("OMNI_MIXED_SAMPLES");
+  return (e && e[0] == '2') ? 2 : 1;
+}
+
 size_t sample_bytes(omni_dtype t) { return t == OMNI_CF32 ? 8 : t == OMNI_CI8 ? 2 : 1; }
 
 hipEvent_t stage_event(omni_plan_s* p, int stage, int end) {
@@ -572,6 +604,21 @@ int launch_general(ArrayPlan& ap, const FusedSetup& fs, int fmt, const void* src
   return OMNI_OK;
 }
 
+// Compile-time-shape kernel over T samples; same slicing policy as the general kernel.
+int launch_ct(ArrayPlan& ap, int fmt, const void* src, int64_t T, int time_block, const float2* tw, hipStream_t st,
+              int* slices) {
+  const int64_t per_slice_groups = (int64_t)ap.fs.F * ap.fs.fp.n_split;
+  int64_t ns = std::max<int64_t>(1, (ap.wg_target + per_slice_groups - 1) / per_slice_groups);
+  ns = std::min<int64_t>(ns, ap.max_slices);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 4));
+  const int64_t tps = (T + ns - 1) / ns;
+  ns = (T + tps - 1) / tps;
+  if (ns * per_slice_groups > INT32_MAX) return fail(OMNI_E_SHAPE, "grid too large");
+  *slices = (int)ns;
+  HIP_TRY(omni::launch_fused_ct(ap.ct_index, fmt, src, T, tps, tw, ap.d_partial, ap.fs.F, (int)ns, time_block, st));
+  return OMNI_OK;
+}
+
 int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, void* vis, hipStream_t st,
                     uint32_t flags, int stage) {
   const bool accumulate = (flags & OMNI_NO_RESET) != 0;
@@ -596,7 +643,9 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         fmt = 0;
       }
       int slices = 1;
-      int rc = launch_general(ap, ap.fs, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices);
+      int rc = ap.kernel == 3
+                   ? launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices)
+                   : launch_general(ap, ap.fs, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices);
       if (rc) return rc;
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, (accumulate || c0 > 0) ? 1 : 0, st));
@@ -613,15 +662,22 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
                                        p->time_block, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 2) {
-    // two 80 KiB work-groups per CU: one round of 512 work-groups
+    // one sample per iteration: two 80 KiB work-groups per CU, one round of 512 work-groups
+    // (two samples per iteration: one 160 KiB work-group per CU, 256 work-groups)
+    const int per_iter = mixed_samples_per_iter();
     const int64_t per_slice_groups = (int64_t)ap.F * 2;
-    int64_t ns = std::max<int64_t>(1, (512 + per_slice_groups / 2) / per_slice_groups);
+    const int64_t target = per_iter == 2 ? 256 : 512;
+    int64_t ns = std::max<int64_t>(1, (target + per_slice_groups / 2) / per_slice_groups);
     ns = std::min<int64_t>(ns, ap.max_slices);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
     const int64_t tps = (T + ns - 1) / ns;
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
-    HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, st));
+    HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), per_iter, volt, T, tps, ap.d_tw32, ap.d_partial, ap.F,
+                                        (int)ns, st));
+  } else if (stage == 0 && T > 0 && ap.kernel == 3) {
+    int rc = launch_ct(ap, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
+    if (rc) return rc;
   } else if (stage == 0 && T > 0) {
     int rc = launch_general(ap, ap.fs, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
     if (rc) return rc;
@@ -663,7 +719,7 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
 std::string tune_key(const ArrayPlan& ap, omni_dtype dtype) {
   std::string k = "gfx950:";
   for (int v : ap.n) k += std::to_string(v) + "x";
-  k += ":F" + std::to_string(ap.F) + ":t" + std::to_string((int)dtype);
+  k += ":F" + std::to_string(ap.F) + ":t" + std::to_string((int)dtype) + ":k" + std::to_string(ap.kernel);
   return k;
 }
 
@@ -695,8 +751,13 @@ void tune_cache_store(const std::string& key, int lcap, int wgt, double ms) {
   std::fclose(fp);
 }
 
+// Times the candidate schedules on zero input and keeps the fastest: for the
+// general kernel, short-DFT cap x time slicing; for the compile-time-shape
+// kernel (fixed fold moduli), time slicing only.  The 8x8x8x8 kernels have a
+// fixed schedule.
 int tune_array(omni_plan_s* p, ArrayPlan& ap) {
-  if (ap.kernel != 0) return OMNI_OK;  // the specialised kernels have a fixed schedule
+  if (ap.kernel != 0 && ap.kernel != 3) return OMNI_OK;
+  const bool ct = ap.kernel == 3;
   const std::string key = tune_key(ap, p->dtype);
   int lc = 0, wg = 0;
   const bool cached = tune_cache_lookup(key, &lc, &wg);
@@ -721,9 +782,14 @@ int tune_array(omni_plan_s* p, ArrayPlan& ap) {
   for (int li = 0; li < 3; ++li) {
     for (int wi = 0; wi < 3; ++wi) {
       if (cached && (lcaps[li] != lc || wgts[wi] != wg)) continue;
+      if (ct && lcaps[li] != ap.lcap) continue;
       FusedSetup fs;
       std::string why;
-      if (plan_fused_axes(axes, Fk, 0, front ? true : ap.single_split, lcaps[li], fs, &why)) continue;
+      if (ct) {
+        fs = ap.fs;
+      } else if (plan_fused_axes(axes, Fk, 0, front ? true : ap.single_split, lcaps[li], fs, &why)) {
+        continue;
+      }
       const int keep_wg = ap.wg_target;
       ap.wg_target = wgts[wi];
       float ms = 0.f;
@@ -731,7 +797,8 @@ int tune_array(omni_plan_s* p, ArrayPlan& ap) {
       int rc = OMNI_OK;
       for (int rep = 0; rep < 2 && rc == OMNI_OK; ++rep) {
         HIP_TRY(hipEventRecord(e0, 0));
-        rc = launch_general(ap, fs, fmt, zero, Tt, p->time_block, tw, 0, &slices);
+        rc = ct ? launch_ct(ap, fmt, zero, Tt, p->time_block, tw, 0, &slices)
+                : launch_general(ap, fs, fmt, zero, Tt, p->time_block, tw, 0, &slices);
         HIP_TRY(hipEventRecord(e1, 0));
         HIP_TRY(hipEventSynchronize(e1));
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -975,7 +1042,10 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
     const ArrayPlan& ap = plan->arrays[i];
     const FusedP& P = ap.fs.fp;
     if (i) s += ",";
-    const char* kname = ap.kernel == 1 ? "fused8x4_fp32" : ap.kernel == 2 ? "fused8x4_mixed" : "fused_fp32";
+    const char* kname = ap.kernel == 1   ? "fused8x4_fp32"
+                        : ap.kernel == 2 ? "fused8x4_mixed"
+                        : ap.kernel == 3 ? "fused_ct_fp32"
+                                         : "fused_fp32";
     s += std::string("{\"kernel\":\"") + kname + "\",\"mode\":\"" + (ap.n_front ? "front" : "direct") +
          "\",\"n_front\":" + std::to_string(ap.n_front) + ",\"chunk_T\":" + std::to_string(ap.chunk_T) +
          ",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) + ",\"F\":" + std::to_string(ap.F) +

@@ -25,7 +25,7 @@
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte read.
 // The next sample's input is prefetched during the current one, and P3/P4 are
 // software-pipelined over a double-buffered chunk buffer (six barriers per
-// sample).
+// iteration of one or two samples).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -116,16 +116,17 @@ __device__ __forceinline__ int l4_row(int comp, int k1, int q, int k2c) {
 
 }  // namespace f8m
 
-template <int FMT>
-__global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* __restrict__ src, int64_t T,
-                                                                    int64_t t_per_slice,
-                                                                    const float2* __restrict__ tw16,
-                                                                    double* __restrict__ partial, int F,
-                                                                    int xcd_groups) {
+// NS time samples are processed per iteration, each with its own LDS buffers
+// (NS = 2: 160 KiB, one work-group per CU, up to 256 VGPRs; NS = 1: 80 KiB,
+// two work-groups per CU, 128 VGPRs).  Both samples add into the same cells.
+template <int FMT, int NS>
+__global__ __launch_bounds__(f8m::NT, NS == 2 ? 2 : 4) void fused8x4_mixed_kernel(
+    const void* __restrict__ src, int64_t T, int64_t t_per_slice, const float2* __restrict__ tw16,
+    double* __restrict__ partial, int F, int xcd_groups) {
   using namespace f8m;
-  __shared__ _Float16 L2[2 * 8 * 8 * 8 * 8];
-  __shared__ _Float16 L3[2 * 8 * 16 * 8 * 8];
-  __shared__ _Float16 L4[2][2 * 16 * 32 * 8];
+  __shared__ _Float16 L2[NS][2 * 8 * 8 * 8 * 8];
+  __shared__ _Float16 L3[NS][2 * 8 * 16 * 8 * 8];
+  __shared__ _Float16 L4[NS][2][2 * 16 * 32 * 8];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -165,64 +166,73 @@ __global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* 
   const int p1_off = ((wave * 8 + (col >> 3)) * 8 + (col & 7)) * 8;  // + 4*8*8 samples for tt = 1
   const int64_t t0 = (int64_t)s * t_per_slice;
   const int64_t t1 = min(T, t0 + t_per_slice);
-  Raw<FMT> raw0, raw1;
-  if (t0 < t1) {
-    const int64_t tile = (t0 * F + f) * 4096;
-    raw0.load(src, tile + p1_off);
-    raw1.load(src, tile + p1_off + 256);
-  }
-  for (int64_t t = t0; t < t1; ++t) {
-    // ---- P1: axis 3 from the prefetched samples; prefetch the next sample
-    {
-      const half8 a0 = raw0.to_half(hh), a1 = raw1.to_half(hh);
-      if (t + 1 < t1) {
-        const int64_t tile = ((t + 1) * F + f) * 4096;
-        raw0.load(src, tile + p1_off);
-        raw1.load(src, tile + p1_off + 256);
-      }
-      // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
-      const bool keep = (col & 1) == h;
-      const int comp = col >> 4, q = (col & 15) >> 1;
+  Raw<FMT> raw[NS][2];
 #pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        floatx16 d = mfma(tt ? a1 : a0, Wf_hi, zero);
-        d = mfma(tt ? a1 : a0, Wf_lo, d);
-        if (keep) {
+  for (int ss = 0; ss < NS; ++ss)
+    if (t0 + ss < t1) {
+      const int64_t tile = ((t0 + ss) * F + f) * 4096;
+      raw[ss][0].load(src, tile + p1_off);
+      raw[ss][1].load(src, tile + p1_off + 256);
+    }
+  const bool keep = (col & 1) == h;
+  for (int64_t t = t0; t < t1; t += NS) {
+    const int nss = (int)min((int64_t)NS, t1 - t);  // samples in this iteration (uniform)
+    // ---- P1: axis 3 from the prefetched samples; prefetch the next ones
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            store4(&L2[l2_row(comp, wave, q, 4 * tt + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-                   d[4 * i + 3]);
+    for (int ss = 0; ss < NS; ++ss) {
+      if (ss < nss) {
+        const half8 a0 = raw[ss][0].to_half(hh), a1 = raw[ss][1].to_half(hh);
+        if (t + NS + ss < t1) {
+          const int64_t tile = ((t + NS + ss) * F + f) * 4096;
+          raw[ss][0].load(src, tile + p1_off);
+          raw[ss][1].load(src, tile + p1_off + 256);
+        }
+        // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
+        const int comp = col >> 4, q = (col & 15) >> 1;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+          floatx16 d = mfma(tt ? a1 : a0, Wf_hi, zero);
+          d = mfma(tt ? a1 : a0, Wf_lo, d);
+          if (keep) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              store4(&L2[ss][l2_row(comp, wave, q, 4 * tt + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+                     d[4 * i + 3]);
+          }
         }
       }
     }
     __syncthreads();
     // ---- P2: axis 2; tile T2 = 2 wave + tt: lines (i0, q, i1) = (wave, 4 tt + r/8, r%8)
-    {
-      const int i1 = col & 7, qa = col >> 3;
-      const int comp = col >> 4, k2 = col & 15;
 #pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        const half8 a = *reinterpret_cast<const half8*>(&L2[l2_row(hh, wave, 4 * tt + qa, i1) * 8]);
-        floatx16 d = mfma(a, Wf_hi, zero);
-        d = mfma(a, Wf_lo, d);
-        // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
+    for (int ss = 0; ss < NS; ++ss) {
+      if (ss < nss) {
+        const int i1 = col & 7, qa = col >> 3;
+        const int comp = col >> 4, k2 = col & 15;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          store4(&L3[l3_row(comp, 4 * tt + i, k2, wave) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-                 d[4 * i + 3]);
+        for (int tt = 0; tt < 2; ++tt) {
+          const half8 a = *reinterpret_cast<const half8*>(&L2[ss][l2_row(hh, wave, 4 * tt + qa, i1) * 8]);
+          floatx16 d = mfma(a, Wf_hi, zero);
+          d = mfma(a, Wf_lo, d);
+          // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            store4(&L3[ss][l3_row(comp, 4 * tt + i, k2, wave) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+                   d[4 * i + 3]);
+        }
       }
     }
     __syncthreads();
-    // ---- P3 (axis 1) for kappa_2 chunk cc into L4[cc & 1]: tile = wave, lines (q, k2c, i0) with
+    // ---- P3 (axis 1) for kappa_2 chunk cc into L4[ss][cc & 1]: tile = wave, lines (q, k2c, i0) with
     //      (q, k2c) index = 4 wave + r/8, i0 = r%8
-    auto pass3 = [&](int cc) {
+    auto pass3 = [&](int ss, int cc) {
       const int idx = 4 * wave + (col >> 3);
       const int q = idx >> 2, k2c = idx & 3, i0 = col & 7;
-      const half8 a = *reinterpret_cast<const half8*>(&L3[l3_row(hh, q, 4 * cc + k2c, i0) * 8]);
+      const half8 a = *reinterpret_cast<const half8*>(&L3[ss][l3_row(hh, q, 4 * cc + k2c, i0) * 8]);
       floatx16 d = mfma(a, Wf_hi, zero);
       d = mfma(a, Wf_lo, d);
       const int comp = col >> 4, k1 = col & 15;
-      _Float16* L = L4[cc & 1];
+      _Float16* L = L4[ss][cc & 1];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int id2 = 4 * wave + i;
@@ -230,27 +240,38 @@ __global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* 
                d[4 * i + 3]);
       }
     };
-    pass3(0);
+#pragma unroll
+    for (int ss = 0; ss < NS; ++ss)
+      if (ss < nss) pass3(ss, 0);
     __syncthreads();
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
       // ---- P4: axis 0 on lines (k1, q, k2c) = (2 wave + tt, r/4, r%4); square and accumulate
-      const _Float16* L = L4[cc & 1];
 #pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        const half8 bop = *reinterpret_cast<const half8*>(&L[l4_row(hh, 2 * wave + tt, col >> 2, col & 3) * 8]);
-        floatx16 d = mfma(Wf_hi, bop, zero);
-        d = mfma(Wf_lo, bop, d);
-        // rows: 4hh + j (re), 8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im)
-        const int base = cc * 16 + tt * 8;
+      for (int ss = 0; ss < NS; ++ss) {
+        if (ss < nss) {
+          const _Float16* L = L4[ss][cc & 1];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
-          acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
+          for (int tt = 0; tt < 2; ++tt) {
+            const half8 bop = *reinterpret_cast<const half8*>(&L[l4_row(hh, 2 * wave + tt, col >> 2, col & 3) * 8]);
+            floatx16 d = mfma(Wf_hi, bop, zero);
+            d = mfma(Wf_lo, bop, d);
+            // rows: 4hh + j (re), 8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im)
+            const int base = cc * 16 + tt * 8;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
+              acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
+            }
+          }
         }
       }
-      if (cc < 3) pass3(cc + 1);
-      if (cc < 3) __syncthreads();
+      if (cc < 3) {
+#pragma unroll
+        for (int ss = 0; ss < NS; ++ss)
+          if (ss < nss) pass3(ss, cc + 1);
+        __syncthreads();
+      }
     }
   }
   // |X|^2 carried 8^-8 = 2^-24 from the four scaled stages
@@ -259,21 +280,24 @@ __global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* 
   for (int i = 0; i < CPL; ++i) out[i * NT + tid] = (double)acc[i] * 16777216.0;
 }
 
-hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16,
-                                 double* partial, int F, int n_slices, hipStream_t st) {
+hipError_t launch_fused8x4_mixed(int fmt, int ns_per_iter, const void* src, int64_t T, int64_t tps,
+                                 const float2* tw16, double* partial, int F, int n_slices, hipStream_t st) {
   const int groups = n_slices * F;
   const int xcd = (groups % 8 == 0) ? 1 : 0;
   const dim3 grid(groups * 2), block(f8m::NT);
-  switch (fmt) {
-    case 1:
-      hipLaunchKernelGGL(fused8x4_mixed_kernel<1>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd);
-      break;
-    case 2:
-      hipLaunchKernelGGL(fused8x4_mixed_kernel<2>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+#define OMNI_MIXED(F_, NS_) \
+  hipLaunchKernelGGL((fused8x4_mixed_kernel<F_, NS_>), grid, block, 0, st, src, T, tps, tw16, partial, F, xcd)
+  if (fmt == 1 && ns_per_iter == 2)
+    OMNI_MIXED(1, 2);
+  else if (fmt == 1)
+    OMNI_MIXED(1, 1);
+  else if (fmt == 2 && ns_per_iter == 2)
+    OMNI_MIXED(2, 2);
+  else if (fmt == 2)
+    OMNI_MIXED(2, 1);
+  else
+    return hipErrorInvalidValue;
+#undef OMNI_MIXED
   return hipGetLastError();
 }
 

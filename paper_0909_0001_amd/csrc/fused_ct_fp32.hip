@@ -1,0 +1,408 @@
+// Fused float32 correlator with a compile-time shape (gfx950).
+//
+// The schedule is the general fused kernel's (fold + short DFT per axis,
+// Fourier cells divided among work-groups by residue classes of axis 0, cells
+// in the same layout), but every extent and stride is a compile-time power of
+// two, so job and address arithmetic reduce to shifts and masks, intermediate
+// arrays ping-pong between two LDS buffers (one barrier per pass), the short
+// DFTs' twiddles live in registers, and the last pass adds |X|^2 straight into
+// the thread's registers.
+//
+// Per axis k: n_k antennas, padded length m_k = 2 n_k, fold modulus r_k,
+// short-DFT length L_k = m_k / r_k; the outputs with frequency = rho (mod r_k)
+// are X[r_k q + rho] = DFT_L(z)[q], z_j = sum_l x[j + l L] w_m^{rho (j + l L)}
+// (the zero-padded DFT of Sec. II.A/II.C split by residue class).  A
+// work-group holds R_k = r_k / S_k residue classes of axis k (S_0 = the split,
+// S_k = 1 otherwise), so its extent along k is E_k = R_k L_k.  Passes run over
+// axis 0 (from HBM), then axes d-1 ... 2 (LDS), then axis 1 (squared).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "plan.hpp"
+
+namespace omni {
+
+namespace ct {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+template <int D_, int N0, int N1, int N2, int N3, int R0, int R1, int R2, int R3, int S0_>
+struct Shape {
+  static constexpr int D = D_;
+  static constexpr int S0 = S0_;
+  static constexpr int n(int k) { return k == 0 ? N0 : k == 1 ? N1 : k == 2 ? N2 : N3; }
+  static constexpr int r(int k) { return k == 0 ? R0 : k == 1 ? R1 : k == 2 ? R2 : R3; }
+  static constexpr int m(int k) { return 2 * n(k); }
+  static constexpr int L(int k) { return m(k) / r(k); }
+  static constexpr int Rw(int k) { return k == 0 ? r(0) / S0 : r(k); }
+  static constexpr int E(int k) { return Rw(k) * L(k); }
+  static constexpr int step(int k) { return k == 0 ? S0 : 1; }
+  // processing order: 0, D-1, D-2, ..., 1
+  static constexpr int axis_of(int p) { return p == 0 ? 0 : D - p; }
+  static constexpr bool done_before(int p, int j) {
+    for (int q = 0; q < p; ++q)
+      if (axis_of(q) == j) return true;
+    return false;
+  }
+  static constexpr int ext(int p, int j) { return done_before(p, j) ? E(j) : n(j); }
+  static constexpr int inner(int p, int k) {
+    int s = 1;
+    for (int j = k + 1; j < D; ++j) s *= ext(p, j);
+    return s;
+  }
+  static constexpr int lines(int p, int k) {
+    int s = 1;
+    for (int j = 0; j < D; ++j)
+      if (j != k) s *= ext(p, j);
+    return s;
+  }
+  static constexpr int size_after(int p) {  // elements of the array after pass p
+    int s = 1;
+    for (int j = 0; j < D; ++j) s *= done_before(p + 1, j) ? E(j) : n(j);
+    return s;
+  }
+  static constexpr int N() {
+    int s = 1;
+    for (int j = 0; j < D; ++j) s *= n(j);
+    return s;
+  }
+  static constexpr int cells() {
+    int s = 1;
+    for (int j = 0; j < D; ++j) s *= E(j);
+    return s;
+  }
+};
+
+template <int FMT>
+__device__ __forceinline__ float2 load(const void* __restrict__ base, int64_t i) {
+  if (FMT == 0) return reinterpret_cast<const float2*>(base)[i];
+  if (FMT == 1) {
+    const char2 v = reinterpret_cast<const char2*>(base)[i];
+    return make_float2((float)v.x, (float)v.y);
+  }
+  const int8_t v = reinterpret_cast<const int8_t*>(base)[i];
+  return make_float2((float)(v >> 4), (float)((int8_t)(v << 4) >> 4));
+}
+
+// Radix-2 DIT DFT of length L (power of two), natural order; w_L^q = w32[q * 32 / L].
+template <int L>
+__device__ __forceinline__ void dft(float2 (&z)[L], const float2 (&w32)[16]) {
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    int j = 0;
+#pragma unroll
+    for (int b = 1, rb = L >> 1; b < L; b <<= 1, rb >>= 1)
+      if (i & b) j |= rb;
+    if (j > i) {
+      const float2 t = z[i];
+      z[i] = z[j];
+      z[j] = t;
+    }
+  }
+#pragma unroll
+  for (int s = 1; s < L; s <<= 1) {
+#pragma unroll
+    for (int k = 0; k < L; k += 2 * s) {
+#pragma unroll
+      for (int j = 0; j < s; ++j) {
+        float2 v = z[k + j + s];
+        if (j != 0) v = cmul(v, w32[j * (32 / (2 * s))]);
+        const float2 u = z[k + j];
+        z[k + j] = cadd(u, v);
+        z[k + j + s] = csub(u, v);
+      }
+    }
+  }
+}
+
+// Fold of one job: z_j = sum_l x[j + l L] w_m^{rho (j + l L)}, j < L.  The
+// blocks l run in a loop (unrolled by two) so that at most 2 L loads are live.
+template <int N, int M, int L, class Get>
+__device__ __forceinline__ void fold(float2 (&z)[L], int rho, const float2* __restrict__ twm, Get get) {
+#pragma unroll
+  for (int j = 0; j < L; ++j) z[j] = make_float2(0.f, 0.f);
+  static_assert(N % L == 0 || L % N == 0, "power-of-two extents");
+  if constexpr (N < L) {  // r = 1: one block, z_j = x_j w^{rho j} for j < N, zero above
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const float2 v = get(j);
+      z[j] = rho ? cmul(v, twm[(rho * j) & (M - 1)]) : v;
+    }
+    return;
+  }
+#pragma unroll 2
+  for (int l = 0; l < N / L; ++l) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const int p = j + l * L;
+      const float2 v = get(p);
+      z[j] = rho ? cadd(z[j], cmul(v, twm[(rho * p) & (M - 1)])) : cadd(z[j], v);
+    }
+  }
+}
+
+}  // namespace ct
+
+template <int FMT, class SH, int NT>
+__global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restrict__ src, int64_t T,
+                                                           int64_t t_per_slice, const float2* __restrict__ tw_glob,
+                                                           double* __restrict__ partial, int F, int xcd_groups,
+                                                           int time_block) {
+  using namespace ct;
+  constexpr int D = SH::D;
+  static_assert(D >= 2 && D <= 4, "compile-time shapes have 2 to 4 axes");
+  constexpr int S0 = SH::S0;
+  constexpr int CELLS = SH::cells();
+  constexpr int N = SH::N();
+  // LDS: two ping-pong buffers sized for the largest intermediate (all but the last pass)
+  constexpr int BUF = [] {
+    int b = 1;
+    for (int p = 0; p < SH::D - 1; ++p) b = b > SH::size_after(p) ? b : SH::size_after(p);
+    return b;
+  }();
+  constexpr int TWN = [] {
+    int s = 0;
+    for (int k = 0; k < SH::D; ++k) s += SH::m(k);
+    return s;
+  }();
+  __shared__ float2 buf[2][BUF];
+  __shared__ float2 tw[TWN];
+
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  int grp, c;
+  if (xcd_groups) {
+    const int xcd = b & 7, j = b >> 3;
+    grp = xcd + 8 * (j / S0);
+    c = j % S0;
+  } else {
+    grp = b / S0;
+    c = b % S0;
+  }
+  const int f = grp % F;
+  const int s = grp / F;
+  for (int i = tid; i < TWN; i += NT) tw[i] = tw_glob[i];
+  // short-DFT twiddles w32^q (q < 16), uniform: from the axis table of m = 32 if present, else derived
+  float2 w32[16];
+  __syncthreads();
+  {
+    // any axis table w_m^q with m >= 2 gives w32^q exactly only for m = 32; build from the largest table
+    int off = 0, mbest = 0, obest = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if (SH::m(k) > mbest) {
+        mbest = SH::m(k);
+        obest = off;
+      }
+      off += SH::m(k);
+    }
+    // w32^q = w_mbest^{q mbest / 32}; the short DFTs (L <= mbest) only use q with q mbest / 32 integral
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w32[q] = ((q * mbest) % 32 == 0) ? tw[obest + (q * mbest) / 32] : make_float2(0.f, 0.f);
+  }
+
+  constexpr int LLAST = SH::L(1 < D ? 1 : 0);
+  constexpr int KLAST = D > 1 ? 1 : 0;
+  constexpr int JOBS_LAST = SH::lines(D - 1, KLAST) * SH::Rw(KLAST);
+  static_assert(JOBS_LAST % NT == 0, "last-pass jobs must fill the work-group evenly");
+  constexpr int RL = JOBS_LAST / NT;
+  constexpr int CPT = RL * LLAST;
+  float acc32[CPT];
+  double acc64[CPT];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    acc32[i] = 0.f;
+    acc64[i] = 0.0;
+  }
+  int tw_off[4] = {0, 0, 0, 0};
+  {
+    int off = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      tw_off[k] = off;
+      off += SH::m(k);
+    }
+  }
+
+  const int64_t t0 = (int64_t)s * t_per_slice;
+  const int64_t t1 = min(T, t0 + t_per_slice);
+  int blk = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t tile = (t * F + f) * (int64_t)N;
+    // ---- pass 0: axis 0 from HBM into buf[0]
+    {
+      constexpr int K = 0, P = 0;
+      constexpr int n = SH::n(K), mm = SH::m(K), L = SH::L(K), RW = SH::Rw(K);
+      constexpr int IN = SH::inner(P, K), LINES = SH::lines(P, K), JOBS = LINES * RW;
+      constexpr int E = SH::E(K);
+#pragma unroll
+      for (int jb = 0; jb < (JOBS + NT - 1) / NT; ++jb) {
+        const int job = jb * NT + tid;
+        if (JOBS % NT == 0 || job < JOBS) {
+          const int i = job % RW, line = job / RW;
+          const int o = line / IN, in = line % IN;
+          const int rho = c + i * SH::step(K);
+          float2 z[L];
+          const int64_t sb = tile + (int64_t)o * n * IN + in;
+          fold<n, mm, L>(z, rho, tw + tw_off[K], [&](int p) { return load<FMT>(src, sb + (int64_t)p * IN); });
+          dft<L>(z, w32);
+#pragma unroll
+          for (int q = 0; q < L; ++q) buf[0][(o * E + i * L + q) * IN + in] = z[q];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- passes 1 .. D-2: axes D-1 ... 2, LDS -> LDS
+    auto mid = [&](auto PC) {
+      constexpr int P = decltype(PC)::value;
+      constexpr int K = SH::axis_of(P);
+      constexpr int n = SH::n(K), mm = SH::m(K), L = SH::L(K), RW = SH::Rw(K);
+      constexpr int IN = SH::inner(P, K), LINES = SH::lines(P, K), JOBS = LINES * RW;
+      constexpr int E = SH::E(K);
+      const float2* sb_ = buf[(P - 1) & 1];
+      float2* db_ = buf[P & 1];
+#pragma unroll
+      for (int jb = 0; jb < (JOBS + NT - 1) / NT; ++jb) {
+        const int job = jb * NT + tid;
+        if (JOBS % NT == 0 || job < JOBS) {
+          const int i = job % RW, line = job / RW;
+          const int o = line / IN, in = line % IN;
+          const int rho = i;
+          float2 z[L];
+          const float2* sp = sb_ + o * n * IN + in;
+          fold<n, mm, L>(z, rho, tw + tw_off[K], [&](int p) { return sp[p * IN]; });
+          dft<L>(z, w32);
+#pragma unroll
+          for (int q = 0; q < L; ++q) db_[(o * E + i * L + q) * IN + in] = z[q];
+        }
+      }
+      __syncthreads();
+    };
+    if constexpr (D > 2) mid(std::integral_constant<int, 1>{});
+    if constexpr (D > 3) mid(std::integral_constant<int, 2>{});
+    // ---- last pass: axis 1, squared into the registers
+    if constexpr (D > 1) {
+      constexpr int P = D - 1, K = 1;
+      constexpr int n = SH::n(K), mm = SH::m(K), L = SH::L(K), RW = SH::Rw(K);
+      constexpr int IN = SH::inner(P, K);
+      const float2* sb_ = buf[(P - 1) & 1];
+#pragma unroll
+      for (int jr = 0; jr < RL; ++jr) {
+        const int job = jr * NT + tid;
+        const int i = job % RW, line = job / RW;
+        const int o = line / IN, in = line % IN;
+        float2 z[L];
+        const float2* sp = sb_ + o * n * IN + in;
+        fold<n, mm, L>(z, i, tw + tw_off[K], [&](int p) { return sp[p * IN]; });
+        dft<L>(z, w32);
+#pragma unroll
+        for (int q = 0; q < L; ++q) acc32[jr * L + q] = fmaf(z[q].x, z[q].x, fmaf(z[q].y, z[q].y, acc32[jr * L + q]));
+      }
+    }
+    __syncthreads();  // the next sample's pass 0 overwrites buf[0]
+    if (++blk == time_block) {
+      blk = 0;
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        acc64[i] += (double)acc32[i];
+        acc32[i] = 0.f;
+      }
+    }
+  }
+  // cells in the layout [E_0][E_1]...[E_{D-1}] (row-major); this thread's job jr covers
+  // line (o, in) of axis 1 and residue i, outputs q at (o * E_1 + i L + q) * IN + in.
+  if constexpr (D > 1) {
+    constexpr int P = D - 1, K = 1;
+    constexpr int L = SH::L(K), RW = SH::Rw(K), E = SH::E(K);
+    constexpr int IN = SH::inner(P, K);
+    double* out = partial + ((int64_t)grp * S0 + c) * CELLS;
+#pragma unroll
+    for (int jr = 0; jr < RL; ++jr) {
+      const int job = jr * NT + tid;
+      const int i = job % RW, line = job / RW;
+      const int o = line / IN, in = line % IN;
+#pragma unroll
+      for (int q = 0; q < L; ++q) out[(o * E + i * L + q) * IN + in] = acc64[jr * L + q] + (double)acc32[jr * L + q];
+    }
+  }
+}
+
+// Shapes with a compile-time kernel.  The planner (api.cpp) must choose the same
+// fold moduli and split; launch_fused_ct returns hipErrorInvalidValue otherwise.
+struct CtEntry {
+  int d, n[4], r[4], s0;
+};
+
+template <int FMT, class SH>
+static hipError_t launch_one(const void* src, int64_t T, int64_t tps, const float2* tw, double* partial, int F,
+                             int n_slices, int time_block, hipStream_t st) {
+  const int groups = n_slices * F;
+  const int xcd = (groups % 8 == 0) ? 1 : 0;
+  hipLaunchKernelGGL((fused_ct_fp32_kernel<FMT, SH, 256>), dim3(groups * SH::S0), dim3(256), 0, st, src, T, tps, tw,
+                     partial, F, xcd, time_block);
+  return hipGetLastError();
+}
+
+// (8,8,4,4): the three-level hierarchy after its 16x16 front; (16,16,16): the
+// 16x16-of-16x16 array after one front axis; (4,4,4,4,4) does not fit d <= 4.
+using ShapeA = ct::Shape<4, 8, 8, 4, 4, 8, 2, 1, 1, 2>;      // cells 8192, split 2
+using ShapeB = ct::Shape<3, 16, 16, 16, 0, 4, 2, 2, 1, 4>;   // cells 8192, split 4
+using ShapeC = ct::Shape<2, 32, 32, 0, 0, 8, 8, 1, 1, 1>;    // 32x32: cells 4096
+using ShapeD = ct::Shape<2, 64, 64, 0, 0, 8, 8, 1, 1, 2>;      // 64x64: cells 8192, split 2
+using ShapeE = ct::Shape<2, 128, 128, 0, 0, 16, 16, 1, 1, 8>;  // 128x128: cells 8192, split 8
+
+const CtEntry kCtShapes[] = {
+    {4, {8, 8, 4, 4}, {8, 2, 1, 1}, 2},
+    {3, {16, 16, 16, 0}, {4, 2, 2, 1}, 4},
+    {2, {32, 32, 0, 0}, {8, 8, 1, 1}, 1},
+    {2, {64, 64, 0, 0}, {8, 8, 1, 1}, 2},
+    {2, {128, 128, 0, 0}, {16, 16, 1, 1}, 8},
+};
+
+int fused_ct_lookup(int d, const int* n) {
+  for (int i = 0; i < (int)(sizeof(kCtShapes) / sizeof(kCtShapes[0])); ++i) {
+    const CtEntry& e = kCtShapes[i];
+    if (e.d != d) continue;
+    bool ok = true;
+    for (int k = 0; k < d; ++k) ok = ok && e.n[k] == n[k];
+    if (ok) return i;
+  }
+  return -1;
+}
+
+void fused_ct_params(int idx, int* r, int* s0) {
+  const CtEntry& e = kCtShapes[idx];
+  for (int k = 0; k < e.d; ++k) r[k] = e.r[k];
+  *s0 = e.s0;
+}
+
+hipError_t launch_fused_ct(int idx, int fmt, const void* src, int64_t T, int64_t tps, const float2* tw,
+                           double* partial, int F, int n_slices, int time_block, hipStream_t st) {
+#define OMNI_CT(SH_)                                                                                          \
+  switch (fmt) {                                                                                              \
+    case 0: return launch_one<0, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, st);                 \
+    case 1: return launch_one<1, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, st);                 \
+    case 2: return launch_one<2, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, st);                 \
+    default: return hipErrorInvalidValue;                                                                     \
+  }
+  switch (idx) {
+    case 0: OMNI_CT(ShapeA)
+    case 1: OMNI_CT(ShapeB)
+    case 2: OMNI_CT(ShapeC)
+    case 3: OMNI_CT(ShapeD)
+    case 4: OMNI_CT(ShapeE)
+    default: return hipErrorInvalidValue;
+  }
+#undef OMNI_CT
+}
+
+}  // namespace omni

@@ -284,7 +284,12 @@ def test_mixed_other_shapes_fall_back_to_fp32_kernel():
 
 @pytest.mark.parametrize(
     "level_dims, dtype, T",
-    [([[4, 4], [4, 4], [4, 4]], "ci8", 150), ([[8, 8], [4, 4], [2, 2]], "cf32", 9), ([[4, 4], [4, 4], [4, 4]], "ci4", 7)],
+    [
+        ([[4, 4], [4, 4], [4, 4]], "ci8", 150),
+        ([[8, 8], [4, 4], [2, 2]], "cf32", 9),
+        ([[4, 4], [4, 4], [4, 4]], "ci4", 7),
+        ([[2, 2], [8, 8], [4, 4]], "ci8", 70),  # rest (8, 8, 4, 4): compile-time-shape kernel
+    ],
 )
 def test_front_mode_full_oracle(level_dims, dtype, T):
     """Shapes whose grid needs front passes; T=150 spans several time chunks of the front workspace."""
@@ -351,14 +356,17 @@ def test_hier16x16_sampled_cells():
     sampled_cells_check(skysim.WORKLOADS["hier16x16"], T=10, F=3)
 
 
-def test_autotuned_plan_matches_oracle():
+@pytest.mark.parametrize("level_dims,kernel", [([[32, 32]], "fused_ct_fp32"), ([[16, 32]], "fused_fp32")])
+def test_autotuned_plan_matches_oracle(level_dims, kernel):
     """A plan made with the autotuner still agrees with the oracle (schedule only changes speed)."""
     gen = torch.Generator().manual_seed(31)
-    raw = random_raw("ci4", 21, 2, 1024, gen)
-    plan = omni.Plan([[32, 32]], None, 2, "ci4", "fp32", tune=True)
+    N = math.prod(level_dims[0])
+    raw = random_raw("ci4", 21, 2, N, gen)
+    plan = omni.Plan(level_dims, None, 2, "ci4", "fp32", tune=True)
     d = plan.describe()
     say("tuned", d)
+    assert f'"kernel":"{kernel}"' in d
     assert '"tuned_ms":0.000000' not in d
     vis = plan.correlate(raw.cuda())
     torch.cuda.synchronize()
-    assert rel_err(vis.cpu().numpy(), oracle_vis(raw, "ci4", [[32, 32]])) <= TOL["fp32"]
+    assert rel_err(vis.cpu().numpy(), oracle_vis(raw, "ci4", level_dims)) <= TOL["fp32"]
