@@ -124,8 +124,9 @@ __device__ __forceinline__ void dft(float2 (&z)[L], const float2 (&w32)[16]) {
   }
 }
 
-// Fold of one job: z_j = sum_l x[j + l L] w_m^{rho (j + l L)}, j < L.  The
-// blocks l run in a loop (unrolled by two) so that at most 2 L loads are live.
+// Fold of one job: z_j = sum_l x[j + l L] w_m^{rho (j + l L)}, j < L, as four
+// FMAs per term (twiddle w_m^0 = 1 included, so that the loop has no branch).
+// The blocks l run in a loop (unrolled by two) so that at most 2 L loads are live.
 template <int N, int M, int L, class Get>
 __device__ __forceinline__ void fold(float2 (&z)[L], int rho, const float2* __restrict__ twm, Get get) {
 #pragma unroll
@@ -135,7 +136,7 @@ __device__ __forceinline__ void fold(float2 (&z)[L], int rho, const float2* __re
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const float2 v = get(j);
-      z[j] = rho ? cmul(v, twm[(rho * j) & (M - 1)]) : v;
+      z[j] = cmul(v, twm[(rho * j) & (M - 1)]);
     }
     return;
   }
@@ -145,14 +146,50 @@ __device__ __forceinline__ void fold(float2 (&z)[L], int rho, const float2* __re
     for (int j = 0; j < L; ++j) {
       const int p = j + l * L;
       const float2 v = get(p);
-      z[j] = rho ? cadd(z[j], cmul(v, twm[(rho * p) & (M - 1)])) : cadd(z[j], v);
+      const float2 w = twm[(rho * p) & (M - 1)];
+      z[j].x = fmaf(v.x, w.x, fmaf(-v.y, w.y, z[j].x));
+      z[j].y = fmaf(v.x, w.y, fmaf(v.y, w.x, z[j].y));
     }
   }
 }
 
 }  // namespace ct
 
-template <int FMT, class SH, int NT>
+// LDS arrays of intermediate values are XOR-swizzled inside blocks of 32
+// float2 (one sweep of the 64 four-byte banks): element e lives at
+// e ^ ((9 (e >> 5)) mod 32).  The passes' lane patterns (runs of consecutive
+// elements, or rows at power-of-two strides) then hit distinct banks.
+__device__ __forceinline__ int swz(int e) { return e ^ (((e >> 5) * 9) & 31); }
+
+template <int FMT>
+struct Sample;
+template <>
+struct Sample<0> {
+  static constexpr int bytes = 8;
+  __device__ static float2 get(const unsigned char* p, int e) { return reinterpret_cast<const float2*>(p)[e]; }
+};
+template <>
+struct Sample<1> {
+  static constexpr int bytes = 2;
+  __device__ static float2 get(const unsigned char* p, int e) {
+    const char2 v = reinterpret_cast<const char2*>(p)[e];
+    return make_float2((float)v.x, (float)v.y);
+  }
+};
+template <>
+struct Sample<2> {
+  static constexpr int bytes = 1;
+  __device__ static float2 get(const unsigned char* p, int e) {
+    const int8_t v = reinterpret_cast<const int8_t*>(p)[e];
+    return make_float2((float)(v >> 4), (float)((int8_t)(v << 4) >> 4));
+  }
+};
+
+// STAGE: the work-group copies each (time, channel) tile into LDS with
+// asynchronous direct-to-LDS loads (global_load_lds_dwordx4), one sample ahead
+// of the transform, so that pass 0 reads LDS and the HBM latency overlaps the
+// later passes.  Requires a 16-byte aligned source (checked by the host).
+template <int FMT, class SH, int NT, bool STAGE>
 __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restrict__ src, int64_t T,
                                                            int64_t t_per_slice, const float2* __restrict__ tw_glob,
                                                            double* __restrict__ partial, int F, int xcd_groups,
@@ -163,18 +200,21 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
   constexpr int S0 = SH::S0;
   constexpr int CELLS = SH::cells();
   constexpr int N = SH::N();
-  // LDS: two ping-pong buffers sized for the largest intermediate (all but the last pass)
-  constexpr int BUF = [] {
-    int b = 1;
-    for (int p = 0; p < SH::D - 1; ++p) b = b > SH::size_after(p) ? b : SH::size_after(p);
-    return b;
-  }();
+  constexpr int SB = Sample<FMT>::bytes;
+  // intermediate arrays: passes 0 and 2 write bufA, pass 1 writes bufB
+  constexpr int BA = SH::size_after(0) > (D > 3 ? SH::size_after(2) : 0) ? SH::size_after(0) : SH::size_after(2);
+  constexpr int BB = D > 2 ? SH::size_after(1) : 32;
+  static_assert(BA % 32 == 0 && BB % 32 == 0, "swizzle blocks");
   constexpr int TWN = [] {
     int s = 0;
     for (int k = 0; k < SH::D; ++k) s += SH::m(k);
     return s;
   }();
-  __shared__ float2 buf[2][BUF];
+  constexpr int RAWB = STAGE ? N * SB : 16;
+  static_assert(!STAGE || RAWB % 1024 == 0, "a staged tile is whole 1 KiB wave loads");
+  __shared__ __attribute__((aligned(16))) unsigned char raw[RAWB];
+  __shared__ float2 bufA[BA];
+  __shared__ float2 bufB[BB];
   __shared__ float2 tw[TWN];
 
   const int tid = threadIdx.x;
@@ -190,12 +230,32 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
   }
   const int f = grp % F;
   const int s = grp / F;
+  const int64_t t0 = (int64_t)s * t_per_slice;
+  const int64_t t1 = min(T, t0 + t_per_slice);
+
+  // asynchronous copy of tile (t, f) into raw: wave w moves 1 KiB pieces w, w + NT/64, ...
+  auto stage = [&](int64_t t) {
+    if constexpr (STAGE) {
+      const unsigned char* g = static_cast<const unsigned char*>(src) + (t * F + f) * (int64_t)N * SB;
+      const int w = tid >> 6, lane = tid & 63;
+#pragma unroll
+      for (int k = 0; k < (RAWB / 1024 + NT / 64 - 1) / (NT / 64); ++k) {
+        const int piece = w + k * (NT / 64);
+        if (piece < RAWB / 1024)
+          __builtin_amdgcn_global_load_lds(g + piece * 1024 + lane * 16,
+                                           (__attribute__((address_space(3))) void*)(raw + piece * 1024), 16, 0, 0);
+      }
+    }
+  };
+  if (t0 < t1) stage(t0);
+
   for (int i = tid; i < TWN; i += NT) tw[i] = tw_glob[i];
-  // short-DFT twiddles w32^q (q < 16), uniform: from the axis table of m = 32 if present, else derived
-  float2 w32[16];
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  // short-DFT twiddles w32^q (q < 16) from the largest axis table: w32^q = w_mb^{q mb / 32}; the
+  // short DFTs (L <= mb) only use q with q mb / 32 integral
+  float2 w32[16];
   {
-    // any axis table w_m^q with m >= 2 gives w32^q exactly only for m = 32; build from the largest table
     int off = 0, mbest = 0, obest = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -205,13 +265,11 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
       }
       off += SH::m(k);
     }
-    // w32^q = w_mbest^{q mbest / 32}; the short DFTs (L <= mbest) only use q with q mbest / 32 integral
 #pragma unroll
     for (int q = 0; q < 16; ++q) w32[q] = ((q * mbest) % 32 == 0) ? tw[obest + (q * mbest) / 32] : make_float2(0.f, 0.f);
   }
-
-  constexpr int LLAST = SH::L(1 < D ? 1 : 0);
-  constexpr int KLAST = D > 1 ? 1 : 0;
+  constexpr int KLAST = 1;
+  constexpr int LLAST = SH::L(KLAST);
   constexpr int JOBS_LAST = SH::lines(D - 1, KLAST) * SH::Rw(KLAST);
   static_assert(JOBS_LAST % NT == 0, "last-pass jobs must fill the work-group evenly");
   constexpr int RL = JOBS_LAST / NT;
@@ -223,44 +281,38 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
     acc32[i] = 0.f;
     acc64[i] = 0.0;
   }
-  int tw_off[4] = {0, 0, 0, 0};
-  {
-    int off = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      tw_off[k] = off;
-      off += SH::m(k);
-    }
-  }
+  constexpr int TWO[4] = {0, SH::m(0), SH::m(0) + SH::m(1), SH::m(0) + SH::m(1) + SH::m(2)};
 
-  const int64_t t0 = (int64_t)s * t_per_slice;
-  const int64_t t1 = min(T, t0 + t_per_slice);
+  // job -> (residue i, line (o, in)): the inner index is fastest, then the residue, then the outer index
   int blk = 0;
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t tile = (t * F + f) * (int64_t)N;
-    // ---- pass 0: axis 0 from HBM into buf[0]
+    // ---- pass 0: axis 0 from the tile into bufA
     {
       constexpr int K = 0, P = 0;
       constexpr int n = SH::n(K), mm = SH::m(K), L = SH::L(K), RW = SH::Rw(K);
       constexpr int IN = SH::inner(P, K), LINES = SH::lines(P, K), JOBS = LINES * RW;
       constexpr int E = SH::E(K);
+      const unsigned char* tile = STAGE ? raw
+                                        : static_cast<const unsigned char*>(src) + (t * F + f) * (int64_t)N * SB;
 #pragma unroll
       for (int jb = 0; jb < (JOBS + NT - 1) / NT; ++jb) {
         const int job = jb * NT + tid;
         if (JOBS % NT == 0 || job < JOBS) {
-          const int i = job % RW, line = job / RW;
-          const int o = line / IN, in = line % IN;
-          const int rho = c + i * SH::step(K);
+          const int in = job % IN, rest = job / IN;
+          const int i = rest % RW, o = rest / RW;
+          int rho = c + i * SH::step(K);
+          if constexpr (IN % 64 == 0) rho = __builtin_amdgcn_readfirstlane(rho);
           float2 z[L];
-          const int64_t sb = tile + (int64_t)o * n * IN + in;
-          fold<n, mm, L>(z, rho, tw + tw_off[K], [&](int p) { return load<FMT>(src, sb + (int64_t)p * IN); });
+          const int sb = o * n * IN + in;
+          fold<n, mm, L>(z, rho, tw + TWO[K], [&](int p) { return Sample<FMT>::get(tile, sb + p * IN); });
           dft<L>(z, w32);
 #pragma unroll
-          for (int q = 0; q < L; ++q) buf[0][(o * E + i * L + q) * IN + in] = z[q];
+          for (int q = 0; q < L; ++q) bufA[swz((o * E + i * L + q) * IN + in)] = z[q];
         }
       }
     }
     __syncthreads();
+    if (t + 1 < t1) stage(t + 1);  // the tile has been consumed: fetch the next one behind the later passes
     // ---- passes 1 .. D-2: axes D-1 ... 2, LDS -> LDS
     auto mid = [&](auto PC) {
       constexpr int P = decltype(PC)::value;
@@ -268,21 +320,20 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
       constexpr int n = SH::n(K), mm = SH::m(K), L = SH::L(K), RW = SH::Rw(K);
       constexpr int IN = SH::inner(P, K), LINES = SH::lines(P, K), JOBS = LINES * RW;
       constexpr int E = SH::E(K);
-      const float2* sb_ = buf[(P - 1) & 1];
-      float2* db_ = buf[P & 1];
+      const float2* sb_ = (P & 1) ? bufA : bufB;
+      float2* db_ = (P & 1) ? bufB : bufA;
 #pragma unroll
       for (int jb = 0; jb < (JOBS + NT - 1) / NT; ++jb) {
         const int job = jb * NT + tid;
         if (JOBS % NT == 0 || job < JOBS) {
-          const int i = job % RW, line = job / RW;
-          const int o = line / IN, in = line % IN;
-          const int rho = i;
+          const int in = job % IN, rest = job / IN;
+          const int i = rest % RW, o = rest / RW;
           float2 z[L];
-          const float2* sp = sb_ + o * n * IN + in;
-          fold<n, mm, L>(z, rho, tw + tw_off[K], [&](int p) { return sp[p * IN]; });
+          const int sb = o * n * IN + in;
+          fold<n, mm, L>(z, i, tw + TWO[K], [&](int p) { return sb_[swz(sb + p * IN)]; });
           dft<L>(z, w32);
 #pragma unroll
-          for (int q = 0; q < L; ++q) db_[(o * E + i * L + q) * IN + in] = z[q];
+          for (int q = 0; q < L; ++q) db_[swz((o * E + i * L + q) * IN + in)] = z[q];
         }
       }
       __syncthreads();
@@ -290,25 +341,26 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
     if constexpr (D > 2) mid(std::integral_constant<int, 1>{});
     if constexpr (D > 3) mid(std::integral_constant<int, 2>{});
     // ---- last pass: axis 1, squared into the registers
-    if constexpr (D > 1) {
-      constexpr int P = D - 1, K = 1;
+    {
+      constexpr int P = D - 1, K = KLAST;
       constexpr int n = SH::n(K), mm = SH::m(K), L = SH::L(K), RW = SH::Rw(K);
       constexpr int IN = SH::inner(P, K);
-      const float2* sb_ = buf[(P - 1) & 1];
+      const float2* sb_ = ((P - 1) & 1) ? bufB : bufA;
 #pragma unroll
       for (int jr = 0; jr < RL; ++jr) {
         const int job = jr * NT + tid;
-        const int i = job % RW, line = job / RW;
-        const int o = line / IN, in = line % IN;
+        const int in = job % IN, rest = job / IN;
+        const int i = rest % RW, o = rest / RW;
         float2 z[L];
-        const float2* sp = sb_ + o * n * IN + in;
-        fold<n, mm, L>(z, i, tw + tw_off[K], [&](int p) { return sp[p * IN]; });
+        const int sb = o * n * IN + in;
+        fold<n, mm, L>(z, i, tw + TWO[K], [&](int p) { return sb_[swz(sb + p * IN)]; });
         dft<L>(z, w32);
 #pragma unroll
         for (int q = 0; q < L; ++q) acc32[jr * L + q] = fmaf(z[q].x, z[q].x, fmaf(z[q].y, z[q].y, acc32[jr * L + q]));
       }
     }
-    __syncthreads();  // the next sample's pass 0 overwrites buf[0]
+    if constexpr (STAGE) __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next tile has landed
+    __syncthreads();  // next pass 0 overwrites bufA and reads the staged tile
     if (++blk == time_block) {
       blk = 0;
 #pragma unroll
@@ -318,18 +370,18 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
       }
     }
   }
-  // cells in the layout [E_0][E_1]...[E_{D-1}] (row-major); this thread's job jr covers
-  // line (o, in) of axis 1 and residue i, outputs q at (o * E_1 + i L + q) * IN + in.
-  if constexpr (D > 1) {
-    constexpr int P = D - 1, K = 1;
+  // cells in the layout [E_0][E_1]...[E_{D-1}] (row-major); job jr of this thread covers line (o, in) of
+  // axis 1 and residue i, its outputs q at (o * E_1 + i L + q) * IN + in.
+  {
+    constexpr int P = D - 1, K = KLAST;
     constexpr int L = SH::L(K), RW = SH::Rw(K), E = SH::E(K);
     constexpr int IN = SH::inner(P, K);
     double* out = partial + ((int64_t)grp * S0 + c) * CELLS;
 #pragma unroll
     for (int jr = 0; jr < RL; ++jr) {
       const int job = jr * NT + tid;
-      const int i = job % RW, line = job / RW;
-      const int o = line / IN, in = line % IN;
+      const int in = job % IN, rest = job / IN;
+      const int i = rest % RW, o = rest / RW;
 #pragma unroll
       for (int q = 0; q < L; ++q) out[(o * E + i * L + q) * IN + in] = acc64[jr * L + q] + (double)acc32[jr * L + q];
     }
@@ -347,8 +399,18 @@ static hipError_t launch_one(const void* src, int64_t T, int64_t tps, const floa
                              int n_slices, int time_block, hipStream_t st) {
   const int groups = n_slices * F;
   const int xcd = (groups % 8 == 0) ? 1 : 0;
-  hipLaunchKernelGGL((fused_ct_fp32_kernel<FMT, SH, 256>), dim3(groups * SH::S0), dim3(256), 0, st, src, T, tps, tw,
-                     partial, F, xcd, time_block);
+  // stage tiles of at most 32 KiB through LDS when the source is 16-byte aligned
+  constexpr int tile_bytes = SH::N() * Sample<FMT>::bytes;
+  const bool aligned = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+  if constexpr (tile_bytes <= 32768 && tile_bytes % 1024 == 0) {
+    if (aligned) {
+      hipLaunchKernelGGL((fused_ct_fp32_kernel<FMT, SH, 256, true>), dim3(groups * SH::S0), dim3(256), 0, st, src,
+                         T, tps, tw, partial, F, xcd, time_block);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((fused_ct_fp32_kernel<FMT, SH, 256, false>), dim3(groups * SH::S0), dim3(256), 0, st, src, T,
+                     tps, tw, partial, F, xcd, time_block);
   return hipGetLastError();
 }
 

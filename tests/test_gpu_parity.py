@@ -370,3 +370,25 @@ def test_autotuned_plan_matches_oracle(level_dims, kernel):
     vis = plan.correlate(raw.cuda())
     torch.cuda.synchronize()
     assert rel_err(vis.cpu().numpy(), oracle_vis(raw, "ci4", level_dims)) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("level_dims,dtype", [([[32, 32]], "ci4"), ([[64, 64]], "ci8"), ([[32, 32]], "cf32")])
+def test_unaligned_input_pointer(level_dims, dtype):
+    """A source pointer that is 4- but not 16-byte aligned takes the unstaged loads and gives the same result."""
+    N = math.prod(dims_of(level_dims))
+    gen = torch.Generator().manual_seed(N + 7)
+    raw = random_raw(dtype, 11, 2, N, gen)
+    flat = raw.reshape(-1)
+    pad = 4 // raw.element_size()  # 4 bytes: the library accepts 4-byte aligned sources
+    big = torch.empty(flat.numel() + pad, dtype=raw.dtype, device="cuda")
+    big[pad:].copy_(flat.cuda())
+    shifted = big[pad:].view(raw.shape)
+    assert shifted.data_ptr() % 16 != 0 and shifted.is_contiguous()
+    say("unaligned", level_dims, dtype, shifted.data_ptr() % 16)
+    plan = omni.Plan(level_dims, None, 2, dtype, "fp32")
+    assert '"kernel":"fused_ct_fp32"' in plan.describe()
+    got = plan.correlate(shifted)
+    ref = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    assert rel_err(got.cpu().numpy(), ref.cpu().numpy()) <= 1e-6
+    assert rel_err(got.cpu().numpy(), oracle_vis(raw, dtype, level_dims)) <= TOL["fp32"]
