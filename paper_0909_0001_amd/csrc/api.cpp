@@ -33,7 +33,7 @@ hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2
 int fused_ct_lookup(int d, const int* n);
 void fused_ct_params(int idx, int* r, int* s0);
 hipError_t launch_fused_ct(int idx, int fmt, const void* src, int64_t T, int64_t tps, const float2* tw,
-                           double* partial, int F, int n_slices, int time_block, hipStream_t st);
+                           double* partial, int F, int n_slices, int time_block, int accumulate, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -604,18 +604,21 @@ int launch_general(ArrayPlan& ap, const FusedSetup& fs, int fmt, const void* src
   return OMNI_OK;
 }
 
-// Compile-time-shape kernel over T samples; same slicing policy as the general kernel.
+// Compile-time-shape kernel over T samples; same slicing policy as the general kernel.  With
+// `accumulate` the kernel adds into the partial sums (at most max_ns slices, those of an earlier launch).
 int launch_ct(ArrayPlan& ap, int fmt, const void* src, int64_t T, int time_block, const float2* tw, hipStream_t st,
-              int* slices) {
+              int* slices, int accumulate = 0, int64_t max_ns = INT32_MAX) {
   const int64_t per_slice_groups = (int64_t)ap.fs.F * ap.fs.fp.n_split;
   int64_t ns = std::max<int64_t>(1, (ap.wg_target + per_slice_groups - 1) / per_slice_groups);
   ns = std::min<int64_t>(ns, ap.max_slices);
+  ns = std::min<int64_t>(ns, max_ns);
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 4));
   const int64_t tps = (T + ns - 1) / ns;
   ns = (T + tps - 1) / tps;
   if (ns * per_slice_groups > INT32_MAX) return fail(OMNI_E_SHAPE, "grid too large");
   *slices = (int)ns;
-  HIP_TRY(omni::launch_fused_ct(ap.ct_index, fmt, src, T, tps, tw, ap.d_partial, ap.fs.F, (int)ns, time_block, st));
+  HIP_TRY(omni::launch_fused_ct(ap.ct_index, fmt, src, T, tps, tw, ap.d_partial, ap.fs.F, (int)ns, time_block,
+                                accumulate, st));
   return OMNI_OK;
 }
 
@@ -624,8 +627,11 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
   const bool accumulate = (flags & OMNI_NO_RESET) != 0;
   if (stage == 0 && T > 0 && ap.n_front > 0) {
     // Front mode: per chunk of samples, front passes to HBM, then the fused
-    // kernel on the remaining axes, then the reduction into the accumulator.
+    // kernel on the remaining axes.  The general kernel's partial sums are
+    // reduced into the accumulator after every chunk; the compile-time-shape
+    // kernel adds the later chunks into the first chunk's slices, reduced once.
     const int s = ap.n_front;
+    int first_slices = 0;
     for (int64_t c0 = 0; c0 < T; c0 += ap.chunk_T) {
       const int64_t tc = std::min<int64_t>(ap.chunk_T, T - c0);
       const void* cur = static_cast<const char*>(volt) + (size_t)(c0 * ap.F * ap.N) * sample_bytes(p->dtype);
@@ -643,13 +649,21 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         fmt = 0;
       }
       int slices = 1;
-      int rc = ap.kernel == 3
-                   ? launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices)
-                   : launch_general(ap, ap.fs, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices);
+      if (ap.kernel == 3) {
+        int rc = c0 == 0 ? launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &first_slices)
+                         : launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices, 1,
+                                     first_slices);
+        if (rc) return rc;
+        continue;
+      }
+      int rc = launch_general(ap, ap.fs, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices);
       if (rc) return rc;
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, (accumulate || c0 > 0) ? 1 : 0, st));
     }
+    if (ap.kernel == 3)
+      HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, first_slices, ap.fs.F, ap.fs.fp.n_split,
+                                          ap.fs.fp.cells_wg, ap.fs.M, accumulate ? 1 : 0, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 1) {
     // three 48 KiB work-groups fit one CU: aim for two full rounds over 256 CUs
     const int64_t per_slice_groups = (int64_t)ap.F * 8;

@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "plan.hpp"
 
@@ -93,9 +94,43 @@ __device__ __forceinline__ float2 load(const void* __restrict__ base, int64_t i)
   return make_float2((float)(v >> 4), (float)((int8_t)(v << 4) >> 4));
 }
 
-// Radix-2 DIT DFT of length L (power of two), natural order; w_L^q = w32[q * 32 / L].
+// w_32^q = exp(-2 pi i q / 32), q < 16, as float32 constants: cos from the
+// first octant table (correctly rounded), sin by symmetry.
+constexpr float kCos32[9] = {0x1p+0f,         0x1.f6297cp-1f, 0x1.d906bcp-1f, 0x1.a9b662p-1f, 0x1.6a09e6p-1f,
+                             0x1.1c73b4p-1f, 0x1.87de2ap-2f, 0x1.8f8b84p-3f, 0.0f};
+constexpr float cos32(int q) { return q <= 8 ? kCos32[q] : -kCos32[16 - q]; }
+constexpr float msin32(int q) { return q <= 8 ? -kCos32[8 - q] : -kCos32[q - 8]; }
+
+// v * w_32^Q with Q a compile-time constant (Q = 0 and Q = 8 (-i) cost nothing)
+template <int Q>
+__device__ __forceinline__ float2 rot32(float2 v) {
+  if constexpr (Q == 0) return v;
+  if constexpr (Q == 8) return make_float2(v.y, -v.x);
+  constexpr float c = cos32(Q), sn = msin32(Q);
+  return make_float2(fmaf(v.x, c, -v.y * sn), fmaf(v.x, sn, v.y * c));
+}
+
+template <int L, int S, int K, int J>
+__device__ __forceinline__ void butterfly(float2 (&z)[L]) {
+  const float2 v = rot32<J * (32 / (2 * S))>(z[K + J + S]);
+  const float2 u = z[K + J];
+  z[K + J] = cadd(u, v);
+  z[K + J + S] = csub(u, v);
+}
+
+template <int L, int S, int K, int... J>
+__device__ __forceinline__ void butterflies(float2 (&z)[L], std::integer_sequence<int, J...>) {
+  (butterfly<L, S, K, J>(z), ...);
+}
+
+template <int L, int S, int... K>
+__device__ __forceinline__ void stage(float2 (&z)[L], std::integer_sequence<int, K...>) {
+  (butterflies<L, S, K * 2 * S>(z, std::make_integer_sequence<int, S>{}), ...);
+}
+
+// Radix-2 DIT DFT of length L <= 32 (power of two), natural order, compile-time twiddles.
 template <int L>
-__device__ __forceinline__ void dft(float2 (&z)[L], const float2 (&w32)[16]) {
+__device__ __forceinline__ void dft(float2 (&z)[L]) {
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     int j = 0;
@@ -108,58 +143,57 @@ __device__ __forceinline__ void dft(float2 (&z)[L], const float2 (&w32)[16]) {
       z[j] = t;
     }
   }
-#pragma unroll
-  for (int s = 1; s < L; s <<= 1) {
-#pragma unroll
-    for (int k = 0; k < L; k += 2 * s) {
-#pragma unroll
-      for (int j = 0; j < s; ++j) {
-        float2 v = z[k + j + s];
-        if (j != 0) v = cmul(v, w32[j * (32 / (2 * s))]);
-        const float2 u = z[k + j];
-        z[k + j] = cadd(u, v);
-        z[k + j + s] = csub(u, v);
-      }
-    }
-  }
+  if constexpr (L >= 2) stage<L, 1>(z, std::make_integer_sequence<int, L / 2>{});
+  if constexpr (L >= 4) stage<L, 2>(z, std::make_integer_sequence<int, L / 4>{});
+  if constexpr (L >= 8) stage<L, 4>(z, std::make_integer_sequence<int, L / 8>{});
+  if constexpr (L >= 16) stage<L, 8>(z, std::make_integer_sequence<int, L / 16>{});
+  if constexpr (L >= 32) stage<L, 16>(z, std::make_integer_sequence<int, L / 32>{});
 }
 
-// Fold of one job: z_j = sum_l x[j + l L] w_m^{rho (j + l L)}, j < L, as four
-// FMAs per term (twiddle w_m^0 = 1 included, so that the loop has no branch).
-// The blocks l run in a loop (unrolled by two) so that at most 2 L loads are live.
+// Fold of one job: z_j = sum_l x[j + l L] w_m^{rho (j + l L)}, j < L, with
+// m = M the padded length and n = N = M / 2 inputs, i.e. l < r / 2 non-zero
+// blocks (r = M / L).  Factored as z_j = w_m^{rho j} sum_l x[j + l L] w_r^{rho l},
+// so that the inner twiddles sit in registers and each input costs four FMAs;
+// the L outer twiddles come from the axis table.
+//   r = 1: rho = 0 and z_j = x_j (j < n), zero above.
+//   r = 2: one block, z_j = w_m^{rho j} x_j.
 template <int N, int M, int L, class Get>
 __device__ __forceinline__ void fold(float2 (&z)[L], int rho, const float2* __restrict__ twm, Get get) {
+  constexpr int R = M / L;
+  static_assert(M == 2 * N && R * L == M, "padded axis");
+  if constexpr (R == 1) {
 #pragma unroll
-  for (int j = 0; j < L; ++j) z[j] = make_float2(0.f, 0.f);
-  static_assert(N % L == 0 || L % N == 0, "power-of-two extents");
-  if constexpr (N < L) {  // r = 1: one block, z_j = x_j w^{rho j} for j < N, zero above
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const float2 v = get(j);
-      z[j] = cmul(v, twm[(rho * j) & (M - 1)]);
-    }
+    for (int j = 0; j < L; ++j) z[j] = j < N ? get(j) : make_float2(0.f, 0.f);
     return;
-  }
-#pragma unroll 2
-  for (int l = 0; l < N / L; ++l) {
+  } else {
+    constexpr int NB = N / L;  // = r / 2 non-zero blocks
+    float2 u[NB];
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-      const int p = j + l * L;
-      const float2 v = get(p);
-      const float2 w = twm[(rho * p) & (M - 1)];
-      z[j].x = fmaf(v.x, w.x, fmaf(-v.y, w.y, z[j].x));
-      z[j].y = fmaf(v.x, w.y, fmaf(v.y, w.x, z[j].y));
+    for (int l = 0; l < NB; ++l) u[l] = twm[(rho * l * L) & (M - 1)];  // w_r^{rho l}
+#pragma unroll
+    for (int j = 0; j < L; ++j) z[j] = get(j);  // l = 0: u_0 = 1
+#pragma unroll
+    for (int l = 1; l < NB; ++l) {
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        const float2 v = get(j + l * L);
+        const float2 w = u[l];
+        z[j].x = fmaf(v.x, w.x, fmaf(-v.y, w.y, z[j].x));
+        z[j].y = fmaf(v.x, w.y, fmaf(v.y, w.x, z[j].y));
+      }
     }
+#pragma unroll
+    for (int j = 1; j < L; ++j) z[j] = cmul(z[j], twm[(rho * j) & (M - 1)]);  // w_m^{rho j}
   }
 }
 
 }  // namespace ct
 
-// LDS arrays of intermediate values are XOR-swizzled inside blocks of 32
-// float2 (one sweep of the 64 four-byte banks): element e lives at
-// e ^ ((9 (e >> 5)) mod 32).  The passes' lane patterns (runs of consecutive
-// elements, or rows at power-of-two strides) then hit distinct banks.
-__device__ __forceinline__ int swz(int e) { return e ^ (((e >> 5) * 9) & 31); }
+// LDS arrays of intermediate values carry one float2 of padding after every
+// 32 (one sweep of the 64 four-byte banks): element e lives at e + e / 32.
+// Rows at power-of-two strides then start on distinct banks, and within a
+// job the offsets stay compile-time constants.
+__device__ __forceinline__ int swz(int e) { return e + (e >> 5); }
 
 template <int FMT>
 struct Sample;
@@ -193,7 +227,7 @@ template <int FMT, class SH, int NT, bool STAGE>
 __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restrict__ src, int64_t T,
                                                            int64_t t_per_slice, const float2* __restrict__ tw_glob,
                                                            double* __restrict__ partial, int F, int xcd_groups,
-                                                           int time_block) {
+                                                           int time_block, int accumulate) {
   using namespace ct;
   constexpr int D = SH::D;
   static_assert(D >= 2 && D <= 4, "compile-time shapes have 2 to 4 axes");
@@ -204,7 +238,7 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
   // intermediate arrays: passes 0 and 2 write bufA, pass 1 writes bufB
   constexpr int BA = SH::size_after(0) > (D > 3 ? SH::size_after(2) : 0) ? SH::size_after(0) : SH::size_after(2);
   constexpr int BB = D > 2 ? SH::size_after(1) : 32;
-  static_assert(BA % 32 == 0 && BB % 32 == 0, "swizzle blocks");
+  static_assert(BA % 32 == 0 && BB % 32 == 0, "padding blocks");
   constexpr int TWN = [] {
     int s = 0;
     for (int k = 0; k < SH::D; ++k) s += SH::m(k);
@@ -213,8 +247,8 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
   constexpr int RAWB = STAGE ? N * SB : 16;
   static_assert(!STAGE || RAWB % 1024 == 0, "a staged tile is whole 1 KiB wave loads");
   __shared__ __attribute__((aligned(16))) unsigned char raw[RAWB];
-  __shared__ float2 bufA[BA];
-  __shared__ float2 bufB[BB];
+  __shared__ float2 bufA[BA + BA / 32];
+  __shared__ float2 bufB[BB + BB / 32];
   __shared__ float2 tw[TWN];
 
   const int tid = threadIdx.x;
@@ -252,22 +286,6 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
   for (int i = tid; i < TWN; i += NT) tw[i] = tw_glob[i];
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  // short-DFT twiddles w32^q (q < 16) from the largest axis table: w32^q = w_mb^{q mb / 32}; the
-  // short DFTs (L <= mb) only use q with q mb / 32 integral
-  float2 w32[16];
-  {
-    int off = 0, mbest = 0, obest = 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      if (SH::m(k) > mbest) {
-        mbest = SH::m(k);
-        obest = off;
-      }
-      off += SH::m(k);
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) w32[q] = ((q * mbest) % 32 == 0) ? tw[obest + (q * mbest) / 32] : make_float2(0.f, 0.f);
-  }
   constexpr int KLAST = 1;
   constexpr int LLAST = SH::L(KLAST);
   constexpr int JOBS_LAST = SH::lines(D - 1, KLAST) * SH::Rw(KLAST);
@@ -305,7 +323,7 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
           float2 z[L];
           const int sb = o * n * IN + in;
           fold<n, mm, L>(z, rho, tw + TWO[K], [&](int p) { return Sample<FMT>::get(tile, sb + p * IN); });
-          dft<L>(z, w32);
+          dft<L>(z);
 #pragma unroll
           for (int q = 0; q < L; ++q) bufA[swz((o * E + i * L + q) * IN + in)] = z[q];
         }
@@ -331,7 +349,7 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
           float2 z[L];
           const int sb = o * n * IN + in;
           fold<n, mm, L>(z, i, tw + TWO[K], [&](int p) { return sb_[swz(sb + p * IN)]; });
-          dft<L>(z, w32);
+          dft<L>(z);
 #pragma unroll
           for (int q = 0; q < L; ++q) db_[swz((o * E + i * L + q) * IN + in)] = z[q];
         }
@@ -354,7 +372,7 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
         float2 z[L];
         const int sb = o * n * IN + in;
         fold<n, mm, L>(z, i, tw + TWO[K], [&](int p) { return sb_[swz(sb + p * IN)]; });
-        dft<L>(z, w32);
+        dft<L>(z);
 #pragma unroll
         for (int q = 0; q < L; ++q) acc32[jr * L + q] = fmaf(z[q].x, z[q].x, fmaf(z[q].y, z[q].y, acc32[jr * L + q]));
       }
@@ -371,7 +389,9 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
     }
   }
   // cells in the layout [E_0][E_1]...[E_{D-1}] (row-major); job jr of this thread covers line (o, in) of
-  // axis 1 and residue i, its outputs q at (o * E_1 + i L + q) * IN + in.
+  // axis 1 and residue i, its outputs q at (o * E_1 + i L + q) * IN + in.  With `accumulate` the sums are
+  // added to what the slot holds (successive launches over time chunks of the same slices).
+  if (t0 >= t1 && accumulate) return;
   {
     constexpr int P = D - 1, K = KLAST;
     constexpr int L = SH::L(K), RW = SH::Rw(K), E = SH::E(K);
@@ -383,7 +403,11 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
       const int in = job % IN, rest = job / IN;
       const int i = rest % RW, o = rest / RW;
 #pragma unroll
-      for (int q = 0; q < L; ++q) out[(o * E + i * L + q) * IN + in] = acc64[jr * L + q] + (double)acc32[jr * L + q];
+      for (int q = 0; q < L; ++q) {
+        const int cell = (o * E + i * L + q) * IN + in;
+        const double v = acc64[jr * L + q] + (double)acc32[jr * L + q];
+        out[cell] = accumulate ? out[cell] + v : v;
+      }
     }
   }
 }
@@ -396,7 +420,7 @@ struct CtEntry {
 
 template <int FMT, class SH>
 static hipError_t launch_one(const void* src, int64_t T, int64_t tps, const float2* tw, double* partial, int F,
-                             int n_slices, int time_block, hipStream_t st) {
+                             int n_slices, int time_block, int accumulate, hipStream_t st) {
   const int groups = n_slices * F;
   const int xcd = (groups % 8 == 0) ? 1 : 0;
   // stage tiles of at most 32 KiB through LDS when the source is 16-byte aligned
@@ -405,12 +429,12 @@ static hipError_t launch_one(const void* src, int64_t T, int64_t tps, const floa
   if constexpr (tile_bytes <= 32768 && tile_bytes % 1024 == 0) {
     if (aligned) {
       hipLaunchKernelGGL((fused_ct_fp32_kernel<FMT, SH, 256, true>), dim3(groups * SH::S0), dim3(256), 0, st, src,
-                         T, tps, tw, partial, F, xcd, time_block);
+                         T, tps, tw, partial, F, xcd, time_block, accumulate);
       return hipGetLastError();
     }
   }
   hipLaunchKernelGGL((fused_ct_fp32_kernel<FMT, SH, 256, false>), dim3(groups * SH::S0), dim3(256), 0, st, src, T,
-                     tps, tw, partial, F, xcd, time_block);
+                     tps, tw, partial, F, xcd, time_block, accumulate);
   return hipGetLastError();
 }
 
@@ -448,12 +472,12 @@ void fused_ct_params(int idx, int* r, int* s0) {
 }
 
 hipError_t launch_fused_ct(int idx, int fmt, const void* src, int64_t T, int64_t tps, const float2* tw,
-                           double* partial, int F, int n_slices, int time_block, hipStream_t st) {
+                           double* partial, int F, int n_slices, int time_block, int accumulate, hipStream_t st) {
 #define OMNI_CT(SH_)                                                                                          \
   switch (fmt) {                                                                                              \
-    case 0: return launch_one<0, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, st);                 \
-    case 1: return launch_one<1, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, st);                 \
-    case 2: return launch_one<2, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, st);                 \
+    case 0: return launch_one<0, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, accumulate, st);                 \
+    case 1: return launch_one<1, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, accumulate, st);                 \
+    case 2: return launch_one<2, SH_>(src, T, tps, tw, partial, F, n_slices, time_block, accumulate, st);                 \
     default: return hipErrorInvalidValue;                                                                     \
   }
   switch (idx) {
