@@ -246,8 +246,14 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
   }();
   constexpr int RAWB = STAGE ? N * SB : 16;
   static_assert(!STAGE || RAWB % 1024 == 0, "a staged tile is whole 1 KiB wave loads");
+  // INPLACE (three axes, float32 tile, one job per thread and column in pass 0): pass 0 writes its
+  // output over the consumed tile instead of bufA, and the next tile is fetched after pass 1.  This
+  // keeps two work-groups per CU for the (16,16,16) grid behind a front pass.
+  constexpr bool INPLACE = STAGE && FMT == 0 && D == 3 && SH::Rw(0) == 1 &&
+                           SH::lines(0, 0) == NT && (BA + BA / 32) * 8 <= RAWB;
   __shared__ __attribute__((aligned(16))) unsigned char raw[RAWB];
-  __shared__ float2 bufA[BA + BA / 32];
+  __shared__ float2 bufA[INPLACE ? 32 : BA + BA / 32];
+  float2* const rawf = reinterpret_cast<float2*>(raw);
   __shared__ float2 bufB[BB + BB / 32];
   __shared__ float2 tw[TWN];
 
@@ -323,14 +329,17 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
           float2 z[L];
           const int sb = o * n * IN + in;
           fold<n, mm, L>(z, rho, tw + TWO[K], [&](int p) { return Sample<FMT>::get(tile, sb + p * IN); });
+          if constexpr (INPLACE) __syncthreads();  // every column has been read before any is overwritten
           dft<L>(z);
+          float2* dst = INPLACE ? rawf : bufA;
 #pragma unroll
-          for (int q = 0; q < L; ++q) bufA[swz((o * E + i * L + q) * IN + in)] = z[q];
+          for (int q = 0; q < L; ++q) dst[swz((o * E + i * L + q) * IN + in)] = z[q];
         }
       }
     }
     __syncthreads();
-    if (t + 1 < t1) stage(t + 1);  // the tile has been consumed: fetch the next one behind the later passes
+    // the tile has been consumed: fetch the next one behind the later passes
+    if (!INPLACE && t + 1 < t1) stage(t + 1);
     // ---- passes 1 .. D-2: axes D-1 ... 2, LDS -> LDS
     auto mid = [&](auto PC) {
       constexpr int P = decltype(PC)::value;
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
       constexpr int n = SH::n(K), mm = SH::m(K), L = SH::L(K), RW = SH::Rw(K);
       constexpr int IN = SH::inner(P, K), LINES = SH::lines(P, K), JOBS = LINES * RW;
       constexpr int E = SH::E(K);
-      const float2* sb_ = (P & 1) ? bufA : bufB;
+      const float2* sb_ = (P & 1) ? (INPLACE ? rawf : bufA) : bufB;
       float2* db_ = (P & 1) ? bufB : bufA;
 #pragma unroll
       for (int jb = 0; jb < (JOBS + NT - 1) / NT; ++jb) {
@@ -357,6 +366,7 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
       __syncthreads();
     };
     if constexpr (D > 2) mid(std::integral_constant<int, 1>{});
+    if (INPLACE && t + 1 < t1) stage(t + 1);  // pass 1 has read pass 0's output out of the tile's space
     if constexpr (D > 3) mid(std::integral_constant<int, 2>{});
     // ---- last pass: axis 1, squared into the registers
     {
