@@ -69,65 +69,116 @@ __device__ __forceinline__ void dft(float2 (&z)[L], const float2* __restrict__ t
 
 }  // namespace fr
 
-// Grid: x over (tile, outer, inner) flattened with inner fastest, y over residues.
+// Grid: x over (tile, outer, inner / V) flattened with inner fastest, y over residues.
 // tiles = time samples x channels of this call; tile stride in the source is
-// src_tile (elements), in the destination dst_tile.
-template <int FMT, int L>
+// src_tile (elements), in the destination dst_tile.  Each thread transforms V
+// consecutive inner indices, so that 1- and 2-byte samples are read as 4- or
+// 8-byte words (V = 4) and the outputs leave as 32-byte runs.
+template <int FMT, int L, int V>
 __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict__ src, float2* __restrict__ dst,
                                                           const float2* __restrict__ twm, int64_t tiles,
                                                           int64_t outer, int n, int m, int r, int64_t inner,
                                                           int64_t src_tile, int64_t dst_tile) {
   using namespace fr;
-  const int64_t per_tile = outer * inner;
+  const int64_t inner_v = inner / V;
+  const int64_t per_tile = outer * inner_v;
   const int64_t total = tiles * per_tile;
   const int rho = blockIdx.y;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t tile = idx / per_tile;
     const int64_t rem = idx - tile * per_tile;
-    const int64_t o = rem / inner, in = rem - o * inner;
+    const int64_t o = rem / inner_v, in = (rem - o * inner_v) * V;
     const int64_t sbase = tile * src_tile + o * n * inner + in;
-    float2 z[L];
+    float2 z[V][L];
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-      float2 acc = make_float2(0.f, 0.f);
+      float2 acc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = make_float2(0.f, 0.f);
       for (int p = j; p < n; p += L) {
-        const float2 v = load<FMT>(src, sbase + (int64_t)p * inner);
-        acc = rho ? cadd(acc, cmul(v, twm[(rho * p) & (m - 1)])) : cadd(acc, v);
+        const float2 w = twm[(rho * p) & (m - 1)];
+        const int64_t e = sbase + (int64_t)p * inner;
+        float2 x[V];
+        if constexpr (V == 1) {
+          x[0] = load<FMT>(src, e);
+        } else if constexpr (FMT == 2) {  // four packed 4-bit samples in one word
+          const uint32_t u = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(src) + e);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const int8_t b = (int8_t)(u >> (8 * v));
+            x[v] = make_float2((float)(b >> 4), (float)((int8_t)(b << 4) >> 4));
+          }
+        } else {  // FMT 1: four int8 pairs in 8 bytes
+          const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const int8_t*>(src) + 2 * e);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const uint32_t h = v < 2 ? u.x : u.y;
+            const int s = 16 * (v & 1);
+            x[v] = make_float2((float)(int8_t)(h >> s), (float)(int8_t)(h >> (s + 8)));
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = cadd(acc[v], cmul(x[v], w));
       }
-      z[j] = acc;
+#pragma unroll
+      for (int v = 0; v < V; ++v) z[v][j] = acc[v];
     }
-    dft<L>(z, twm, r);
+#pragma unroll
+    for (int v = 0; v < V; ++v) dft<L>(z[v], twm, r);
     const int64_t dbase = tile * dst_tile + o * m * inner + in;
 #pragma unroll
-    for (int q = 0; q < L; ++q) dst[dbase + (int64_t)(r * q + rho) * inner] = z[q];
+    for (int q = 0; q < L; ++q) {
+      float2* d = dst + dbase + (int64_t)(r * q + rho) * inner;
+      if constexpr (V == 4) {
+        reinterpret_cast<float4*>(d)[0] = make_float4(z[0][q].x, z[0][q].y, z[1][q].x, z[1][q].y);
+        reinterpret_cast<float4*>(d)[1] = make_float4(z[2][q].x, z[2][q].y, z[3][q].x, z[3][q].y);
+      } else {
+        d[0] = z[0][q];
+      }
+    }
   }
 }
 
 hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2* twm, int64_t tiles, int64_t outer,
                              int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st) {
   const int L = m / r;
-  const int64_t total = tiles * outer * inner;
+  // packed integer samples: four inner indices per thread when the word loads stay aligned
+  const int V = (fmt != 0 && L <= 16 && inner % 4 == 0 && src_tile % 4 == 0 &&
+                 (reinterpret_cast<uintptr_t>(src) & 7) == 0)
+                    ? 4
+                    : 1;
+  const int64_t total = tiles * outer * (inner / V);
   int64_t g = (total + 255) / 256;
   if (g > 65536) g = 65536;
   const dim3 grid((unsigned)g, (unsigned)r), block(256);
-#define OMNI_FRONT(F_, L_)                                                                                     \
-  hipLaunchKernelGGL((front_axis_kernel<F_, L_>), grid, block, 0, st, src, dst, twm, tiles, outer, n, m, r, inner, \
-                     src_tile, dst_tile)
-#define OMNI_FRONT_L(F_)         \
-  switch (L) {                   \
-    case 2: OMNI_FRONT(F_, 2); break;   \
-    case 4: OMNI_FRONT(F_, 4); break;   \
-    case 8: OMNI_FRONT(F_, 8); break;   \
-    case 16: OMNI_FRONT(F_, 16); break; \
-    case 32: OMNI_FRONT(F_, 32); break; \
-    default: return hipErrorInvalidValue; \
+#define OMNI_FRONT(F_, L_, V_)                                                                                  \
+  hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_>), grid, block, 0, st, src, dst, twm, tiles, outer, n, m, r, \
+                     inner, src_tile, dst_tile)
+#define OMNI_FRONT_L(F_, V_)                              \
+  switch (L) {                                            \
+    case 2: OMNI_FRONT(F_, 2, V_); break;                 \
+    case 4: OMNI_FRONT(F_, 4, V_); break;                 \
+    case 8: OMNI_FRONT(F_, 8, V_); break;                 \
+    case 16: OMNI_FRONT(F_, 16, V_); break;               \
+    case 32:                                              \
+      if (V_ != 1) return hipErrorInvalidValue;           \
+      OMNI_FRONT(F_, 32, 1);                              \
+      break;                                              \
+    default: return hipErrorInvalidValue;                 \
   }
-  switch (fmt) {
-    case 0: OMNI_FRONT_L(0); break;
-    case 1: OMNI_FRONT_L(1); break;
-    case 2: OMNI_FRONT_L(2); break;
-    default: return hipErrorInvalidValue;
+  if (fmt == 0) {
+    OMNI_FRONT_L(0, 1)
+  } else if (fmt == 1 && V == 4) {
+    OMNI_FRONT_L(1, 4)
+  } else if (fmt == 1) {
+    OMNI_FRONT_L(1, 1)
+  } else if (fmt == 2 && V == 4) {
+    OMNI_FRONT_L(2, 4)
+  } else if (fmt == 2) {
+    OMNI_FRONT_L(2, 1)
+  } else {
+    return hipErrorInvalidValue;
   }
 #undef OMNI_FRONT_L
 #undef OMNI_FRONT

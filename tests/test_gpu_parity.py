@@ -372,8 +372,17 @@ def test_autotuned_plan_matches_oracle(level_dims, kernel):
     assert rel_err(vis.cpu().numpy(), oracle_vis(raw, "ci4", level_dims)) <= TOL["fp32"]
 
 
-@pytest.mark.parametrize("level_dims,dtype", [([[32, 32]], "ci4"), ([[64, 64]], "ci8"), ([[32, 32]], "cf32")])
-def test_unaligned_input_pointer(level_dims, dtype):
+@pytest.mark.parametrize(
+    "level_dims,dtype,kernel",
+    [
+        ([[32, 32]], "ci4", "fused_ct_fp32"),
+        ([[64, 64]], "ci8", "fused_ct_fp32"),
+        ([[32, 32]], "cf32", "fused_ct_fp32"),
+        ([[2, 2], [8, 8], [4, 4]], "ci8", "fused_ct_fp32"),  # front pass on a word-unaligned source
+        ([[4, 4], [4, 4], [4, 4]], "ci4", "fused_fp32"),
+    ],
+)
+def test_unaligned_input_pointer(level_dims, dtype, kernel):
     """A source pointer that is 4- but not 16-byte aligned takes the unstaged loads and gives the same result."""
     N = math.prod(dims_of(level_dims))
     gen = torch.Generator().manual_seed(N + 7)
@@ -386,7 +395,7 @@ def test_unaligned_input_pointer(level_dims, dtype):
     assert shifted.data_ptr() % 16 != 0 and shifted.is_contiguous()
     say("unaligned", level_dims, dtype, shifted.data_ptr() % 16)
     plan = omni.Plan(level_dims, None, 2, dtype, "fp32")
-    assert '"kernel":"fused_ct_fp32"' in plan.describe()
+    assert f'"kernel":"{kernel}"' in plan.describe()
     got = plan.correlate(shifted)
     ref = plan.correlate(raw.cuda())
     torch.cuda.synchronize()
