@@ -15,6 +15,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace omni {
 
 // A[f][kmap[c][cell]] (+)= sum_s partial[s][f][c][cell], float64, fixed summation order.
@@ -82,6 +84,68 @@ __global__ void inverse_axis_kernel(const void* __restrict__ src, void* __restri
   }
 }
 
+// The same axis transform with the m inputs of TC columns staged in LDS, so
+// that each input is read from HBM once instead of once per output lag.
+// Columns are the flattened (outer, inner) index pairs; a work-group takes TC
+// consecutive columns and produces their (2n - 1) lags.  m <= 256.
+template <bool REAL_IN, bool LAST, int TC>
+__global__ __launch_bounds__(256) void inverse_axis_tiled_kernel(const void* __restrict__ src, void* __restrict__ dst,
+                                                                 const double2* __restrict__ twi, int64_t outer,
+                                                                 int m, int n, int64_t inner, double scale) {
+  using Elem = typename std::conditional<REAL_IN, double, double2>::type;
+  __shared__ Elem a[4096];  // m * TC <= 4096
+  __shared__ double2 w[256];
+  const int nout = 2 * n - 1;
+  const int64_t cols = outer * inner;
+  const int64_t col0 = (int64_t)blockIdx.x * TC;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < m; q += 256) w[q] = twi[q];
+  const Elem* s = static_cast<const Elem*>(src);
+  // load order: consecutive threads take consecutive inner indices where the tile has them
+  const int in_run = inner >= TC ? TC : (TC % inner == 0 ? (int)inner : 1);
+  for (int l = tid; l < m * TC; l += 256) {
+    const int r = l % in_run, rest = l / in_run;
+    const int k = rest % m;
+    const int c = (rest / m) * in_run + r;
+    const int64_t col = col0 + c;
+    if (col < cols) {
+      const int64_t ou = col / inner, in = col - ou * inner;
+      a[k * TC + c] = s[(ou * m + k) * inner + in];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nout * TC; idx += 256) {
+    const int c = idx % TC, o = idx / TC;
+    const int64_t col = col0 + c;
+    if (col >= cols) continue;
+    const int delta = o - (n - 1);
+    const int dm = ((delta % m) + m) % m;
+    double re = 0.0, im = 0.0;
+    int e = 0;
+    for (int k = 0; k < m; ++k) {
+      const double2 wk = w[e];
+      if constexpr (REAL_IN) {
+        const double v = a[k * TC + c];
+        re = fma(v, wk.x, re);
+        im = fma(v, wk.y, im);
+      } else {
+        const double2 v = a[k * TC + c];
+        re = fma(v.x, wk.x, fma(-v.y, wk.y, re));
+        im = fma(v.x, wk.y, fma(v.y, wk.x, im));
+      }
+      e += dm;
+      if (e >= m) e -= m;
+    }
+    const int64_t ou = col / inner, in = col - ou * inner;
+    const int64_t oi = (ou * nout + o) * inner + in;
+    if constexpr (LAST) {
+      reinterpret_cast<float2*>(dst)[oi] = make_float2((float)(re * scale), (float)(im * scale));
+    } else {
+      reinterpret_cast<double2*>(dst)[oi] = make_double2(re, im);
+    }
+  }
+}
+
 // Twiddle generator, float64 on the device: for each table entry (m, q, sign)
 // w = exp(sign * 2 pi i q / m), evaluated with sincospi on the exact reduced
 // ratio 2q/m.  Writes float32 copies for the forward kernels and float64
@@ -123,6 +187,35 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
 
 hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* dst, const double2* twi,
                                int64_t outer, int m, int n, int64_t inner, double scale, hipStream_t st) {
+  const int64_t cols = outer * inner;
+  if (m <= 256 && cols >= (m <= 64 ? 64 : 16) * 256) {
+    // TC columns per work-group (m * TC <= 4096 elements of LDS), at least 256 work-groups
+    const dim3 b(256);
+#define OMNI_INV_TILED(TC_)                                                                                          \
+  do {                                                                                                               \
+    const int64_t nb = (cols + TC_ - 1) / TC_;                                                                       \
+    if (nb > INT32_MAX) return hipErrorInvalidValue;                                                                 \
+    const dim3 g((unsigned)nb);                                                                                      \
+    if (real_in && last)                                                                                             \
+      hipLaunchKernelGGL((inverse_axis_tiled_kernel<true, true, TC_>), g, b, 0, st, src, dst, twi, outer, m, n,     \
+                         inner, scale);                                                                              \
+    else if (real_in)                                                                                                \
+      hipLaunchKernelGGL((inverse_axis_tiled_kernel<true, false, TC_>), g, b, 0, st, src, dst, twi, outer, m, n,    \
+                         inner, scale);                                                                              \
+    else if (last)                                                                                                   \
+      hipLaunchKernelGGL((inverse_axis_tiled_kernel<false, true, TC_>), g, b, 0, st, src, dst, twi, outer, m, n,    \
+                         inner, scale);                                                                              \
+    else                                                                                                             \
+      hipLaunchKernelGGL((inverse_axis_tiled_kernel<false, false, TC_>), g, b, 0, st, src, dst, twi, outer, m, n,   \
+                         inner, scale);                                                                              \
+  } while (0)
+    if (m <= 64)
+      OMNI_INV_TILED(64);
+    else
+      OMNI_INV_TILED(16);
+#undef OMNI_INV_TILED
+    return hipGetLastError();
+  }
   const int64_t total = outer * (2 * n - 1) * inner;
   const dim3 g(grid_for(total, 256)), b(256);
   if (real_in && last)
