@@ -77,6 +77,8 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 #define OMNI_PLAN_TIMING 0x2u    /* record HIP events around each stage of every correlate call  */
 #define OMNI_PLAN_TUNE 0x4u      /* autotune the general kernel's schedule at plan time (timed on  \
                                     an all-zero input; choice cached in the file OMNI_TUNE_CACHE) */
+#define OMNI_PLAN_GRAPH 0x8u     /* run every correlate call as one HIP graph whose arrays are     \
+                                    parallel branches (captured on first use, replayed after)    */
 
 /* flags argument of omni_correlate* */
 #define OMNI_NO_RESET 0x1u    /* add this call's samples to the running accumulator            */
@@ -133,7 +135,14 @@ int omni_plan_batch(omni_plan_t* out, int32_t n_arrays, const omni_array_desc* a
  * OMNI_E_HIP. */
 int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream, uint32_t flags);
 
-/* Batched form: volt[i] / vis[i] belong to array i of the batch plan. */
+/* Batched form: volt[i] / vis[i] belong to array i of the batch plan.
+ * Without OMNI_PLAN_GRAPH the arrays run one after another on `stream`.  With
+ * it, the plan captures the whole call (all arrays, all stages) into one HIP
+ * graph in which each array is an independent branch on a stream of its own,
+ * so that the arrays' kernels overlap and fill each other's tails; the graph
+ * is launched on `stream` and replayed while T, flags and the volt / vis
+ * pointers stay the same (any change re-captures).  Results are identical to
+ * the sequential form.  The graph holds no memset nodes. */
 int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, void* const* vis, void* stream,
                          uint32_t flags);
 
@@ -169,14 +178,16 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed);
 typedef enum {
   OMNI_STAGE_FORWARD = 0, /* forward transform + |X|^2 + time integration kernel(s)  */
   OMNI_STAGE_REDUCE = 1,  /* partial-sum reduction into the float64 accumulator      */
-  OMNI_STAGE_INVERSE = 2  /* inverse transform to visibilities                       */
+  OMNI_STAGE_INVERSE = 2, /* inverse transform to visibilities                       */
+  OMNI_STAGE_CALL = 3     /* the whole correlate call, on the caller's stream        */
 } omni_stage;
 
 /* Durations in milliseconds of `stage` over the most recent correlate calls
  * (oldest first; at most 256 calls are remembered; for a batch plan the
  * stage spans all arrays).  Waits for the recorded events.  Writes at most
  * `max` values to ms and the count to *n.  OMNI_E_STATE without
- * OMNI_PLAN_TIMING. */
+ * OMNI_PLAN_TIMING, and for stages 0-2 of an OMNI_PLAN_GRAPH plan (its
+ * arrays' stages overlap; only OMNI_STAGE_CALL is recorded). */
 int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n);
 
 /* Release the plan (waits for its last stream first).  NULL is a no-op. */

@@ -34,7 +34,8 @@ FORMS = {"fp32": 0, "mixed": 1}
 PLAN_HOST_ONLY = 0x1
 PLAN_TIMING = 0x2
 PLAN_TUNE = 0x4
-STAGES = {"forward": 0, "reduce": 1, "inverse": 2}
+PLAN_GRAPH = 0x8
+STAGES = {"forward": 0, "reduce": 1, "inverse": 2, "call": 3}
 NO_RESET = 0x1
 NO_FINALIZE = 0x2
 
@@ -156,9 +157,15 @@ class Plan:
         batch: Sequence[tuple] | None = None,
         timing: bool = False,
         tune: bool = False,
+        graph: bool = False,
     ):
         self._h = ctypes.c_void_p()
-        flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_TIMING if timing else 0) | (PLAN_TUNE if tune else 0)
+        flags = (
+            (PLAN_HOST_ONLY if host_only else 0)
+            | (PLAN_TIMING if timing else 0)
+            | (PLAN_TUNE if tune else 0)
+            | (PLAN_GRAPH if graph else 0)
+        )
         opts = _Opts(DTYPES[dtype], FORMS[form], time_block, flags)
         self.dtype, self.form = dtype, form
         self._keep = []

@@ -106,11 +106,26 @@ struct ArrayPlan {
 
 constexpr int kTimingRing = 256;
 
+constexpr int kStages = 4;  // forward, reduce, inverse, whole call
+
 struct omni_plan_s {
   std::vector<ArrayPlan> arrays;
   bool timing = false;
   // [call % ring][stage][begin/end]
   std::vector<hipEvent_t> ev;
+  // OMNI_PLAN_GRAPH: one branch stream per array, fork / join events, the
+  // captured graph and the call it was captured for
+  bool graph = false;
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> join;
+  hipStream_t capture = nullptr;
+  hipEvent_t fork = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t gx = nullptr;
+  int64_t g_T = -1;
+  uint32_t g_flags = 0;
+  std::vector<const void*> g_volt;
+  std::vector<void*> g_vis;
   int64_t n_calls = 0;
   omni_dtype dtype = OMNI_CF32;
   omni_form form = OMNI_FORM_FP32;
@@ -574,7 +589,7 @@ int mixed_samples_per_iter() {
 size_t sample_bytes(omni_dtype t) { return t == OMNI_CF32 ? 8 : t == OMNI_CI8 ? 2 : 1; }
 
 hipEvent_t stage_event(omni_plan_s* p, int stage, int end) {
-  return p->ev[(size_t)(((p->n_calls % kTimingRing) * 3 + stage) * 2 + end)];
+  return p->ev[(size_t)(((p->n_calls % kTimingRing) * kStages + stage) * 2 + end)];
 }
 
 // Records the stage's begin event before the first array and its end event after the last.
@@ -840,6 +855,90 @@ int tune_array(omni_plan_s* p, ArrayPlan& ap) {
   return OMNI_OK;
 }
 
+// Streams and events of an OMNI_PLAN_GRAPH plan (default priority, non-blocking streams).
+int make_graph_resources(omni_plan_s* p) {
+  p->graph = true;
+  p->branch.assign(p->arrays.size(), nullptr);
+  p->join.assign(p->arrays.size(), nullptr);
+  HIP_TRY(hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+  for (size_t i = 0; i < p->arrays.size(); ++i) {
+    HIP_TRY(hipStreamCreateWithFlags(&p->branch[i], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming));
+  }
+  return OMNI_OK;
+}
+
+void drop_graph(omni_plan_s* p) {
+  if (p->gx) hipGraphExecDestroy(p->gx);
+  if (p->g) hipGraphDestroy(p->g);
+  p->gx = nullptr;
+  p->g = nullptr;
+  p->g_T = -1;
+}
+
+// Everything a plan owns on the device (safe on a partly built plan).
+void destroy_plan_resources(omni_plan_s* p) {
+  drop_graph(p);
+  for (auto& e : p->ev)
+    if (e) hipEventDestroy(e);
+  p->ev.clear();
+  for (auto& e : p->join)
+    if (e) hipEventDestroy(e);
+  for (auto& s : p->branch)
+    if (s) hipStreamDestroy(s);
+  p->join.clear();
+  p->branch.clear();
+  if (p->fork) hipEventDestroy(p->fork);
+  if (p->capture) hipStreamDestroy(p->capture);
+  p->fork = nullptr;
+  p->capture = nullptr;
+  for (auto& ap : p->arrays) free_array(ap);
+}
+
+// Capture one correlate call of a graph plan: the fork event on the capture
+// stream, each array's three stages on its branch stream, the joins back.
+int capture_call(omni_plan_s* p, const void* const* volt, int64_t T, void* const* vis, uint32_t flags) {
+  drop_graph(p);
+  HIP_TRY(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
+  int rc = OMNI_OK;
+  hipError_t e = hipEventRecord(p->fork, p->capture);
+  for (size_t i = 0; i < p->arrays.size() && rc == OMNI_OK && e == hipSuccess; ++i) {
+    e = hipStreamWaitEvent(p->branch[i], p->fork, 0);
+    for (int stage = 0; stage < 3 && rc == OMNI_OK && e == hipSuccess; ++stage)
+      rc = correlate_array(p, p->arrays[i], T > 0 ? volt[i] : nullptr, T,
+                           (flags & OMNI_NO_FINALIZE) ? nullptr : vis[i], p->branch[i], flags, stage);
+    if (rc == OMNI_OK && e == hipSuccess) e = hipEventRecord(p->join[i], p->branch[i]);
+    if (rc == OMNI_OK && e == hipSuccess) e = hipStreamWaitEvent(p->capture, p->join[i], 0);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(p->capture, &g);  // always end the capture
+  if (rc != OMNI_OK || e != hipSuccess || e_end != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    if (rc != OMNI_OK) return rc;
+    return fail(OMNI_E_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e_end));
+  }
+  p->g = g;
+  HIP_TRY(hipGraphInstantiate(&p->gx, p->g, nullptr, nullptr, 0));
+  p->g_T = T;
+  p->g_flags = flags;
+  p->g_volt.assign(volt ? volt : nullptr, volt ? volt + p->arrays.size() : nullptr);
+  p->g_vis.assign(vis ? vis : nullptr, vis ? vis + p->arrays.size() : nullptr);
+  return OMNI_OK;
+}
+
+bool same_call(const omni_plan_s* p, const void* const* volt, int64_t T, void* const* vis, uint32_t flags) {
+  if (!p->gx || p->g_T != T || p->g_flags != flags) return false;
+  for (size_t i = 0; i < p->arrays.size(); ++i) {
+    const void* v = (T > 0 && volt) ? volt[i] : nullptr;
+    const void* o = ((flags & OMNI_NO_FINALIZE) || !vis) ? nullptr : vis[i];
+    const void* gv = (T > 0 && !p->g_volt.empty()) ? p->g_volt[i] : nullptr;
+    const void* go = ((flags & OMNI_NO_FINALIZE) || p->g_vis.empty()) ? nullptr : p->g_vis[i];
+    if (v != gv || o != go) return false;
+  }
+  return true;
+}
+
 int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, const omni_opts* opts) {
   if (!out) return fail(OMNI_E_INVAL, "out is NULL");
   *out = nullptr;
@@ -848,7 +947,8 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   if (o.dtype < OMNI_CF32 || o.dtype > OMNI_CI4) return fail(OMNI_E_INVAL, "unknown dtype");
   if (o.form != OMNI_FORM_FP32 && o.form != OMNI_FORM_MIXED) return fail(OMNI_E_INVAL, "unknown form");
   if (o.time_block < 0) return fail(OMNI_E_INVAL, "time_block < 0");
-  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING | OMNI_PLAN_TUNE)) return fail(OMNI_E_INVAL, "unknown plan flag");
+  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING | OMNI_PLAN_TUNE | OMNI_PLAN_GRAPH))
+    return fail(OMNI_E_INVAL, "unknown plan flag");
   omni_plan_s* p = new (std::nothrow) omni_plan_s;
   if (!p) return fail(OMNI_E_NOMEM, "host allocation failed");
   p->dtype = o.dtype;
@@ -872,7 +972,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
       return rc;
     }
     if (p->timing) {
-      p->ev.assign((size_t)kTimingRing * 3 * 2, nullptr);
+      p->ev.assign((size_t)kTimingRing * kStages * 2, nullptr);
       for (auto& e : p->ev) {
         if (hipEventCreate(&e) != hipSuccess) {
           for (auto& e2 : p->ev)
@@ -882,11 +982,19 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
         }
       }
     }
+    if (o.flags & OMNI_PLAN_GRAPH) {
+      rc = make_graph_resources(p);
+      if (rc) {
+        destroy_plan_resources(p);
+        delete p;
+        return rc;
+      }
+    }
     for (auto& ap : p->arrays) {
       rc = alloc_array(ap);
       if (rc == OMNI_OK && (o.flags & OMNI_PLAN_TUNE)) rc = tune_array(p, ap);
       if (rc) {
-        for (auto& a2 : p->arrays) free_array(a2);
+        destroy_plan_resources(p);
         delete p;
         return rc;
       }
@@ -939,15 +1047,25 @@ int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, v
     hipGetDevice(&cur);
     if (cur != plan->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    for (int stage = 0; stage < 3; ++stage) {
-      for (size_t i = 0; i < na; ++i) {
-        mark(plan, stage, 0, i == 0, st);
-        int rc = correlate_array(plan, plan->arrays[i], T > 0 ? volt[i] : nullptr, T,
-                                 (flags & OMNI_NO_FINALIZE) ? nullptr : vis[i], st, flags, stage);
+    mark(plan, OMNI_STAGE_CALL, 0, true, st);
+    if (plan->graph) {
+      if (!same_call(plan, volt, T, vis, flags)) {
+        int rc = capture_call(plan, volt, T, vis, flags);
         if (rc) return rc;
-        mark(plan, stage, 1, i + 1 == na, st);
+      }
+      HIP_TRY(hipGraphLaunch(plan->gx, st));
+    } else {
+      for (int stage = 0; stage < 3; ++stage) {
+        for (size_t i = 0; i < na; ++i) {
+          mark(plan, stage, 0, i == 0, st);
+          int rc = correlate_array(plan, plan->arrays[i], T > 0 ? volt[i] : nullptr, T,
+                                   (flags & OMNI_NO_FINALIZE) ? nullptr : vis[i], st, flags, stage);
+          if (rc) return rc;
+          mark(plan, stage, 1, i + 1 == na, st);
+        }
       }
     }
+    mark(plan, OMNI_STAGE_CALL, 1, true, st);
     if (plan->timing) ++plan->n_calls;
     return OMNI_OK;
   } catch (...) {
@@ -1093,13 +1211,15 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
 int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n) {
   if (!plan || !n || (max > 0 && !ms)) return fail(OMNI_E_INVAL, "NULL argument");
   if (!plan->timing) return fail(OMNI_E_STATE, "plan was not made with OMNI_PLAN_TIMING");
-  if (stage < 0 || stage > 2) return fail(OMNI_E_INVAL, "unknown stage");
+  if (stage < 0 || stage >= kStages) return fail(OMNI_E_INVAL, "unknown stage");
+  if (plan->graph && stage != OMNI_STAGE_CALL)
+    return fail(OMNI_E_STATE, "a graph plan records only the whole call (its arrays' stages overlap)");
   const int64_t avail = std::min<int64_t>(plan->n_calls, kTimingRing);
   const int64_t cnt = std::min<int64_t>(avail, max);
   for (int64_t j = 0; j < cnt; ++j) {
     const int64_t call = plan->n_calls - cnt + j;
-    hipEvent_t b = plan->ev[(size_t)(((call % kTimingRing) * 3 + stage) * 2 + 0)];
-    hipEvent_t e = plan->ev[(size_t)(((call % kTimingRing) * 3 + stage) * 2 + 1)];
+    hipEvent_t b = plan->ev[(size_t)(((call % kTimingRing) * kStages + stage) * 2 + 0)];
+    hipEvent_t e = plan->ev[(size_t)(((call % kTimingRing) * kStages + stage) * 2 + 1)];
     HIP_TRY(hipEventSynchronize(e));
     float t = 0.f;
     HIP_TRY(hipEventElapsedTime(&t, b, e));
@@ -1112,9 +1232,7 @@ int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, in
 int omni_destroy(omni_plan_t plan) {
   if (!plan) return OMNI_OK;
   if (!plan->host_only) hipDeviceSynchronize();
-  for (auto& e : plan->ev)
-    if (e) hipEventDestroy(e);
-  for (auto& ap : plan->arrays) free_array(ap);
+  destroy_plan_resources(plan);
   delete plan;
   return OMNI_OK;
 }

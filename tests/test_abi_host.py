@@ -113,3 +113,22 @@ def test_unsupported_shapes_are_refused_not_crashed():
     with pytest.raises(omni.OmniError) as ei:
         omni.Plan([[33, 2]], None, 1, host_only=True)
     assert omni.STATUS[ei.value.code] == "OMNI_E_SHAPE"
+
+
+def test_plan_flags_are_validated():
+    """Unknown plan flags are refused; the graph flag is accepted on a host-only plan."""
+    opts = omni._Opts(omni.DTYPES["ci8"], omni.FORMS["fp32"], 0, omni.PLAN_HOST_ONLY | 0x10)
+    h = ctypes.c_void_p()
+    dims = np.array([[4, 4]], dtype=np.int32)
+    rc = omni.lib.omni_plan(ctypes.byref(h), 1, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 1,
+                            ctypes.byref(opts))
+    assert omni.STATUS[rc] == "OMNI_E_INVAL"
+    p = omni.Plan([[4, 4]], None, 1, "ci8", host_only=True, graph=True)
+    assert p.vis_shape() == (1, 7, 7)
+
+
+def test_stage_times_need_a_timing_plan():
+    p = omni.Plan([[4, 4]], None, 1, host_only=True)
+    with pytest.raises(omni.OmniError) as ei:
+        p.stage_times("call")
+    assert omni.STATUS[ei.value.code] == "OMNI_E_STATE"

@@ -401,3 +401,58 @@ def test_unaligned_input_pointer(level_dims, dtype, kernel):
     torch.cuda.synchronize()
     assert rel_err(got.cpu().numpy(), ref.cpu().numpy()) <= 1e-6
     assert rel_err(got.cpu().numpy(), oracle_vis(raw, dtype, level_dims)) <= TOL["fp32"]
+
+
+BATCH = [([[8, 8]], None, 3), ([[4, 4], [4, 4]], None, 2), ([[32, 32]], None, 2), ([[2, 2], [8, 8], [4, 4]], None, 2)]
+
+
+def batch_raw(dtype, T, seed):
+    gen = torch.Generator().manual_seed(seed)
+    return [random_raw(dtype, T, F, math.prod(dims_of(ld)), gen) for ld, _, F in BATCH]
+
+
+def test_batch_plan_matches_oracle_per_array():
+    """One batch plan over arrays of different shapes equals the oracle array by array."""
+    raws = batch_raw("ci8", 23, 5)
+    plan = omni.Plan(batch=BATCH, dtype="ci8")
+    say("batch", [ld for ld, _, _ in BATCH])
+    outs = plan.correlate_batch([r.cuda() for r in raws])
+    torch.cuda.synchronize()
+    for (ld, _, _), r, o in zip(BATCH, raws, outs):
+        assert rel_err(o.cpu().numpy(), oracle_vis(r, "ci8", ld)) <= TOL["fp32"]
+
+
+def test_graph_batch_replays_match_sequential():
+    """A graph plan (arrays as parallel branches of one captured graph) gives the sequential plan's bytes on
+    every replay, with eager work and synchronisations between replays; new pointers or T re-capture."""
+    raws = batch_raw("ci4", 41, 6)
+    volts = [r.cuda() for r in raws]
+    seq = omni.Plan(batch=BATCH, dtype="ci4")
+    ref = [o.clone() for o in seq.correlate_batch(volts)]
+    gp = omni.Plan(batch=BATCH, dtype="ci4", graph=True, timing=True)
+    outs = [torch.empty(gp.vis_shape(i), dtype=torch.complex64, device="cuda") for i in range(len(BATCH))]
+    for rep in range(4):
+        for o in outs:
+            o.zero_()
+        gp.correlate_batch(volts, outs=outs)
+        junk = torch.randn(1 << 20, device="cuda") * 2.0  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), f"replay {rep}"
+    assert len(gp.stage_times("call")) == 4
+    with pytest.raises(omni.OmniError):
+        gp.stage_times("forward")
+    # a different T (and source pointers) re-captures
+    short = [v[:17].contiguous() for v in volts]
+    ref2 = [o.clone() for o in seq.correlate_batch(short)]
+    got2 = gp.correlate_batch(short)
+    torch.cuda.synchronize()
+    for a, b in zip(got2, ref2):
+        assert torch.equal(a, b)
+    # split integration through the graph: first part, then the rest with NO_RESET
+    gp.correlate_batch([v[:20].contiguous() for v in volts], flags=omni.NO_FINALIZE)
+    got3 = gp.correlate_batch([v[20:].contiguous() for v in volts], flags=omni.NO_RESET)
+    torch.cuda.synchronize()
+    for (ld, _, _), r, o in zip(BATCH, raws, got3):
+        assert rel_err(o.cpu().numpy(), oracle_vis(r, "ci4", ld)) <= TOL["fp32"]
