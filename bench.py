@@ -10,6 +10,11 @@ The JSON line's `value` is the workload's own arithmetic form (the float32
 form for the 8x8-of-8x8 workload); the other form is timed on the same input
 bytes and reported under `other_form`.
 
+`--workload batch4` times the four-array batch (32x32, 64x64, 128x128 and
+16x16-of-16x16, 64 channels each, T = 2048, 4-bit samples) as one batched call:
+the graph plan (one HIP graph, one branch per array) is the headline and the
+same arrays run one after another are reported beside it.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 
@@ -119,8 +124,109 @@ def run_form(omni, w, raw, form, steps, warmup):
     return {"ms": ms, "stages": stages, "kernel": desc["arrays"][0]["kernel"] + "_kernel", "vis": vis, "plan": plan}
 
 
-def cpu_oracle_baseline(raw_cpu, w, budget_s=10.0, max_channels=8):
+BATCH4 = ["grid32", "grid64", "grid128", "hier16x16"]
+
+
+def run_batch(omni, ws, raws, graph, steps, warmup):
+    """Plan the arrays as one batch (optionally as a graph plan), warm up, time `steps` batched calls."""
+    import torch
+
+    plan = omni.Plan(batch=[(w.level_dims, w.A, w.nchan) for w in ws], dtype=ws[0].dtype, form="fp32",
+                     timing=True, graph=graph)
+    outs = [torch.empty(plan.vis_shape(i), dtype=torch.complex64, device=raws[0].device) for i in range(len(ws))]
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.correlate_batch(raws, outs=outs, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.correlate_batch(raws, outs=outs, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    calls = plan.stage_times("call", steps)
+    log(f"bench[batch4 graph={graph}]: {ms:.3f} ms/call (call events: median {sorted(calls)[len(calls) // 2]:.3f})")
+    return {"ms": ms, "call_ms": calls, "outs": outs, "plan": plan}
+
+
+def bench_batch4(args) -> int:
+    import numpy as np
+    import torch
+
+    import paper_0909_0001_amd as omni
+    import skysim
+
+    ws = [skysim.WORKLOADS[n] for n in BATCH4]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    raws = []
+    for w in ws:
+        log(f"bench: generating {w.name} N={w.N} F={w.nchan} T={w.T} {w.dtype}")
+        raws.append(skysim.make_voltages(w, device=dev))
+    torch.cuda.synchronize()
+    g = run_batch(omni, ws, raws, True, args.steps, args.warmup)
+    seq = run_batch(omni, ws, raws, False, args.steps, args.warmup)
+    same = all(torch.equal(a, b) for a, b in zip(g["outs"], seq["outs"]))
+    work = sum(w.antenna_samples() for w in ws)
+    flops = sum(fp32_form_flops_per_as(w.dims) * w.antenna_samples() for w in ws)
+    ms = g["ms"]
+    achieved = flops / (ms / 1e3) / 1e12
+    cpu = None
+    err = {"graph_equals_sequential_bytes": same}
+    if not args.no_cpu_baseline:
+        w0 = ws[0]
+        rate, nch, secs, ref = cpu_oracle_baseline(raws[0].cpu(), w0, budget_s=args.cpu_budget)
+        got = g["outs"][0].cpu().numpy().reshape(w0.nchan, -1)
+        c = got.shape[1] // 2
+        err[f"{w0.name}_max_over_lags_vs_oracle_{nch}ch"] = max(
+            float(np.max(np.abs(got[f] - ref[f])) / abs(ref[f][c])) for f in ref)
+        cpu = {"value": rate, "unit": "antenna-samples/s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+               "sample": f"{nch} of {w0.nchan} channels of the {w0.name} array x all {w0.T} samples ({secs:.1f} s)"}
+    out = {
+        "metric": METRIC,
+        "value": work / (ms / 1e3),
+        "unit": "antenna-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch4: arrays 32x32, 64x64, 128x128, 16x16-of-16x16; 64 channels each, T=2048, ci4 "
+            "voltages, fp32 form, one batched call as a HIP graph with one branch per array",
+            "arrays": {w.name: {"N": w.N, "F": w.nchan, "T": w.T} for w in ws},
+            "sample_format": "ci4",
+            "form": "fp32",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+            "traffic": None,
+            "kernel": "whole batched call",
+            "kernel_ms": round(ms, 4),
+            "algorithmic_flops_per_antenna_sample": {w.name: fp32_form_flops_per_as(w.dims) for w in ws},
+        },
+        "cpu_baseline": cpu,
+        "error_vs_oracle": err,
+        "tolerance": {"fp32": 1e-5},
+        "sequential": {"ms_per_step": seq["ms"], "value": work / (seq["ms"] / 1e3),
+                       "graph_speedup": seq["ms"] / ms},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_oracle_baseline(raw_cpu, w, budget_s=10.0, max_channels=None):
     """Time the oracle (as it stands) on whole channels until ~budget_s of work."""
+    max_channels = w.nchan if max_channels is None else max_channels
     import oracle
 
     T = raw_cpu.shape[0]
@@ -144,7 +250,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hier8x8")
+    ap.add_argument("--workload", default="hier8x8", help="a workload name of skysim.WORKLOADS, or batch4")
     ap.add_argument("--form", default=None, help="fp32 | mixed (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -162,6 +268,8 @@ def main() -> int:
         return 2
     if args.copy_calibration:
         return copy_calibration()
+    if args.workload == "batch4":
+        return bench_batch4(args)
 
     import numpy as np
     import torch
