@@ -170,25 +170,34 @@ def test_empty_time_gives_zero():
     assert not out.abs().max().item()
 
 
-def test_split_integration_and_resume():
+@pytest.mark.parametrize(
+    "level_dims,T,split",
+    [
+        ([[4, 4], [2, 4]], 50, 20),  # general kernel
+        ([[32, 32]], 50, 20),  # compile-time-shape kernel
+        ([[2, 2], [8, 8], [4, 4]], 150, 70),  # front passes, several time chunks, compile-time-shape kernel
+        ([[4, 4], [4, 4], [4, 4]], 150, 70),  # front passes, general kernel
+    ],
+)
+def test_split_integration_and_resume(level_dims, T, split):
     """T = T1 + T2 with OMNI_NO_RESET, and a checkpoint/resume of the accumulator, equal one call."""
-    level_dims = [[4, 4], [2, 4]]
-    N = 128
+    N = math.prod(dims_of(level_dims))
     gen = torch.Generator().manual_seed(5)
-    raw = random_raw("ci8", 50, 2, N, gen).cuda()
+    raw = random_raw("ci8", T, 2, N, gen).cuda()
+    say("split/resume", level_dims, T, split)
     plan = omni.Plan(level_dims, None, 2, "ci8")
     full = plan.correlate(raw).clone()
-    plan.correlate(raw[:20].contiguous(), flags=omni.NO_FINALIZE)
-    part = plan.correlate(raw[20:].contiguous(), flags=omni.NO_RESET)
+    plan.correlate(raw[:split].contiguous(), flags=omni.NO_FINALIZE)
+    part = plan.correlate(raw[split:].contiguous(), flags=omni.NO_RESET)
     torch.cuda.synchronize()
     assert torch.allclose(full, part, rtol=0, atol=1e-6 * full.abs().max().item())
-    # checkpoint after 20 samples, resume in a fresh plan
-    plan.correlate(raw[:20].contiguous(), flags=omni.NO_FINALIZE)
+    # checkpoint after `split` samples, resume in a fresh plan
+    plan.correlate(raw[:split].contiguous(), flags=omni.NO_FINALIZE)
     ck = np.zeros(plan.accumulator_bytes() // 8)
     plan.accumulator_get(ck)
     plan2 = omni.Plan(level_dims, None, 2, "ci8")
     plan2.accumulator_set(ck)
-    resumed = plan2.correlate(raw[20:].contiguous(), flags=omni.NO_RESET)
+    resumed = plan2.correlate(raw[split:].contiguous(), flags=omni.NO_RESET)
     torch.cuda.synchronize()
     assert torch.allclose(full, resumed, rtol=0, atol=1e-6 * full.abs().max().item())
 
