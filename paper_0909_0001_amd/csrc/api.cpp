@@ -120,6 +120,7 @@ struct omni_plan_s {
   std::vector<hipEvent_t> join;
   hipStream_t capture = nullptr;
   hipEvent_t fork = nullptr;
+  hipEvent_t g_done = nullptr;  // recorded after every launch of the graph
   hipGraph_t g = nullptr;
   hipGraphExec_t gx = nullptr;
   int64_t g_T = -1;
@@ -862,6 +863,7 @@ int make_graph_resources(omni_plan_s* p) {
   p->join.assign(p->arrays.size(), nullptr);
   HIP_TRY(hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&p->g_done, hipEventDisableTiming));
   for (size_t i = 0; i < p->arrays.size(); ++i) {
     HIP_TRY(hipStreamCreateWithFlags(&p->branch[i], hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming));
@@ -869,7 +871,10 @@ int make_graph_resources(omni_plan_s* p) {
   return OMNI_OK;
 }
 
+// The executable graph may still be running from the caller's last launch:
+// wait for that launch before the graph is destroyed.
 void drop_graph(omni_plan_s* p) {
+  if (p->gx && p->g_done) hipEventSynchronize(p->g_done);
   if (p->gx) hipGraphExecDestroy(p->gx);
   if (p->g) hipGraphDestroy(p->g);
   p->gx = nullptr;
@@ -890,8 +895,10 @@ void destroy_plan_resources(omni_plan_s* p) {
   p->join.clear();
   p->branch.clear();
   if (p->fork) hipEventDestroy(p->fork);
+  if (p->g_done) hipEventDestroy(p->g_done);
   if (p->capture) hipStreamDestroy(p->capture);
   p->fork = nullptr;
+  p->g_done = nullptr;
   p->capture = nullptr;
   for (auto& ap : p->arrays) free_array(ap);
 }
@@ -1054,6 +1061,7 @@ int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, v
         if (rc) return rc;
       }
       HIP_TRY(hipGraphLaunch(plan->gx, st));
+      HIP_TRY(hipEventRecord(plan->g_done, st));
     } else {
       for (int stage = 0; stage < 3; ++stage) {
         for (size_t i = 0; i < na; ++i) {

@@ -15,15 +15,14 @@
 
 #include <stdint.h>
 
+#include "shortdft.hpp"
+
 namespace omni {
 
 namespace fr {
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
-}
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+using sd::cadd;
+using sd::cmul;
 
 template <int FMT>
 __device__ __forceinline__ float2 load(const void* __restrict__ base, int64_t i) {
@@ -36,33 +35,25 @@ __device__ __forceinline__ float2 load(const void* __restrict__ base, int64_t i)
   return make_float2((float)(v >> 4), (float)((int8_t)(v << 4) >> 4));
 }
 
-// Radix-2 DIT DFT of length L (power of two), natural order; w_L^q = tw[q * (m / L)].
-template <int L>
-__device__ __forceinline__ void dft(float2 (&z)[L], const float2* __restrict__ tw, int stride) {
+// V samples at consecutive inner indices starting at element e
+template <int FMT, int V>
+__device__ __forceinline__ void load_v(const void* __restrict__ src, int64_t e, float2 (&x)[V]) {
+  if constexpr (V == 1) {
+    x[0] = load<FMT>(src, e);
+  } else if constexpr (FMT == 2) {  // four packed 4-bit samples in one word
+    const uint32_t u = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(src) + e);
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
-    int j = 0;
-#pragma unroll
-    for (int b = 1, rb = L >> 1; b < L; b <<= 1, rb >>= 1)
-      if (i & b) j |= rb;
-    if (j > i) {
-      const float2 t = z[i];
-      z[i] = z[j];
-      z[j] = t;
+    for (int v = 0; v < V; ++v) {
+      const int8_t b = (int8_t)(u >> (8 * v));
+      x[v] = make_float2((float)(b >> 4), (float)((int8_t)(b << 4) >> 4));
     }
-  }
+  } else {  // FMT 1: four int8 pairs in 8 bytes
+    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const int8_t*>(src) + 2 * e);
 #pragma unroll
-  for (int s = 1; s < L; s <<= 1) {
-#pragma unroll
-    for (int k = 0; k < L; k += 2 * s) {
-#pragma unroll
-      for (int j = 0; j < s; ++j) {
-        float2 v = z[k + j + s];
-        if (j != 0) v = cmul(v, tw[j * (L / (2 * s)) * stride]);
-        const float2 u = z[k + j];
-        z[k + j] = cadd(u, v);
-        z[k + j + s] = csub(u, v);
-      }
+    for (int v = 0; v < V; ++v) {
+      const uint32_t h = v < 2 ? u.x : u.y;
+      const int s = 16 * (v & 1);
+      x[v] = make_float2((float)(int8_t)(h >> s), (float)(int8_t)(h >> (s + 8)));
     }
   }
 }
@@ -73,13 +64,18 @@ __device__ __forceinline__ void dft(float2 (&z)[L], const float2* __restrict__ t
 // tiles = time samples x channels of this call; tile stride in the source is
 // src_tile (elements), in the destination dst_tile.  Each thread transforms V
 // consecutive inner indices, so that 1- and 2-byte samples are read as 4- or
-// 8-byte words (V = 4) and the outputs leave as 32-byte runs.
-template <int FMT, int L, int V>
+// 8-byte words (V = 4) and the outputs leave as 32-byte runs.  R = m / L is
+// the fold modulus, a compile-time constant so that all n loads of a thread
+// are issued before the arithmetic that consumes them: n = L R / 2 inputs, one
+// block of L per l < R / 2 (for R = 1, the first L / 2 of one block).
+template <int FMT, int L, int V, int R>
 __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict__ src, float2* __restrict__ dst,
                                                           const float2* __restrict__ twm, int64_t tiles,
-                                                          int64_t outer, int n, int m, int r, int64_t inner,
-                                                          int64_t src_tile, int64_t dst_tile) {
+                                                          int64_t outer, int64_t inner, int64_t src_tile,
+                                                          int64_t dst_tile) {
   using namespace fr;
+  constexpr int M = L * R, N = M / 2;
+  constexpr int NB = R >= 2 ? R / 2 : 1;
   const int64_t inner_v = inner / V;
   const int64_t per_tile = outer * inner_v;
   const int64_t total = tiles * per_tile;
@@ -89,47 +85,31 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
     const int64_t tile = idx / per_tile;
     const int64_t rem = idx - tile * per_tile;
     const int64_t o = rem / inner_v, in = (rem - o * inner_v) * V;
-    const int64_t sbase = tile * src_tile + o * n * inner + in;
+    const int64_t sbase = tile * src_tile + o * N * inner + in;
     float2 z[V][L];
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-      float2 acc[V];
+    for (int blk = 0; blk < NB; ++blk) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[v] = make_float2(0.f, 0.f);
-      for (int p = j; p < n; p += L) {
-        const float2 w = twm[(rho * p) & (m - 1)];
-        const int64_t e = sbase + (int64_t)p * inner;
-        float2 x[V];
-        if constexpr (V == 1) {
-          x[0] = load<FMT>(src, e);
-        } else if constexpr (FMT == 2) {  // four packed 4-bit samples in one word
-          const uint32_t u = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(src) + e);
+      for (int j = 0; j < L; ++j) {
+        const int p = j + blk * L;
+        if (p >= N) {
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            const int8_t b = (int8_t)(u >> (8 * v));
-            x[v] = make_float2((float)(b >> 4), (float)((int8_t)(b << 4) >> 4));
-          }
-        } else {  // FMT 1: four int8 pairs in 8 bytes
-          const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const int8_t*>(src) + 2 * e);
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            const uint32_t h = v < 2 ? u.x : u.y;
-            const int s = 16 * (v & 1);
-            x[v] = make_float2((float)(int8_t)(h >> s), (float)(int8_t)(h >> (s + 8)));
-          }
+          for (int v = 0; v < V; ++v) z[v][j] = make_float2(0.f, 0.f);
+          continue;
         }
+        float2 x[V];
+        load_v<FMT, V>(src, sbase + (int64_t)p * inner, x);
+        const float2 w = twm[(rho * p) & (M - 1)];  // w_m^{rho p}, uniform across the block
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = cadd(acc[v], cmul(x[v], w));
+        for (int v = 0; v < V; ++v) z[v][j] = blk == 0 ? cmul(x[v], w) : cadd(z[v][j], cmul(x[v], w));
       }
-#pragma unroll
-      for (int v = 0; v < V; ++v) z[v][j] = acc[v];
     }
 #pragma unroll
-    for (int v = 0; v < V; ++v) dft<L>(z[v], twm, r);
-    const int64_t dbase = tile * dst_tile + o * m * inner + in;
+    for (int v = 0; v < V; ++v) sd::dft<L>(z[v]);
+    const int64_t dbase = tile * dst_tile + o * M * inner + in;
 #pragma unroll
     for (int q = 0; q < L; ++q) {
-      float2* d = dst + dbase + (int64_t)(r * q + rho) * inner;
+      float2* d = dst + dbase + (int64_t)(R * q + rho) * inner;
       if constexpr (V == 4) {
         reinterpret_cast<float4*>(d)[0] = make_float4(z[0][q].x, z[0][q].y, z[1][q].x, z[1][q].y);
         reinterpret_cast<float4*>(d)[1] = make_float4(z[2][q].x, z[2][q].y, z[3][q].x, z[3][q].y);
@@ -143,6 +123,7 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
 hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2* twm, int64_t tiles, int64_t outer,
                              int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st) {
   const int L = m / r;
+  if (m != 2 * n || L * r != m) return hipErrorInvalidValue;
   // packed integer samples: four inner indices per thread when the word loads stay aligned
   const int V = (fmt != 0 && L <= 16 && inner % 4 == 0 && src_tile % 4 == 0 &&
                  (reinterpret_cast<uintptr_t>(src) & 7) == 0)
@@ -152,35 +133,32 @@ hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2
   int64_t g = (total + 255) / 256;
   if (g > 65536) g = 65536;
   const dim3 grid((unsigned)g, (unsigned)r), block(256);
-#define OMNI_FRONT(F_, L_, V_)                                                                                  \
-  hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_>), grid, block, 0, st, src, dst, twm, tiles, outer, n, m, r, \
-                     inner, src_tile, dst_tile)
-#define OMNI_FRONT_L(F_, V_)                              \
-  switch (L) {                                            \
-    case 2: OMNI_FRONT(F_, 2, V_); break;                 \
-    case 4: OMNI_FRONT(F_, 4, V_); break;                 \
-    case 8: OMNI_FRONT(F_, 8, V_); break;                 \
-    case 16: OMNI_FRONT(F_, 16, V_); break;               \
-    case 32:                                              \
-      if (V_ != 1) return hipErrorInvalidValue;           \
-      OMNI_FRONT(F_, 32, 1);                              \
-      break;                                              \
-    default: return hipErrorInvalidValue;                 \
-  }
+#define OMNI_FRONT(F_, L_, V_, R_)                                                                           \
+  hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_>), grid, block, 0, st, src, dst, twm, tiles, outer, inner, \
+                     src_tile, dst_tile)
+  // the planner's fold moduli: L = 16 for m >= 16 (r = m / 16), else r = 1 and L = m
+#define OMNI_FRONT_LR(F_, V_)                              \
+  if (r == 1 && L == 2) OMNI_FRONT(F_, 2, V_, 1);          \
+  else if (r == 1 && L == 4) OMNI_FRONT(F_, 4, V_, 1);     \
+  else if (r == 1 && L == 8) OMNI_FRONT(F_, 8, V_, 1);     \
+  else if (r == 1 && L == 16) OMNI_FRONT(F_, 16, V_, 1);   \
+  else if (r == 2 && L == 16) OMNI_FRONT(F_, 16, V_, 2);   \
+  else if (r == 4 && L == 16) OMNI_FRONT(F_, 16, V_, 4);   \
+  else return hipErrorInvalidValue;
   if (fmt == 0) {
-    OMNI_FRONT_L(0, 1)
+    OMNI_FRONT_LR(0, 1)
   } else if (fmt == 1 && V == 4) {
-    OMNI_FRONT_L(1, 4)
+    OMNI_FRONT_LR(1, 4)
   } else if (fmt == 1) {
-    OMNI_FRONT_L(1, 1)
+    OMNI_FRONT_LR(1, 1)
   } else if (fmt == 2 && V == 4) {
-    OMNI_FRONT_L(2, 4)
+    OMNI_FRONT_LR(2, 4)
   } else if (fmt == 2) {
-    OMNI_FRONT_L(2, 1)
+    OMNI_FRONT_LR(2, 1)
   } else {
     return hipErrorInvalidValue;
   }
-#undef OMNI_FRONT_L
+#undef OMNI_FRONT_LR
 #undef OMNI_FRONT
   return hipGetLastError();
 }
