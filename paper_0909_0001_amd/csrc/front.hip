@@ -40,15 +40,22 @@ template <int FMT, int V>
 __device__ __forceinline__ void load_v(const void* __restrict__ src, int64_t e, float2 (&x)[V]) {
   if constexpr (V == 1) {
     x[0] = load<FMT>(src, e);
-  } else if constexpr (FMT == 2) {  // four packed 4-bit samples in one word
-    const uint32_t u = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(src) + e);
+  } else if constexpr (FMT == 2) {  // V packed 4-bit samples in one 2- or 4-byte word
+    const uint32_t u = V == 4 ? *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(src) + e)
+                              : (uint32_t)*reinterpret_cast<const uint16_t*>(static_cast<const uint8_t*>(src) + e);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const int8_t b = (int8_t)(u >> (8 * v));
       x[v] = make_float2((float)(b >> 4), (float)((int8_t)(b << 4) >> 4));
     }
-  } else {  // FMT 1: four int8 pairs in 8 bytes
-    const uint2 u = *reinterpret_cast<const uint2*>(static_cast<const int8_t*>(src) + 2 * e);
+  } else {  // FMT 1: V int8 pairs in 2 V bytes
+    uint2 u;
+    if constexpr (V == 4) {
+      u = *reinterpret_cast<const uint2*>(static_cast<const int8_t*>(src) + 2 * e);
+    } else {
+      u.x = *reinterpret_cast<const uint32_t*>(static_cast<const int8_t*>(src) + 2 * e);
+      u.y = 0;
+    }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const uint32_t h = v < 2 ? u.x : u.y;
@@ -113,6 +120,8 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
       if constexpr (V == 4) {
         reinterpret_cast<float4*>(d)[0] = make_float4(z[0][q].x, z[0][q].y, z[1][q].x, z[1][q].y);
         reinterpret_cast<float4*>(d)[1] = make_float4(z[2][q].x, z[2][q].y, z[3][q].x, z[3][q].y);
+      } else if constexpr (V == 2) {
+        reinterpret_cast<float4*>(d)[0] = make_float4(z[0][q].x, z[0][q].y, z[1][q].x, z[1][q].y);
       } else {
         d[0] = z[0][q];
       }
@@ -125,9 +134,9 @@ hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2
   const int L = m / r;
   if (m != 2 * n || L * r != m) return hipErrorInvalidValue;
   // packed integer samples: four inner indices per thread when the word loads stay aligned
-  const int V = (fmt != 0 && L <= 16 && inner % 4 == 0 && src_tile % 4 == 0 &&
-                 (reinterpret_cast<uintptr_t>(src) & 7) == 0)
-                    ? 4
+  const int V = (fmt != 0 && L <= 16 && inner % 2 == 0 && src_tile % 2 == 0 &&
+                 (reinterpret_cast<uintptr_t>(src) & 3) == 0)
+                    ? 2
                     : 1;
   const int64_t total = tiles * outer * (inner / V);
   int64_t g = (total + 255) / 256;
@@ -147,12 +156,12 @@ hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2
   else return hipErrorInvalidValue;
   if (fmt == 0) {
     OMNI_FRONT_LR(0, 1)
-  } else if (fmt == 1 && V == 4) {
-    OMNI_FRONT_LR(1, 4)
+  } else if (fmt == 1 && V == 2) {
+    OMNI_FRONT_LR(1, 2)
   } else if (fmt == 1) {
     OMNI_FRONT_LR(1, 1)
-  } else if (fmt == 2 && V == 4) {
-    OMNI_FRONT_LR(2, 4)
+  } else if (fmt == 2 && V == 2) {
+    OMNI_FRONT_LR(2, 2)
   } else if (fmt == 2) {
     OMNI_FRONT_LR(2, 1)
   } else {
