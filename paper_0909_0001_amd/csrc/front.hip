@@ -93,6 +93,45 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
     const int64_t rem = idx - tile * per_tile;
     const int64_t o = rem / inner_v, in = (rem - o * inner_v) * V;
     const int64_t sbase = tile * src_tile + o * N * inner + in;
+    const int64_t dbase = tile * dst_tile + o * M * inner + in;
+    auto store = [&](const float2(&zz)[V][L], int res) {
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        float2* d = dst + dbase + (int64_t)(R * q + res) * inner;
+        if constexpr (V == 4) {
+          reinterpret_cast<float4*>(d)[0] = make_float4(zz[0][q].x, zz[0][q].y, zz[1][q].x, zz[1][q].y);
+          reinterpret_cast<float4*>(d)[1] = make_float4(zz[2][q].x, zz[2][q].y, zz[3][q].x, zz[3][q].y);
+        } else if constexpr (V == 2) {
+          reinterpret_cast<float4*>(d)[0] = make_float4(zz[0][q].x, zz[0][q].y, zz[1][q].x, zz[1][q].y);
+        } else {
+          d[0] = zz[0][q];
+        }
+      }
+    };
+    if constexpr (R == 2) {
+      // n = L: both residues use the same inputs, z_j = w_m^{rho j} x_j; one thread does both
+      float2 x[V][L], z[V][L];
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        float2 xv[V];
+        load_v<FMT, V>(src, sbase + (int64_t)j * inner, xv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v][j] = z[v][j] = xv[v];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) sd::dft<L>(z[v]);
+      store(z, 0);
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        const float2 w = twm[j];  // w_m^j
+#pragma unroll
+        for (int v = 0; v < V; ++v) z[v][j] = j ? cmul(x[v][j], w) : x[v][j];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) sd::dft<L>(z[v]);
+      store(z, 1);
+      continue;
+    }
     float2 z[V][L];
 #pragma unroll
     for (int blk = 0; blk < NB; ++blk) {
@@ -113,19 +152,7 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) sd::dft<L>(z[v]);
-    const int64_t dbase = tile * dst_tile + o * M * inner + in;
-#pragma unroll
-    for (int q = 0; q < L; ++q) {
-      float2* d = dst + dbase + (int64_t)(R * q + rho) * inner;
-      if constexpr (V == 4) {
-        reinterpret_cast<float4*>(d)[0] = make_float4(z[0][q].x, z[0][q].y, z[1][q].x, z[1][q].y);
-        reinterpret_cast<float4*>(d)[1] = make_float4(z[2][q].x, z[2][q].y, z[3][q].x, z[3][q].y);
-      } else if constexpr (V == 2) {
-        reinterpret_cast<float4*>(d)[0] = make_float4(z[0][q].x, z[0][q].y, z[1][q].x, z[1][q].y);
-      } else {
-        d[0] = z[0][q];
-      }
-    }
+    store(z, rho);
   }
 }
 
@@ -141,7 +168,8 @@ hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2
   const int64_t total = tiles * outer * (inner / V);
   int64_t g = (total + 255) / 256;
   if (g > 65536) g = 65536;
-  const dim3 grid((unsigned)g, (unsigned)r), block(256);
+  // r = 2: one thread computes both residue classes from the same inputs
+  const dim3 grid((unsigned)g, (unsigned)(r == 2 ? 1 : r)), block(256);
 #define OMNI_FRONT(F_, L_, V_, R_)                                                                           \
   hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_>), grid, block, 0, st, src, dst, twm, tiles, outer, inner, \
                      src_tile, dst_tile)
