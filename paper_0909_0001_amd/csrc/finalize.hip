@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void inverse_axis_tiled_kernel(const void* __r
                                                                  const double2* __restrict__ twi, int64_t outer,
                                                                  int m, int n, int64_t inner, double scale) {
   using Elem = typename std::conditional<REAL_IN, double, double2>::type;
-  __shared__ Elem a[4096];  // m * TC <= 4096
+  __shared__ Elem a[TC == 32 ? 2048 : 4096];  // m * TC: m <= 64 for TC = 32, m <= 256 for TC = 16
   __shared__ double2 w[256];
   const int nout = 2 * n - 1;
   const int64_t cols = outer * inner;
@@ -188,8 +188,8 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
 hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* dst, const double2* twi,
                                int64_t outer, int m, int n, int64_t inner, double scale, hipStream_t st) {
   const int64_t cols = outer * inner;
-  if (m <= 256 && cols >= (m <= 64 ? 64 : 16) * 256) {
-    // TC columns per work-group (m * TC <= 4096 elements of LDS), at least 256 work-groups
+  if (m <= 256 && cols >= (m <= 64 ? 32 : 16) * 256) {
+    // TC columns per work-group (m * TC <= 2048 or 4096 elements of LDS), at least 256 work-groups
     const dim3 b(256);
 #define OMNI_INV_TILED(TC_)                                                                                          \
   do {                                                                                                               \
@@ -210,7 +210,7 @@ hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* d
                          inner, scale);                                                                              \
   } while (0)
     if (m <= 64)
-      OMNI_INV_TILED(64);
+      OMNI_INV_TILED(32);
     else
       OMNI_INV_TILED(16);
 #undef OMNI_INV_TILED
