@@ -78,7 +78,7 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 #define OMNI_PLAN_TUNE 0x4u      /* autotune the general kernel's schedule at plan time (timed on  \
                                     an all-zero input; choice cached in the file OMNI_TUNE_CACHE) */
 #define OMNI_PLAN_GRAPH 0x8u     /* run every correlate call as one HIP graph whose arrays are     \
-                                    parallel branches (captured on first use, replayed after)    */
+                                    parallel branches (first call captured, later calls replay)  */
 
 /* flags argument of omni_correlate* */
 #define OMNI_NO_RESET 0x1u    /* add this call's samples to the running accumulator            */
@@ -137,12 +137,14 @@ int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, voi
 
 /* Batched form: volt[i] / vis[i] belong to array i of the batch plan.
  * Without OMNI_PLAN_GRAPH the arrays run one after another on `stream`.  With
- * it, the plan captures the whole call (all arrays, all stages) into one HIP
+ * it, the plan captures its first call (all arrays, all stages) into one HIP
  * graph in which each array is an independent branch on a stream of its own,
  * so that the arrays' kernels overlap and fill each other's tails; the graph
- * is launched on `stream` and replayed while T, flags and the volt / vis
- * pointers stay the same (any change re-captures).  Results are identical to
- * the sequential form.  The graph holds no memset nodes. */
+ * is launched on `stream` and every later call replays it.  Later calls must
+ * repeat the first call's T, flags and volt / vis pointers (the buffers'
+ * contents may change): any other call returns OMNI_E_STATE (make another
+ * plan for another call shape).  Results are identical to the sequential
+ * form.  The graph holds no memset nodes. */
 int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, void* const* vis, void* stream,
                          uint32_t flags);
 

@@ -1057,6 +1057,11 @@ int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, v
     mark(plan, OMNI_STAGE_CALL, 0, true, st);
     if (plan->graph) {
       if (!same_call(plan, volt, T, vis, flags)) {
+        // Re-capturing a live plan is switched off: the process crashed inside such a call on the GPU
+        // (after a series of captures) and the cause has not been found.  One plan, one call shape.
+        if (plan->gx)
+          return fail(OMNI_E_STATE,
+                      "graph plan: T, flags and buffers must repeat the first (captured) call; make another plan");
         int rc = capture_call(plan, volt, T, vis, flags);
         if (rc) return rc;
       }
