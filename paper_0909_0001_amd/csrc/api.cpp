@@ -28,12 +28,16 @@ hipError_t launch_fused8x4_fp32(int fmt, const void* src, int64_t T, int64_t tps
                                 int F, int n_slices, int time_block, hipStream_t st);
 hipError_t launch_fused8x4_mixed(int fmt, int ns_per_iter, const void* src, int64_t T, int64_t tps,
                                  const float2* tw16, double* partial, int F, int n_slices, hipStream_t st);
-hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2* twm, int64_t tiles, int64_t outer,
-                             int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st);
+hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* twm, int64_t tiles, int64_t outer,
+                             int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st,
+                             bool half16, float scale);
 int fused_ct_lookup(int d, const int* n);
 void fused_ct_params(int idx, int* r, int* s0);
 hipError_t launch_fused_ct(int idx, int fmt, const void* src, int64_t T, int64_t tps, const float2* tw,
                            double* partial, int F, int n_slices, int time_block, int accumulate, hipStream_t st);
+int fused16x3_cell(int cell);
+hipError_t launch_fused16x3_mixed(const void* src, int64_t T, int64_t tps, const float2* tw, double* partial, int F,
+                                  int n_slices, int time_block, int accumulate, double out_scale, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -74,7 +78,8 @@ struct ArrayPlan {
   std::vector<int> n;       // axes with n > 1 (or a single axis when N == 1), in order
   int64_t N = 0, M = 0, n_out = 0;
   FusedSetup fs;            // schedule of the fused kernel (all axes, or the axes after the front)
-  int kernel = 0;  // 0: general; 1: 8x8x8x8 float32; 2: 8x8x8x8 mixed (MFMA); 3: compile-time shape (float32)
+  int kernel = 0;  // 0: general; 1: 8x8x8x8 float32; 2: 8x8x8x8 mixed (MFMA); 3: compile-time shape (float32);
+                   // 4: (16,16,16) behind a front pass, mixed (MFMA), float16 front workspace
   int ct_index = -1;         // entry of the compile-time shape table (kernel 3)
   int lcap = 32;             // longest short DFT the general kernel may use (autotuned)
   int wg_target = 1024;      // work-groups the general kernel's time slicing aims for (autotuned)
@@ -343,6 +348,25 @@ int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_s
   return OMNI_OK;
 }
 
+// The (16,16,16) mixed kernel behind one front pass: work-group = (slice, front
+// channel), all 32768 cells, cell order given by fused16x3_cell.  The front
+// pass writes float16 (scaled by 1/16), which halves its workspace: twice the
+// samples per chunk.
+void plan_fused16x3_mixed(ArrayPlan& ap) {
+  ap.kernel = 4;
+  FusedSetup& fs = ap.fs;
+  fs.M = 32768;
+  fs.N = 4096;
+  fs.fp.n_split = 1;
+  fs.fp.cells_wg = 32768;
+  fs.kmap.assign(32768, 0);
+  for (int c = 0; c < 32768; ++c) fs.kmap[(size_t)c] = omni::fused16x3_cell(c);
+  const int64_t per_t = (int64_t)ap.F * 2 * ap.n[0] * (ap.N / ap.n[0]) * 4;  // float16 complex
+  ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t(2) << 30) / per_t));
+  // workspace in float2 units: chunk_T * F * m_0 * (N / n_0) float16 complex values of 4 bytes
+  ap.front_elems = (ap.chunk_T * per_t / 4 * 4 + 7) / 8;
+}
+
 // The 8x8x8x8 float32 kernel: work-group = (slice, channel, residue c of axis 0 mod 8);
 // its cell i (of 32) in thread tid is written at i * 256 + tid and holds
 // line l = tid + 256 (i / 16), output o = i % 16 of the last (axis 1) transform.
@@ -502,6 +526,9 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   }
   if (form == OMNI_FORM_FP32 && eight4) plan_fused8x4(ap);
   if (form == OMNI_FORM_MIXED && eight4 && dtype != OMNI_CF32) plan_fused8x4_mixed(ap);
+  if (form == OMNI_FORM_MIXED && dtype != OMNI_CF32 && ap.n_front == 1 &&
+      std::vector<int>(ap.n.begin() + 1, ap.n.end()) == std::vector<int>{16, 16, 16})
+    plan_fused16x3_mixed(ap);
   const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
   ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
   // inverse in groups of channels whose float64 workspace fits 512 MiB
@@ -657,14 +684,25 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         const int nk = ap.n[k], mk = 2 * nk;
         inner /= nk;
         float2* dst = ap.d_y[k & 1];
+        const bool h16 = ap.kernel == 4 && k == s - 1;  // float16 planar operands for the mixed kernel
         HIP_TRY(omni::launch_front_axis(fmt, cur, dst, ap.d_tw32 + tw_off, tc * ap.F, outer, nk, mk, ap.front_r[k],
-                                        inner, outer * nk * inner, outer * mk * inner, st));
+                                        inner, outer * nk * inner, outer * mk * inner, st, h16,
+                                        h16 ? 1.f / (float)nk : 1.f));
         outer *= mk;
         tw_off += mk;
         cur = dst;
         fmt = 0;
       }
       int slices = 1;
+      if (ap.kernel == 4) {
+        // all front channels of the chunk in one slice (2048 work-groups for 64 channels)
+        // the front pass scaled by 1/n_0 and each of the three passes by 1/16: undo on |X|^2
+        const double unscale = (double)ap.n[0] * 4096.0;
+        HIP_TRY(omni::launch_fused16x3_mixed(cur, tc, tc, ap.d_tw32 + ap.front_tw_base, ap.d_partial, (int)ap.fs.F, 1,
+                                             p->time_block, c0 > 0 ? 1 : 0, unscale * unscale, st));
+        first_slices = 1;
+        continue;
+      }
       if (ap.kernel == 3) {
         int rc = c0 == 0 ? launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &first_slices)
                          : launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices, 1,
@@ -677,7 +715,7 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, (accumulate || c0 > 0) ? 1 : 0, st));
     }
-    if (ap.kernel == 3)
+    if (ap.kernel == 3 || ap.kernel == 4)
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, first_slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, accumulate ? 1 : 0, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 1) {
@@ -1190,6 +1228,7 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
     const char* kname = ap.kernel == 1   ? "fused8x4_fp32"
                         : ap.kernel == 2 ? "fused8x4_mixed"
                         : ap.kernel == 3 ? "fused_ct_fp32"
+                        : ap.kernel == 4 ? "fused16x3_mixed"
                                          : "fused_fp32";
     s += std::string("{\"kernel\":\"") + kname + "\",\"mode\":\"" + (ap.n_front ? "front" : "direct") +
          "\",\"n_front\":" + std::to_string(ap.n_front) + ",\"chunk_T\":" + std::to_string(ap.chunk_T) +

@@ -75,11 +75,15 @@ __device__ __forceinline__ void load_v(const void* __restrict__ src, int64_t e, 
 // the fold modulus, a compile-time constant so that all n loads of a thread
 // are issued before the arithmetic that consumes them: n = L R / 2 inputs, one
 // block of L per l < R / 2 (for R = 1, the first L / 2 of one block).
-template <int FMT, int L, int V, int R>
-__global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict__ src, float2* __restrict__ dst,
+//
+// H16: the output is float16, scaled by `scale`, in planar blocks: for every
+// (tile, outer index, Fourier index) the inner run of real parts, then that of
+// imaginary parts (the operand layout of the float16 matrix-core kernel).
+template <int FMT, int L, int V, int R, bool H16>
+__global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict__ src, void* __restrict__ dst_,
                                                           const float2* __restrict__ twm, int64_t tiles,
                                                           int64_t outer, int64_t inner, int64_t src_tile,
-                                                          int64_t dst_tile) {
+                                                          int64_t dst_tile, float scale) {
   using namespace fr;
   constexpr int M = L * R, N = M / 2;
   constexpr int NB = R >= 2 ? R / 2 : 1;
@@ -95,6 +99,21 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
     const int64_t sbase = tile * src_tile + o * N * inner + in;
     const int64_t dbase = tile * dst_tile + o * M * inner + in;
     auto store = [&](const float2(&zz)[V][L], int res) {
+      if constexpr (H16) {
+        _Float16* const d16 = static_cast<_Float16*>(dst_);
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+          // planar block of (tile, o, kappa): 2 * inner halves
+          _Float16* d = d16 + ((tile * outer + o) * M + (R * q + res)) * 2 * inner + in;
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            d[v] = (_Float16)(zz[v][q].x * scale);
+            d[inner + v] = (_Float16)(zz[v][q].y * scale);
+          }
+        }
+        return;
+      }
+      float2* const dst = static_cast<float2*>(dst_);
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         float2* d = dst + dbase + (int64_t)(R * q + res) * inner;
@@ -156,8 +175,10 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
   }
 }
 
-hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2* twm, int64_t tiles, int64_t outer,
-                             int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st) {
+// half16: float16 planar output scaled by `scale` (see H16 above); else float32 complex.
+hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* twm, int64_t tiles, int64_t outer,
+                             int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st,
+                             bool half16, float scale) {
   const int L = m / r;
   if (m != 2 * n || L * r != m) return hipErrorInvalidValue;
   // packed integer samples: four inner indices per thread when the word loads stay aligned
@@ -170,9 +191,15 @@ hipError_t launch_front_axis(int fmt, const void* src, float2* dst, const float2
   if (g > 65536) g = 65536;
   // r = 2: one thread computes both residue classes from the same inputs
   const dim3 grid((unsigned)g, (unsigned)(r == 2 ? 1 : r)), block(256);
-#define OMNI_FRONT(F_, L_, V_, R_)                                                                           \
-  hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_>), grid, block, 0, st, src, dst, twm, tiles, outer, inner, \
-                     src_tile, dst_tile)
+#define OMNI_FRONT(F_, L_, V_, R_)                                                                             \
+  do {                                                                                                          \
+    if (half16)                                                                                                 \
+      hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_, true>), grid, block, 0, st, src, dst, twm, tiles,   \
+                         outer, inner, src_tile, dst_tile, scale);                                              \
+    else                                                                                                        \
+      hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_, false>), grid, block, 0, st, src, dst, twm, tiles,  \
+                         outer, inner, src_tile, dst_tile, scale);                                              \
+  } while (0)
   // the planner's fold moduli: L = 16 for m >= 16 (r = m / 16), else r = 1 and L = m
 #define OMNI_FRONT_LR(F_, V_)                              \
   if (r == 1 && L == 2) OMNI_FRONT(F_, 2, V_, 1);          \

@@ -1,0 +1,236 @@
+// Fused mixed-precision kernel for the (16,16,16) grid that remains of the
+// 16x16-of-16x16 array after its front pass (gfx950, float16 matrix cores).
+//
+// Input: one float16 tile per (time sample, Fourier "channel" of the front
+// axis), planar [re | im][a][b][c], 16 antennas per axis, scaled by 1/16.
+// Every axis' zero-padded 32-point DFT (Sec. II.A/II.C) is a dense 32 x 16
+// complex matrix product per line, real-embedded
+//   [Re y ; Im y] = [[Re W, -Im W], [Im W, Re W]] [Re x ; Im x]   (K = 32),
+// on v_mfma_f32_32x32x16_f16 (float16 operands, float32 accumulation), with W
+// split into float16 hi + lo parts (two MFMAs per product) and scaled by 1/16
+// (exact; it keeps every float16 intermediate within the input's range).  The
+// |X|^2 accumulators carry those scales; `out_scale` restores them when they
+// are written out.
+//
+// Work-group = (time slice, channel), 512 threads; it owns all 32768 cells of
+// the channel, 64 float32 accumulators per lane.  Per sample:
+//   A  axis c, lines (a, b): data x W^T, 8 row tiles x 2 column tiles -> LB
+//   then for each half of kappa_b:
+//   B  axis b, lines (a, kappa_c): data x W^T -> LC (that half of kappa_b)
+//   C  axis a, lines (kappa_b, kappa_c): W x data, so that the real and the
+//      imaginary row of an output land in the same lane -> |X|^2 in registers.
+// In A and B the rows of a tile are lines ordered with the next pass'
+// contracted axis fastest, so a lane stores 4 consecutive values of it with
+// one 8-byte LDS write and the next pass reads an operand with one 16-byte
+// read.  The next sample's tile is copied into LDS (direct-to-LDS loads)
+// during B and C.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace omni {
+
+namespace m163 {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int NT = 512;
+constexpr int CELLS = 32768;
+constexpr int SLOTS = 64;  // accumulators per lane
+
+__device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// LB [comp][a][kappa_c][b] and LC [comp][kappa_b mod 16][kappa_c][a], in halves
+__device__ __forceinline__ int lb_at(int comp, int a, int kc, int b) { return ((comp * 16 + a) * 32 + kc) * 16 + b; }
+__device__ __forceinline__ int lc_at(int comp, int kb, int kc, int a) { return ((comp * 16 + kb) * 32 + kc) * 16 + a; }
+
+__device__ __forceinline__ half4 to_half4(const floatx16& d, int g) {
+  half4 v;
+  v[0] = (_Float16)d[4 * g];
+  v[1] = (_Float16)d[4 * g + 1];
+  v[2] = (_Float16)d[4 * g + 2];
+  v[3] = (_Float16)d[4 * g + 3];
+  return v;
+}
+
+}  // namespace m163
+
+// Grid: n_slices x F work-groups (F = channels of this launch), 512 threads.
+// src: [T][F][2][4096] halves; tw: w_32^q, q < 32 (float32); partial:
+// [n_slices][F][32768] float64 in the cell order given by fused16x3_cell.
+__global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __restrict__ src, int64_t T,
+                                                              int64_t t_per_slice, const float2* __restrict__ tw,
+                                                              double* __restrict__ partial, int F, int time_block,
+                                                              int accumulate, double out_scale) {
+  using namespace m163;
+  __shared__ __attribute__((aligned(16))) _Float16 LB[2 * 16 * 32 * 16];
+  __shared__ __attribute__((aligned(16))) _Float16 LC[2 * 16 * 32 * 16];
+  __shared__ __attribute__((aligned(16))) _Float16 RAW[2 * 4096];  // the sample's tile, staged
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
+  const int ch = blockIdx.x % F;
+  const int s = blockIdx.x / F;
+  const int64_t t0 = (int64_t)s * t_per_slice;
+  const int64_t t1 = min(T, t0 + t_per_slice);
+
+  // DFT operand of this lane, for column / row tile u (kappa in [16u, 16u + 16)) and K step ks:
+  // output (co = n32 / 16, kappa = 16u + n32 % 16), input (ci = h, j = 8 ks + i)
+  half8 Wh[2][2], Wl[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int kap = 16 * u + (n32 & 15), j = 8 * ks + i;
+        const float2 wv = tw[(kap * j) & 31];
+        const bool co = n32 >= 16, ci = h != 0;
+        const float v = (!co ? (!ci ? wv.x : -wv.y) : (!ci ? wv.y : wv.x)) * 0.0625f;
+        const _Float16 hi = (_Float16)v;
+        Wh[u][ks][i] = hi;
+        Wl[u][ks][i] = (_Float16)(v - (float)hi);
+      }
+    }
+  }
+
+  // asynchronous copy of the tile of sample t into RAW (direct-to-LDS loads; wave w moves 1 KiB pieces w, w + 8)
+  auto stage = [&](int64_t t) {
+    const unsigned char* g = reinterpret_cast<const unsigned char*>(src + (t * F + ch) * 8192);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int piece = w + 8 * k;
+      __builtin_amdgcn_global_load_lds(g + piece * 1024 + l * 16,
+                                       (__attribute__((address_space(3))) void*)(reinterpret_cast<unsigned char*>(RAW) +
+                                                                                 piece * 1024),
+                                       16, 0, 0);
+    }
+  };
+
+  float acc[SLOTS];
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) acc[i] = 0.f;
+  double* out = partial + ((int64_t)s * F + ch) * CELLS;
+  bool flushed = false;
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) {
+      const int cell = i * NT + tid;
+      const double v = (double)acc[i] * out_scale;
+      out[cell] = (accumulate || flushed) ? out[cell] + v : v;
+      acc[i] = 0.f;
+    }
+    flushed = true;
+  };
+
+  if (t0 < t1) stage(t0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int blk = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    // ---- A: axis c; row tile w holds lines (a = 2w + n32 / 16, b = n32 % 16), this lane's half h reads
+    // component h of c = 8 ks .. 8 ks + 7
+    {
+      half8 xa[2];
+      const int line = (2 * w + (n32 >> 4)) * 16 + (n32 & 15);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) xa[ks] = *reinterpret_cast<const half8*>(&RAW[h * 4096 + line * 16 + 8 * ks]);
+      const int co = n32 >> 4;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        floatx16 d = {};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          d = mfma(xa[ks], Wh[u][ks], d);
+          d = mfma(xa[ks], Wl[u][ks], d);
+        }
+        // column n32: (co, kappa_c = 16 u + n32 % 16); rows 8g + 4h + e: b = 8 (g & 1) + 4h + e, a = 2w + g / 2
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int a = 2 * w + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
+          *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * u + (n32 & 15), b0)]) = to_half4(d, g);
+        }
+      }
+    }
+    __syncthreads();
+    if (t + 1 < t1) stage(t + 1);  // RAW has been read: fetch the next tile behind passes B and C
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      // ---- B: axis b, row tiles 2w, 2w + 1 of lines (a = m % 16, kappa_c = 2 mt + m / 16), columns = this
+      // half of kappa_b
+#pragma unroll
+      for (int jm = 0; jm < 2; ++jm) {
+        const int mt = 2 * w + jm;
+        const int a_in = n32 & 15, kc_in = 2 * mt + (n32 >> 4);
+        floatx16 d = {};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const half8 x = *reinterpret_cast<const half8*>(&LB[lb_at(h, a_in, kc_in, 8 * ks)]);
+          d = mfma(x, Wh[half][ks], d);
+          d = mfma(x, Wl[half][ks], d);
+        }
+        const int co = n32 >> 4, kb = n32 & 15;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int a0 = 8 * (g & 1) + 4 * h, kc = 2 * mt + (g >> 1);
+          *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d, g);
+        }
+      }
+      __syncthreads();
+      // ---- C: axis a, column tiles (lines kappa_b mod 16 = 2w + j, kappa_c = n32), row tiles u
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int kb = 2 * w + j;
+        half8 x[2];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) x[ks] = *reinterpret_cast<const half8*>(&LC[lc_at(h, kb, n32, 8 * ks)]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          floatx16 d = {};
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks) {
+            d = mfma(Wh[u][ks], x[ks], d);
+            d = mfma(Wl[u][ks], x[ks], d);
+          }
+          // rows r < 8 hold Re and rows r + 8 Im of the same kappa_a
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            float& a_ = acc[((half * 2 + j) * 2 + u) * 8 + r];
+            a_ = fmaf(d[r], d[r], fmaf(d[r + 8], d[r + 8], a_));
+          }
+        }
+      }
+      if (half == 0) __syncthreads();  // pass B of the second half overwrites LC
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next tile has landed
+    __syncthreads();
+    if (++blk == time_block) {
+      blk = 0;
+      flush();
+    }
+  }
+  if (blk > 0 || !flushed) flush();
+}
+
+// Natural index (kappa_a * 32 + kappa_b) * 32 + kappa_c of cell `cell` (= slot * 512 + thread).
+int fused16x3_cell(int cell) {
+  const int slot = cell / 512, tid = cell % 512;
+  const int w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
+  const int r = slot % 8, u = (slot / 8) % 2, j = (slot / 16) % 2, half = slot / 32;
+  const int ka = 16 * u + 8 * (r / 4) + 4 * h + (r % 4);
+  const int kb = 16 * half + 2 * w + j;
+  const int kc = n32;
+  return (ka * 32 + kb) * 32 + kc;
+}
+
+hipError_t launch_fused16x3_mixed(const void* src, int64_t T, int64_t tps, const float2* tw, double* partial, int F,
+                                  int n_slices, int time_block, int accumulate, double out_scale, hipStream_t st) {
+  if ((reinterpret_cast<uintptr_t>(src) & 15) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused16x3_mixed_kernel, dim3((unsigned)(n_slices * F)), dim3(512), 0, st,
+                     static_cast<const _Float16*>(src), T, tps, tw, partial, F, time_block, accumulate, out_scale);
+  return hipGetLastError();
+}
+
+}  // namespace omni
