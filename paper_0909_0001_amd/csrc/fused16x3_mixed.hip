@@ -44,9 +44,26 @@ __device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// LB [comp][a][kappa_c][b] and LC [comp][kappa_b mod 16][kappa_c][a], in halves
-__device__ __forceinline__ int lb_at(int comp, int a, int kc, int b) { return ((comp * 16 + a) * 32 + kc) * 16 + b; }
-__device__ __forceinline__ int lc_at(int comp, int kb, int kc, int a) { return ((comp * 16 + kb) * 32 + kc) * 16 + a; }
+// LB [comp][a][kappa_c][b] and LC [comp][kappa_b mod 16][kappa_c][a], in halves.  Blocks of 32 rows
+// of 16 halves carry 8 halves of padding (consecutive blocks start 4 banks apart), and inside a row
+// the 4-half units are XOR-swizzled by bit 3 of kappa_c and by the component: the 8-byte stores of
+// passes A and B (32 lanes: 2 components x 16 rows) and the 16-byte loads of passes B and C (16
+// lanes) then touch 64 distinct banks.  A 16-byte load of component 1 returns its two halves swapped.
+constexpr int BLK = 520;         // 32 x 16 + 8
+constexpr int CMP = 16 * BLK;    // component stride
+constexpr int LSZ = 2 * CMP;
+__device__ __forceinline__ int lb_at(int comp, int a, int kc, int b) {
+  return comp * CMP + a * BLK + kc * 16 + (b ^ (kc & 8) ^ (4 * comp));
+}
+__device__ __forceinline__ int lc_at(int comp, int kb, int kc, int a) {
+  return comp * CMP + kb * BLK + kc * 16 + (a ^ (kc & 8) ^ (4 * comp));
+}
+// 8 consecutive halves j0 .. j0 + 7 (j0 a multiple of 8) of a swizzled row
+__device__ __forceinline__ half8 load8(const _Float16* row, int j0, int kc, int comp) {
+  half8 v = *reinterpret_cast<const half8*>(row + (j0 ^ (kc & 8)));
+  if (comp) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
+  return v;
+}
 
 __device__ __forceinline__ half4 to_half4(const floatx16& d, int g) {
   half4 v;
@@ -67,8 +84,8 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
                                                               double* __restrict__ partial, int F, int time_block,
                                                               int accumulate, double out_scale) {
   using namespace m163;
-  __shared__ __attribute__((aligned(16))) _Float16 LB[2 * 16 * 32 * 16];
-  __shared__ __attribute__((aligned(16))) _Float16 LC[2 * 16 * 32 * 16];
+  __shared__ __attribute__((aligned(16))) _Float16 LB[LSZ];
+  __shared__ __attribute__((aligned(16))) _Float16 LC[LSZ];
   __shared__ __attribute__((aligned(16))) _Float16 RAW[2 * 4096];  // the sample's tile, staged
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
   const int ch = blockIdx.x % F;
@@ -167,7 +184,7 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
         floatx16 d = {};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          const half8 x = *reinterpret_cast<const half8*>(&LB[lb_at(h, a_in, kc_in, 8 * ks)]);
+          const half8 x = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, kc_in, h);
           d = mfma(x, Wh[half][ks], d);
           d = mfma(x, Wl[half][ks], d);
         }
@@ -185,7 +202,7 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
         const int kb = 2 * w + j;
         half8 x[2];
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) x[ks] = *reinterpret_cast<const half8*>(&LC[lc_at(h, kb, n32, 8 * ks)]);
+        for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMP + kb * BLK + n32 * 16], 8 * ks, n32, h);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           floatx16 d = {};
