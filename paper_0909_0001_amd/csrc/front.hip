@@ -105,10 +105,21 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
         for (int q = 0; q < L; ++q) {
           // planar block of (tile, o, kappa): 2 * inner halves
           _Float16* d = d16 + ((tile * outer + o) * M + (R * q + res)) * 2 * inner + in;
+          if constexpr (V == 2) {  // one 4-byte store per plane
+            typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+            half2_t re, im;
+            re[0] = (_Float16)(zz[0][q].x * scale);
+            re[1] = (_Float16)(zz[1][q].x * scale);
+            im[0] = (_Float16)(zz[0][q].y * scale);
+            im[1] = (_Float16)(zz[1][q].y * scale);
+            *reinterpret_cast<half2_t*>(d) = re;
+            *reinterpret_cast<half2_t*>(d + inner) = im;
+          } else {
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            d[v] = (_Float16)(zz[v][q].x * scale);
-            d[inner + v] = (_Float16)(zz[v][q].y * scale);
+            for (int v = 0; v < V; ++v) {
+              d[v] = (_Float16)(zz[v][q].x * scale);
+              d[inner + v] = (_Float16)(zz[v][q].y * scale);
+            }
           }
         }
         return;
