@@ -36,6 +36,10 @@ void fused_ct_params(int idx, int* r, int* s0);
 hipError_t launch_fused_ct(int idx, int fmt, const void* src, int64_t T, int64_t tps, const float2* tw,
                            double* partial, int F, int n_slices, int time_block, int accumulate, hipStream_t st);
 int fused16x3_cell(int cell);
+int fused8844_cell(int cell);
+hipError_t launch_fused8844_mixed(const void* src, int64_t T, int64_t tps, const float2* tw16, const float2* tw8,
+                                  double* partial, int F, int n_slices, int time_block, int accumulate,
+                                  double out_scale, hipStream_t st);
 hipError_t launch_fused16x3_mixed(const void* src, int64_t T, int64_t tps, const float2* tw, double* partial, int F,
                                   int n_slices, int time_block, int accumulate, double out_scale, hipStream_t st);
 }  // namespace omni
@@ -79,7 +83,8 @@ struct ArrayPlan {
   int64_t N = 0, M = 0, n_out = 0;
   FusedSetup fs;            // schedule of the fused kernel (all axes, or the axes after the front)
   int kernel = 0;  // 0: general; 1: 8x8x8x8 float32; 2: 8x8x8x8 mixed (MFMA); 3: compile-time shape (float32);
-                   // 4: (16,16,16) behind a front pass, mixed (MFMA), float16 front workspace
+                   // 4: (16,16,16) behind a front pass, mixed (MFMA), float16 front workspace;
+                   // 5: (8,8,4,4) behind two front passes, mixed (MFMA), float16 front workspace
   int ct_index = -1;         // entry of the compile-time shape table (kernel 3)
   int lcap = 32;             // longest short DFT the general kernel may use (autotuned)
   int wg_target = 1024;      // work-groups the general kernel's time slicing aims for (autotuned)
@@ -348,23 +353,39 @@ int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_s
   return OMNI_OK;
 }
 
-// The (16,16,16) mixed kernel behind one front pass: work-group = (slice, front
-// channel), all 32768 cells, cell order given by fused16x3_cell.  The front
-// pass writes float16 (scaled by 1/16), which halves its workspace: twice the
+// Matrix-core kernels behind the front passes: kernel 4 for the (16,16,16)
+// grid behind one front pass, kernel 5 for (8,8,4,4) behind two.  Work-group
+// = (slice, front channel), all the channel's cells, cell order given by
+// fused16x3_cell / fused8844_cell.  The last front pass writes float16 planar
+// operands (scaled by 1/n of its axis), which halves that workspace: twice the
 // samples per chunk.
-void plan_fused16x3_mixed(ArrayPlan& ap) {
-  ap.kernel = 4;
+void plan_mixed_behind_front(ArrayPlan& ap, int kernel) {
+  ap.kernel = kernel;
   FusedSetup& fs = ap.fs;
-  fs.M = 32768;
-  fs.N = 4096;
+  const int s = ap.n_front;
+  int64_t ms = 1, ns = 1;
+  for (int k = 0; k < s; ++k) {
+    ms *= 2 * ap.n[k];
+    ns *= ap.n[k];
+  }
+  const int64_t rest_n = ap.N / ns;
+  fs.N = rest_n;
+  fs.M = ap.M / ms;
   fs.fp.n_split = 1;
-  fs.fp.cells_wg = 32768;
-  fs.kmap.assign(32768, 0);
-  for (int c = 0; c < 32768; ++c) fs.kmap[(size_t)c] = omni::fused16x3_cell(c);
-  const int64_t per_t = (int64_t)ap.F * 2 * ap.n[0] * (ap.N / ap.n[0]) * 4;  // float16 complex
+  fs.fp.cells_wg = (int32_t)fs.M;
+  fs.kmap.assign((size_t)fs.M, 0);
+  for (int c = 0; c < (int)fs.M; ++c)
+    fs.kmap[(size_t)c] = kernel == 4 ? omni::fused16x3_cell(c) : omni::fused8844_cell(c);
+  // bytes per time sample of the last (float16) front output; earlier front outputs are float32
+  const int64_t per_t = (int64_t)ap.F * ms * rest_n * 4;
   ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t(2) << 30) / per_t));
-  // workspace in float2 units: chunk_T * F * m_0 * (N / n_0) float16 complex values of 4 bytes
-  ap.front_elems = (ap.chunk_T * per_t / 4 * 4 + 7) / 8;
+  ap.front_elems = (ap.chunk_T * per_t + 7) / 8;  // float2 units
+  int64_t mm = 1, nn = ap.N;
+  for (int k = 0; k + 1 < s; ++k) {
+    mm *= 2 * ap.n[k];
+    nn /= ap.n[k];
+    ap.front_elems = std::max(ap.front_elems, ap.chunk_T * ap.F * mm * nn);
+  }
 }
 
 // The 8x8x8x8 float32 kernel: work-group = (slice, channel, residue c of axis 0 mod 8);
@@ -528,7 +549,10 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   if (form == OMNI_FORM_MIXED && eight4 && dtype != OMNI_CF32) plan_fused8x4_mixed(ap);
   if (form == OMNI_FORM_MIXED && dtype != OMNI_CF32 && ap.n_front == 1 &&
       std::vector<int>(ap.n.begin() + 1, ap.n.end()) == std::vector<int>{16, 16, 16})
-    plan_fused16x3_mixed(ap);
+    plan_mixed_behind_front(ap, 4);
+  if (form == OMNI_FORM_MIXED && dtype != OMNI_CF32 && ap.n_front == 2 &&
+      std::vector<int>(ap.n.begin() + 2, ap.n.end()) == std::vector<int>{8, 8, 4, 4})
+    plan_mixed_behind_front(ap, 5);
   const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
   ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
   // inverse in groups of channels whose float64 workspace fits 512 MiB
@@ -684,7 +708,7 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         const int nk = ap.n[k], mk = 2 * nk;
         inner /= nk;
         float2* dst = ap.d_y[k & 1];
-        const bool h16 = ap.kernel == 4 && k == s - 1;  // float16 planar operands for the mixed kernel
+        const bool h16 = (ap.kernel == 4 || ap.kernel == 5) && k == s - 1;  // float16 operands, matrix cores
         HIP_TRY(omni::launch_front_axis(fmt, cur, dst, ap.d_tw32 + tw_off, tc * ap.F, outer, nk, mk, ap.front_r[k],
                                         inner, outer * nk * inner, outer * mk * inner, st, h16,
                                         h16 ? 1.f / (float)nk : 1.f));
@@ -703,6 +727,15 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         first_slices = 1;
         continue;
       }
+      if (ap.kernel == 5) {
+        // the last front pass scaled by 1/n_1, the passes by 1/16, 1/8, 1/8: undo on |X|^2
+        const double unscale = (double)ap.n[1] * 1024.0;
+        const float2* tw = ap.d_tw32 + ap.front_tw_base;  // tables of the rest axes: 16, 16, 8, 8 entries
+        HIP_TRY(omni::launch_fused8844_mixed(cur, tc, tc, tw, tw + 32, ap.d_partial, (int)ap.fs.F, 1, p->time_block,
+                                             c0 > 0 ? 1 : 0, unscale * unscale, st));
+        first_slices = 1;
+        continue;
+      }
       if (ap.kernel == 3) {
         int rc = c0 == 0 ? launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &first_slices)
                          : launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices, 1,
@@ -715,7 +748,7 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, (accumulate || c0 > 0) ? 1 : 0, st));
     }
-    if (ap.kernel == 3 || ap.kernel == 4)
+    if (ap.kernel >= 3)
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, first_slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, accumulate ? 1 : 0, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 1) {
@@ -1229,6 +1262,7 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
                         : ap.kernel == 2 ? "fused8x4_mixed"
                         : ap.kernel == 3 ? "fused_ct_fp32"
                         : ap.kernel == 4 ? "fused16x3_mixed"
+                        : ap.kernel == 5 ? "fused8844_mixed"
                                          : "fused_fp32";
     s += std::string("{\"kernel\":\"") + kname + "\",\"mode\":\"" + (ap.n_front ? "front" : "direct") +
          "\",\"n_front\":" + std::to_string(ap.n_front) + ",\"chunk_T\":" + std::to_string(ap.chunk_T) +

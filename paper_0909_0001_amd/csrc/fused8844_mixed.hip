@@ -1,0 +1,240 @@
+// Fused mixed-precision kernel for the (8,8,4,4) grid that remains of the
+// three-level 16x16 / 8x8 / 4x4 hierarchy after its two front passes (gfx950,
+// float16 matrix cores).
+//
+// Input: one float16 tile per (time sample, Fourier "channel" of the front
+// axes), planar [re | im][a][b][c][d] (8, 8, 4, 4 antennas), scaled by the
+// front pass.  The zero-padded DFTs (Sec. II.A/II.C) are dense complex matrix
+// products, real-embedded as in the other matrix-core kernels,
+//   [Re y ; Im y] = [[Re W, -Im W], [Im W, Re W]] [Re x ; Im x],
+// on v_mfma_f32_32x32x16_f16 with W split into float16 hi + lo parts:
+//   P1 axes c and d together: the 8x8 outputs of the 4x4 inputs (Kronecker
+//      product of two 8 x 4 DFTs, K = 32), lines (a, b), W scaled by 1/16
+//   P2 axis b: 16 x 8, lines (a, kappa_cd), W scaled by 1/8
+//   P3 axis a: 16 x 8, W x data, lines (kappa_b, kappa_cd), so that the real
+//      and imaginary row of an output land in one lane -> |X|^2 in registers.
+// The scales keep every float16 intermediate within the input's range;
+// `out_scale` undoes them on |X|^2.  Work-group = (time slice, channel), 512
+// threads, all 16384 cells of the channel, 32 float32 accumulators per lane.
+// LDS rows are padded and XOR-swizzled so that the 8-byte stores (32 lanes:
+// 2 components x 16 rows) and the 16-byte operand loads (16 lanes) touch
+// distinct banks.  The next sample's tile is copied into LDS (direct-to-LDS
+// loads) behind P2 and P3.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace omni {
+
+namespace m8844 {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int NT = 512;
+constexpr int CELLS = 16384;
+constexpr int SLOTS = 32;
+
+__device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// LB [comp][a 8][kappa_cd 64][b 8]: a-blocks of 64 rows of 8 halves, padded by 16 halves (8 banks);
+// the two 4-half units of a row are swapped for component 1.
+constexpr int LB_BLK = 64 * 8 + 16;
+constexpr int LB_CMP = 8 * LB_BLK;
+// LC [comp][kappa_b 16][kappa_cd 64][a 8]: kappa_b-blocks padded by 8 halves (4 banks)
+constexpr int LC_BLK = 64 * 8 + 8;
+constexpr int LC_CMP = 16 * LC_BLK;
+
+__device__ __forceinline__ int lb_at(int comp, int a, int kcd, int b) {
+  return comp * LB_CMP + a * LB_BLK + kcd * 8 + (b ^ (4 * comp));
+}
+__device__ __forceinline__ int lc_at(int comp, int kb, int kcd, int a) {
+  return comp * LC_CMP + kb * LC_BLK + kcd * 8 + (a ^ (4 * comp));
+}
+// the 8 halves of a row (component comp), in logical order
+__device__ __forceinline__ half8 load_row(const _Float16* row, int comp) {
+  half8 v = *reinterpret_cast<const half8*>(row);
+  if (comp) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
+  return v;
+}
+
+__device__ __forceinline__ half4 to_half4(const floatx16& d, int g) {
+  half4 v;
+  v[0] = (_Float16)d[4 * g];
+  v[1] = (_Float16)d[4 * g + 1];
+  v[2] = (_Float16)d[4 * g + 2];
+  v[3] = (_Float16)d[4 * g + 3];
+  return v;
+}
+
+// real-embedded entry: output component co, input component ci of w (scaled)
+__device__ __forceinline__ float embed(float2 w, bool co, bool ci) {
+  return !co ? (!ci ? w.x : -w.y) : (!ci ? w.y : w.x);
+}
+
+}  // namespace m8844
+
+// Grid: n_slices x F work-groups, 512 threads.  src: [T][F][2][1024] halves;
+// tw16 / tw8: w_16^q (q < 16) and w_8^q (q < 8), float32; partial:
+// [n_slices][F][16384] float64 in the cell order of fused8844_cell.
+__global__ __launch_bounds__(512) void fused8844_mixed_kernel(const _Float16* __restrict__ src, int64_t T,
+                                                              int64_t t_per_slice, const float2* __restrict__ tw16,
+                                                              const float2* __restrict__ tw8,
+                                                              double* __restrict__ partial, int F, int time_block,
+                                                              int accumulate, double out_scale) {
+  using namespace m8844;
+  __shared__ __attribute__((aligned(16))) _Float16 RAW[2 * 1024];
+  __shared__ __attribute__((aligned(16))) _Float16 LB[2 * LB_CMP];
+  __shared__ __attribute__((aligned(16))) _Float16 LC[2 * LC_CMP];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
+  const bool co = n32 >= 16;
+  const int ch = blockIdx.x % F;
+  const int s = blockIdx.x / F;
+  const int64_t t0 = (int64_t)s * t_per_slice;
+  const int64_t t1 = min(T, t0 + t_per_slice);
+
+  // P1 operand of this wave's column tile ct = w % 4: column n32 = (co, kappa_cd = 16 ct + n32 % 16),
+  // K = (ci = h, j = 8 ks + i) with j = 4 c + d; w = w_8^{kc c} w_8^{kd d} / 16
+  const int ct = w & 3, mt1 = w >> 2;
+  half8 W1h[2], W1l[2];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int kcd = 16 * ct + (n32 & 15), j = 8 * ks + i;
+      const int kc = kcd >> 3, kd = kcd & 7, c = j >> 2, d = j & 3;
+      const float2 wc = tw8[(kc * c) & 7], wd = tw8[(kd * d) & 7];
+      const float2 wv = make_float2(wc.x * wd.x - wc.y * wd.y, wc.x * wd.y + wc.y * wd.x);
+      const float v = embed(wv, co, h != 0) * 0.0625f;
+      const _Float16 hi = (_Float16)v;
+      W1h[ks][i] = hi;
+      W1l[ks][i] = (_Float16)(v - (float)hi);
+    }
+  }
+  // P2 / P3 operand: output (co, kappa = n32 % 16), K = (ci = h, j = i < 8): w_16^{kappa j} / 8
+  half8 W2h, W2l;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float v = embed(tw16[((n32 & 15) * i) & 15], co, h != 0) * 0.125f;
+    const _Float16 hi = (_Float16)v;
+    W2h[i] = hi;
+    W2l[i] = (_Float16)(v - (float)hi);
+  }
+
+  // asynchronous copy of the tile of sample t into RAW: 4 KiB, one 1 KiB piece for each of waves 0-3
+  auto stage = [&](int64_t t) {
+    if (w < 4) {
+      const unsigned char* g = reinterpret_cast<const unsigned char*>(src + (t * F + ch) * 2048);
+      __builtin_amdgcn_global_load_lds(g + w * 1024 + l * 16,
+                                       (__attribute__((address_space(3))) void*)(reinterpret_cast<unsigned char*>(RAW) +
+                                                                                 w * 1024),
+                                       16, 0, 0);
+    }
+  };
+
+  float acc[SLOTS];
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) acc[i] = 0.f;
+  double* out = partial + ((int64_t)s * F + ch) * CELLS;
+  bool flushed = false;
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) {
+      const int cell = i * NT + tid;
+      const double v = (double)acc[i] * out_scale;
+      out[cell] = (accumulate || flushed) ? out[cell] + v : v;
+      acc[i] = 0.f;
+    }
+    flushed = true;
+  };
+
+  if (t0 < t1) stage(t0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int blk = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    // ---- P1: row tile mt1 (lines mt1 * 32 + n32 = a * 8 + b), column tile ct
+    {
+      const int line = mt1 * 32 + n32;
+      half8 x[2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) x[ks] = *reinterpret_cast<const half8*>(&RAW[h * 1024 + line * 16 + 8 * ks]);
+      floatx16 d = {};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        d = mfma(x[ks], W1h[ks], d);
+        d = mfma(x[ks], W1l[ks], d);
+      }
+      // rows 8g + 4h + e: line mt1 * 32 + 8g + 4h + e -> a = 4 mt1 + g, b = 4h + e
+      const int kcd = 16 * ct + (n32 & 15);
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        *reinterpret_cast<half4*>(&LB[lb_at(co, 4 * mt1 + g, kcd, 4 * h)]) = to_half4(d, g);
+    }
+    __syncthreads();
+    if (t + 1 < t1) stage(t + 1);  // RAW has been read
+    // ---- P2: row tiles 2w, 2w + 1 (lines mt * 32 + n32: a = n32 % 8, kappa_cd = 4 mt + n32 / 8)
+#pragma unroll
+    for (int jm = 0; jm < 2; ++jm) {
+      const int mt = 2 * w + jm;
+      const int a_in = n32 & 7, kcd_in = 4 * mt + (n32 >> 3);
+      const half8 x = load_row(&LB[h * LB_CMP + a_in * LB_BLK + kcd_in * 8], h);
+      floatx16 d = {};
+      d = mfma(x, W2h, d);
+      d = mfma(x, W2l, d);
+      // column n32: (co, kappa_b = n32 % 16); rows 8g + 4h + e: a = 4h + e, kappa_cd = 4 mt + g
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        *reinterpret_cast<half4*>(&LC[lc_at(co, n32 & 15, 4 * mt + g, 4 * h)]) = to_half4(d, g);
+    }
+    __syncthreads();
+    // ---- P3: column tiles nt = 4w + j (lines nt * 32 + n32: kappa_b = nt / 2, kappa_cd = 32 (nt % 2) + n32)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int nt = 4 * w + j;
+      const int kb = nt >> 1, kcd = 32 * (nt & 1) + n32;
+      const half8 x = load_row(&LC[h * LC_CMP + kb * LC_BLK + kcd * 8], h);
+      floatx16 d = {};
+      d = mfma(W2h, x, d);
+      d = mfma(W2l, x, d);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        float& a_ = acc[j * 8 + r];
+        a_ = fmaf(d[r], d[r], fmaf(d[r + 8], d[r + 8], a_));
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next tile has landed
+    __syncthreads();
+    if (++blk == time_block) {
+      blk = 0;
+      flush();
+    }
+  }
+  if (blk > 0 || !flushed) flush();
+}
+
+// Natural index ((kappa_a * 16 + kappa_b) * 8 + kappa_c) * 8 + kappa_d of cell `cell` (= slot * 512 + thread).
+int fused8844_cell(int cell) {
+  const int slot = cell / 512, tid = cell % 512;
+  const int w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
+  const int r = slot % 8, j = slot / 8;
+  const int nt = 4 * w + j;
+  const int kb = nt >> 1, kcd = 32 * (nt & 1) + n32;
+  const int ka = 8 * (r / 4) + 4 * h + (r % 4);
+  return (ka * 16 + kb) * 64 + kcd;
+}
+
+hipError_t launch_fused8844_mixed(const void* src, int64_t T, int64_t tps, const float2* tw16, const float2* tw8,
+                                  double* partial, int F, int n_slices, int time_block, int accumulate,
+                                  double out_scale, hipStream_t st) {
+  if ((reinterpret_cast<uintptr_t>(src) & 15) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused8844_mixed_kernel, dim3((unsigned)(n_slices * F)), dim3(512), 0, st,
+                     static_cast<const _Float16*>(src), T, tps, tw16, tw8, partial, F, time_block, accumulate,
+                     out_scale);
+  return hipGetLastError();
+}
+
+}  // namespace omni

@@ -383,6 +383,27 @@ def test_mixed_16x3_small_full_oracle():
         assert err <= TOL["mixed"]
 
 
+def test_mixed_8844_small_full_oracle():
+    """Mixed form behind two front passes: (2, 2, 8, 8, 4, 4) grid (float16 front workspace, the (8,8,4,4)
+    matrix-core kernel), every lag against the oracle, several time blocks and chunks."""
+    level_dims = [[2, 2], [8, 8], [4, 4]]
+    N = math.prod(dims_of(level_dims))
+    for dtype, T in (("ci4", 9), ("ci8", 70)):
+        gen = torch.Generator().manual_seed(N + T + 1)
+        raw = random_raw(dtype, T, 2, N, gen)
+        say("mixed 8844", level_dims, dtype, T)
+        vis, plan = gpu_vis(level_dims, raw, dtype, form="mixed", time_block=16)
+        assert '"kernel":"fused8844_mixed"' in plan.describe()
+        err = rel_err(vis, oracle_vis(raw, dtype, level_dims))
+        say("mixed 8844 error", err)
+        assert err <= TOL["mixed"]
+
+
+def test_mixed_hier3_sampled_cells():
+    """The three-level hierarchy in the mixed form at full N: sampled cells and Fourier cells."""
+    sampled_cells_check(skysim.WORKLOADS["hier3"], T=12, F=2, form="mixed", kernel="fused8844_mixed")
+
+
 def test_mixed_hier16x16_sampled_cells():
     """The 16x16-of-16x16 array in the mixed form at full N: sampled cells and Fourier cells."""
     sampled_cells_check(skysim.WORKLOADS["hier16x16"], T=10, F=3, form="mixed", kernel="fused16x3_mixed")
