@@ -80,7 +80,7 @@ __device__ __forceinline__ float embed(float2 w, bool co, bool ci) {
 // Grid: n_slices x F work-groups, 512 threads.  src: [T][F][2][1024] halves;
 // tw16 / tw8: w_16^q (q < 16) and w_8^q (q < 8), float32; partial:
 // [n_slices][F][16384] float64 in the cell order of fused8844_cell.
-__global__ __launch_bounds__(512) void fused8844_mixed_kernel(const _Float16* __restrict__ src, int64_t T,
+__global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16* __restrict__ src, int64_t T,
                                                               int64_t t_per_slice, const float2* __restrict__ tw16,
                                                               const float2* __restrict__ tw8,
                                                               double* __restrict__ partial, int F, int time_block,
