@@ -76,9 +76,14 @@ def recorded_traffic(kernel: str, workload: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_0909_0001_amd", "csrc", rec.get("source", "-"))
-    if not os.path.isfile(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
+    # one or more sources (space-separated) with their hashes in the same order
+    names, hashes = rec.get("source", "-").split(), rec.get("source_sha256", "").split()
+    if len(names) != len(hashes):
         return None
+    for name, want in zip(names, hashes):
+        src = os.path.join(ROOT, "paper_0909_0001_amd", "csrc", name)
+        if not os.path.isfile(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != want:
+            return None
     return float(rec["traffic_bytes"])
 
 
