@@ -708,14 +708,16 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         const int nk = ap.n[k], mk = 2 * nk;
         inner /= nk;
         float2* dst = ap.d_y[k & 1];
-        const bool h16 = (ap.kernel == 4 || ap.kernel == 5) && k == s - 1;  // float16 operands, matrix cores
+        // float16 planar output: the last pass before a matrix-core kernel (its operands), and for the
+        // three-level kernel also the first (halves the traffic between the two front passes)
+        const bool h16 = (ap.kernel == 4 && k == s - 1) || ap.kernel == 5;
         HIP_TRY(omni::launch_front_axis(fmt, cur, dst, ap.d_tw32 + tw_off, tc * ap.F, outer, nk, mk, ap.front_r[k],
                                         inner, outer * nk * inner, outer * mk * inner, st, h16,
                                         h16 ? 1.f / (float)nk : 1.f));
         outer *= mk;
         tw_off += mk;
         cur = dst;
-        fmt = 0;
+        fmt = h16 ? 3 : 0;
       }
       int slices = 1;
       if (ap.kernel == 4) {
@@ -728,8 +730,8 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         continue;
       }
       if (ap.kernel == 5) {
-        // the last front pass scaled by 1/n_1, the passes by 1/16, 1/8, 1/8: undo on |X|^2
-        const double unscale = (double)ap.n[1] * 1024.0;
+        // the front passes scaled by 1/n_0 and 1/n_1, the kernel's passes by 1/16, 1/8, 1/8: undo on |X|^2
+        const double unscale = (double)ap.n[0] * (double)ap.n[1] * 1024.0;
         const float2* tw = ap.d_tw32 + ap.front_tw_base;  // tables of the rest axes: 16, 16, 8, 8 entries
         HIP_TRY(omni::launch_fused8844_mixed(cur, tc, tc, tw, tw + 32, ap.d_partial, (int)ap.fs.F, 1, p->time_block,
                                              c0 > 0 ? 1 : 0, unscale * unscale, st));

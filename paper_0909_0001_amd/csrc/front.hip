@@ -98,6 +98,18 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
     const int64_t o = rem / inner_v, in = (rem - o * inner_v) * V;
     const int64_t sbase = tile * src_tile + o * N * inner + in;
     const int64_t dbase = tile * dst_tile + o * M * inner + in;
+    // V inputs of row p; FMT 3 reads float16 planar blocks of (tile, o): N * inner real parts, then as many
+    // imaginary parts (the H16 output of a previous front pass)
+    auto ld = [&](int p, float2(&xv)[V]) {
+      if constexpr (FMT == 3) {
+        const _Float16* h = static_cast<const _Float16*>(src);
+        const int64_t re = 2 * (sbase - in) + in + (int64_t)p * inner, plane = (int64_t)N * inner;
+#pragma unroll
+        for (int v = 0; v < V; ++v) xv[v] = make_float2((float)h[re + v], (float)h[re + plane + v]);
+      } else {
+        load_v<FMT, V>(src, sbase + (int64_t)p * inner, xv);
+      }
+    };
     auto store = [&](const float2(&zz)[V][L], int res) {
       if constexpr (H16) {
         _Float16* const d16 = static_cast<_Float16*>(dst_);
@@ -144,7 +156,7 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
 #pragma unroll
       for (int j = 0; j < L; ++j) {
         float2 xv[V];
-        load_v<FMT, V>(src, sbase + (int64_t)j * inner, xv);
+        ld(j, xv);
 #pragma unroll
         for (int v = 0; v < V; ++v) x[v][j] = z[v][j] = xv[v];
       }
@@ -174,7 +186,7 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
           continue;
         }
         float2 x[V];
-        load_v<FMT, V>(src, sbase + (int64_t)p * inner, x);
+        ld(p, x);
         const float2 w = twm[(rho * p) & (M - 1)];  // w_m^{rho p}, uniform across the block
 #pragma unroll
         for (int v = 0; v < V; ++v) z[v][j] = blk == 0 ? cmul(x[v], w) : cadd(z[v][j], cmul(x[v], w));
@@ -186,6 +198,7 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
   }
 }
 
+// fmt: 0 float32 complex, 1 ci8, 2 ci4, 3 float16 planar blocks (the H16 output of a front pass).
 // half16: float16 planar output scaled by `scale` (see H16 above); else float32 complex.
 hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* twm, int64_t tiles, int64_t outer,
                              int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st,
@@ -196,7 +209,7 @@ hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* 
   const int V = (fmt != 0 && L <= 16 && inner % 2 == 0 && src_tile % 2 == 0 &&
                  (reinterpret_cast<uintptr_t>(src) & 3) == 0)
                     ? 2
-                    : 1;
+                    : 1;  // fmt 3 (float16 planar) reads its halves one by one, two inner indices per thread
   const int64_t total = tiles * outer * (inner / V);
   int64_t g = (total + 255) / 256;
   if (g > 65536) g = 65536;
@@ -226,6 +239,10 @@ hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* 
     OMNI_FRONT_LR(1, 2)
   } else if (fmt == 1) {
     OMNI_FRONT_LR(1, 1)
+  } else if (fmt == 3 && V == 2) {
+    OMNI_FRONT_LR(3, 2)
+  } else if (fmt == 3) {
+    OMNI_FRONT_LR(3, 1)
   } else if (fmt == 2 && V == 2) {
     OMNI_FRONT_LR(2, 2)
   } else if (fmt == 2) {
