@@ -117,6 +117,11 @@ struct ArrayPlan {
 constexpr int kTimingRing = 256;
 
 constexpr int kStages = 4;  // forward, reduce, inverse, whole call
+// Front mode: each of the two workspaces holds at most kFrontBytes (8 GiB: the partial sums are
+// read-modified-written once per chunk, so fewer, larger chunks save that traffic), and a chunk at most
+// kChunkMax samples.
+constexpr int64_t kFrontBytes = int64_t(8) << 30;
+constexpr int64_t kChunkMax = 256;
 
 struct omni_plan_s {
   std::vector<ArrayPlan> arrays;
@@ -378,7 +383,7 @@ void plan_mixed_behind_front(ArrayPlan& ap, int kernel) {
     fs.kmap[(size_t)c] = kernel == 4 ? omni::fused16x3_cell(c) : omni::fused8844_cell(c);
   // bytes per time sample of the last (float16) front output; earlier front outputs are float32
   const int64_t per_t = (int64_t)ap.F * ms * rest_n * 4;
-  ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t(2) << 30) / per_t));
+  ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kFrontBytes / per_t));
   ap.front_elems = (ap.chunk_T * per_t + 7) / 8;  // float2 units
   int64_t mm = 1, nn = ap.N;
   for (int k = 0; k + 1 < s; ++k) {
@@ -459,9 +464,9 @@ int plan_front(ArrayPlan& ap, std::string* why) {
       ap.front_tw_base = tw_base;
       ap.front_r.assign(s, 1);
       for (int k = 0; k < s; ++k) ap.front_r[k] = std::max(1, 2 * ap.n[k] / 16);
-      // time chunk: the largest front output (after the last front pass) <= 2 GiB
+      // time chunk: the largest front output (after the last front pass) <= kFrontBytes
       const int64_t per_t = (int64_t)ap.F * MS * (ap.N / NS) * (int64_t)sizeof(float2);
-      ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t(2) << 30) / per_t));
+      ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kFrontBytes / per_t));
       ap.front_elems = 0;
       int64_t mm = 1, nn = ap.N;
       for (int k = 0; k < s; ++k) {
@@ -1033,7 +1038,9 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   if (!p) return fail(OMNI_E_NOMEM, "host allocation failed");
   p->dtype = o.dtype;
   p->form = o.form;
-  p->time_block = o.time_block > 0 ? o.time_block : 64;
+  // default float32 block: 64 samples; 256 in the mixed form, whose matrix-core kernels add each block into
+  // float64 partial sums in HBM (a float32 sum of 256 non-negative terms stays within 2^-16 relative)
+  p->time_block = o.time_block > 0 ? o.time_block : (o.form == OMNI_FORM_MIXED ? 256 : 64);
   p->host_only = (o.flags & OMNI_PLAN_HOST_ONLY) != 0;
   p->timing = (o.flags & OMNI_PLAN_TIMING) != 0 && !p->host_only;
   p->arrays.resize(arrays.size());
