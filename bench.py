@@ -298,7 +298,7 @@ def main() -> int:
     if args.gpus != 1 or world != 1:
         print(
             "bench.py: the correlator runs on one GPU; a multi-GPU run (channels or time blocks sharded one per "
-            f"GPU) is not part of this build (asked for --gpus {args.gpus}, WORLD_SIZE {world})",
+            f"GPU) is not implemented (asked for --gpus {args.gpus}, WORLD_SIZE {world})",
             file=sys.stderr,
         )
         return 2
