@@ -26,7 +26,7 @@ hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* d
 hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, double2* tw64, hipStream_t st);
 hipError_t launch_fused8x4_fp32(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16, double* partial,
                                 int F, int n_slices, int time_block, hipStream_t st);
-hipError_t launch_fused8x4_mixed(int fmt, int ns_per_iter, const void* src, int64_t T, int64_t tps,
+hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps,
                                  const float2* tw16, double* partial, int F, int n_slices, hipStream_t st);
 hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* twm, int64_t tiles, int64_t outer,
                              int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st,
@@ -636,13 +636,6 @@ int check_device(int* dev) {
 
 int fmt_of(omni_dtype t) { return (int)t; }
 
-// Samples per iteration of the 8x8x8x8 mixed kernel: one (two 80 KiB work-groups per CU) by default;
-// OMNI_MIXED_SAMPLES=2 selects two samples per iteration in one 160 KiB work-group per CU.
-int mixed_samples_per_iter() {
-  const char* e = std::getenv("OMNI_MIXED_SAMPLES");
-  return (e && e[0] == '2') ? 2 : 1;
-}
-
 size_t sample_bytes(omni_dtype t) { return t == OMNI_CF32 ? 8 : t == OMNI_CI8 ? 2 : 1; }
 
 hipEvent_t stage_event(omni_plan_s* p, int stage, int end) {
@@ -770,18 +763,16 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
                                        p->time_block, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 2) {
-    // one sample per iteration: two 80 KiB work-groups per CU, one round of 512 work-groups
-    // (two samples per iteration: one 160 KiB work-group per CU, 256 work-groups)
-    const int per_iter = mixed_samples_per_iter();
+    // two 80 KiB work-groups per CU: one round of 512 work-groups
     const int64_t per_slice_groups = (int64_t)ap.F * 2;
-    const int64_t target = per_iter == 2 ? 256 : 512;
+    const int64_t target = 512;
     int64_t ns = std::max<int64_t>(1, (target + per_slice_groups / 2) / per_slice_groups);
     ns = std::min<int64_t>(ns, ap.max_slices);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
     const int64_t tps = (T + ns - 1) / ns;
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
-    HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), per_iter, volt, T, tps, ap.d_tw32, ap.d_partial, ap.F,
+    HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F,
                                         (int)ns, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 3) {
     int rc = launch_ct(ap, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);

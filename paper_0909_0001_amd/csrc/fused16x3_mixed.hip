@@ -22,8 +22,8 @@
 // In A and B the rows of a tile are lines ordered with the next pass'
 // contracted axis fastest, so a lane stores 4 consecutive values of it with
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte
-// read.  The next sample's tile is copied into LDS (direct-to-LDS loads)
-// during B and C.
+// read.  Each lane loads its pass-A operands of the next sample straight from
+// HBM into registers during B and C.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -86,7 +86,6 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   using namespace m163;
   __shared__ __attribute__((aligned(16))) _Float16 LB[LSZ];
   __shared__ __attribute__((aligned(16))) _Float16 LC[LSZ];
-  __shared__ __attribute__((aligned(16))) _Float16 RAW[2 * 4096];  // the sample's tile, staged
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
   const int ch = blockIdx.x % F;
   const int s = blockIdx.x / F;
@@ -113,17 +112,13 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
     }
   }
 
-  // asynchronous copy of the tile of sample t into RAW (direct-to-LDS loads; wave w moves 1 KiB pieces w, w + 8)
-  auto stage = [&](int64_t t) {
-    const unsigned char* g = reinterpret_cast<const unsigned char*>(src + (t * F + ch) * 8192);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int piece = w + 8 * k;
-      __builtin_amdgcn_global_load_lds(g + piece * 1024 + l * 16,
-                                       (__attribute__((address_space(3))) void*)(reinterpret_cast<unsigned char*>(RAW) +
-                                                                                 piece * 1024),
-                                       16, 0, 0);
-    }
+  // pass A operand of this lane: line (a = 2w + n32 / 16, b = n32 % 16), component h, the 16 values of c;
+  // read straight from HBM into registers, one sample ahead
+  const int a_line = (2 * w + (n32 >> 4)) * 16 + (n32 & 15);
+  auto load_xa = [&](int64_t t, half8* xa) {
+    const half8* g = reinterpret_cast<const half8*>(src + (t * F + ch) * 8192 + h * 4096 + a_line * 16);
+    xa[0] = g[0];
+    xa[1] = g[1];
   };
 
   float acc[SLOTS];
@@ -132,28 +127,34 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   double* out = partial + ((int64_t)s * F + ch) * CELLS;
   bool flushed = false;
   auto flush = [&]() {
+    // addresses formed here (the empty asm keeps them out of the time loop); loads in groups of 8
+    double* o = out + tid;
+    asm volatile("" : "+v"(o));
+    if (accumulate || flushed) {
 #pragma unroll
-    for (int i = 0; i < SLOTS; ++i) {
-      const int cell = i * NT + tid;
-      const double v = (double)acc[i] * out_scale;
-      out[cell] = (accumulate || flushed) ? out[cell] + v : v;
-      acc[i] = 0.f;
+      for (int i0 = 0; i0 < SLOTS; i0 += 8) {
+        double prev[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) prev[k] = o[(i0 + k) * NT];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[(i0 + k) * NT] = prev[k] + (double)acc[i0 + k] * out_scale;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SLOTS; ++i) o[i * NT] = (double)acc[i] * out_scale;
     }
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) acc[i] = 0.f;
     flushed = true;
   };
 
-  if (t0 < t1) stage(t0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+  half8 xa[2];
+  if (t0 < t1) load_xa(t0, xa);
   int blk = 0;
   for (int64_t t = t0; t < t1; ++t) {
     // ---- A: axis c; row tile w holds lines (a = 2w + n32 / 16, b = n32 % 16), this lane's half h reads
     // component h of c = 8 ks .. 8 ks + 7
     {
-      half8 xa[2];
-      const int line = (2 * w + (n32 >> 4)) * 16 + (n32 & 15);
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) xa[ks] = *reinterpret_cast<const half8*>(&RAW[h * 4096 + line * 16 + 8 * ks]);
       const int co = n32 >> 4;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -171,8 +172,9 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
         }
       }
     }
+    // the next sample's operands behind passes B and C (the last iteration re-reads its own)
+    load_xa(min(t + 1, t1 - 1), xa);
     __syncthreads();
-    if (t + 1 < t1) stage(t + 1);  // RAW has been read: fetch the next tile behind passes B and C
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       // ---- B: axis b, row tiles 2w, 2w + 1 of lines (a = m % 16, kappa_c = 2 mt + m / 16), columns = this
@@ -221,8 +223,8 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
       }
       if (half == 0) __syncthreads();  // pass B of the second half overwrites LC
     }
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next tile has landed
-    __syncthreads();
+    // no barrier here: pass A of the next sample writes LB, which every wave finished reading before the
+    // barrier ahead of the last pass C, and pass B writes LC only after the barrier behind that pass A
     if (++blk == time_block) {
       blk = 0;
       flush();

@@ -18,8 +18,8 @@
 // threads, all 16384 cells of the channel, 32 float32 accumulators per lane.
 // LDS rows are padded and XOR-swizzled so that the 8-byte stores (32 lanes:
 // 2 components x 16 rows) and the 16-byte operand loads (16 lanes) touch
-// distinct banks.  The next sample's tile is copied into LDS (direct-to-LDS
-// loads) behind P2 and P3.
+// distinct banks.  Each lane loads its P1 operands of the next sample straight
+// from HBM into registers behind P2 and P3.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -86,7 +86,6 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
                                                               double* __restrict__ partial, int F, int time_block,
                                                               int accumulate, double out_scale) {
   using namespace m8844;
-  __shared__ __attribute__((aligned(16))) _Float16 RAW[2 * 1024];
   __shared__ __attribute__((aligned(16))) _Float16 LB[2 * LB_CMP];
   __shared__ __attribute__((aligned(16))) _Float16 LC[2 * LC_CMP];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
@@ -124,15 +123,13 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
     W2l[i] = (_Float16)(v - (float)hi);
   }
 
-  // asynchronous copy of the tile of sample t into RAW: 4 KiB, one 1 KiB piece for each of waves 0-3
-  auto stage = [&](int64_t t) {
-    if (w < 4) {
-      const unsigned char* g = reinterpret_cast<const unsigned char*>(src + (t * F + ch) * 2048);
-      __builtin_amdgcn_global_load_lds(g + w * 1024 + l * 16,
-                                       (__attribute__((address_space(3))) void*)(reinterpret_cast<unsigned char*>(RAW) +
-                                                                                 w * 1024),
-                                       16, 0, 0);
-    }
+  // P1 operand of this lane: row tile mt1, line mt1 * 32 + n32 = a * 8 + b, component h, 16 halves
+  // (j = 4 c + d); read straight from HBM into registers, one sample ahead
+  const int p1_line = mt1 * 32 + n32;
+  auto load_x1 = [&](int64_t t, half8* x1) {
+    const half8* g = reinterpret_cast<const half8*>(src + (t * F + ch) * 2048 + h * 1024 + p1_line * 16);
+    x1[0] = g[0];
+    x1[1] = g[1];
   };
 
   float acc[SLOTS];
@@ -141,32 +138,38 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
   double* out = partial + ((int64_t)s * F + ch) * CELLS;
   bool flushed = false;
   auto flush = [&]() {
+    // addresses formed here (the empty asm keeps them out of the time loop); loads in groups of 8
+    double* o = out + tid;
+    asm volatile("" : "+v"(o));
+    if (accumulate || flushed) {
 #pragma unroll
-    for (int i = 0; i < SLOTS; ++i) {
-      const int cell = i * NT + tid;
-      const double v = (double)acc[i] * out_scale;
-      out[cell] = (accumulate || flushed) ? out[cell] + v : v;
-      acc[i] = 0.f;
+      for (int i0 = 0; i0 < SLOTS; i0 += 8) {
+        double prev[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) prev[k] = o[(i0 + k) * NT];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[(i0 + k) * NT] = prev[k] + (double)acc[i0 + k] * out_scale;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SLOTS; ++i) o[i * NT] = (double)acc[i] * out_scale;
     }
+#pragma unroll
+    for (int i = 0; i < SLOTS; ++i) acc[i] = 0.f;
     flushed = true;
   };
 
-  if (t0 < t1) stage(t0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+  half8 x1[2];
+  if (t0 < t1) load_x1(t0, x1);
   int blk = 0;
   for (int64_t t = t0; t < t1; ++t) {
     // ---- P1: row tile mt1 (lines mt1 * 32 + n32 = a * 8 + b), column tile ct
     {
-      const int line = mt1 * 32 + n32;
-      half8 x[2];
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) x[ks] = *reinterpret_cast<const half8*>(&RAW[h * 1024 + line * 16 + 8 * ks]);
       floatx16 d = {};
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        d = mfma(x[ks], W1h[ks], d);
-        d = mfma(x[ks], W1l[ks], d);
+        d = mfma(x1[ks], W1h[ks], d);
+        d = mfma(x1[ks], W1l[ks], d);
       }
       // rows 8g + 4h + e: line mt1 * 32 + 8g + 4h + e -> a = 4 mt1 + g, b = 4h + e
       const int kcd = 16 * ct + (n32 & 15);
@@ -174,8 +177,9 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
       for (int g = 0; g < 4; ++g)
         *reinterpret_cast<half4*>(&LB[lb_at(co, 4 * mt1 + g, kcd, 4 * h)]) = to_half4(d, g);
     }
+    // the next sample's operands (the last iteration re-reads its own: no conditional copy)
+    load_x1(min(t + 1, t1 - 1), x1);
     __syncthreads();
-    if (t + 1 < t1) stage(t + 1);  // RAW has been read
     // ---- P2: row tiles 2w, 2w + 1 (lines mt * 32 + n32: a = n32 % 8, kappa_cd = 4 mt + n32 / 8)
 #pragma unroll
     for (int jm = 0; jm < 2; ++jm) {
@@ -206,8 +210,8 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
         a_ = fmaf(d[r], d[r], fmaf(d[r + 8], d[r + 8], a_));
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the next tile has landed
-    __syncthreads();
+    // no barrier here: P1 of the next sample writes LB, which every wave finished reading before the
+    // barrier ahead of P3, and P2 writes LC only after the barrier behind that P1
     if (++blk == time_block) {
       blk = 0;
       flush();

@@ -25,7 +25,7 @@
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte read.
 // The next sample's input is prefetched during the current one, and P3/P4 are
 // software-pipelined over a double-buffered chunk buffer (six barriers per
-// iteration of one or two samples).
+// sample).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -61,38 +61,48 @@ __device__ __forceinline__ void store4(_Float16* p, float a, float b, float c, f
   *reinterpret_cast<half4*>(p) = v;
 }
 
-// Raw input of one P1 operand: 8 samples along i3 (16 bytes of ci8, 8 of ci4).
+// Raw input of one P1 operand: 8 samples along i3 (16 bytes of ci8, 8 of ci4),
+// converted to float16 without int -> float conversions: a small integer u
+// (0 <= u < 1024) becomes the float16 1024 + u by placing u in the low
+// mantissa bits under the exponent byte 0x64; subtracting 1024 + bias (bias =
+// 128 for int8, 8 for int4, the offset that made u non-negative) is exact.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t biased_pair(uint32_t bytes, uint32_t sel) {
+  return __builtin_amdgcn_perm(0x64646464u, bytes, sel);  // selector byte 4 = 0x64, 0-3 = bytes
+}
+__device__ __forceinline__ half8 unbias(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3, float bias) {
+  const _Float16 b = (_Float16)(1024.f + bias);
+  const half2v bb = {b, b};
+  const half2v h0 = __builtin_bit_cast(half2v, p0) - bb, h1 = __builtin_bit_cast(half2v, p1) - bb;
+  const half2v h2 = __builtin_bit_cast(half2v, p2) - bb, h3 = __builtin_bit_cast(half2v, p3) - bb;
+  const half4 lo = __builtin_shufflevector(h0, h1, 0, 1, 2, 3), hi = __builtin_shufflevector(h2, h3, 0, 1, 2, 3);
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
 template <int FMT>
 struct Raw;
 template <>
-struct Raw<1> {
+struct Raw<1> {  // word k = [re 2k, im 2k, re 2k+1, im 2k+1] (int8)
   uint4 v;
   __device__ __forceinline__ void load(const void* __restrict__ base, int64_t sample) {
     v = *reinterpret_cast<const uint4*>(reinterpret_cast<const int8_t*>(base) + 2 * sample);
   }
   __device__ __forceinline__ half8 to_half(int comp) const {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    half8 r;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = (_Float16)(float)(int8_t)(w[i >> 1] >> (16 * (i & 1) + 8 * comp));
-    return r;
+    const uint32_t sel = comp ? 0x04030401u : 0x04020400u;
+    return unbias(biased_pair(v.x ^ 0x80808080u, sel), biased_pair(v.y ^ 0x80808080u, sel),
+                  biased_pair(v.z ^ 0x80808080u, sel), biased_pair(v.w ^ 0x80808080u, sel), 128.f);
   }
 };
 template <>
-struct Raw<2> {
+struct Raw<2> {  // byte i of word k = sample 4k + i, real part in the high nibble (int4)
   uint2 v;
   __device__ __forceinline__ void load(const void* __restrict__ base, int64_t sample) {
     v = *reinterpret_cast<const uint2*>(reinterpret_cast<const int8_t*>(base) + sample);
   }
   __device__ __forceinline__ half8 to_half(int comp) const {
-    const uint32_t w[2] = {v.x, v.y};
-    half8 r;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int8_t byte = (int8_t)(w[i >> 2] >> (8 * (i & 3)));
-      r[i] = (_Float16)(float)(comp == 0 ? (byte >> 4) : ((int8_t)(byte << 4) >> 4));
-    }
-    return r;
+    const uint32_t x = v.x ^ 0x88888888u, y = v.y ^ 0x88888888u;
+    const uint32_t ux = (comp ? x : x >> 4) & 0x0F0F0F0Fu, uy = (comp ? y : y >> 4) & 0x0F0F0F0Fu;
+    return unbias(biased_pair(ux, 0x04010400u), biased_pair(ux, 0x04030402u), biased_pair(uy, 0x04010400u),
+                  biased_pair(uy, 0x04030402u), 8.f);
   }
 };
 
@@ -116,17 +126,18 @@ __device__ __forceinline__ int l4_row(int comp, int k1, int q, int k2c) {
 
 }  // namespace f8m
 
-// NS time samples are processed per iteration, each with its own LDS buffers
-// (NS = 2: 160 KiB, one work-group per CU, up to 256 VGPRs; NS = 1: 80 KiB,
-// two work-groups per CU, 128 VGPRs).  Both samples add into the same cells.
-template <int FMT, int NS>
-__global__ __launch_bounds__(f8m::NT, NS == 2 ? 2 : 4) void fused8x4_mixed_kernel(
-    const void* __restrict__ src, int64_t T, int64_t t_per_slice, const float2* __restrict__ tw16,
-    double* __restrict__ partial, int F, int xcd_groups) {
+// One time sample per iteration in 80 KiB of LDS: two work-groups per CU, up
+// to 128 VGPRs per lane.
+template <int FMT>
+__global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* __restrict__ src, int64_t T,
+                                                                   int64_t t_per_slice,
+                                                                   const float2* __restrict__ tw16,
+                                                                   double* __restrict__ partial, int F,
+                                                                   int xcd_groups) {
   using namespace f8m;
-  __shared__ _Float16 L2[NS][2 * 8 * 8 * 8 * 8];
-  __shared__ _Float16 L3[NS][2 * 8 * 16 * 8 * 8];
-  __shared__ _Float16 L4[NS][2][2 * 16 * 32 * 8];
+  __shared__ _Float16 L2[2 * 8 * 8 * 8 * 8];
+  __shared__ _Float16 L3[2 * 8 * 16 * 8 * 8];
+  __shared__ _Float16 L4[2][2 * 16 * 32 * 8];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -166,73 +177,66 @@ __global__ __launch_bounds__(f8m::NT, NS == 2 ? 2 : 4) void fused8x4_mixed_kerne
   const int p1_off = ((wave * 8 + (col >> 3)) * 8 + (col & 7)) * 8;  // + 4*8*8 samples for tt = 1
   const int64_t t0 = (int64_t)s * t_per_slice;
   const int64_t t1 = min(T, t0 + t_per_slice);
-  Raw<FMT> raw[NS][2];
-#pragma unroll
-  for (int ss = 0; ss < NS; ++ss)
-    if (t0 + ss < t1) {
-      const int64_t tile = ((t0 + ss) * F + f) * 4096;
-      raw[ss][0].load(src, tile + p1_off);
-      raw[ss][1].load(src, tile + p1_off + 256);
-    }
+  Raw<FMT> raw[2];
+  if (t0 < t1) {
+    const int64_t tile = (t0 * F + f) * 4096;
+    raw[0].load(src, tile + p1_off);
+    raw[1].load(src, tile + p1_off + 256);
+  }
   const bool keep = (col & 1) == h;
-  for (int64_t t = t0; t < t1; t += NS) {
-    const int nss = (int)min((int64_t)NS, t1 - t);  // samples in this iteration (uniform)
-    // ---- P1: axis 3 from the prefetched samples; prefetch the next ones
+  for (int64_t t = t0; t < t1; ++t) {
+    // ---- P1: axis 3 from the prefetched sample
+    const half8 a0 = raw[0].to_half(hh), a1 = raw[1].to_half(hh);
+    {
+      // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
+      const int comp = col >> 4, q = (col & 15) >> 1;
 #pragma unroll
-    for (int ss = 0; ss < NS; ++ss) {
-      if (ss < nss) {
-        const half8 a0 = raw[ss][0].to_half(hh), a1 = raw[ss][1].to_half(hh);
-        if (t + NS + ss < t1) {
-          const int64_t tile = ((t + NS + ss) * F + f) * 4096;
-          raw[ss][0].load(src, tile + p1_off);
-          raw[ss][1].load(src, tile + p1_off + 256);
-        }
-        // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
-        const int comp = col >> 4, q = (col & 15) >> 1;
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-          floatx16 d = mfma(tt ? a1 : a0, Wf_hi, zero);
-          d = mfma(tt ? a1 : a0, Wf_lo, d);
-          if (keep) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              store4(&L2[ss][l2_row(comp, wave, q, 4 * tt + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-                     d[4 * i + 3]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // ---- P2: axis 2; tile T2 = 2 wave + tt: lines (i0, q, i1) = (wave, 4 tt + r/8, r%8)
-#pragma unroll
-    for (int ss = 0; ss < NS; ++ss) {
-      if (ss < nss) {
-        const int i1 = col & 7, qa = col >> 3;
-        const int comp = col >> 4, k2 = col & 15;
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-          const half8 a = *reinterpret_cast<const half8*>(&L2[ss][l2_row(hh, wave, 4 * tt + qa, i1) * 8]);
-          floatx16 d = mfma(a, Wf_hi, zero);
-          d = mfma(a, Wf_lo, d);
-          // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
+      for (int tt = 0; tt < 2; ++tt) {
+        floatx16 d = mfma(tt ? a1 : a0, Wf_hi, zero);
+        d = mfma(tt ? a1 : a0, Wf_lo, d);
+        if (keep) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            store4(&L3[ss][l3_row(comp, 4 * tt + i, k2, wave) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+            store4(&L2[l2_row(comp, wave, q, 4 * tt + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
                    d[4 * i + 3]);
         }
       }
     }
     __syncthreads();
-    // ---- P3 (axis 1) for kappa_2 chunk cc into L4[ss][cc & 1]: tile = wave, lines (q, k2c, i0) with
+    // prefetch the next sample (the last iteration re-reads its own) into the raw registers, which P1
+    // has consumed: an unconditional load needs no second copy of them
+    {
+      const int64_t tile = (min(t + 1, t1 - 1) * F + f) * 4096;
+      raw[0].load(src, tile + p1_off);
+      raw[1].load(src, tile + p1_off + 256);
+    }
+    // ---- P2: axis 2; tile T2 = 2 wave + tt: lines (i0, q, i1) = (wave, 4 tt + r/8, r%8)
+    {
+      const int i1 = col & 7, qa = col >> 3;
+      const int comp = col >> 4, k2 = col & 15;
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        const half8 a = *reinterpret_cast<const half8*>(&L2[l2_row(hh, wave, 4 * tt + qa, i1) * 8]);
+        floatx16 d = mfma(a, Wf_hi, zero);
+        d = mfma(a, Wf_lo, d);
+        // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          store4(&L3[l3_row(comp, 4 * tt + i, k2, wave) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+                 d[4 * i + 3]);
+      }
+    }
+    __syncthreads();
+    // ---- P3 (axis 1) for kappa_2 chunk cc into L4[cc & 1]: tile = wave, lines (q, k2c, i0) with
     //      (q, k2c) index = 4 wave + r/8, i0 = r%8
-    auto pass3 = [&](int ss, int cc) {
+    auto pass3 = [&](int cc) {
       const int idx = 4 * wave + (col >> 3);
       const int q = idx >> 2, k2c = idx & 3, i0 = col & 7;
-      const half8 a = *reinterpret_cast<const half8*>(&L3[ss][l3_row(hh, q, 4 * cc + k2c, i0) * 8]);
+      const half8 a = *reinterpret_cast<const half8*>(&L3[l3_row(hh, q, 4 * cc + k2c, i0) * 8]);
       floatx16 d = mfma(a, Wf_hi, zero);
       d = mfma(a, Wf_lo, d);
       const int comp = col >> 4, k1 = col & 15;
-      _Float16* L = L4[ss][cc & 1];
+      _Float16* L = L4[cc & 1];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int id2 = 4 * wave + i;
@@ -240,36 +244,27 @@ __global__ __launch_bounds__(f8m::NT, NS == 2 ? 2 : 4) void fused8x4_mixed_kerne
                d[4 * i + 3]);
       }
     };
-#pragma unroll
-    for (int ss = 0; ss < NS; ++ss)
-      if (ss < nss) pass3(ss, 0);
+    pass3(0);
     __syncthreads();
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
       // ---- P4: axis 0 on lines (k1, q, k2c) = (2 wave + tt, r/4, r%4); square and accumulate
+      const _Float16* L = L4[cc & 1];
 #pragma unroll
-      for (int ss = 0; ss < NS; ++ss) {
-        if (ss < nss) {
-          const _Float16* L = L4[ss][cc & 1];
+      for (int tt = 0; tt < 2; ++tt) {
+        const half8 bop = *reinterpret_cast<const half8*>(&L[l4_row(hh, 2 * wave + tt, col >> 2, col & 3) * 8]);
+        floatx16 d = mfma(Wf_hi, bop, zero);
+        d = mfma(Wf_lo, bop, d);
+        // rows: 4hh + j (re), 8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im)
+        const int base = cc * 16 + tt * 8;
 #pragma unroll
-          for (int tt = 0; tt < 2; ++tt) {
-            const half8 bop = *reinterpret_cast<const half8*>(&L[l4_row(hh, 2 * wave + tt, col >> 2, col & 3) * 8]);
-            floatx16 d = mfma(Wf_hi, bop, zero);
-            d = mfma(Wf_lo, bop, d);
-            // rows: 4hh + j (re), 8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im)
-            const int base = cc * 16 + tt * 8;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
-              acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
-            }
-          }
+        for (int j = 0; j < 4; ++j) {
+          acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
+          acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
         }
       }
       if (cc < 3) {
-#pragma unroll
-        for (int ss = 0; ss < NS; ++ss)
-          if (ss < nss) pass3(ss, cc + 1);
+        pass3(cc + 1);
         __syncthreads();
       }
     }
@@ -280,24 +275,17 @@ __global__ __launch_bounds__(f8m::NT, NS == 2 ? 2 : 4) void fused8x4_mixed_kerne
   for (int i = 0; i < CPL; ++i) out[i * NT + tid] = (double)acc[i] * 16777216.0;
 }
 
-hipError_t launch_fused8x4_mixed(int fmt, int ns_per_iter, const void* src, int64_t T, int64_t tps,
-                                 const float2* tw16, double* partial, int F, int n_slices, hipStream_t st) {
+hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16,
+                                 double* partial, int F, int n_slices, hipStream_t st) {
   const int groups = n_slices * F;
   const int xcd = (groups % 8 == 0) ? 1 : 0;
   const dim3 grid(groups * 2), block(f8m::NT);
-#define OMNI_MIXED(F_, NS_) \
-  hipLaunchKernelGGL((fused8x4_mixed_kernel<F_, NS_>), grid, block, 0, st, src, T, tps, tw16, partial, F, xcd)
-  if (fmt == 1 && ns_per_iter == 2)
-    OMNI_MIXED(1, 2);
-  else if (fmt == 1)
-    OMNI_MIXED(1, 1);
-  else if (fmt == 2 && ns_per_iter == 2)
-    OMNI_MIXED(2, 2);
+  if (fmt == 1)
+    hipLaunchKernelGGL(fused8x4_mixed_kernel<1>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd);
   else if (fmt == 2)
-    OMNI_MIXED(2, 1);
+    hipLaunchKernelGGL(fused8x4_mixed_kernel<2>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd);
   else
     return hipErrorInvalidValue;
-#undef OMNI_MIXED
   return hipGetLastError();
 }
 
