@@ -417,24 +417,25 @@ void plan_fused8x4(ArrayPlan& ap) {
 }
 
 // The 8x8x8x8 mixed-precision kernel: work-group = (slice, channel, residue h of
-// kappa_3 mod 2), 512 threads; cell idx (of 64) of thread tid is written at
-// idx * 512 + tid.  With wave = tid / 64, lane = tid % 64, col = lane % 32,
-// hh = lane / 32 and idx = ((cc * 2 + tt) * 2 + i') * 4 + j it holds
-// kappa_0 = 8 i' + 4 hh + j, kappa_1 = 2 wave + tt, kappa_2 = 4 cc + col % 4,
-// kappa_3 = 2 (col / 4) + h.
+// kappa_3 mod 2), 1024 threads; cell idx (of 32) of thread tid is written at
+// idx * 1024 + tid.  With wave = tid / 64, lane = tid % 64, col = lane % 32,
+// hh = lane / 32, idx = ((cc * 2 + tt) * 2 + i') * 4 + j and idx2 = 32 tt + col
+// it holds kappa_0 = 8 i' + 4 hh + j, kappa_1 = wave, kappa_2 = 8 cc + idx2 % 8,
+// kappa_3 = 2 (idx2 / 8) + h.
 void plan_fused8x4_mixed(ArrayPlan& ap) {
   ap.kernel = 2;
   FusedP& P = ap.fs.fp;
   P.n_split = 2;
   P.cells_wg = 32768;
-  ap.fs.cpt = 64;
+  ap.fs.cpt = 32;
   for (int h = 0; h < 2; ++h) {
-    for (int idx = 0; idx < 64; ++idx) {
-      for (int tid = 0; tid < 512; ++tid) {
+    for (int idx = 0; idx < 32; ++idx) {
+      for (int tid = 0; tid < 1024; ++tid) {
         const int wave = tid >> 6, lane = tid & 63, col = lane & 31, hh = lane >> 5;
         const int cc = idx >> 4, tt = (idx >> 3) & 1, ip = (idx >> 2) & 1, j = idx & 3;
-        const int k0 = 8 * ip + 4 * hh + j, k1 = 2 * wave + tt, k2 = 4 * cc + (col & 3), k3 = 2 * (col >> 2) + h;
-        ap.fs.kmap[(size_t)(h * 32768 + idx * 512 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
+        const int idx2 = 32 * tt + col;
+        const int k0 = 8 * ip + 4 * hh + j, k1 = wave, k2 = 8 * cc + (idx2 & 7), k3 = 2 * (idx2 >> 3) + h;
+        ap.fs.kmap[(size_t)(h * 32768 + idx * 1024 + tid)] = ((k0 * 16 + k1) * 16 + k2) * 16 + k3;
       }
     }
   }
@@ -763,9 +764,9 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
                                        p->time_block, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 2) {
-    // two 80 KiB work-groups per CU: one round of 512 work-groups
+    // one 112 KiB work-group of 1024 threads per CU: one round of 256 work-groups
     const int64_t per_slice_groups = (int64_t)ap.F * 2;
-    const int64_t target = 512;
+    const int64_t target = 256;
     int64_t ns = std::max<int64_t>(1, (target + per_slice_groups / 2) / per_slice_groups);
     ns = std::min<int64_t>(ns, ap.max_slices);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));

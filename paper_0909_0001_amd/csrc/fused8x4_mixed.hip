@@ -11,21 +11,21 @@
 // 1/8 (folded into W, exact), which bounds every float16 intermediate by the
 // input's maximum magnitude; the 2^24 on |X|^2 is undone at the end.
 //
-// Work-group = (time slice, channel f, residue h of kappa_3 mod 2), 512 threads
-// (8 waves).  It owns the 32768 cells with kappa_3 = h (mod 2); each lane keeps
-// 64 of them in float32 registers for the whole slice.  Per time sample:
+// Work-group = (time slice, channel f, residue h of kappa_3 mod 2), 1024
+// threads (16 waves).  It owns the 32768 cells with kappa_3 = h (mod 2); each
+// lane keeps 32 of them in float32 registers for the whole slice.  Per time
+// sample (one 32-line tile per wave and pass, two in P4):
 //   P1 axis 3 (i3) straight from HBM; of its 16 outputs the 8 with
 //      kappa_3 = 2q + h are kept -> LDS L2
 //   P2 axis 2, 16 outputs -> L3
-//   P3 axis 1 and P4 axis 0 in four chunks of kappa_2: P3 -> L4, then P4 squares
+//   P3 axis 1 and P4 axis 0 in two halves of kappa_2: P3 -> L4, then P4 squares
 //   the modulus (real and imaginary rows of an output land in the same lane)
 //   and accumulates.
 // In every pass the 32 lines of a tile are ordered with the next pass'
 // contracted axis fastest, so each lane stores 4 consecutive values of it with
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte read.
 // The next sample's input is prefetched during the current one, and P3/P4 are
-// software-pipelined over a double-buffered chunk buffer (six barriers per
-// sample).
+// software-pipelined over a double-buffered L4 (four barriers per sample).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -38,8 +38,8 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int NT = 512;
-constexpr int CPL = 64;  // cells per lane
+constexpr int NT = 1024;
+constexpr int CPL = 32;  // cells per lane
 
 __device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -113,31 +113,31 @@ struct Raw<2> {  // byte i of word k = sample 4k + i, real part in the high nibb
 // with a bank model of the six access patterns: at most 2-way conflicts).
 //   L2 [comp][i0][q][i1 ^ (q/2) ^ 4 comp][i2]   (P1 -> P2)
 //   L3 [comp][q][k2][i0 ^ (k2/2 % 8)][i1]       (P2 -> P3)
-//   L4 [buf][comp][k1][(4 q + k2c) ^ k1][i0]    (P3 -> P4)
+//   L4 [buf][comp][k1][(8 q + k2c) ^ k1][i0]    (P3 -> P4)
 __device__ __forceinline__ int l2_row(int comp, int i0, int q, int i1) {
   return ((comp * 8 + i0) * 8 + q) * 8 + (i1 ^ (q >> 1) ^ (4 * comp));
 }
 __device__ __forceinline__ int l3_row(int comp, int q, int k2, int i0) {
   return ((comp * 8 + q) * 16 + k2) * 8 + (i0 ^ ((k2 >> 1) & 7));
 }
-__device__ __forceinline__ int l4_row(int comp, int k1, int q, int k2c) {
-  return (comp * 16 + k1) * 32 + ((4 * q + k2c) ^ k1);
+__device__ __forceinline__ int l4_row(int comp, int k1, int idx2) {
+  return (comp * 16 + k1) * 64 + (idx2 ^ k1);
 }
 
 }  // namespace f8m
 
-// One time sample per iteration in 80 KiB of LDS: two work-groups per CU, up
-// to 128 VGPRs per lane.
+// One time sample per iteration, 1024 threads (16 waves) in 112 KiB of LDS:
+// one work-group per CU, up to 128 VGPRs per lane.
 template <int FMT>
-__global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* __restrict__ src, int64_t T,
-                                                                   int64_t t_per_slice,
-                                                                   const float2* __restrict__ tw16,
-                                                                   double* __restrict__ partial, int F,
-                                                                   int xcd_groups) {
+__global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __restrict__ src, int64_t T,
+                                                                int64_t t_per_slice,
+                                                                const float2* __restrict__ tw16,
+                                                                double* __restrict__ partial, int F,
+                                                                int xcd_groups) {
   using namespace f8m;
   __shared__ _Float16 L2[2 * 8 * 8 * 8 * 8];
   __shared__ _Float16 L3[2 * 8 * 16 * 8 * 8];
-  __shared__ _Float16 L4[2][2 * 16 * 32 * 8];
+  __shared__ _Float16 L4[2][2 * 16 * 64 * 8];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -173,101 +173,98 @@ __global__ __launch_bounds__(f8m::NT, 4) void fused8x4_mixed_kernel(const void* 
   for (int i = 0; i < CPL; ++i) acc[i] = 0.f;
   const floatx16 zero = {};
 
-  // P1 tiles of this wave: T1 = 2 wave + tt; line r = col -> (i0, i1, i2) = (wave, 4 tt + r/8, r%8)
-  const int p1_off = ((wave * 8 + (col >> 3)) * 8 + (col & 7)) * 8;  // + 4*8*8 samples for tt = 1
+  // wave w = 2 i0 + tt.  P1 tile: lines r = col -> (i0, i1, i2) = (w / 2, 4 tt + r / 8, r % 8)
+  const int i0w = wave >> 1, tw = wave & 1;
+  const int p1_off = ((i0w * 8 + 4 * tw + (col >> 3)) * 8 + (col & 7)) * 8;
   const int64_t t0 = (int64_t)s * t_per_slice;
   const int64_t t1 = min(T, t0 + t_per_slice);
-  Raw<FMT> raw[2];
-  if (t0 < t1) {
-    const int64_t tile = (t0 * F + f) * 4096;
-    raw[0].load(src, tile + p1_off);
-    raw[1].load(src, tile + p1_off + 256);
-  }
+  Raw<FMT> raw;
+  if (t0 < t1) raw.load(src, (t0 * F + f) * 4096 + p1_off);
   const bool keep = (col & 1) == h;
   for (int64_t t = t0; t < t1; ++t) {
     // ---- P1: axis 3 from the prefetched sample
-    const half8 a0 = raw[0].to_half(hh), a1 = raw[1].to_half(hh);
     {
+      const half8 a = raw.to_half(hh);
+      floatx16 d = mfma(a, Wf_hi, zero);
+      d = mfma(a, Wf_lo, d);
       // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
       const int comp = col >> 4, q = (col & 15) >> 1;
+      if (keep) {
 #pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        floatx16 d = mfma(tt ? a1 : a0, Wf_hi, zero);
-        d = mfma(tt ? a1 : a0, Wf_lo, d);
-        if (keep) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            store4(&L2[l2_row(comp, wave, q, 4 * tt + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-                   d[4 * i + 3]);
-        }
+        for (int i = 0; i < 4; ++i)
+          store4(&L2[l2_row(comp, i0w, q, 4 * tw + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+                 d[4 * i + 3]);
       }
     }
     __syncthreads();
     // prefetch the next sample (the last iteration re-reads its own) into the raw registers, which P1
     // has consumed: an unconditional load needs no second copy of them
+    raw.load(src, (min(t + 1, t1 - 1) * F + f) * 4096 + p1_off);
+    // ---- P2: axis 2; lines (i0, q, i1) = (w / 2, 4 tt + r / 8, r % 8)
     {
-      const int64_t tile = (min(t + 1, t1 - 1) * F + f) * 4096;
-      raw[0].load(src, tile + p1_off);
-      raw[1].load(src, tile + p1_off + 256);
-    }
-    // ---- P2: axis 2; tile T2 = 2 wave + tt: lines (i0, q, i1) = (wave, 4 tt + r/8, r%8)
-    {
-      const int i1 = col & 7, qa = col >> 3;
-      const int comp = col >> 4, k2 = col & 15;
-#pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        const half8 a = *reinterpret_cast<const half8*>(&L2[l2_row(hh, wave, 4 * tt + qa, i1) * 8]);
-        floatx16 d = mfma(a, Wf_hi, zero);
-        d = mfma(a, Wf_lo, d);
-        // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          store4(&L3[l3_row(comp, 4 * tt + i, k2, wave) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-                 d[4 * i + 3]);
-      }
-    }
-    __syncthreads();
-    // ---- P3 (axis 1) for kappa_2 chunk cc into L4[cc & 1]: tile = wave, lines (q, k2c, i0) with
-    //      (q, k2c) index = 4 wave + r/8, i0 = r%8
-    auto pass3 = [&](int cc) {
-      const int idx = 4 * wave + (col >> 3);
-      const int q = idx >> 2, k2c = idx & 3, i0 = col & 7;
-      const half8 a = *reinterpret_cast<const half8*>(&L3[l3_row(hh, q, 4 * cc + k2c, i0) * 8]);
+      const half8 a = *reinterpret_cast<const half8*>(&L2[l2_row(hh, i0w, 4 * tw + (col >> 3), col & 7) * 8]);
       floatx16 d = mfma(a, Wf_hi, zero);
       d = mfma(a, Wf_lo, d);
-      const int comp = col >> 4, k1 = col & 15;
-      _Float16* L = L4[cc & 1];
+      // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
+      const int comp = col >> 4, k2 = col & 15;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int id2 = 4 * wave + i;
-        store4(&L[l4_row(comp, k1, id2 >> 2, id2 & 3) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+      for (int i = 0; i < 4; ++i)
+        store4(&L3[l3_row(comp, 4 * tw + i, k2, i0w) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
                d[4 * i + 3]);
+    }
+    __syncthreads();
+    // ---- P3 (axis 1) for kappa_2 half cc into L4[cc]: lines (idx2, i0) = (4 w + r / 8, r % 8) with
+    //      idx2 = 8 q + k2c, kappa_2 = 8 cc + k2c
+    auto pass3_mfma = [&](int cc) {
+      const int idx2 = 4 * wave + (col >> 3);
+      const half8 a =
+          *reinterpret_cast<const half8*>(&L3[l3_row(hh, idx2 >> 3, 8 * cc + (idx2 & 7), col & 7) * 8]);
+      const floatx16 d = mfma(a, Wf_hi, zero);
+      return mfma(a, Wf_lo, d);
+    };
+    auto pass3_store = [&](int cc, const floatx16& d) {
+      const int comp = col >> 4, k1 = col & 15;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        store4(&L4[cc][l4_row(comp, k1, 4 * wave + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+               d[4 * i + 3]);
+    };
+    // ---- P4 (axis 0) on lines (k1, idx2) = (w, 32 tt + r): W x data, rows of d: 4hh + j (re),
+    //      8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im); square and accumulate
+    auto pass4_mfma = [&](int cc, int tt) {
+      const half8 bop = *reinterpret_cast<const half8*>(&L4[cc][l4_row(hh, wave, 32 * tt + col) * 8]);
+      const floatx16 d = mfma(Wf_hi, bop, zero);
+      return mfma(Wf_lo, bop, d);
+    };
+    auto pass4_square = [&](int cc, int tt, const floatx16& d) {
+      const int base = cc * 16 + tt * 8;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
+        acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
       }
     };
-    pass3(0);
+    pass3_store(0, pass3_mfma(0));
     __syncthreads();
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      // ---- P4: axis 0 on lines (k1, q, k2c) = (2 wave + tt, r/4, r%4); square and accumulate
-      const _Float16* L = L4[cc & 1];
-#pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        const half8 bop = *reinterpret_cast<const half8*>(&L[l4_row(hh, 2 * wave + tt, col >> 2, col & 3) * 8]);
-        floatx16 d = mfma(Wf_hi, bop, zero);
-        d = mfma(Wf_lo, bop, d);
-        // rows: 4hh + j (re), 8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im)
-        const int base = cc * 16 + tt * 8;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
-          acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
-        }
-      }
-      if (cc < 3) {
-        pass3(cc + 1);
-        __syncthreads();
-      }
+    {
+      // the matrix products of the next step are issued ahead of the vector work on the previous one
+      const floatx16 d0 = pass4_mfma(0, 0);
+      const floatx16 d1 = pass4_mfma(0, 1);
+      const floatx16 d3 = pass3_mfma(1);
+      pass4_square(0, 0, d0);
+      pass4_square(0, 1, d1);
+      pass3_store(1, d3);
     }
+    __syncthreads();
+    {
+      const floatx16 d0 = pass4_mfma(1, 0);
+      const floatx16 d1 = pass4_mfma(1, 1);
+      pass4_square(1, 0, d0);
+      pass4_square(1, 1, d1);
+    }
+    // no barrier here: P1 of the next sample writes L2 (read by P2 before the barrier ahead of P3), P2
+    // writes L3 only after the barrier behind that P1 (P3 has read L3 by then), and the P3 store of L4[0]
+    // comes after the barrier behind P2 (P4 has read L4[0] before the barrier ahead of P4 on L4[1])
   }
   // |X|^2 carried 8^-8 = 2^-24 from the four scaled stages
   double* out = partial + ((int64_t)grp * 2 + h) * 32768;
