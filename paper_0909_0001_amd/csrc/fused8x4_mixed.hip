@@ -24,8 +24,8 @@
 // In every pass the 32 lines of a tile are ordered with the next pass'
 // contracted axis fastest, so each lane stores 4 consecutive values of it with
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte read.
-// The next sample's input is prefetched during the current one, and P3/P4 are
-// software-pipelined over a double-buffered L4 (four barriers per sample).
+// The next sample's input is prefetched during the current one, and the passes
+// are software-pipelined over samples (two barriers per sample).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -181,90 +181,100 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
   Raw<FMT> raw;
   if (t0 < t1) raw.load(src, (t0 * F + f) * 4096 + p1_off);
   const bool keep = (col & 1) == h;
+
+  // ---- P1: axis 3 from the prefetched sample, then the next sample's prefetch (the last sample
+  //      re-reads its own: an unconditional load into the consumed registers needs no second copy)
+  auto pass1 = [&](int64_t t_next) {
+    const half8 a = raw.to_half(hh);
+    floatx16 d = mfma(a, Wf_hi, zero);
+    d = mfma(a, Wf_lo, d);
+    raw.load(src, (t_next * F + f) * 4096 + p1_off);
+    // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
+    const int comp = col >> 4, q = (col & 15) >> 1;
+    if (keep) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        store4(&L2[l2_row(comp, i0w, q, 4 * tw + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+               d[4 * i + 3]);
+    }
+  };
+  // ---- P2: axis 2; lines (i0, q, i1) = (w / 2, 4 tt + r / 8, r % 8)
+  auto pass2_mfma = [&]() {
+    const half8 a = *reinterpret_cast<const half8*>(&L2[l2_row(hh, i0w, 4 * tw + (col >> 3), col & 7) * 8]);
+    const floatx16 d = mfma(a, Wf_hi, zero);
+    return mfma(a, Wf_lo, d);
+  };
+  auto pass2_store = [&](const floatx16& d) {
+    // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
+    const int comp = col >> 4, k2 = col & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      store4(&L3[l3_row(comp, 4 * tw + i, k2, i0w) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+             d[4 * i + 3]);
+  };
+  // ---- P3 (axis 1) for kappa_2 half cc into L4[cc]: lines (idx2, i0) = (4 w + r / 8, r % 8) with
+  //      idx2 = 8 q + k2c, kappa_2 = 8 cc + k2c
+  auto pass3_mfma = [&](int cc) {
+    const int idx2 = 4 * wave + (col >> 3);
+    const half8 a =
+        *reinterpret_cast<const half8*>(&L3[l3_row(hh, idx2 >> 3, 8 * cc + (idx2 & 7), col & 7) * 8]);
+    const floatx16 d = mfma(a, Wf_hi, zero);
+    return mfma(a, Wf_lo, d);
+  };
+  auto pass3_store = [&](int cc, const floatx16& d) {
+    const int comp = col >> 4, k1 = col & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      store4(&L4[cc][l4_row(comp, k1, 4 * wave + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
+             d[4 * i + 3]);
+  };
+  // ---- P4 (axis 0) on lines (k1, idx2) = (w, 32 tt + r): W x data, rows of d: 4hh + j (re),
+  //      8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im); square and accumulate
+  auto pass4_mfma = [&](int cc, int tt) {
+    const half8 bop = *reinterpret_cast<const half8*>(&L4[cc][l4_row(hh, wave, 32 * tt + col) * 8]);
+    const floatx16 d = mfma(Wf_hi, bop, zero);
+    return mfma(Wf_lo, bop, d);
+  };
+  auto pass4_square = [&](int cc, int tt, const floatx16& d) {
+    const int base = cc * 16 + tt * 8;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
+      acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
+    }
+  };
+
+  // Two phases per sample, software-pipelined over samples: phase A runs P1 of sample t + 1 and P3 of
+  // sample t, phase B runs P2 of t + 1 and P4 of t.  Each buffer is written in one phase and read in the
+  // other (L2: P1 -> P2, L3: P2 -> P3, L4: P3 -> P4), so one barrier after each phase suffices.
+  if (t0 < t1) {
+    pass1(min(t0 + 1, t1 - 1));
+    __syncthreads();
+    pass2_store(pass2_mfma());
+    __syncthreads();
+  }
   for (int64_t t = t0; t < t1; ++t) {
-    // ---- P1: axis 3 from the prefetched sample
+    const bool more = t + 1 < t1;  // uniform
     {
-      const half8 a = raw.to_half(hh);
-      floatx16 d = mfma(a, Wf_hi, zero);
-      d = mfma(a, Wf_lo, d);
-      // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
-      const int comp = col >> 4, q = (col & 15) >> 1;
-      if (keep) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          store4(&L2[l2_row(comp, i0w, q, 4 * tw + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-                 d[4 * i + 3]);
-      }
+      const floatx16 d0 = pass3_mfma(0);
+      const floatx16 d1 = pass3_mfma(1);
+      if (more) pass1(min(t + 2, t1 - 1));
+      pass3_store(0, d0);
+      pass3_store(1, d1);
     }
     __syncthreads();
-    // prefetch the next sample (the last iteration re-reads its own) into the raw registers, which P1
-    // has consumed: an unconditional load needs no second copy of them
-    raw.load(src, (min(t + 1, t1 - 1) * F + f) * 4096 + p1_off);
-    // ---- P2: axis 2; lines (i0, q, i1) = (w / 2, 4 tt + r / 8, r % 8)
     {
-      const half8 a = *reinterpret_cast<const half8*>(&L2[l2_row(hh, i0w, 4 * tw + (col >> 3), col & 7) * 8]);
-      floatx16 d = mfma(a, Wf_hi, zero);
-      d = mfma(a, Wf_lo, d);
-      // column -> (comp, k2); rows -> q = 4 tt + i, i1 = 4 hh + j
-      const int comp = col >> 4, k2 = col & 15;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        store4(&L3[l3_row(comp, 4 * tw + i, k2, i0w) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-               d[4 * i + 3]);
-    }
-    __syncthreads();
-    // ---- P3 (axis 1) for kappa_2 half cc into L4[cc]: lines (idx2, i0) = (4 w + r / 8, r % 8) with
-    //      idx2 = 8 q + k2c, kappa_2 = 8 cc + k2c
-    auto pass3_mfma = [&](int cc) {
-      const int idx2 = 4 * wave + (col >> 3);
-      const half8 a =
-          *reinterpret_cast<const half8*>(&L3[l3_row(hh, idx2 >> 3, 8 * cc + (idx2 & 7), col & 7) * 8]);
-      const floatx16 d = mfma(a, Wf_hi, zero);
-      return mfma(a, Wf_lo, d);
-    };
-    auto pass3_store = [&](int cc, const floatx16& d) {
-      const int comp = col >> 4, k1 = col & 15;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        store4(&L4[cc][l4_row(comp, k1, 4 * wave + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-               d[4 * i + 3]);
-    };
-    // ---- P4 (axis 0) on lines (k1, idx2) = (w, 32 tt + r): W x data, rows of d: 4hh + j (re),
-    //      8 + 4hh + j (re), 16 + 4hh + j (im), 24 + 4hh + j (im); square and accumulate
-    auto pass4_mfma = [&](int cc, int tt) {
-      const half8 bop = *reinterpret_cast<const half8*>(&L4[cc][l4_row(hh, wave, 32 * tt + col) * 8]);
-      const floatx16 d = mfma(Wf_hi, bop, zero);
-      return mfma(Wf_lo, bop, d);
-    };
-    auto pass4_square = [&](int cc, int tt, const floatx16& d) {
-      const int base = cc * 16 + tt * 8;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        acc[base + j] = fmaf(d[j], d[j], fmaf(d[8 + j], d[8 + j], acc[base + j]));
-        acc[base + 4 + j] = fmaf(d[4 + j], d[4 + j], fmaf(d[12 + j], d[12 + j], acc[base + 4 + j]));
-      }
-    };
-    pass3_store(0, pass3_mfma(0));
-    __syncthreads();
-    {
-      // the matrix products of the next step are issued ahead of the vector work on the previous one
       const floatx16 d0 = pass4_mfma(0, 0);
       const floatx16 d1 = pass4_mfma(0, 1);
-      const floatx16 d3 = pass3_mfma(1);
+      if (more) pass2_store(pass2_mfma());
       pass4_square(0, 0, d0);
+      const floatx16 d2 = pass4_mfma(1, 0);
       pass4_square(0, 1, d1);
-      pass3_store(1, d3);
+      const floatx16 d3 = pass4_mfma(1, 1);
+      pass4_square(1, 0, d2);
+      pass4_square(1, 1, d3);
     }
     __syncthreads();
-    {
-      const floatx16 d0 = pass4_mfma(1, 0);
-      const floatx16 d1 = pass4_mfma(1, 1);
-      pass4_square(1, 0, d0);
-      pass4_square(1, 1, d1);
-    }
-    // no barrier here: P1 of the next sample writes L2 (read by P2 before the barrier ahead of P3), P2
-    // writes L3 only after the barrier behind that P1 (P3 has read L3 by then), and the P3 store of L4[0]
-    // comes after the barrier behind P2 (P4 has read L4[0] before the barrier ahead of P4 on L4[1])
   }
   // |X|^2 carried 8^-8 = 2^-24 from the four scaled stages
   double* out = partial + ((int64_t)grp * 2 + h) * 32768;
