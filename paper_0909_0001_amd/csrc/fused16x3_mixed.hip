@@ -15,15 +15,15 @@
 // Work-group = (time slice, channel), 512 threads; it owns all 32768 cells of
 // the channel, 64 float32 accumulators per lane.  Per sample:
 //   A  axis c, lines (a, b): data x W^T, 8 row tiles x 2 column tiles -> LB
-//   then for each half of kappa_b:
-//   B  axis b, lines (a, kappa_c): data x W^T -> LC (that half of kappa_b)
+//   B  axis b, lines (a, kappa_c): data x W^T, both halves of kappa_b -> LC
 //   C  axis a, lines (kappa_b, kappa_c): W x data, so that the real and the
 //      imaginary row of an output land in the same lane -> |X|^2 in registers.
 // In A and B the rows of a tile are lines ordered with the next pass'
 // contracted axis fastest, so a lane stores 4 consecutive values of it with
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte
-// read.  Each lane loads its pass-A operands of the next sample straight from
-// HBM into registers during B and C.
+// read.  Each lane loads its pass-A operands straight from HBM into registers,
+// one sample ahead, and the passes are software-pipelined over samples (two
+// barriers per sample).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -44,19 +44,19 @@ __device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// LB [comp][a][kappa_c][b] and LC [comp][kappa_b mod 16][kappa_c][a], in halves.  Blocks of 32 rows
+// LB [comp][a][kappa_c][b] and LC [comp][kappa_b][kappa_c][a], in halves.  Blocks of 32 rows
 // of 16 halves carry 8 halves of padding (consecutive blocks start 4 banks apart), and inside a row
 // the 4-half units are XOR-swizzled by bit 3 of kappa_c and by the component: the 8-byte stores of
 // passes A and B (32 lanes: 2 components x 16 rows) and the 16-byte loads of passes B and C (16
 // lanes) then touch 64 distinct banks.  A 16-byte load of component 1 returns its two halves swapped.
 constexpr int BLK = 520;         // 32 x 16 + 8
-constexpr int CMP = 16 * BLK;    // component stride
-constexpr int LSZ = 2 * CMP;
+constexpr int CMP = 16 * BLK;    // component stride of LB (16 values of a)
+constexpr int CMPC = 32 * BLK;   // component stride of LC (all 32 values of kappa_b)
 __device__ __forceinline__ int lb_at(int comp, int a, int kc, int b) {
   return comp * CMP + a * BLK + kc * 16 + (b ^ (kc & 8) ^ (4 * comp));
 }
 __device__ __forceinline__ int lc_at(int comp, int kb, int kc, int a) {
-  return comp * CMP + kb * BLK + kc * 16 + (a ^ (kc & 8) ^ (4 * comp));
+  return comp * CMPC + kb * BLK + kc * 16 + (a ^ (kc & 8) ^ (4 * comp));
 }
 // 8 consecutive halves j0 .. j0 + 7 (j0 a multiple of 8) of a swizzled row
 __device__ __forceinline__ half8 load8(const _Float16* row, int j0, int kc, int comp) {
@@ -84,8 +84,8 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
                                                               double* __restrict__ partial, int F, int time_block,
                                                               int accumulate, double out_scale) {
   using namespace m163;
-  __shared__ __attribute__((aligned(16))) _Float16 LB[LSZ];
-  __shared__ __attribute__((aligned(16))) _Float16 LC[LSZ];
+  __shared__ __attribute__((aligned(16))) _Float16 LB[2 * CMP];
+  __shared__ __attribute__((aligned(16))) _Float16 LC[2 * CMPC];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
   const int ch = blockIdx.x % F;
   const int s = blockIdx.x / F;
@@ -149,82 +149,97 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   };
 
   half8 xa[2];
-  if (t0 < t1) load_xa(t0, xa);
-  int blk = 0;
-  for (int64_t t = t0; t < t1; ++t) {
-    // ---- A: axis c; row tile w holds lines (a = 2w + n32 / 16, b = n32 % 16), this lane's half h reads
-    // component h of c = 8 ks .. 8 ks + 7
-    {
-      const int co = n32 >> 4;
+  // ---- A: axis c; row tile w holds lines (a = 2w + n32 / 16, b = n32 % 16), this lane's half h reads
+  // component h of c = 8 ks .. 8 ks + 7
+  auto pass_a = [&]() {
+    const int co = n32 >> 4;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      floatx16 d = {};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        d = mfma(xa[ks], Wh[u][ks], d);
+        d = mfma(xa[ks], Wl[u][ks], d);
+      }
+      // column n32: (co, kappa_c = 16 u + n32 % 16); rows 8g + 4h + e: b = 8 (g & 1) + 4h + e, a = 2w + g / 2
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int a = 2 * w + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
+        *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * u + (n32 & 15), b0)]) = to_half4(d, g);
+      }
+    }
+  };
+  // ---- B: axis b, row tiles 2w, 2w + 1 of lines (a = m % 16, kappa_c = 2 mt + m / 16), columns = one half
+  // of kappa_b
+  auto pass_b = [&](int half) {
+#pragma unroll
+    for (int jm = 0; jm < 2; ++jm) {
+      const int mt = 2 * w + jm;
+      const int a_in = n32 & 15, kc_in = 2 * mt + (n32 >> 4);
+      floatx16 d = {};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const half8 x = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, kc_in, h);
+        d = mfma(x, Wh[half][ks], d);
+        d = mfma(x, Wl[half][ks], d);
+      }
+      const int co = n32 >> 4, kb = 16 * half + (n32 & 15);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int a0 = 8 * (g & 1) + 4 * h, kc = 2 * mt + (g >> 1);
+        *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d, g);
+      }
+    }
+  };
+  // ---- C: axis a, column tiles (lines kappa_b = 16 half + 2w + j, kappa_c = n32), row tiles u
+  auto pass_c = [&](int half) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int kb = 16 * half + 2 * w + j;
+      half8 x[2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMPC + kb * BLK + n32 * 16], 8 * ks, n32, h);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         floatx16 d = {};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          d = mfma(xa[ks], Wh[u][ks], d);
-          d = mfma(xa[ks], Wl[u][ks], d);
+          d = mfma(Wh[u][ks], x[ks], d);
+          d = mfma(Wl[u][ks], x[ks], d);
         }
-        // column n32: (co, kappa_c = 16 u + n32 % 16); rows 8g + 4h + e: b = 8 (g & 1) + 4h + e, a = 2w + g / 2
+        // rows r < 8 hold Re and rows r + 8 Im of the same kappa_a
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int a = 2 * w + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
-          *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * u + (n32 & 15), b0)]) = to_half4(d, g);
+        for (int r = 0; r < 8; ++r) {
+          float& a_ = acc[((half * 2 + j) * 2 + u) * 8 + r];
+          a_ = fmaf(d[r], d[r], fmaf(d[r + 8], d[r + 8], a_));
         }
       }
     }
-    // the next sample's operands behind passes B and C (the last iteration re-reads its own)
-    load_xa(min(t + 1, t1 - 1), xa);
+  };
+
+  // Two phases per sample, software-pipelined over samples: phase 1 runs A of sample t + 1 and C of
+  // sample t, phase 2 runs B of t + 1.  LB is written in phase 1 and read in phase 2, LC the other way
+  // round, so one barrier after each phase suffices.  Operands are loaded one sample ahead of A; in the
+  // last iteration A and B run on a repeated sample and their outputs are never read.
+  if (t0 < t1) {
+    load_xa(t0, xa);
+    pass_a();
+    load_xa(min(t0 + 1, t1 - 1), xa);
     __syncthreads();
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      // ---- B: axis b, row tiles 2w, 2w + 1 of lines (a = m % 16, kappa_c = 2 mt + m / 16), columns = this
-      // half of kappa_b
-#pragma unroll
-      for (int jm = 0; jm < 2; ++jm) {
-        const int mt = 2 * w + jm;
-        const int a_in = n32 & 15, kc_in = 2 * mt + (n32 >> 4);
-        floatx16 d = {};
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          const half8 x = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, kc_in, h);
-          d = mfma(x, Wh[half][ks], d);
-          d = mfma(x, Wl[half][ks], d);
-        }
-        const int co = n32 >> 4, kb = n32 & 15;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int a0 = 8 * (g & 1) + 4 * h, kc = 2 * mt + (g >> 1);
-          *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d, g);
-        }
-      }
-      __syncthreads();
-      // ---- C: axis a, column tiles (lines kappa_b mod 16 = 2w + j, kappa_c = n32), row tiles u
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int kb = 2 * w + j;
-        half8 x[2];
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMP + kb * BLK + n32 * 16], 8 * ks, n32, h);
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          floatx16 d = {};
-#pragma unroll
-          for (int ks = 0; ks < 2; ++ks) {
-            d = mfma(Wh[u][ks], x[ks], d);
-            d = mfma(Wl[u][ks], x[ks], d);
-          }
-          // rows r < 8 hold Re and rows r + 8 Im of the same kappa_a
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            float& a_ = acc[((half * 2 + j) * 2 + u) * 8 + r];
-            a_ = fmaf(d[r], d[r], fmaf(d[r + 8], d[r + 8], a_));
-          }
-        }
-      }
-      if (half == 0) __syncthreads();  // pass B of the second half overwrites LC
-    }
-    // no barrier here: pass A of the next sample writes LB, which every wave finished reading before the
-    // barrier ahead of the last pass C, and pass B writes LC only after the barrier behind that pass A
+    pass_b(0);
+    pass_b(1);
+    __syncthreads();
+  }
+  int blk = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    pass_a();
+    load_xa(min(t + 2, t1 - 1), xa);
+    pass_c(0);
+    pass_c(1);
+    __syncthreads();
+    pass_b(0);
+    pass_b(1);
+    __syncthreads();
     if (++blk == time_block) {
       blk = 0;
       flush();

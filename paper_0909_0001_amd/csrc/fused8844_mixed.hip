@@ -18,8 +18,9 @@
 // threads, all 16384 cells of the channel, 32 float32 accumulators per lane.
 // LDS rows are padded and XOR-swizzled so that the 8-byte stores (32 lanes:
 // 2 components x 16 rows) and the 16-byte operand loads (16 lanes) touch
-// distinct banks.  Each lane loads its P1 operands of the next sample straight
-// from HBM into registers behind P2 and P3.
+// distinct banks.  Each lane loads its P1 operands straight from HBM into
+// registers, one sample ahead, and the passes are software-pipelined over
+// samples (two barriers per sample).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -125,9 +126,14 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
 
   // P1 operand of this lane: row tile mt1, line mt1 * 32 + n32 = a * 8 + b, component h, 16 halves
   // (j = 4 c + d); read straight from HBM into registers, one sample ahead
-  const int p1_line = mt1 * 32 + n32;
+  // (a wave-uniform tile address plus a 32-bit lane offset, added at each load: the empty asm keeps
+  // the compiler from holding a 64-bit address per lane across the loop)
+  const int p1_byte = (h * 1024 + (mt1 * 32 + n32) * 16) * 2;
   auto load_x1 = [&](int64_t t, half8* x1) {
-    const half8* g = reinterpret_cast<const half8*>(src + (t * F + ch) * 2048 + h * 1024 + p1_line * 16);
+    const char* tile = reinterpret_cast<const char*>(src + (t * F + ch) * 2048);
+    int off = p1_byte;
+    asm volatile("" : "+v"(off));
+    const half8* g = reinterpret_cast<const half8*>(tile + off);
     x1[0] = g[0];
     x1[1] = g[1];
   };
@@ -160,27 +166,22 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
   };
 
   half8 x1[2];
-  if (t0 < t1) load_x1(t0, x1);
-  int blk = 0;
-  for (int64_t t = t0; t < t1; ++t) {
-    // ---- P1: row tile mt1 (lines mt1 * 32 + n32 = a * 8 + b), column tile ct
-    {
-      floatx16 d = {};
+  // ---- P1: row tile mt1 (lines mt1 * 32 + n32 = a * 8 + b), column tile ct
+  auto pass1 = [&]() {
+    floatx16 d = {};
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        d = mfma(x1[ks], W1h[ks], d);
-        d = mfma(x1[ks], W1l[ks], d);
-      }
-      // rows 8g + 4h + e: line mt1 * 32 + 8g + 4h + e -> a = 4 mt1 + g, b = 4h + e
-      const int kcd = 16 * ct + (n32 & 15);
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-        *reinterpret_cast<half4*>(&LB[lb_at(co, 4 * mt1 + g, kcd, 4 * h)]) = to_half4(d, g);
+    for (int ks = 0; ks < 2; ++ks) {
+      d = mfma(x1[ks], W1h[ks], d);
+      d = mfma(x1[ks], W1l[ks], d);
     }
-    // the next sample's operands (the last iteration re-reads its own: no conditional copy)
-    load_x1(min(t + 1, t1 - 1), x1);
-    __syncthreads();
-    // ---- P2: row tiles 2w, 2w + 1 (lines mt * 32 + n32: a = n32 % 8, kappa_cd = 4 mt + n32 / 8)
+    // rows 8g + 4h + e: line mt1 * 32 + 8g + 4h + e -> a = 4 mt1 + g, b = 4h + e
+    const int kcd = 16 * ct + (n32 & 15);
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      *reinterpret_cast<half4*>(&LB[lb_at(co, 4 * mt1 + g, kcd, 4 * h)]) = to_half4(d, g);
+  };
+  // ---- P2: row tiles 2w, 2w + 1 (lines mt * 32 + n32: a = n32 % 8, kappa_cd = 4 mt + n32 / 8)
+  auto pass2 = [&]() {
 #pragma unroll
     for (int jm = 0; jm < 2; ++jm) {
       const int mt = 2 * w + jm;
@@ -194,8 +195,9 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
       for (int g = 0; g < 4; ++g)
         *reinterpret_cast<half4*>(&LC[lc_at(co, n32 & 15, 4 * mt + g, 4 * h)]) = to_half4(d, g);
     }
-    __syncthreads();
-    // ---- P3: column tiles nt = 4w + j (lines nt * 32 + n32: kappa_b = nt / 2, kappa_cd = 32 (nt % 2) + n32)
+  };
+  // ---- P3: column tiles nt = 4w + j (lines nt * 32 + n32: kappa_b = nt / 2, kappa_cd = 32 (nt % 2) + n32)
+  auto pass3 = [&]() {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int nt = 4 * w + j;
@@ -210,8 +212,28 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
         a_ = fmaf(d[r], d[r], fmaf(d[r + 8], d[r + 8], a_));
       }
     }
-    // no barrier here: P1 of the next sample writes LB, which every wave finished reading before the
-    // barrier ahead of P3, and P2 writes LC only after the barrier behind that P1
+  };
+
+  // Two phases per sample, software-pipelined over samples: phase 1 runs P1 of sample t + 1 and P3 of
+  // sample t, phase 2 runs P2 of t + 1.  LB is written in phase 1 and read in phase 2, LC the other way
+  // round, so one barrier after each phase suffices.  Operands are loaded one sample ahead of P1; in the
+  // last iteration P1 and P2 run on a repeated sample and their outputs are never read.
+  if (t0 < t1) {
+    load_x1(t0, x1);
+    pass1();
+    load_x1(min(t0 + 1, t1 - 1), x1);
+    __syncthreads();
+    pass2();
+    __syncthreads();
+  }
+  int blk = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    pass1();
+    load_x1(min(t + 2, t1 - 1), x1);
+    pass3();
+    __syncthreads();
+    pass2();
+    __syncthreads();
     if (++blk == time_block) {
       blk = 0;
       flush();
