@@ -108,7 +108,7 @@ struct ArrayPlan {
   int32_t* d_kmap = nullptr;
   double* d_A = nullptr;
   double* d_partial = nullptr;
-  double2* d_ws[2] = {nullptr, nullptr};
+  float2* d_ws[2] = {nullptr, nullptr};  // inverse-transform intermediates (complex float32)
   float2* d_y[2] = {nullptr, nullptr};
 };
 
@@ -561,8 +561,8 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
     plan_mixed_behind_front(ap, 5);
   const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
   ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
-  // inverse in groups of channels whose float64 workspace fits 512 MiB
-  ap.inv_group = (int)std::max<int64_t>(1, std::min<int64_t>(ap.F, (int64_t(512) << 20) / (ap.M * 16)));
+  // inverse in groups of channels whose complex float32 workspace fits 1 GiB per buffer
+  ap.inv_group = (int)std::max<int64_t>(1, std::min<int64_t>(ap.F, (int64_t(1) << 30) / (ap.M * 8)));
   return OMNI_OK;
 }
 
@@ -600,7 +600,7 @@ int alloc_array(ArrayPlan& ap) {
   HIP_TRY(hipMalloc(&ap.d_kmap, ap.fs.kmap.size() * sizeof(int32_t)));
   HIP_TRY(hipMalloc(&ap.d_A, accA));
   HIP_TRY(hipMalloc(&ap.d_partial, accA * (size_t)ap.max_slices));
-  const size_t ws = (size_t)ap.inv_group * ap.M * sizeof(double2);
+  const size_t ws = (size_t)ap.inv_group * ap.M * sizeof(float2);
   HIP_TRY(hipMalloc(&ap.d_ws[0], ws));
   HIP_TRY(hipMalloc(&ap.d_ws[1], ws));
   if (ap.n_front > 0) {

@@ -41,10 +41,11 @@ __global__ void fill_f64_kernel(double* __restrict__ p, int64_t n, double v) {
     p[i] = v;
 }
 
-// One axis of the inverse transform.  Source [outer][m][inner] (real if REAL_IN,
-// else complex float64), destination [outer][2n-1][inner].  twi[q] =
-// exp(+2 pi i q / m).  Output lag index o corresponds to Delta = o - (n-1).
-// If LAST, the destination is complex64 scaled by `scale`.
+// One axis of the inverse transform.  Source [outer][m][inner] (the real
+// float64 accumulator if REAL_IN, else complex float32 from the previous axis),
+// destination [outer][2n-1][inner] complex float32 (scaled by `scale` if LAST).
+// Each lag is summed in float64; only the stored intermediates are float32.
+// twi[q] = exp(+2 pi i q / m).  Output lag index o corresponds to Delta = o - (n-1).
 template <bool REAL_IN, bool LAST>
 __global__ void inverse_axis_kernel(const void* __restrict__ src, void* __restrict__ dst,
                                     const double2* __restrict__ twi, int64_t outer, int m, int n, int64_t inner,
@@ -69,18 +70,16 @@ __global__ void inverse_axis_kernel(const void* __restrict__ src, void* __restri
         re = fma(a, w.x, re);
         im = fma(a, w.y, im);
       } else {
-        const double2 a = reinterpret_cast<const double2*>(src)[base + (int64_t)k * inner];
-        re = fma(a.x, w.x, fma(-a.y, w.y, re));
-        im = fma(a.x, w.y, fma(a.y, w.x, im));
+        const float2 af = reinterpret_cast<const float2*>(src)[base + (int64_t)k * inner];
+        const double ax = af.x, ay = af.y;
+        re = fma(ax, w.x, fma(-ay, w.y, re));
+        im = fma(ax, w.y, fma(ay, w.x, im));
       }
       e += dm;
       if (e >= m) e -= m;
     }
-    if (LAST) {
-      reinterpret_cast<float2*>(dst)[i] = make_float2((float)(re * scale), (float)(im * scale));
-    } else {
-      reinterpret_cast<double2*>(dst)[i] = make_double2(re, im);
-    }
+    const double sc = LAST ? scale : 1.0;
+    reinterpret_cast<float2*>(dst)[i] = make_float2((float)(re * sc), (float)(im * sc));
   }
 }
 
@@ -92,7 +91,7 @@ template <bool REAL_IN, bool LAST, int TC>
 __global__ __launch_bounds__(256) void inverse_axis_tiled_kernel(const void* __restrict__ src, void* __restrict__ dst,
                                                                  const double2* __restrict__ twi, int64_t outer,
                                                                  int m, int n, int64_t inner, double scale) {
-  using Elem = typename std::conditional<REAL_IN, double, double2>::type;
+  using Elem = typename std::conditional<REAL_IN, double, float2>::type;
   __shared__ Elem a[TC == 32 ? 2048 : 4096];  // m * TC: m <= 64 for TC = 32, m <= 256 for TC = 16
   __shared__ double2 w[256];
   const int nout = 2 * n - 1;
@@ -129,20 +128,18 @@ __global__ __launch_bounds__(256) void inverse_axis_tiled_kernel(const void* __r
         re = fma(v, wk.x, re);
         im = fma(v, wk.y, im);
       } else {
-        const double2 v = a[k * TC + c];
-        re = fma(v.x, wk.x, fma(-v.y, wk.y, re));
-        im = fma(v.x, wk.y, fma(v.y, wk.x, im));
+        const float2 v = a[k * TC + c];
+        const double vx = v.x, vy = v.y;
+        re = fma(vx, wk.x, fma(-vy, wk.y, re));
+        im = fma(vx, wk.y, fma(vy, wk.x, im));
       }
       e += dm;
       if (e >= m) e -= m;
     }
     const int64_t ou = col / inner, in = col - ou * inner;
     const int64_t oi = (ou * nout + o) * inner + in;
-    if constexpr (LAST) {
-      reinterpret_cast<float2*>(dst)[oi] = make_float2((float)(re * scale), (float)(im * scale));
-    } else {
-      reinterpret_cast<double2*>(dst)[oi] = make_double2(re, im);
-    }
+    const double sc = LAST ? scale : 1.0;
+    reinterpret_cast<float2*>(dst)[oi] = make_float2((float)(re * sc), (float)(im * sc));
   }
 }
 
