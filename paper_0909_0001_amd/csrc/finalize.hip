@@ -143,6 +143,69 @@ __global__ __launch_bounds__(256) void inverse_axis_tiled_kernel(const void* __r
   }
 }
 
+// The same axis transform for a power-of-two m <= 32 as a radix-2 FFT in
+// registers: one thread per column (consecutive threads take consecutive inner
+// indices), all m outputs y_j = sum_k a_k exp(+2 pi i k j / m) in float64, of
+// which the 2n - 1 = m - 1 lags Delta = j (j < n) and Delta = j - m (j > n) are
+// stored.  O(m log m) work per column instead of O(m^2).
+template <int M>
+constexpr int bitrev(int k) {
+  int r = 0;
+  for (int b = 1; b < M; b <<= 1) r = (r << 1) | ((k / b) & 1);
+  return r;
+}
+
+template <int M, bool REAL_IN, bool LAST>
+__global__ __launch_bounds__(256) void inverse_axis_fft_kernel(const void* __restrict__ src, void* __restrict__ dst,
+                                                               const double2* __restrict__ twi, int64_t outer,
+                                                               int64_t inner, double scale) {
+  constexpr int NOUT = M - 1, NH = M / 2;
+  __shared__ double2 w[NH];  // exp(+2 pi i q / M), q < M / 2
+  for (int q = threadIdx.x; q < NH; q += blockDim.x) w[q] = twi[q];
+  __syncthreads();
+  const int64_t cols = outer * inner;
+  const double sc = LAST ? scale : 1.0;
+  for (int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; col < cols;
+       col += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ou = col / inner, in = col - ou * inner;
+    double2 x[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int64_t at = (ou * M + k) * inner + in;
+      if constexpr (REAL_IN) {
+        x[bitrev<M>(k)] = make_double2(static_cast<const double*>(src)[at], 0.0);
+      } else {
+        const float2 v = static_cast<const float2*>(src)[at];
+        x[bitrev<M>(k)] = make_double2(v.x, v.y);
+      }
+    }
+#pragma unroll
+    for (int len = 2; len <= M; len <<= 1) {
+#pragma unroll
+      for (int i = 0; i < M; i += len) {
+#pragma unroll
+        for (int j = 0; j < len / 2; ++j) {
+          const double2 u = x[i + j];
+          double2 v = x[i + j + len / 2];
+          if (j > 0) {
+            const double2 wj = w[j * (M / len)];  // exp(+2 pi i j / len)
+            v = make_double2(fma(v.x, wj.x, -v.y * wj.y), fma(v.x, wj.y, v.y * wj.x));
+          }
+          x[i + j] = make_double2(u.x + v.x, u.y + v.y);
+          x[i + j + len / 2] = make_double2(u.x - v.x, u.y - v.y);
+        }
+      }
+    }
+    float2* d = static_cast<float2*>(dst);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      const int delta = o - (NH - 1);
+      const double2 y = x[delta >= 0 ? delta : delta + M];
+      d[(ou * NOUT + o) * inner + in] = make_float2((float)(y.x * sc), (float)(y.y * sc));
+    }
+  }
+}
+
 // Twiddle generator, float64 on the device: for each table entry (m, q, sign)
 // w = exp(sign * 2 pi i q / m), evaluated with sincospi on the exact reduced
 // ratio 2q/m.  Writes float32 copies for the forward kernels and float64
@@ -182,9 +245,30 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int M>
+static hipError_t launch_inverse_fft(bool real_in, bool last, const void* src, void* dst, const double2* twi,
+                                     int64_t outer, int64_t inner, double scale, hipStream_t st) {
+  const dim3 g(grid_for(outer * inner, 256)), b(256);
+  if (real_in && last)
+    hipLaunchKernelGGL((inverse_axis_fft_kernel<M, true, true>), g, b, 0, st, src, dst, twi, outer, inner, scale);
+  else if (real_in)
+    hipLaunchKernelGGL((inverse_axis_fft_kernel<M, true, false>), g, b, 0, st, src, dst, twi, outer, inner, scale);
+  else if (last)
+    hipLaunchKernelGGL((inverse_axis_fft_kernel<M, false, true>), g, b, 0, st, src, dst, twi, outer, inner, scale);
+  else
+    hipLaunchKernelGGL((inverse_axis_fft_kernel<M, false, false>), g, b, 0, st, src, dst, twi, outer, inner, scale);
+  return hipGetLastError();
+}
+
 hipError_t launch_inverse_axis(bool real_in, bool last, const void* src, void* dst, const double2* twi,
                                int64_t outer, int m, int n, int64_t inner, double scale, hipStream_t st) {
   const int64_t cols = outer * inner;
+  if (m == 2 * n) {
+    if (m == 4) return launch_inverse_fft<4>(real_in, last, src, dst, twi, outer, inner, scale, st);
+    if (m == 8) return launch_inverse_fft<8>(real_in, last, src, dst, twi, outer, inner, scale, st);
+    if (m == 16) return launch_inverse_fft<16>(real_in, last, src, dst, twi, outer, inner, scale, st);
+    if (m == 32) return launch_inverse_fft<32>(real_in, last, src, dst, twi, outer, inner, scale, st);
+  }
   if (m <= 256 && cols >= (m <= 64 ? 32 : 16) * 256) {
     // TC columns per work-group (m * TC <= 2048 or 4096 elements of LDS), at least 256 work-groups
     const dim3 b(256);
