@@ -44,24 +44,30 @@ __device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// LB [comp][a][kappa_c][b] and LC [comp][kappa_b][kappa_c][a], in halves.  Blocks of 32 rows
-// of 16 halves carry 8 halves of padding (consecutive blocks start 4 banks apart), and inside a row
-// the 4-half units are XOR-swizzled by bit 3 of kappa_c and by the component: the 8-byte stores of
-// passes A and B (32 lanes: 2 components x 16 rows) and the 16-byte loads of passes B and C (16
-// lanes) then touch 64 distinct banks.  A 16-byte load of component 1 returns its two halves swapped.
+// LB [comp][a][kappa_c][b] and LC [comp][kappa_b][kappa_c][a], in halves: rows of 16 halves (four
+// 4-half units), blocks of 32 rows padded by 8 halves (so consecutive blocks start 16 bytes apart modulo
+// 256).  Measured on gfx950, an 8-byte store is served 16 lanes at a time from 32 banks (a 128-byte
+// window) and a 16-byte load 16 lanes at a time from 64 banks (256 bytes).  The units of a row are
+// XOR-permuted: in LB by (kappa_c / 4) % 4, in LC by bit 3 of kappa_b (bit 0 of the unit) and bit 3 of
+// kappa_c (bit 1).  Then each 8-byte store (16 lanes: 16 consecutive rows of LB, or the same row of
+// 16 LC blocks) and each 16-byte load (16 lanes: 16 LB blocks, or 16 consecutive LC rows) meets every
+// bank at most once.
 constexpr int BLK = 520;         // 32 x 16 + 8
 constexpr int CMP = 16 * BLK;    // component stride of LB (16 values of a)
 constexpr int CMPC = 32 * BLK;   // component stride of LC (all 32 values of kappa_b)
+__device__ __forceinline__ int lb_x(int kc) { return (kc >> 2) & 3; }
+__device__ __forceinline__ int lc_x(int kb, int kc) { return ((kb >> 3) & 1) | (((kc >> 3) & 1) << 1); }
 __device__ __forceinline__ int lb_at(int comp, int a, int kc, int b) {
-  return comp * CMP + a * BLK + kc * 16 + (b ^ (kc & 8) ^ (4 * comp));
+  return comp * CMP + a * BLK + kc * 16 + (b ^ (4 * lb_x(kc)));
 }
 __device__ __forceinline__ int lc_at(int comp, int kb, int kc, int a) {
-  return comp * CMPC + kb * BLK + kc * 16 + (a ^ (kc & 8) ^ (4 * comp));
+  return comp * CMPC + kb * BLK + kc * 16 + (a ^ (4 * lc_x(kb, kc)));
 }
-// 8 consecutive halves j0 .. j0 + 7 (j0 a multiple of 8) of a swizzled row
-__device__ __forceinline__ half8 load8(const _Float16* row, int j0, int kc, int comp) {
-  half8 v = *reinterpret_cast<const half8*>(row + (j0 ^ (kc & 8)));
-  if (comp) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
+// 8 consecutive halves j0 .. j0 + 7 (j0 a multiple of 8) of a row whose units are permuted by x: the
+// aligned 16 bytes holding them, with their two units in swapped order when x is odd
+__device__ __forceinline__ half8 load8(const _Float16* row, int j0, int x) {
+  half8 v = *reinterpret_cast<const half8*>(row + (j0 ^ (8 * (x >> 1))));
+  if (x & 1) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
   return v;
 }
 
@@ -86,7 +92,9 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   using namespace m163;
   __shared__ __attribute__((aligned(16))) _Float16 LB[2 * CMP];
   __shared__ __attribute__((aligned(16))) _Float16 LC[2 * CMPC];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
+  // (the wave index read as a wave-uniform value: the unit order of the operand loads depends on it alone)
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, h = l >> 5,
+            n32 = l & 31;
   const int ch = blockIdx.x % F;
   const int s = blockIdx.x / F;
   const int64_t t0 = (int64_t)s * t_per_slice;
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
       floatx16 d = {};
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        const half8 x = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, kc_in, h);
+        const half8 x = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, lb_x(kc_in));
         d = mfma(x, Wh[half][ks], d);
         d = mfma(x, Wl[half][ks], d);
       }
@@ -198,7 +206,7 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
       const int kb = 16 * half + 2 * w + j;
       half8 x[2];
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMPC + kb * BLK + n32 * 16], 8 * ks, n32, h);
+      for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMPC + kb * BLK + n32 * 16], 8 * ks, lc_x(kb, n32));
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         floatx16 d = {};

@@ -16,11 +16,11 @@
 // The scales keep every float16 intermediate within the input's range;
 // `out_scale` undoes them on |X|^2.  Work-group = (time slice, channel), 512
 // threads, all 16384 cells of the channel, 32 float32 accumulators per lane.
-// LDS rows are padded and XOR-swizzled so that the 8-byte stores (32 lanes:
-// 2 components x 16 rows) and the 16-byte operand loads (16 lanes) touch
-// distinct banks.  Each lane loads its P1 operands straight from HBM into
-// registers, one sample ahead, and the passes are software-pipelined over
-// samples (two barriers per sample).
+// LDS rows are padded and their units swapped per row so that the 8-byte
+// stores and the 16-byte operand loads (16 lanes at a time each) touch distinct
+// banks.  Each lane loads its P1 operands straight from HBM into registers, one
+// sample ahead, and the passes are software-pipelined over samples (two
+// barriers per sample).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -41,24 +41,27 @@ __device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// LB [comp][a 8][kappa_cd 64][b 8]: a-blocks of 64 rows of 8 halves, padded by 16 halves (8 banks);
-// the two 4-half units of a row are swapped for component 1.
+// LB [comp][a 8][kappa_cd 64][b 8]: a-blocks of 64 rows of 8 halves, padded by 16 halves;
+// LC [comp][kappa_b 16][kappa_cd 64][a 8]: kappa_b-blocks padded by 8 halves.  Measured on gfx950, an
+// 8-byte store is served 16 lanes at a time from 32 banks (a 128-byte window) and a 16-byte load 16
+// lanes at a time from 64 banks (256 bytes); the two 4-half units of a row are swapped for rows with
+// bit 3 of kappa_cd set (LB) or of kappa_b set (LC), so that the stores of 16 consecutive rows (LB) or
+// of one row in 16 blocks (LC) meet every bank once.  The loads take whole rows and undo the swap.
 constexpr int LB_BLK = 64 * 8 + 16;
 constexpr int LB_CMP = 8 * LB_BLK;
-// LC [comp][kappa_b 16][kappa_cd 64][a 8]: kappa_b-blocks padded by 8 halves (4 banks)
 constexpr int LC_BLK = 64 * 8 + 8;
 constexpr int LC_CMP = 16 * LC_BLK;
 
 __device__ __forceinline__ int lb_at(int comp, int a, int kcd, int b) {
-  return comp * LB_CMP + a * LB_BLK + kcd * 8 + (b ^ (4 * comp));
+  return comp * LB_CMP + a * LB_BLK + kcd * 8 + (b ^ (4 * ((kcd >> 3) & 1)));
 }
 __device__ __forceinline__ int lc_at(int comp, int kb, int kcd, int a) {
-  return comp * LC_CMP + kb * LC_BLK + kcd * 8 + (a ^ (4 * comp));
+  return comp * LC_CMP + kb * LC_BLK + kcd * 8 + (a ^ (4 * ((kb >> 3) & 1)));
 }
-// the 8 halves of a row (component comp), in logical order
-__device__ __forceinline__ half8 load_row(const _Float16* row, int comp) {
+// the 8 halves of a row, in logical order (its units are stored swapped when `swapped`)
+__device__ __forceinline__ half8 load_row(const _Float16* row, int swapped) {
   half8 v = *reinterpret_cast<const half8*>(row);
-  if (comp) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
+  if (swapped) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
   return v;
 }
 
@@ -89,7 +92,9 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
   using namespace m8844;
   __shared__ __attribute__((aligned(16))) _Float16 LB[2 * LB_CMP];
   __shared__ __attribute__((aligned(16))) _Float16 LC[2 * LC_CMP];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
+  // (the wave index read as a wave-uniform value: the unit order of the operand loads depends on it alone)
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, h = l >> 5,
+            n32 = l & 31;
   const bool co = n32 >= 16;
   const int ch = blockIdx.x % F;
   const int s = blockIdx.x / F;
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
     for (int jm = 0; jm < 2; ++jm) {
       const int mt = 2 * w + jm;
       const int a_in = n32 & 7, kcd_in = 4 * mt + (n32 >> 3);
-      const half8 x = load_row(&LB[h * LB_CMP + a_in * LB_BLK + kcd_in * 8], h);
+      const half8 x = load_row(&LB[h * LB_CMP + a_in * LB_BLK + kcd_in * 8], (kcd_in >> 3) & 1);
       floatx16 d = {};
       d = mfma(x, W2h, d);
       d = mfma(x, W2l, d);
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
     for (int j = 0; j < 4; ++j) {
       const int nt = 4 * w + j;
       const int kb = nt >> 1, kcd = 32 * (nt & 1) + n32;
-      const half8 x = load_row(&LC[h * LC_CMP + kb * LC_BLK + kcd * 8], h);
+      const half8 x = load_row(&LC[h * LC_CMP + kb * LC_BLK + kcd * 8], (kb >> 3) & 1);
       floatx16 d = {};
       d = mfma(W2h, x, d);
       d = mfma(W2l, x, d);

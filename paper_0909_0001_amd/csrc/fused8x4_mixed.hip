@@ -107,18 +107,20 @@ struct Raw<2> {  // byte i of word k = sample 4k + i, real part in the high nibb
 };
 
 // LDS layouts (float16).  A 16-byte operand row holds the 8 values of one
-// component along the axis the next pass contracts.  Rows are XOR-swizzled
-// within their block so that the 8-byte stores of a pass and the 16-byte
-// operand loads of the next one both spread over the 64 LDS banks (chosen
-// with a bank model of the six access patterns: at most 2-way conflicts).
-//   L2 [comp][i0][q][i1 ^ (q/2) ^ 4 comp][i2]   (P1 -> P2)
-//   L3 [comp][q][k2][i0 ^ (k2/2 % 8)][i1]       (P2 -> P3)
+// component along the axis the next pass contracts, as two 4-value units.
+// Measured on gfx950, an 8-byte store is served 16 lanes at a time from 32
+// banks (a 128-byte window) and a 16-byte load 16 lanes at a time from 64 banks
+// (256 bytes).  Rows are XOR-permuted within their block, and in L3 the two
+// units of a row are swapped for kappa_2 >= 8, so that the stores of each pass
+// and the loads of the next meet every bank once (the P3 -> P4 stores: twice).
+//   L2 [comp][i0][q][i1 ^ q][i2]                (P1 -> P2)
+//   L3 [comp][q][k2][i0 ^ (k2 % 8)][i1]         (P2 -> P3; units swapped for k2 >= 8)
 //   L4 [buf][comp][k1][(8 q + k2c) ^ k1][i0]    (P3 -> P4)
 __device__ __forceinline__ int l2_row(int comp, int i0, int q, int i1) {
-  return ((comp * 8 + i0) * 8 + q) * 8 + (i1 ^ (q >> 1) ^ (4 * comp));
+  return ((comp * 8 + i0) * 8 + q) * 8 + (i1 ^ q);
 }
 __device__ __forceinline__ int l3_row(int comp, int q, int k2, int i0) {
-  return ((comp * 8 + q) * 16 + k2) * 8 + (i0 ^ ((k2 >> 1) & 7));
+  return ((comp * 8 + q) * 16 + k2) * 8 + (i0 ^ (k2 & 7));
 }
 __device__ __forceinline__ int l4_row(int comp, int k1, int idx2) {
   return (comp * 16 + k1) * 64 + (idx2 ^ k1);
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
   __shared__ _Float16 L4[2][2 * 16 * 64 * 8];
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = lane & 31, hh = lane >> 5;
   const int b = blockIdx.x;
   int grp, h;
@@ -209,15 +211,15 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
     const int comp = col >> 4, k2 = col & 15;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      store4(&L3[l3_row(comp, 4 * tw + i, k2, i0w) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
-             d[4 * i + 3]);
+      store4(&L3[l3_row(comp, 4 * tw + i, k2, i0w) * 8 + 4 * (hh ^ (k2 >> 3))], d[4 * i], d[4 * i + 1],
+             d[4 * i + 2], d[4 * i + 3]);
   };
   // ---- P3 (axis 1) for kappa_2 half cc into L4[cc]: lines (idx2, i0) = (4 w + r / 8, r % 8) with
   //      idx2 = 8 q + k2c, kappa_2 = 8 cc + k2c
   auto pass3_mfma = [&](int cc) {
     const int idx2 = 4 * wave + (col >> 3);
-    const half8 a =
-        *reinterpret_cast<const half8*>(&L3[l3_row(hh, idx2 >> 3, 8 * cc + (idx2 & 7), col & 7) * 8]);
+    half8 a = *reinterpret_cast<const half8*>(&L3[l3_row(hh, idx2 >> 3, 8 * cc + (idx2 & 7), col & 7) * 8]);
+    if (cc) a = __builtin_shufflevector(a, a, 4, 5, 6, 7, 0, 1, 2, 3);  // units stored swapped for k2 >= 8
     const floatx16 d = mfma(a, Wf_hi, zero);
     return mfma(a, Wf_lo, d);
   };
