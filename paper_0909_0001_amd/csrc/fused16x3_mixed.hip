@@ -12,8 +12,9 @@
 // |X|^2 accumulators carry those scales; `out_scale` restores them when they
 // are written out.
 //
-// Work-group = (time slice, channel), 512 threads; it owns all 32768 cells of
-// the channel, 64 float32 accumulators per lane.  Per sample:
+// Work-group = (time slice, channel), 1024 threads (16 waves, one work-group
+// per CU); it owns all 32768 cells of the channel, 32 float32 accumulators per
+// lane.  Per sample (one A tile, two B tiles and four C tiles per wave):
 //   A  axis c, lines (a, b): data x W^T, 8 row tiles x 2 column tiles -> LB
 //   B  axis b, lines (a, kappa_c): data x W^T, both halves of kappa_b -> LC
 //   C  axis a, lines (kappa_b, kappa_c): W x data, so that the real and the
@@ -36,9 +37,9 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int NT = 512;
+constexpr int NT = 1024;
 constexpr int CELLS = 32768;
-constexpr int SLOTS = 64;  // accumulators per lane
+constexpr int SLOTS = 32;  // accumulators per lane
 
 __device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -82,10 +83,10 @@ __device__ __forceinline__ half4 to_half4(const floatx16& d, int g) {
 
 }  // namespace m163
 
-// Grid: n_slices x F work-groups (F = channels of this launch), 512 threads.
+// Grid: n_slices x F work-groups (F = channels of this launch), 1024 threads.
 // src: [T][F][2][4096] halves; tw: w_32^q, q < 32 (float32); partial:
 // [n_slices][F][32768] float64 in the cell order given by fused16x3_cell.
-__global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __restrict__ src, int64_t T,
+__global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* __restrict__ src, int64_t T,
                                                               int64_t t_per_slice, const float2* __restrict__ tw,
                                                               double* __restrict__ partial, int F, int time_block,
                                                               int accumulate, double out_scale) {
@@ -100,29 +101,38 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   const int64_t t0 = (int64_t)s * t_per_slice;
   const int64_t t1 = min(T, t0 + t_per_slice);
 
-  // DFT operand of this lane, for column / row tile u (kappa in [16u, 16u + 16)) and K step ks:
-  // output (co = n32 / 16, kappa = 16u + n32 % 16), input (ci = h, j = 8 ks + i)
-  half8 Wh[2][2], Wl[2][2];
+  // DFT operand of this lane for K step ks: output (co = n32 / 16, kappa = n32 % 16), input (ci = h,
+  // j = 8 ks + i).  The outputs kappa + 16 use the same operand with the odd inputs negated
+  // (w_32^{(kappa + 16) j} = (-1)^j w_32^{kappa j}), applied to the data by flip_odd.
+  half8 Wh[2], Wl[2];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int kap = 16 * u + (n32 & 15), j = 8 * ks + i;
-        const float2 wv = tw[(kap * j) & 31];
-        const bool co = n32 >= 16, ci = h != 0;
-        const float v = (!co ? (!ci ? wv.x : -wv.y) : (!ci ? wv.y : wv.x)) * 0.0625f;
-        const _Float16 hi = (_Float16)v;
-        Wh[u][ks][i] = hi;
-        Wl[u][ks][i] = (_Float16)(v - (float)hi);
-      }
+    for (int i = 0; i < 8; ++i) {
+      const int kap = n32 & 15, j = 8 * ks + i;
+      const float2 wv = tw[(kap * j) & 31];
+      const bool co = n32 >= 16, ci = h != 0;
+      const float v = (!co ? (!ci ? wv.x : -wv.y) : (!ci ? wv.y : wv.x)) * 0.0625f;
+      const _Float16 hi = (_Float16)v;
+      Wh[ks][i] = hi;
+      Wl[ks][i] = (_Float16)(v - (float)hi);
     }
   }
+  // negate the odd entries (the high half of each 32-bit word) when `mask` is 0x80000000
+  auto flip_odd = [](half8 v, uint32_t mask) {
+    uint4 b = __builtin_bit_cast(uint4, v);
+    b.x ^= mask;
+    b.y ^= mask;
+    b.z ^= mask;
+    b.w ^= mask;
+    return __builtin_bit_cast(half8, b);
+  };
 
-  // pass A operand of this lane: line (a = 2w + n32 / 16, b = n32 % 16), component h, the 16 values of c;
-  // read straight from HBM into registers, one sample ahead
-  const int a_line = (2 * w + (n32 >> 4)) * 16 + (n32 & 15);
+  // pass A tile of wave w: row tile rt = w % 8 (lines a = 2 rt + n32 / 16, b = n32 % 16), column tile
+  // ua = w / 8 (kappa_c in [16 ua, 16 ua + 16)).  The lane's operand: component h, the 16 values of c,
+  // read straight from HBM into registers, one sample ahead.
+  const int rt = w & 7, ua = w >> 3;
+  const int a_line = (2 * rt + (n32 >> 4)) * 16 + (n32 & 15);
   auto load_xa = [&](int64_t t, half8* xa) {
     const half8* g = reinterpret_cast<const half8*>(src + (t * F + ch) * 8192 + h * 4096 + a_line * 16);
     xa[0] = g[0];
@@ -157,53 +167,49 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   };
 
   half8 xa[2];
-  // ---- A: axis c; row tile w holds lines (a = 2w + n32 / 16, b = n32 % 16), this lane's half h reads
-  // component h of c = 8 ks .. 8 ks + 7
+  // ---- A: axis c on this wave's tile (rt, ua); this lane's half h reads component h of c = 8 ks .. 8 ks + 7
   auto pass_a = [&]() {
     const int co = n32 >> 4;
+    const uint32_t mask = (uint32_t)ua << 31;
+    floatx16 d = {};
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      floatx16 d = {};
+    for (int ks = 0; ks < 2; ++ks) {
+      const half8 x = flip_odd(xa[ks], mask);
+      d = mfma(x, Wh[ks], d);
+      d = mfma(x, Wl[ks], d);
+    }
+    // column n32: (co, kappa_c = 16 ua + n32 % 16); rows 8g + 4h + e: b = 8 (g & 1) + 4h + e, a = 2 rt + g / 2
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        d = mfma(xa[ks], Wh[u][ks], d);
-        d = mfma(xa[ks], Wl[u][ks], d);
-      }
-      // column n32: (co, kappa_c = 16 u + n32 % 16); rows 8g + 4h + e: b = 8 (g & 1) + 4h + e, a = 2w + g / 2
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int a = 2 * w + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
-        *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * u + (n32 & 15), b0)]) = to_half4(d, g);
-      }
+    for (int g = 0; g < 4; ++g) {
+      const int a = 2 * rt + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
+      *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * ua + (n32 & 15), b0)]) = to_half4(d, g);
     }
   };
-  // ---- B: axis b, row tiles 2w, 2w + 1 of lines (a = m % 16, kappa_c = 2 mt + m / 16), columns = one half
-  // of kappa_b
+  // ---- B: axis b, row tile mt = w of lines (a = m % 16, kappa_c = 2 mt + m / 16), columns = one half of
+  // kappa_b
   auto pass_b = [&](int half) {
+    const int mt = w;
+    const int a_in = n32 & 15, kc_in = 2 * mt + (n32 >> 4);
+    floatx16 d = {};
 #pragma unroll
-    for (int jm = 0; jm < 2; ++jm) {
-      const int mt = 2 * w + jm;
-      const int a_in = n32 & 15, kc_in = 2 * mt + (n32 >> 4);
-      floatx16 d = {};
+    for (int ks = 0; ks < 2; ++ks) {
+      const half8 x = flip_odd(load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, lb_x(kc_in)),
+                               (uint32_t)half << 31);
+      d = mfma(x, Wh[ks], d);
+      d = mfma(x, Wl[ks], d);
+    }
+    const int co = n32 >> 4, kb = 16 * half + (n32 & 15);
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const half8 x = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, lb_x(kc_in));
-        d = mfma(x, Wh[half][ks], d);
-        d = mfma(x, Wl[half][ks], d);
-      }
-      const int co = n32 >> 4, kb = 16 * half + (n32 & 15);
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int a0 = 8 * (g & 1) + 4 * h, kc = 2 * mt + (g >> 1);
-        *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d, g);
-      }
+    for (int g = 0; g < 4; ++g) {
+      const int a0 = 8 * (g & 1) + 4 * h, kc = 2 * mt + (g >> 1);
+      *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d, g);
     }
   };
-  // ---- C: axis a, column tiles (lines kappa_b = 16 half + 2w + j, kappa_c = n32), row tiles u
-  auto pass_c = [&](int half) {
+  // ---- C: axis a, column tiles (lines kappa_b = 2w + j, kappa_c = n32), row tiles u
+  auto pass_c = [&]() {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int kb = 16 * half + 2 * w + j;
+      const int kb = 2 * w + j;
       half8 x[2];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMPC + kb * BLK + n32 * 16], 8 * ks, lc_x(kb, n32));
@@ -212,13 +218,14 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
         floatx16 d = {};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          d = mfma(Wh[u][ks], x[ks], d);
-          d = mfma(Wl[u][ks], x[ks], d);
+          const half8 xu = u ? flip_odd(x[ks], 0x80000000u) : x[ks];
+          d = mfma(Wh[ks], xu, d);
+          d = mfma(Wl[ks], xu, d);
         }
         // rows r < 8 hold Re and rows r + 8 Im of the same kappa_a
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-          float& a_ = acc[((half * 2 + j) * 2 + u) * 8 + r];
+          float& a_ = acc[(j * 2 + u) * 8 + r];
           a_ = fmaf(d[r], d[r], fmaf(d[r + 8], d[r + 8], a_));
         }
       }
@@ -242,8 +249,7 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   for (int64_t t = t0; t < t1; ++t) {
     pass_a();
     load_xa(min(t + 2, t1 - 1), xa);
-    pass_c(0);
-    pass_c(1);
+    pass_c();
     __syncthreads();
     pass_b(0);
     pass_b(1);
@@ -256,13 +262,13 @@ __global__ __launch_bounds__(512) void fused16x3_mixed_kernel(const _Float16* __
   if (blk > 0 || !flushed) flush();
 }
 
-// Natural index (kappa_a * 32 + kappa_b) * 32 + kappa_c of cell `cell` (= slot * 512 + thread).
+// Natural index (kappa_a * 32 + kappa_b) * 32 + kappa_c of cell `cell` (= slot * 1024 + thread).
 int fused16x3_cell(int cell) {
-  const int slot = cell / 512, tid = cell % 512;
+  const int slot = cell / 1024, tid = cell % 1024;
   const int w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
-  const int r = slot % 8, u = (slot / 8) % 2, j = (slot / 16) % 2, half = slot / 32;
+  const int r = slot % 8, u = (slot / 8) % 2, j = slot / 16;
   const int ka = 16 * u + 8 * (r / 4) + 4 * h + (r % 4);
-  const int kb = 16 * half + 2 * w + j;
+  const int kb = 2 * w + j;
   const int kc = n32;
   return (ka * 32 + kb) * 32 + kc;
 }
@@ -270,7 +276,7 @@ int fused16x3_cell(int cell) {
 hipError_t launch_fused16x3_mixed(const void* src, int64_t T, int64_t tps, const float2* tw, double* partial, int F,
                                   int n_slices, int time_block, int accumulate, double out_scale, hipStream_t st) {
   if ((reinterpret_cast<uintptr_t>(src) & 15) != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fused16x3_mixed_kernel, dim3((unsigned)(n_slices * F)), dim3(512), 0, st,
+  hipLaunchKernelGGL(fused16x3_mixed_kernel, dim3((unsigned)(n_slices * F)), dim3(m163::NT), 0, st,
                      static_cast<const _Float16*>(src), T, tps, tw, partial, F, time_block, accumulate, out_scale);
   return hipGetLastError();
 }
