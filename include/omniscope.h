@@ -69,7 +69,8 @@ typedef enum { OMNI_CF32 = 0, OMNI_CI8 = 1, OMNI_CI4 = 2 } omni_dtype;
  *                    twiddles split into float16 hi + lo parts, per-stage
  *                    power-of-two scaling.  Error <= 2e-3 of zero-lag power.
  * Both forms integrate |X|^2 in float32 over short blocks of time samples and
- * then in float64, and run the inverse transform in float64. */
+ * then in float64, and run the inverse transform with float64 sums (complex
+ * float32 between its axes). */
 typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 
 /* omni_opts.flags */
