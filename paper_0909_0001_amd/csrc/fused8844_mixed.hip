@@ -46,7 +46,8 @@ __device__ __forceinline__ floatx16 mfma(half8 a, half8 b, floatx16 c) {
 // 8-byte store is served 16 lanes at a time from 32 banks (a 128-byte window) and a 16-byte load 16
 // lanes at a time from 64 banks (256 bytes); the two 4-half units of a row are swapped for rows with
 // bit 3 of kappa_cd set (LB) or of kappa_b set (LC), so that the stores of 16 consecutive rows (LB) or
-// of one row in 16 blocks (LC) meet every bank once.  The loads take whole rows and undo the swap.
+// of one row in 16 blocks (LC) meet every bank once.  The loads take whole rows; the swap is absorbed
+// by the DFT operand (the rows a wave loads are all swapped, or none).
 constexpr int LB_BLK = 64 * 8 + 16;
 constexpr int LB_CMP = 8 * LB_BLK;
 constexpr int LC_BLK = 64 * 8 + 8;
@@ -57,12 +58,6 @@ __device__ __forceinline__ int lb_at(int comp, int a, int kcd, int b) {
 }
 __device__ __forceinline__ int lc_at(int comp, int kb, int kcd, int a) {
   return comp * LC_CMP + kb * LC_BLK + kcd * 8 + (a ^ (4 * ((kb >> 3) & 1)));
-}
-// the 8 halves of a row, in logical order (its units are stored swapped when `swapped`)
-__device__ __forceinline__ half8 load_row(const _Float16* row, int swapped) {
-  half8 v = *reinterpret_cast<const half8*>(row);
-  if (swapped) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
-  return v;
 }
 
 __device__ __forceinline__ half4 to_half4(const floatx16& d, int g) {
@@ -119,11 +114,15 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
       W1l[ks][i] = (_Float16)(v - (float)hi);
     }
   }
-  // P2 / P3 operand: output (co, kappa = n32 % 16), K = (ci = h, j = i < 8): w_16^{kappa j} / 8
+  // P2 / P3 operand: output (co, kappa = n32 % 16), K = (ci = h, j < 8): w_16^{kappa j} / 8.  In odd waves
+  // every row that P2 and P3 load from LDS has its two units swapped (bit 3 of kappa_cd, resp. of
+  // kappa_b, equals the wave's bit 0), so there the operand takes input j = i ^ 4 at position i instead
+  // of swapping the loaded data back.
+  const int sw = w & 1;
   half8 W2h, W2l;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const float v = embed(tw16[((n32 & 15) * i) & 15], co, h != 0) * 0.125f;
+    const float v = embed(tw16[((n32 & 15) * (i ^ (4 * sw))) & 15], co, h != 0) * 0.125f;
     const _Float16 hi = (_Float16)v;
     W2h[i] = hi;
     W2l[i] = (_Float16)(v - (float)hi);
@@ -191,7 +190,7 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
     for (int jm = 0; jm < 2; ++jm) {
       const int mt = 2 * w + jm;
       const int a_in = n32 & 7, kcd_in = 4 * mt + (n32 >> 3);
-      const half8 x = load_row(&LB[h * LB_CMP + a_in * LB_BLK + kcd_in * 8], (kcd_in >> 3) & 1);
+      const half8 x = *reinterpret_cast<const half8*>(&LB[h * LB_CMP + a_in * LB_BLK + kcd_in * 8]);
       floatx16 d = {};
       d = mfma(x, W2h, d);
       d = mfma(x, W2l, d);
@@ -201,13 +200,13 @@ __global__ __launch_bounds__(512, 4) void fused8844_mixed_kernel(const _Float16*
         *reinterpret_cast<half4*>(&LC[lc_at(co, n32 & 15, 4 * mt + g, 4 * h)]) = to_half4(d, g);
     }
   };
-  // ---- P3: column tiles nt = 4w + j (lines nt * 32 + n32: kappa_b = nt / 2, kappa_cd = 32 (nt % 2) + n32)
+  // ---- P3: four column tiles j of lines (kappa_b, kappa_cd = 32 (j % 2) + n32) with
+  //      kappa_b = 8 (w % 2) + 2 (w / 2) + j / 2: bit 3 of kappa_b is the wave's bit 0
   auto pass3 = [&]() {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int nt = 4 * w + j;
-      const int kb = nt >> 1, kcd = 32 * (nt & 1) + n32;
-      const half8 x = load_row(&LC[h * LC_CMP + kb * LC_BLK + kcd * 8], (kb >> 3) & 1);
+      const int kb = 8 * sw + 2 * (w >> 1) + (j >> 1), kcd = 32 * (j & 1) + n32;
+      const half8 x = *reinterpret_cast<const half8*>(&LC[h * LC_CMP + kb * LC_BLK + kcd * 8]);
       floatx16 d = {};
       d = mfma(W2h, x, d);
       d = mfma(W2l, x, d);
@@ -252,8 +251,7 @@ int fused8844_cell(int cell) {
   const int slot = cell / 512, tid = cell % 512;
   const int w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
   const int r = slot % 8, j = slot / 8;
-  const int nt = 4 * w + j;
-  const int kb = nt >> 1, kcd = 32 * (nt & 1) + n32;
+  const int kb = 8 * (w & 1) + 2 * (w >> 1) + (j >> 1), kcd = 32 * (j & 1) + n32;
   const int ka = 8 * (r / 4) + 4 * h + (r % 4);
   return (ka * 16 + kb) * 64 + kcd;
 }
