@@ -64,12 +64,10 @@ __device__ __forceinline__ int lb_at(int comp, int a, int kc, int b) {
 __device__ __forceinline__ int lc_at(int comp, int kb, int kc, int a) {
   return comp * CMPC + kb * BLK + kc * 16 + (a ^ (4 * lc_x(kb, kc)));
 }
-// 8 consecutive halves j0 .. j0 + 7 (j0 a multiple of 8) of a row whose units are permuted by x: the
-// aligned 16 bytes holding them, with their two units in swapped order when x is odd
+// the aligned 16 bytes of a row (units permuted by x) that hold its halves j0 .. j0 + 7 (j0 a multiple of
+// 8); their two units come in swapped order when x is odd, which the caller's DFT operand absorbs
 __device__ __forceinline__ half8 load8(const _Float16* row, int j0, int x) {
-  half8 v = *reinterpret_cast<const half8*>(row + (j0 ^ (8 * (x >> 1))));
-  if (x & 1) v = __builtin_shufflevector(v, v, 4, 5, 6, 7, 0, 1, 2, 3);
-  return v;
+  return *reinterpret_cast<const half8*>(row + (j0 ^ (8 * (x >> 1))));
 }
 
 __device__ __forceinline__ half4 to_half4(const floatx16& d, int g) {
@@ -102,14 +100,18 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
   const int64_t t1 = min(T, t0 + t_per_slice);
 
   // DFT operand of this lane for K step ks: output (co = n32 / 16, kappa = n32 % 16), input (ci = h,
-  // j = 8 ks + i).  The outputs kappa + 16 use the same operand with the odd inputs negated
-  // (w_32^{(kappa + 16) j} = (-1)^j w_32^{kappa j}), applied to the data by flip_odd.
+  // j = 8 ks + (i ^ 4 sw)).  The outputs kappa + 16 use the same operand with the odd inputs negated
+  // (w_32^{(kappa + 16) j} = (-1)^j w_32^{kappa j}), applied to the data by flip_odd.  In waves with
+  // sw = 1 every operand row loaded in passes B and C has its two 4-half units swapped (bit 0 of the
+  // rows' unit permutation equals bit 1 of the wave index, see pass C's tiles), and pass A loads its
+  // operand swapped likewise, so the operand takes input 8 ks + (i ^ 4) at position i.
+  const int sw = (w >> 1) & 1;
   half8 Wh[2], Wl[2];
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int kap = n32 & 15, j = 8 * ks + i;
+      const int kap = n32 & 15, j = 8 * ks + (i ^ (4 * sw));
       const float2 wv = tw[(kap * j) & 31];
       const bool co = n32 >= 16, ci = h != 0;
       const float v = (!co ? (!ci ? wv.x : -wv.y) : (!ci ? wv.y : wv.x)) * 0.0625f;
@@ -133,10 +135,19 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
   // read straight from HBM into registers, one sample ahead.
   const int rt = w & 7, ua = w >> 3;
   const int a_line = (2 * rt + (n32 >> 4)) * 16 + (n32 & 15);
+  // (in waves with sw = 1 the two 8-byte halves of each 16-byte operand are loaded in swapped order)
+  // (a wave-uniform tile address plus a 32-bit lane offset, added at each load: the empty asm keeps the
+  // compiler from holding 64-bit lane addresses across the loop)
+  const int xa_byte = (h * 4096 + a_line * 16) * 2;
   auto load_xa = [&](int64_t t, half8* xa) {
-    const half8* g = reinterpret_cast<const half8*>(src + (t * F + ch) * 8192 + h * 4096 + a_line * 16);
-    xa[0] = g[0];
-    xa[1] = g[1];
+    int off = xa_byte;
+    asm volatile("" : "+v"(off));
+    const uint2* g = reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(src + (t * F + ch) * 8192) + off);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const uint2 lo = g[2 * ks + sw], hi = g[2 * ks + 1 - sw];
+      xa[ks] = __builtin_bit_cast(half8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+    }
   };
 
   float acc[SLOTS];
@@ -205,11 +216,12 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
       *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d, g);
     }
   };
-  // ---- C: axis a, column tiles (lines kappa_b = 2w + j, kappa_c = n32), row tiles u
+  // ---- C: axis a, column tiles (lines kappa_b, kappa_c = n32), row tiles u; kappa_b takes the bits
+  //      (j, w0, w2, w1, w3) of j and the wave index, so that its bit 3 is sw
   auto pass_c = [&]() {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int kb = 2 * w + j;
+      const int kb = j + 2 * (w & 1) + 4 * ((w >> 2) & 1) + 8 * sw + 16 * (w >> 3);
       half8 x[2];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMPC + kb * BLK + n32 * 16], 8 * ks, lc_x(kb, n32));
@@ -268,7 +280,7 @@ int fused16x3_cell(int cell) {
   const int w = tid >> 6, l = tid & 63, h = l >> 5, n32 = l & 31;
   const int r = slot % 8, u = (slot / 8) % 2, j = slot / 16;
   const int ka = 16 * u + 8 * (r / 4) + 4 * h + (r % 4);
-  const int kb = 2 * w + j;
+  const int kb = j + 2 * (w & 1) + 4 * ((w >> 2) & 1) + 8 * ((w >> 1) & 1) + 16 * (w >> 3);
   const int kc = n32;
   return (ka * 32 + kb) * 32 + kc;
 }
