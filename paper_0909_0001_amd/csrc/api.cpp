@@ -381,6 +381,9 @@ void plan_mixed_behind_front(ArrayPlan& ap, int kernel) {
   fs.kmap.assign((size_t)fs.M, 0);
   for (int c = 0; c < (int)fs.M; ++c)
     fs.kmap[(size_t)c] = kernel == 4 ? omni::fused16x3_cell(c) : omni::fused8844_cell(c);
+  // what `describe` reports for the matrix-core kernels (static LDS of the kernels)
+  fs.cpt = 32;
+  fs.lds = kernel == 4 ? 99840 : 50176;
   // bytes per time sample of the last (float16) front output; earlier front outputs are float32
   const int64_t per_t = (int64_t)ap.F * ms * rest_n * 4;
   ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kFrontBytes / per_t));
@@ -428,6 +431,7 @@ void plan_fused8x4_mixed(ArrayPlan& ap) {
   P.n_split = 2;
   P.cells_wg = 32768;
   ap.fs.cpt = 32;
+  ap.fs.lds = 114688;
   for (int h = 0; h < 2; ++h) {
     for (int idx = 0; idx < 32; ++idx) {
       for (int tid = 0; tid < 1024; ++tid) {
