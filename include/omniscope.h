@@ -88,7 +88,7 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 typedef struct {
   omni_dtype dtype;   /* sample format of the voltages                        */
   omni_form form;     /* arithmetic form of the forward transform             */
-  int32_t time_block; /* samples per float32 block before the float64 add; 0 = default (64, mixed 256) */
+  int32_t time_block; /* samples per float32 block before the float64 add; 0 = default (64, mixed 1024) */
   uint32_t flags;     /* OMNI_PLAN_* flags                                    */
 } omni_opts;
 

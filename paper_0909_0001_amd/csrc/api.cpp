@@ -27,7 +27,8 @@ hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, 
 hipError_t launch_fused8x4_fp32(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16, double* partial,
                                 int F, int n_slices, int time_block, hipStream_t st);
 hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps,
-                                 const float2* tw16, double* partial, int F, int n_slices, hipStream_t st);
+                                 const float2* tw16, double* partial, int F, int n_slices, int time_block,
+                                 hipStream_t st);
 hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* twm, int64_t tiles, int64_t outer,
                              int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st,
                              bool half16, float scale);
@@ -778,7 +779,7 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
     HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F,
-                                        (int)ns, st));
+                                        (int)ns, p->time_block, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 3) {
     int rc = launch_ct(ap, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
     if (rc) return rc;
@@ -1034,9 +1035,10 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   if (!p) return fail(OMNI_E_NOMEM, "host allocation failed");
   p->dtype = o.dtype;
   p->form = o.form;
-  // default float32 block: 64 samples; 256 in the mixed form, whose matrix-core kernels add each block into
-  // float64 partial sums in HBM (a float32 sum of 256 non-negative terms stays within 2^-16 relative)
-  p->time_block = o.time_block > 0 ? o.time_block : (o.form == OMNI_FORM_MIXED ? 256 : 64);
+  // default float32 block: 64 samples; 1024 in the mixed form, whose matrix-core kernels add each block into
+  // float64 partial sums in HBM (a float32 sum of 1024 non-negative terms stays within 2^-14 relative,
+  // far inside the form's 2e-3)
+  p->time_block = o.time_block > 0 ? o.time_block : (o.form == OMNI_FORM_MIXED ? 1024 : 64);
   p->host_only = (o.flags & OMNI_PLAN_HOST_ONLY) != 0;
   p->timing = (o.flags & OMNI_PLAN_TIMING) != 0 && !p->host_only;
   p->arrays.resize(arrays.size());

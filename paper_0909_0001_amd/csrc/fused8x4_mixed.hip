@@ -135,7 +135,7 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
                                                                 int64_t t_per_slice,
                                                                 const float2* __restrict__ tw16,
                                                                 double* __restrict__ partial, int F,
-                                                                int xcd_groups) {
+                                                                int xcd_groups, int time_block) {
   using namespace f8m;
   __shared__ _Float16 L2[2 * 8 * 8 * 8 * 8];
   __shared__ _Float16 L3[2 * 8 * 16 * 8 * 8];
@@ -190,7 +190,6 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
     const half8 a = raw.to_half(hh);
     floatx16 d = mfma(a, Wf_hi, zero);
     d = mfma(a, Wf_lo, d);
-    raw.load(src, (t_next * F + f) * 4096 + p1_off);
     // column: kappa_3 = col % 16 (re / im halves); keep kappa_3 = 2q + h.  rows: i1 = 4 tt + i, i2 = 4 hh + j
     const int comp = col >> 4, q = (col & 15) >> 1;
     if (keep) {
@@ -199,6 +198,10 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
         store4(&L2[l2_row(comp, i0w, q, 4 * tw + i) * 8 + 4 * hh], d[4 * i], d[4 * i + 1], d[4 * i + 2],
                d[4 * i + 3]);
     }
+    // the prefetch goes out after everything above, so that no wait for another memory access (a
+    // register reload, say) can stall on it before its data are needed
+    __builtin_amdgcn_sched_barrier(0);
+    raw.load(src, (t_next * F + f) * 4096 + p1_off);
   };
   // ---- P2: axis 2; lines (i0, q, i1) = (w / 2, 4 tt + r / 8, r % 8)
   auto pass2_mfma = [&]() {
@@ -255,6 +258,32 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
     pass2_store(pass2_mfma());
     __syncthreads();
   }
+  // float32 blocks of time_block samples are added into the float64 partial sums of this work-group
+  // (the first block stores; |X|^2 carried 8^-8 = 2^-24 from the four scaled stages)
+  double* const out = partial + ((int64_t)grp * 2 + h) * 32768;
+  bool flushed = false;
+  auto flush = [&]() {
+    // addresses formed here (the empty asm keeps them out of the time loop); loads in groups of 4
+    double* o = out + tid;
+    asm volatile("" : "+v"(o));
+    if (flushed) {
+#pragma unroll
+      for (int i0 = 0; i0 < CPL; i0 += 4) {
+        double prev[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) prev[k] = o[(i0 + k) * NT];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[(i0 + k) * NT] = prev[k] + (double)acc[i0 + k] * 16777216.0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) o[i * NT] = (double)acc[i] * 16777216.0;
+    }
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) acc[i] = 0.f;
+    flushed = true;
+  };
+  int blk = 0;
   for (int64_t t = t0; t < t1; ++t) {
     const bool more = t + 1 < t1;  // uniform
     {
@@ -277,22 +306,25 @@ __global__ __launch_bounds__(f8m::NT) void fused8x4_mixed_kernel(const void* __r
       pass4_square(1, 1, d3);
     }
     __syncthreads();
+    if (++blk == time_block) {
+      blk = 0;
+      flush();
+    }
   }
-  // |X|^2 carried 8^-8 = 2^-24 from the four scaled stages
-  double* out = partial + ((int64_t)grp * 2 + h) * 32768;
-#pragma unroll
-  for (int i = 0; i < CPL; ++i) out[i * NT + tid] = (double)acc[i] * 16777216.0;
+  if (blk > 0 || !flushed) flush();
 }
 
 hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tps, const float2* tw16,
-                                 double* partial, int F, int n_slices, hipStream_t st) {
+                                 double* partial, int F, int n_slices, int time_block, hipStream_t st) {
   const int groups = n_slices * F;
   const int xcd = (groups % 8 == 0) ? 1 : 0;
   const dim3 grid(groups * 2), block(f8m::NT);
   if (fmt == 1)
-    hipLaunchKernelGGL(fused8x4_mixed_kernel<1>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd);
+    hipLaunchKernelGGL(fused8x4_mixed_kernel<1>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd,
+                       time_block);
   else if (fmt == 2)
-    hipLaunchKernelGGL(fused8x4_mixed_kernel<2>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd);
+    hipLaunchKernelGGL(fused8x4_mixed_kernel<2>, grid, block, 0, st, src, T, tps, tw16, partial, F, xcd,
+                       time_block);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -242,14 +242,15 @@ def test_ci4_extremes():
 # ---------------------------------------------------------------------------
 
 
-@pytest.mark.parametrize("dtype", ["ci8", "ci4"])
-def test_mixed_hier8x8_small(dtype):
-    """8x8-of-8x8 geometry, few samples, ragged channel count, both integer formats."""
+@pytest.mark.parametrize("dtype,time_block", [("ci8", 0), ("ci4", 0), ("ci8", 4)])
+def test_mixed_hier8x8_small(dtype, time_block):
+    """8x8-of-8x8 geometry, few samples, ragged channel count, both integer formats; a short float32 block
+    makes the kernel add several blocks into its float64 partial sums."""
     w = skysim.WORKLOADS["hier8x8-mixed"]
     gen = torch.Generator().manual_seed(17)
     raw = random_raw(dtype, 75, 5, w.N, gen)
-    say("mixed hier8x8 T=75 F=5", dtype)
-    vis, plan = gpu_vis(w.level_dims, raw, dtype, "mixed")
+    say("mixed hier8x8 T=75 F=5", dtype, "time_block", time_block)
+    vis, plan = gpu_vis(w.level_dims, raw, dtype, "mixed", time_block=time_block)
     assert '"fused8x4_mixed"' in plan.describe()
     ref = oracle_vis(raw, dtype, w.level_dims)
     err = rel_err(vis, ref)
