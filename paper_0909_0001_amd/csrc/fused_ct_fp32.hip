@@ -282,8 +282,10 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
       }
     }
     __syncthreads();
-    // the tile has been consumed: fetch the next one behind the later passes
-    if (!INPLACE && t + 1 < t1) stage(t + 1);
+    // the tile has been consumed: fetch the next one behind the later passes.  Every barrier after the
+    // copy waits for it (the copy writes LDS), so it is issued ahead of the last pass that has no
+    // barrier before the end of the sample: right here for D <= 3, after the middle passes for D = 4.
+    if (!INPLACE && D <= 3 && t + 1 < t1) stage(t + 1);
     // ---- passes 1 .. D-2: axes D-1 ... 2, LDS -> LDS
     auto mid = [&](auto PC) {
       constexpr int P = decltype(PC)::value;
@@ -312,6 +314,7 @@ __global__ __launch_bounds__(NT) void fused_ct_fp32_kernel(const void* __restric
     if constexpr (D > 2) mid(std::integral_constant<int, 1>{});
     if (INPLACE && t + 1 < t1) stage(t + 1);  // pass 1 has read pass 0's output out of the tile's space
     if constexpr (D > 3) mid(std::integral_constant<int, 2>{});
+    if (!INPLACE && D > 3 && t + 1 < t1) stage(t + 1);
     // ---- last pass: axis 1, squared into the registers
     {
       constexpr int P = D - 1, K = KLAST;
