@@ -32,6 +32,8 @@ hipError_t launch_fused8x4_mixed(int fmt, const void* src, int64_t T, int64_t tp
 hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* twm, int64_t tiles, int64_t outer,
                              int n, int m, int r, int64_t inner, int64_t src_tile, int64_t dst_tile, hipStream_t st,
                              bool half16, float scale);
+hipError_t launch_front2_16x16(int fmt, const void* src, void* dst, const float2* tw32, int64_t tiles, int64_t rest,
+                               float scale, hipStream_t st);
 int fused_ct_lookup(int d, const int* n);
 void fused_ct_params(int idx, int* r, int* s0);
 hipError_t launch_fused_ct(int idx, int fmt, const void* src, int64_t T, int64_t tps, const float2* tw,
@@ -708,7 +710,17 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
       const void* cur = static_cast<const char*>(volt) + (size_t)(c0 * ap.F * ap.N) * sample_bytes(p->dtype);
       int fmt = fmt_of(p->dtype);
       int64_t outer = 1, inner = ap.N, tw_off = 0;
-      for (int k = 0; k < s; ++k) {
+      // the three-level mixed path: both 16 x 16 front passes in one kernel (8-bit or 4-bit samples, 16-byte
+      // aligned rows); else one pass per axis
+      int k0 = 0;
+      const int64_t rest = ap.N / 256;
+      if (ap.kernel == 5 && s == 2 && ap.n[0] == 16 && ap.n[1] == 16 && (fmt == 1 || fmt == 2) && rest % 32 == 0 &&
+          (reinterpret_cast<uintptr_t>(cur) & 15) == 0 && ((rest * (fmt == 1 ? 2 : 1)) & 15) == 0) {
+        HIP_TRY(omni::launch_front2_16x16(fmt, cur, ap.d_y[1], ap.d_tw32, tc * ap.F, rest, 1.f / 16.f, st));
+        k0 = 2;
+        cur = ap.d_y[1];
+      }
+      for (int k = k0; k < s; ++k) {
         const int nk = ap.n[k], mk = 2 * nk;
         inner /= nk;
         float2* dst = ap.d_y[k & 1];

@@ -198,6 +198,111 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
   }
 }
 
+// Both front passes of a 16 x 16 outer level in one kernel, float16 planar
+// output (for the three-level matrix-core kernel).  Work-group = (tile, block
+// of RB = 32 consecutive rest indices), 256 threads: the 16 x 16 x RB raw
+// samples are copied to LDS (one row of RB samples per thread); then for each
+// half h of kappa_0 (kappa_0 = 2q + h): axis 0 (z_j = x_j w_32^{h j}, 16-point
+// DFT, scaled by 1/16) into an LDS block of float16 [q][i1][r], then axis 1
+// (the two residues of kappa_1 from the same 16 inputs, scaled by 1/16)
+// straight to HBM.  The output is the one the two separate passes write,
+// without their float16 intermediate in HBM: for (tile, kappa_0, kappa_1) the
+// rest-many real parts, then the imaginary parts.
+template <int FMT>
+__global__ __launch_bounds__(256, 4) void front2_16x16_kernel(const void* __restrict__ src, _Float16* __restrict__ dst,
+                                                               const float2* __restrict__ tw32, int64_t rest,
+                                                               float scale) {
+  using namespace fr;
+  constexpr int RB = 32, SB = FMT == 1 ? 2 : 1;  // rest block; bytes per sample
+  constexpr int ROW = RB * SB;                     // bytes of one (i0, i1) row in LDS
+  __shared__ __attribute__((aligned(16))) uint8_t raw[256 * ROW];
+  __shared__ __attribute__((aligned(16))) _Float16 mid[2][16 * 16 * RB];  // [re | im][q][i1][r]
+  const int tid = threadIdx.x;
+  const int64_t nrb = rest / RB;
+  const int64_t tile = blockIdx.x / nrb;
+  const int64_t rb = blockIdx.x - tile * nrb;
+  {
+    const uint4* g = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(src) +
+                                                    ((tile * 256 + tid) * rest + rb * RB) * SB);
+    uint4* l = reinterpret_cast<uint4*>(raw + tid * ROW);
+#pragma unroll
+    for (int k = 0; k < ROW / 16; ++k) l[k] = g[k];
+  }
+  __syncthreads();
+  auto sample = [&](int row, int r) -> float2 {
+    if constexpr (FMT == 1) {
+      const int8_t* b = reinterpret_cast<const int8_t*>(raw + row * ROW + 2 * r);
+      return make_float2((float)b[0], (float)b[1]);
+    } else {
+      const int8_t b = (int8_t)raw[row * ROW + r];
+      return make_float2((float)(b >> 4), (float)((int8_t)(b << 4) >> 4));
+    }
+  };
+  _Float16* const out_tile = dst + tile * (32 * 32 * 2 * rest) + rb * RB;
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    // ---- axis 0 for kappa_0 = 2q + h: jobs (i1, r), r fastest
+#pragma unroll 1
+    for (int jj = 0; jj < 2; ++jj) {
+      const int job = jj * 256 + tid, i1 = job / RB, r = job % RB;
+      float2 z[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const float2 x = sample(j * 16 + i1, r);
+        z[j] = (h && j) ? cmul(x, tw32[j]) : x;
+      }
+      sd::dft<16>(z);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        mid[0][(q * 16 + i1) * RB + r] = (_Float16)(z[q].x * 0.0625f);
+        mid[1][(q * 16 + i1) * RB + r] = (_Float16)(z[q].y * 0.0625f);
+      }
+    }
+    __syncthreads();
+    // ---- axis 1 on (q, r): both residues of kappa_1 from the same 16 inputs (read twice), r fastest
+#pragma unroll 1
+    for (int jj = 0; jj < 2; ++jj) {
+      const int job = jj * 256 + tid, q = job / RB, r = job % RB;
+      _Float16* const o = out_tile + (int64_t)(2 * q + h) * 32 * 2 * rest + r;  // (kappa_0, kappa_1 = 0)
+#pragma unroll 1
+      for (int res = 0; res < 2; ++res) {
+        float2 z[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const float2 y = make_float2((float)mid[0][(q * 16 + j) * RB + r], (float)mid[1][(q * 16 + j) * RB + r]);
+          z[j] = (res && j) ? cmul(y, tw32[j]) : y;
+        }
+        sd::dft<16>(z);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {  // kappa_1 = 2k + res
+          o[(2 * k + res) * 2 * rest] = (_Float16)(z[k].x * scale);
+          o[(2 * k + res) * 2 * rest + rest] = (_Float16)(z[k].y * scale);
+        }
+      }
+    }
+    __syncthreads();  // the next half overwrites mid
+  }
+}
+
+// Both front passes of a 16 x 16 outer level (fmt 1 ci8 or 2 ci4) into float16 planar blocks, each pass
+// scaled by 1/16 (the second by `scale`); tw32: w_32^q.  rest % 32 == 0, 16-byte aligned rows.
+hipError_t launch_front2_16x16(int fmt, const void* src, void* dst, const float2* tw32, int64_t tiles, int64_t rest,
+                               float scale, hipStream_t st) {
+  const int sb = fmt == 1 ? 2 : 1;
+  if ((fmt != 1 && fmt != 2) || rest % 32 != 0 || (reinterpret_cast<uintptr_t>(src) & 15) != 0 ||
+      ((rest * sb) & 15) != 0)
+    return hipErrorInvalidValue;
+  const int64_t blocks = tiles * (rest / 32);
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  if (fmt == 1)
+    hipLaunchKernelGGL(front2_16x16_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, src,
+                       static_cast<_Float16*>(dst), tw32, rest, scale);
+  else
+    hipLaunchKernelGGL(front2_16x16_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, src,
+                       static_cast<_Float16*>(dst), tw32, rest, scale);
+  return hipGetLastError();
+}
+
 // fmt: 0 float32 complex, 1 ci8, 2 ci4, 3 float16 planar blocks (the H16 output of a front pass).
 // half16: float16 planar output scaled by `scale` (see H16 above); else float32 complex.
 hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* twm, int64_t tiles, int64_t outer,
