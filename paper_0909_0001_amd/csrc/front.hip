@@ -219,8 +219,12 @@ __global__ __launch_bounds__(256, 4) void front2_16x16_kernel(const void* __rest
   __shared__ __attribute__((aligned(16))) _Float16 mid[2][16 * 16 * RB];  // [re | im][q][i1][r]
   const int tid = threadIdx.x;
   const int64_t nrb = rest / RB;
-  const int64_t tile = blockIdx.x / nrb;
-  const int64_t rb = blockIdx.x - tile * nrb;
+  // consecutive work-groups go to the 8 XCDs in turn; remap so that the blocks of one XCD take consecutive
+  // rest blocks, which share 128-byte lines of the raw rows (in that XCD's L2)
+  int64_t b = blockIdx.x;
+  if ((gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
+  const int64_t tile = b / nrb;
+  const int64_t rb = b - tile * nrb;
   {
     const uint4* g = reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(src) +
                                                     ((tile * 256 + tid) * rest + rb * RB) * SB);
