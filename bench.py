@@ -38,6 +38,7 @@ METRIC = "antenna-samples/s correlated (N·T·F/s) vs FP32 FFT form, at stated r
 # dense fp16 MFMA 2.5 PFLOP/s, HBM 8 TB/s.
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP16_MFMA_TFLOPS = 2500.0
+PEAK_INT8_MFMA_TOPS = 5000.0  # dense int8 matrix-core peak (no sparsity)
 
 
 def log(*a):
@@ -151,6 +152,27 @@ def run_form(omni, w, raw, form, steps, warmup):
         stages[k] = sum(v) / len(v)
     log(f"bench[{form}]: {ms:.3f} ms/step (wall {wall:.3f}); " + ", ".join(f"{k} {v:.3f} ms" for k, v in stages.items()))
     return {"ms": ms, "stages": stages, "kernel": desc["arrays"][0]["kernel"] + "_kernel", "vis": vis, "plan": plan}
+
+
+def run_direct(omni, w, raw, steps, warmup):
+    """Time `steps` calls of the GPU direct N^2 correlator (the comparison baseline) on the same input."""
+    import torch
+
+    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, "fp32")
+    vis = torch.empty(plan.vis_shape(), dtype=torch.complex64, device=raw.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, warmup)):
+        plan.direct_correlate(raw, out=vis, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.direct_correlate(raw, out=vis, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    log(f"bench[direct]: {ms:.3f} ms/step")
+    return {"ms": ms, "vis": vis, "plan": plan}
 
 
 BATCH4 = ["grid32", "grid64", "grid128", "hier16x16"]
@@ -291,6 +313,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-other-form", action="store_true", help="time only the main form")
+    ap.add_argument("--direct", action="store_true", help="also time the direct N^2 correlator at any N")
+    ap.add_argument("--no-direct", action="store_true", help="never time the direct N^2 correlator")
     ap.add_argument("--copy-calibration", action="store_true", help="only run 3 x 1 GiB device copies")
     args = ap.parse_args()
 
@@ -326,6 +350,9 @@ def main() -> int:
     alt = None
     if not args.no_other_form and not (other == "mixed" and w.dtype == "cf32"):
         alt = run_form(omni, w, raw, other, args.steps, args.warmup)
+    direct = None
+    if w.dtype != "cf32" and not args.no_direct and (args.direct or w.N <= 16384):
+        direct = run_direct(omni, w, raw, args.steps, args.warmup)
     work = w.antenna_samples()
     ms_per_step = main_res["ms"]
     value = work / (ms_per_step / 1e3)
@@ -334,7 +361,7 @@ def main() -> int:
     err = {}
     if w.dtype != "ci4":
         power = (raw.to(torch.float64) ** 2).sum(dim=(0, 2, 3))
-        for tag, res in ((form, main_res), (other, alt)):
+        for tag, res in ((form, main_res), (other, alt), ("direct", direct)):
             if res is None:
                 continue
             vh = res["vis"].reshape(w.nchan, -1)
@@ -345,7 +372,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         raw_cpu = raw.cpu()
         rate, nch, secs, ref = cpu_oracle_baseline(raw_cpu, w, budget_s=args.cpu_budget)
-        for tag, res in ((form, main_res), (other, alt)):
+        for tag, res in ((form, main_res), (other, alt), ("direct", direct)):
             if res is None:
                 continue
             got = res["vis"].cpu().numpy().reshape(w.nchan, -1)
@@ -398,6 +425,19 @@ def main() -> int:
             "stage_ms": alt["stages"],
             "roofline": roofline_of(w, alt, work),
             "speedup_vs_main_form": main_res["ms"] / alt["ms"],
+        }
+    if direct is not None:
+        # int8 products of the pairs a <= b: 4 real products (2 ops each) per pair, sample and channel
+        ops = 4.0 * w.N * (w.N + 1) * w.T * w.nchan
+        tops = ops / (direct["ms"] / 1e3) / 1e12
+        out["direct_n2"] = {
+            "config": f"{w.name}, same input bytes, GPU direct N^2 correlator (int8 matrix cores, exact sums)",
+            "value": work / (direct["ms"] / 1e3),
+            "ms_per_step": direct["ms"],
+            "int8_tops": round(tops, 2),
+            "frac_of_int8_peak": round(tops / PEAK_INT8_MFMA_TOPS, 4),
+            "speedup_of_main_form": direct["ms"] / main_res["ms"],
+            "speedup_of_other_form": direct["ms"] / alt["ms"] if alt is not None else None,
         }
     print(json.dumps(out), flush=True)
     return 0

@@ -149,6 +149,29 @@ int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, voi
 int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, void* const* vis, void* stream,
                          uint32_t flags);
 
+/* Direct N^2 correlator on the GPU, the comparison baseline for the FFT forms
+ * (the generic correlator whose cost grows as the number of antenna pairs,
+ * Sec. I): every pair's product x_a conj(x_b) summed over the T samples and
+ * binned by index difference Delta = idx(a) - idx(b), i.e. the visibility
+ * hypercube of Sec. II.D, Eq. ProofEq2, by its definition.  Same input and
+ * output layout as omni_correlate (complex64 [F][2n_1-1]...[2n_d-1], centred).
+ * Integer samples only (plan dtype OMNI_CI8 or OMNI_CI4); int8 matrix-core
+ * products with int32 sums over at most 32768 samples per launch and int64
+ * sums after that, so the result is exact up to its final rounding to float32.
+ * Requires a single-array plan with N a multiple of 128, fewer than 2^24 pairs
+ * of blocks of 128 consecutive antennas, and at most 2048 index differences
+ * per block pair (prod_k (2 e_k + 1) <= 2048, e_k the largest extent of a block
+ * along axis k: 465 for a 16 x 16 grid, 675 for 8x8 tiles of 8x8).  The first
+ * call allocates the plan's direct-correlator buffers (F x cells x 16 bytes of
+ * int64 sums, the block-pair list); the call does not touch the plan's FFT
+ * accumulator.  Asynchronous on `stream`, like omni_correlate.
+ *   volt : device [T][F][N] samples, 8-byte (ci8) / 4-byte (ci4) aligned; may be NULL iff T == 0.
+ *   vis  : device complex64 visibilities (written, never read).
+ * Errors: OMNI_E_INVAL (bad pointer, alignment or T), OMNI_E_STATE (host-only
+ * or batch plan, float samples), OMNI_E_SHAPE (N or block boxes outside the
+ * limits above), OMNI_E_NOMEM, OMNI_E_HIP. */
+int omni_direct_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream);
+
 /* Number of arrays in the plan (1 for omni_plan). */
 int omni_n_arrays(omni_plan_t plan, int32_t* n);
 

@@ -45,6 +45,7 @@ EXPORTS = [
     "omni_plan_batch",
     "omni_correlate",
     "omni_correlate_batch",
+    "omni_direct_correlate",
     "omni_n_arrays",
     "omni_vis_shape",
     "omni_baselines",
@@ -103,6 +104,7 @@ def _load():
         "omni_plan_batch": (ctypes.c_int, [ctypes.POINTER(P), i32, ctypes.POINTER(_ArrayDesc), ctypes.POINTER(_Opts)]),
         "omni_correlate": (ctypes.c_int, [P, P, i64, P, P, u32]),
         "omni_correlate_batch": (ctypes.c_int, [P, ctypes.POINTER(P), i64, ctypes.POINTER(P), P, u32]),
+        "omni_direct_correlate": (ctypes.c_int, [P, P, i64, P, P]),
         "omni_n_arrays": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
         "omni_vis_shape": (ctypes.c_int, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
         "omni_baselines": (ctypes.c_int, [P, i32, ctypes.POINTER(ctypes.c_double)]),
@@ -247,6 +249,19 @@ class Plan:
             dev = volt.device if volt is not None else torch.device("cuda")
             out = torch.empty(self.vis_shape(0), dtype=torch.complex64, device=dev)
         self.correlate_into(volt if volt is not None else 0, T, out if out is not None else 0, stream, flags)
+        return out
+
+    def direct_correlate(self, volt, out=None, stream=None):
+        """Direct N^2 correlator (comparison baseline, integer samples): device [T, F, N(, 2)] -> complex64
+        visibilities [F, 2n_1-1, ...], exact up to the final rounding to float32."""
+        import torch
+
+        if not volt.is_cuda or not volt.is_contiguous():
+            raise ValueError("voltages must be a contiguous device tensor")
+        if out is None:
+            out = torch.empty(self.vis_shape(0), dtype=torch.complex64, device=volt.device)
+        _check(lib.omni_direct_correlate(self._h, volt.data_ptr(), int(volt.shape[0]), out.data_ptr(),
+                                         _stream_handle(stream)))
         return out
 
     def correlate_batch(self, volts, flags: int = 0, outs=None, stream=None):

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "direct.hpp"
 #include "plan.hpp"
 
 namespace omni {
@@ -113,6 +114,12 @@ struct ArrayPlan {
   double* d_partial = nullptr;
   float2* d_ws[2] = {nullptr, nullptr};  // inverse-transform intermediates (complex float32)
   float2* d_y[2] = {nullptr, nullptr};
+  // direct N^2 correlator (set up by its first call): per-channel int64 half-sums, block pairs, block boxes
+  unsigned long long* d_dc_G = nullptr;
+  int32_t* d_dc_pairs = nullptr;
+  int32_t* d_dc_blk = nullptr;
+  int64_t dc_pairs = 0;
+  omni::DirectGeom dc_geom;
 };
 
 }  // namespace
@@ -583,6 +590,11 @@ void free_array(ArrayPlan& ap) {
   hipFree(ap.d_ws[1]);
   hipFree(ap.d_y[0]);
   hipFree(ap.d_y[1]);
+  hipFree(ap.d_dc_G);
+  hipFree(ap.d_dc_pairs);
+  hipFree(ap.d_dc_blk);
+  ap.d_dc_G = nullptr;
+  ap.d_dc_pairs = ap.d_dc_blk = nullptr;
   ap.d_tw32 = nullptr;
   ap.d_tw64 = nullptr;
   ap.d_kmap = nullptr;
@@ -1101,6 +1113,68 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   return OMNI_OK;
 }
 
+// Direct correlator set-up: blocks of 128 consecutive antennas, the coordinate box of each block, the block
+// pairs I <= J, and the int64 half-sum buffer.  Every pair's Delta box must fit the kernel's LDS bins; the
+// bound used is prod_k (2 max_B ext_k(B) + 1) over the blocks' per-axis extents.
+int direct_setup(ArrayPlan& ap) {
+  using omni::kDirectMaxD;
+  using omni::kDirectTile;
+  const int d = (int)ap.dims.size();
+  if (d < 1 || d > kDirectMaxD) return fail(OMNI_E_SHAPE, "direct correlator: 1 to 8 axes");
+  if (ap.N % kDirectTile != 0) return fail(OMNI_E_SHAPE, "direct correlator: N must be a multiple of 128");
+  const int64_t nbk = ap.N / kDirectTile;
+  const int64_t n_pairs = nbk * (nbk + 1) / 2;
+  // one work-group of 256 threads per block pair: the grid's x extent in threads must stay below 2^32
+  if (n_pairs >= (int64_t(1) << 24)) return fail(OMNI_E_SHAPE, "direct correlator: N too large (2^24 block pairs or more)");
+  omni::DirectGeom g;
+  g.d = d;
+  int64_t n_out = 1;
+  for (int k = d - 1; k >= 0; --k) {
+    g.n[k] = ap.dims[(size_t)k];
+    g.gstride[k] = n_out;
+    n_out *= 2 * (int64_t)ap.dims[(size_t)k] - 1;
+  }
+  g.n_out = n_out;
+  std::vector<int32_t> blk((size_t)(nbk * kDirectMaxD * 2), 0);
+  std::vector<int> ext((size_t)d, 0);
+  std::vector<int> c((size_t)d, 0);
+  for (int64_t B = 0; B < nbk; ++B) {
+    int32_t* b = &blk[(size_t)(B * kDirectMaxD * 2)];
+    for (int64_t r = 0; r < kDirectTile; ++r) {
+      int64_t a = B * kDirectTile + r;
+      for (int k = d - 1; k >= 0; --k) {
+        c[(size_t)k] = (int)(a % ap.dims[(size_t)k]);
+        a /= ap.dims[(size_t)k];
+      }
+      for (int k = 0; k < d; ++k) {
+        if (r == 0 || c[(size_t)k] < b[2 * k]) b[2 * k] = c[(size_t)k];
+        if (r == 0 || c[(size_t)k] > b[2 * k + 1]) b[2 * k + 1] = c[(size_t)k];
+      }
+    }
+    for (int k = 0; k < d; ++k) ext[(size_t)k] = std::max(ext[(size_t)k], b[2 * k + 1] - b[2 * k]);
+  }
+  int64_t box = 1;
+  for (int k = 0; k < d; ++k) box *= 2 * (int64_t)ext[(size_t)k] + 1;
+  if (box > omni::kDirectMaxBins)
+    return fail(OMNI_E_SHAPE, "direct correlator: a block pair spans " + std::to_string(box) +
+                                  " index differences (at most " + std::to_string(omni::kDirectMaxBins) + ")");
+  std::vector<int32_t> pairs((size_t)(2 * n_pairs));
+  size_t q = 0;
+  for (int64_t I = 0; I < nbk; ++I)
+    for (int64_t J = I; J < nbk; ++J) {
+      pairs[q++] = (int32_t)I;
+      pairs[q++] = (int32_t)J;
+    }
+  HIP_TRY(hipMalloc(&ap.d_dc_blk, blk.size() * sizeof(int32_t)));
+  HIP_TRY(hipMalloc(&ap.d_dc_pairs, pairs.size() * sizeof(int32_t)));
+  HIP_TRY(hipMalloc(&ap.d_dc_G, (size_t)ap.F * (size_t)n_out * 2 * sizeof(unsigned long long)));
+  HIP_TRY(hipMemcpy(ap.d_dc_blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ap.d_dc_pairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  ap.dc_pairs = n_pairs;
+  ap.dc_geom = g;
+  return OMNI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1181,6 +1255,43 @@ int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, voi
   const void* v[1] = {volt};
   void* o[1] = {vis};
   return omni_correlate_batch(plan, v, T, o, stream, flags);
+}
+
+int omni_direct_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream) {
+  try {
+    if (!plan) return fail(OMNI_E_INVAL, "plan is NULL");
+    if (plan->host_only) return fail(OMNI_E_STATE, "plan was made with OMNI_PLAN_HOST_ONLY");
+    if (plan->arrays.size() != 1) return fail(OMNI_E_STATE, "direct correlator: single-array plans only");
+    if (plan->dtype != OMNI_CI8 && plan->dtype != OMNI_CI4)
+      return fail(OMNI_E_STATE, "direct correlator: integer samples (ci8, ci4) only");
+    if (T < 0) return fail(OMNI_E_INVAL, "T < 0");
+    if (T > 0 && !volt) return fail(OMNI_E_INVAL, "volt is NULL");
+    if (!vis) return fail(OMNI_E_INVAL, "vis is NULL");
+    const int sb = plan->dtype == OMNI_CI8 ? 2 : 1;
+    if (T > 0 && (reinterpret_cast<uintptr_t>(volt) & (uintptr_t)(4 * sb - 1)))
+      return fail(OMNI_E_INVAL, sb == 2 ? "voltage pointer not 8-byte aligned" : "voltage pointer not 4-byte aligned");
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (cur != plan->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
+    ArrayPlan& ap = plan->arrays[0];
+    if (!ap.d_dc_G) {
+      const int rc = direct_setup(ap);
+      if (rc) return rc;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const omni::DirectGeom& g = ap.dc_geom;
+    HIP_TRY(omni::launch_direct_zero(ap.d_dc_G, (int64_t)ap.F * g.n_out * 2, st));
+    const int64_t tstride = (int64_t)ap.F * ap.N * sb;  // bytes per time sample
+    for (int64_t t0 = 0; t0 < T; t0 += omni::kDirectMaxT) {
+      const int64_t tc = std::min<int64_t>(omni::kDirectMaxT, T - t0);
+      HIP_TRY(omni::launch_direct_tiles((int)plan->dtype, static_cast<const uint8_t*>(volt) + t0 * tstride, tc, ap.N,
+                                        ap.F, ap.d_dc_pairs, ap.dc_pairs, ap.d_dc_blk, g, ap.d_dc_G, st));
+    }
+    HIP_TRY(omni::launch_direct_finalize(ap.d_dc_G, vis, g.n_out, ap.F, st));
+    return OMNI_OK;
+  } catch (...) {
+    return fail(OMNI_E_NOMEM, "unexpected host exception");
+  }
 }
 
 int omni_n_arrays(omni_plan_t plan, int32_t* n) {

@@ -1,0 +1,272 @@
+// Direct N^2 correlator: the pairwise product x_a conj(x_b) of every antenna
+// pair, summed over time and binned by index difference Delta = idx(a) - idx(b)
+// (the definition of the visibility hypercube, Sec. II.D, Eq. ProofEq2, and the
+// generic correlator whose N^2 cost the paper's method replaces, Sec. I).  It
+// is the comparison baseline for the FFT forms on the same device; its result
+// is exact (integer products and sums) until the final conversion to float.
+//
+// Integer samples only (ci8, ci4).  Per channel, C = sum_t x_t x_t^H is a
+// Hermitian N x N product with the time samples as the contracted axis; with
+// real and imaginary parts as separate int8 planes,
+//     Re C = Xr Xr^T + Xi Xi^T,   Im C = Xi Xr^T - Xr Xi^T,
+// four int8 matrix-core products (v_mfma_i32_32x32x32_i8, int32 sums), the
+// imaginary part's two terms in separate accumulators so that no int8 operand
+// is negated (-128 has no int8 negation).
+//
+// Work-group = (block pair I <= J of 128 consecutive antennas, channel).  Each
+// step stages 32 time samples of both blocks in LDS, transposed to one row of
+// 32 bytes (padded to 48: conflict-free 16-byte row reads) per antenna and
+// plane.  After the last step every pair (a in I, b in J, a <= b) adds its
+// sums into LDS bins covering the box of Delta values the two blocks can form
+// (64-bit integer LDS atomics), and the box is added into the channel's int64
+// half-sum G (global 64-bit atomics, one per nonzero bin).  Pairs a > b are
+// the conjugates of pairs a < b at -Delta, so the finalize step forms
+//     V[Delta] = G[Delta] + conj G[-Delta]  (Delta != 0),   V[0] = G[0].
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "direct.hpp"
+
+namespace omni {
+namespace dc {
+
+constexpr int NT = 256;     // 4 waves, each a 64 x 64 quarter of the 128 x 128 pair tile
+constexpr int KS = 32;      // time samples per step (the MFMA's contracted length)
+constexpr int RS = 48;      // LDS bytes per antenna row of one plane
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ v16i mfma(v4i a, v4i b, v16i c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// 4 consecutive antennas of one sample -> their real and imaginary int8 parts, antenna j in byte j.
+template <int FMT>
+__device__ __forceinline__ void load4(const uint8_t* p, uint32_t& re, uint32_t& im) {
+  if constexpr (FMT == 1) {  // ci8: (re, im) byte pairs
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    re = (u.x & 0xffu) | ((u.x >> 8) & 0xff00u) | ((u.y << 16) & 0xff0000u) | ((u.y << 8) & 0xff000000u);
+    im = ((u.x >> 8) & 0xffu) | ((u.x >> 16) & 0xff00u) | ((u.y << 8) & 0xff0000u) | (u.y & 0xff000000u);
+  } else {  // ci4: one byte, re = high nibble, im = low nibble, two's complement
+    const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
+    re = 0;
+    im = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int b = (int)(int8_t)(u >> (8 * j));
+      re |= (uint32_t)((b >> 4) & 0xff) << (8 * j);
+      im |= (uint32_t)(((int)(int8_t)(b << 4) >> 4) & 0xff) << (8 * j);
+    }
+  }
+}
+
+// byte j of w[s] -> byte s of the result (4 x 4 byte transpose, one output column)
+__device__ __forceinline__ uint32_t column(const uint32_t (&w)[4], int j) {
+  return ((w[0] >> (8 * j)) & 0xffu) | (((w[1] >> (8 * j)) & 0xffu) << 8) | (((w[2] >> (8 * j)) & 0xffu) << 16) |
+         (((w[3] >> (8 * j)) & 0xffu) << 24);
+}
+
+template <int FMT>
+__global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restrict__ src, int64_t T, int64_t N,
+                                                        int F, const int32_t* __restrict__ pairs,
+                                                        const int32_t* __restrict__ blk, DirectGeom g,
+                                                        unsigned long long* __restrict__ G) {
+  constexpr int SB = FMT == 1 ? 2 : 1;  // bytes per sample
+  __shared__ __attribute__((aligned(16))) uint8_t pl[4][kDirectTile * RS];  // Ar, Ai, Br, Bi
+  __shared__ unsigned long long bins[kDirectMaxBins][2];
+  __shared__ int alpha[kDirectTile], beta[kDirectTile];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int f = blockIdx.y;
+  const int I = pairs[2 * blockIdx.x], J = pairs[2 * blockIdx.x + 1];
+  const int64_t aI = (int64_t)I * kDirectTile, aJ = (int64_t)J * kDirectTile;
+
+  // ---- the Delta box of this block pair: Delta_k = c_k(a) - c_k(b) in [minI - maxJ, maxI - minJ]
+  int size[kDirectMaxD], stride[kDirectMaxD];
+  int nb = 1;
+  for (int k = g.d - 1; k >= 0; --k) {
+    const int* bi = blk + ((int64_t)I * kDirectMaxD + k) * 2;
+    const int* bj = blk + ((int64_t)J * kDirectMaxD + k) * 2;
+    size[k] = (bi[1] - bi[0]) + (bj[1] - bj[0]) + 1;
+    stride[k] = nb;
+    nb *= size[k];
+  }
+  if (nb > kDirectMaxBins) return;  // the planner never launches such a pair
+  // bin(a, b) = alpha[a - aI] + beta[b - aJ], alpha = sum_k (c_k(a) - minI_k) stride_k,
+  // beta = sum_k (maxJ_k - c_k(b)) stride_k
+  {
+    const bool isA = tid < kDirectTile;
+    const int r = isA ? tid : tid - kDirectTile;
+    int64_t a = (isA ? aI : aJ) + r;
+    const int B = isA ? I : J;
+    int acc = 0;
+    for (int k = g.d - 1; k >= 0; --k) {
+      const int c = (int)(a % g.n[k]);
+      a /= g.n[k];
+      const int* bb = blk + ((int64_t)B * kDirectMaxD + k) * 2;
+      acc += (isA ? c - bb[0] : bb[1] - c) * stride[k];
+    }
+    (isA ? alpha : beta)[r] = acc;
+  }
+  for (int q = tid; q < nb; q += NT) bins[q][0] = bins[q][1] = 0ull;
+
+  // ---- staging item: samples 4 tg .. 4 tg + 3 of the step, antennas 4 ag .. 4 ag + 3 of each block
+  const int tg = tid >> 5, ag = tid & 31;
+  const int64_t row_stride = (int64_t)F * N;  // samples between consecutive times
+  const uint8_t* const pA = src + ((int64_t)f * N + aI + 4 * ag) * SB;
+  const uint8_t* const pB = src + ((int64_t)f * N + aJ + 4 * ag) * SB;
+  uint32_t ar[4], ai[4], br[4], bi[4];
+  auto load = [&](int64_t t0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t t = t0 + 4 * tg + s;
+      if (t < T) {
+        load4<FMT>(pA + t * row_stride * SB, ar[s], ai[s]);
+        load4<FMT>(pB + t * row_stride * SB, br[s], bi[s]);
+      } else {
+        ar[s] = ai[s] = br[s] = bi[s] = 0u;
+      }
+    }
+  };
+
+  v16i cre[2][2], cip[2][2], cin[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cre[i][j][r] = cip[i][j][r] = cin[i][j][r] = 0;
+
+  const int mw = (w >> 1) * 64, nw = (w & 1) * 64;
+  const int orow = lane & 31, ok = 16 * (lane >> 5);
+  load(0);
+  for (int64_t t0 = 0; t0 < T; t0 += KS) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = (4 * ag + j) * RS + 4 * tg;
+      *reinterpret_cast<uint32_t*>(&pl[0][o]) = column(ar, j);
+      *reinterpret_cast<uint32_t*>(&pl[1][o]) = column(ai, j);
+      *reinterpret_cast<uint32_t*>(&pl[2][o]) = column(br, j);
+      *reinterpret_cast<uint32_t*>(&pl[3][o]) = column(bi, j);
+    }
+    __syncthreads();
+    if (t0 + KS < T) load(t0 + KS);
+    v4i xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int oa = (mw + 32 * i + orow) * RS + ok, ob = (nw + 32 * i + orow) * RS + ok;
+      xr[i] = *reinterpret_cast<const v4i*>(&pl[0][oa]);
+      xi[i] = *reinterpret_cast<const v4i*>(&pl[1][oa]);
+      yr[i] = *reinterpret_cast<const v4i*>(&pl[2][ob]);
+      yi[i] = *reinterpret_cast<const v4i*>(&pl[3][ob]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cre[i][j] = mfma(xr[i], yr[j], cre[i][j]);
+        cre[i][j] = mfma(xi[i], yi[j], cre[i][j]);
+        cip[i][j] = mfma(xi[i], yr[j], cip[i][j]);
+        cin[i][j] = mfma(xr[i], yi[j], cin[i][j]);
+      }
+    __syncthreads();
+  }
+
+  // ---- bin: accumulator r of lane l holds pair (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = nw + 32 * j + (lane & 31);
+      const int bn = beta[n];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = mw + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (I == J && m > n) continue;  // a > b: the conjugate of (b, a)
+        const int q = alpha[m] + bn;
+        const long long re = (long long)cre[i][j][r];
+        const long long im = (long long)cip[i][j][r] - (long long)cin[i][j][r];
+        if (re) atomicAdd(&bins[q][0], (unsigned long long)re);
+        if (im) atomicAdd(&bins[q][1], (unsigned long long)im);
+      }
+    }
+  __syncthreads();
+
+  // ---- box -> the channel's half-sum G (centred layout of the visibility hypercube)
+  unsigned long long* const Gf = G + (int64_t)f * g.n_out * 2;
+  for (int q = tid; q < nb; q += NT) {
+    const unsigned long long re = bins[q][0], im = bins[q][1];
+    if (!re && !im) continue;
+    int rem = q;
+    int64_t gi = 0;
+    for (int k = g.d - 1; k >= 0; --k) {
+      const int c = rem % size[k];
+      rem /= size[k];
+      const int* bi = blk + ((int64_t)I * kDirectMaxD + k) * 2;
+      const int* bj = blk + ((int64_t)J * kDirectMaxD + k) * 2;
+      const int delta = bi[0] - bj[1] + c;
+      gi += (int64_t)(delta + g.n[k] - 1) * g.gstride[k];
+    }
+    if (re) atomicAdd(&Gf[2 * gi], re);
+    if (im) atomicAdd(&Gf[2 * gi + 1], im);
+  }
+}
+
+// V[Delta] = G[Delta] + conj G[-Delta] (Delta != 0), V[0] = G[0]; the centred layout is symmetric, so
+// -Delta is the mirrored linear index.
+__global__ void direct_finalize_kernel(const long long* __restrict__ G, float2* __restrict__ vis, int64_t n_out,
+                                       int64_t total) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = i / n_out, k = i - f * n_out, km = n_out - 1 - k;
+    const long long* gf = G + f * n_out * 2;
+    long long re = gf[2 * k], im = gf[2 * k + 1];
+    if (km != k) {
+      re += gf[2 * km];
+      im -= gf[2 * km + 1];
+    }
+    vis[i] = make_float2((float)re, (float)im);
+  }
+}
+
+__global__ void direct_zero_kernel(unsigned long long* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+}  // namespace dc
+
+hipError_t launch_direct_zero(unsigned long long* G, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  dc::direct_zero_kernel<<<(unsigned)blocks, 256, 0, st>>>(G, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_tiles(int fmt, const void* src, int64_t T, int64_t N, int F, const int32_t* pairs,
+                               int64_t n_pairs, const int32_t* blk, const DirectGeom& g, unsigned long long* G,
+                               hipStream_t st) {
+  if (T <= 0) return hipSuccess;
+  if (T > kDirectMaxT || N % kDirectTile != 0 || n_pairs <= 0 || n_pairs * dc::NT >= (int64_t(1) << 32) || F <= 0 || F > 65535 ||
+      g.d < 1 || g.d > kDirectMaxD)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)n_pairs, (unsigned)F);
+  if (fmt == 1)
+    dc::direct_tile_kernel<1><<<grid, dc::NT, 0, st>>>(static_cast<const uint8_t*>(src), T, N, F, pairs, blk, g, G);
+  else if (fmt == 2)
+    dc::direct_tile_kernel<2><<<grid, dc::NT, 0, st>>>(static_cast<const uint8_t*>(src), T, N, F, pairs, blk, g, G);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_finalize(const unsigned long long* G, void* vis, int64_t n_out, int F, hipStream_t st) {
+  const int64_t total = n_out * F;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  dc::direct_finalize_kernel<<<(unsigned)blocks, 256, 0, st>>>(reinterpret_cast<const long long*>(G),
+                                                              static_cast<float2*>(vis), n_out, total);
+  return hipGetLastError();
+}
+
+}  // namespace omni

@@ -548,3 +548,75 @@ def test_graph_batch_resumes_an_integration():
     torch.cuda.synchronize()
     for (ld, _, _), r, o in zip(BATCH, raws, got):
         assert rel_err(o.cpu().numpy(), oracle_vis(r, "ci8", ld)) <= TOL["fp32"]
+
+
+# ---------------------------------------------------------------------------
+# GPU direct N^2 correlator (comparison baseline): exact integer sums, rounded once to float32
+
+
+def assert_rounded_once(got, ref):
+    """Each component of `got` is the float32 rounding of the exact `ref` (|error| <= 2^-24 |ref|)."""
+    got = got.astype(np.complex128)
+    for part in (np.real, np.imag):
+        g, r = part(got), part(ref)
+        assert np.all(np.abs(g - r) <= np.abs(r) * 2.0**-24), float(np.max(np.abs(g - r)))
+
+
+@pytest.mark.parametrize("dtype", ["ci8", "ci4"])
+@pytest.mark.parametrize(
+    "level_dims,T,F",
+    [([[16, 16]], 77, 3), ([[4, 4], [4, 4]], 40, 2), ([[2, 8], [4, 4]], 33, 1), ([[8, 16]], 1, 2)],
+    ids=["16x16", "4x4x4x4", "2x8x4x4", "8x16_T1"],
+)
+def test_direct_correlator_matches_oracle(level_dims, T, F, dtype):
+    gen = torch.Generator().manual_seed(11)
+    N = math.prod(dims_of(level_dims))
+    raw = random_raw(dtype, T, F, N, gen)
+    say("direct correlator", level_dims, dtype, "T", T, "F", F)
+    plan = omni.Plan(level_dims, None, F, dtype, "fp32")
+    vis = plan.direct_correlate(raw.cuda())
+    torch.cuda.synchronize()
+    assert_rounded_once(vis.cpu().numpy(), oracle_vis(raw, dtype, level_dims))
+
+
+def test_direct_correlator_extremes_two_launches():
+    """ci8 -128 everywhere over T = 40000 > 32768 samples (two launches, largest int32 pair sums)."""
+    T, F, level_dims = 40000, 1, [[8, 16]]
+    raw = torch.full((T, F, 128, 2), -128, dtype=torch.int8)
+    raw[::3, :, ::5, 1] = 127
+    say("direct correlator extremes T", T)
+    plan = omni.Plan(level_dims, None, F, "ci8", "fp32")
+    vis = plan.direct_correlate(raw.cuda())
+    torch.cuda.synchronize()
+    assert_rounded_once(vis.cpu().numpy(), oracle_vis(raw, "ci8", level_dims))
+
+
+def test_direct_correlator_empty_and_errors():
+    plan = omni.Plan([[16, 16]], None, 2, "ci8", "fp32")
+    vis = plan.direct_correlate(torch.zeros((0, 2, 256, 2), dtype=torch.int8, device="cuda"))
+    torch.cuda.synchronize()
+    assert not vis.abs().any()
+    with pytest.raises(omni.OmniError) as e:
+        omni.Plan([[16, 16]], None, 1, "cf32", "fp32").direct_correlate(torch.zeros((4, 1, 256, 2), device="cuda"))
+    assert e.value.code == -7  # OMNI_E_STATE: float samples
+    with pytest.raises(omni.OmniError, match="multiple of 128"):
+        omni.Plan([[10, 10]], None, 1, "ci8", "fp32").direct_correlate(
+            torch.zeros((4, 1, 100, 2), dtype=torch.int8, device="cuda"))
+
+
+def test_direct_correlator_agrees_with_fft_forms_full_size():
+    """hier8x8 at full size (F=64, T=4096, ci8): direct (exact) vs the float32 and mixed FFT forms."""
+    w = skysim.WORKLOADS["hier8x8"]
+    say("direct correlator vs FFT forms: hier8x8 full size")
+    raw = skysim.make_voltages(w, device="cuda")
+    d = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, "fp32").direct_correlate(raw)
+    for form in ("fp32", "mixed"):
+        v = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form).correlate(raw)
+        torch.cuda.synchronize()
+        e = rel_err(v.cpu().numpy(), d.cpu().numpy().astype(np.complex128))
+        say("direct vs", form, e)
+        assert e <= TOL[form]
+    xf = raw.double()
+    power = (xf**2).sum(dim=(0, 2, 3)).cpu().numpy()
+    dh = d.cpu().numpy().reshape(w.nchan, -1)
+    assert np.array_equal(dh[:, dh.shape[1] // 2].real, power.astype(np.float32))
