@@ -16,7 +16,7 @@
 // Work-group = (block pair I <= J of 128 consecutive antennas, channel).  Each
 // step stages 32 time samples of both blocks in LDS, transposed to one row of
 // 32 bytes (padded to 48: conflict-free 16-byte row reads) per antenna and
-// plane.  After the last step every pair (a in I, b in J, a <= b) adds its
+// plane; the next step's samples are loaded into registers meanwhile.  After the last step every pair (a in I, b in J, a <= b) adds its
 // sums into LDS bins covering the box of Delta values the two blocks can form
 // (64-bit integer LDS atomics), and the box is added into the channel's int64
 // half-sum G (global 64-bit atomics, one per nonzero bin).  Pairs a > b are
@@ -33,8 +33,10 @@ namespace omni {
 namespace dc {
 
 constexpr int NT = 256;     // 4 waves, each a 64 x 64 quarter of the 128 x 128 pair tile
-constexpr int KS = 32;      // time samples per step (the MFMA's contracted length)
-constexpr int RS = 48;      // LDS bytes per antenna row of one plane
+constexpr int KS = 32;      // time samples per step (the contracted length of one matrix-core product;
+                            // 64- and 128-sample steps measured slower)
+constexpr int QS = KS / 32; // quads of 4 samples per thread and block per step
+constexpr int RS = KS + 16; // LDS bytes per antenna row of one plane (padded: conflict-free 16-byte reads)
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
                                                         const int32_t* __restrict__ blk, DirectGeom g,
                                                         unsigned long long* __restrict__ G) {
   constexpr int SB = FMT == 1 ? 2 : 1;  // bytes per sample
-  __shared__ __attribute__((aligned(16))) uint8_t pl[4][kDirectTile * RS];  // Ar, Ai, Br, Bi
+  __shared__ __attribute__((aligned(16))) uint8_t pl[4][kDirectTile * RS];  // Ar, Ai, Br, Bi: [antenna][sample]
   __shared__ unsigned long long bins[kDirectMaxBins][2];
   __shared__ int alpha[kDirectTile], beta[kDirectTile];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -111,23 +113,26 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   }
   for (int q = tid; q < nb; q += NT) bins[q][0] = bins[q][1] = 0ull;
 
-  // ---- staging item: samples 4 tg .. 4 tg + 3 of the step, antennas 4 ag .. 4 ag + 3 of each block
+  // ---- staging items: samples 4 tq .. 4 tq + 3 of the step (tq = tid / 32 + 8 u, u < QS),
+  // antennas 4 ag .. 4 ag + 3 of each block
   const int tg = tid >> 5, ag = tid & 31;
   const int64_t row_stride = (int64_t)F * N;  // samples between consecutive times
   const uint8_t* const pA = src + ((int64_t)f * N + aI + 4 * ag) * SB;
   const uint8_t* const pB = src + ((int64_t)f * N + aJ + 4 * ag) * SB;
-  uint32_t ar[4], ai[4], br[4], bi[4];
+  uint32_t ar[QS][4], ai[QS][4], br[QS][4], bi[QS][4];
   auto load = [&](int64_t t0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t t = t0 + 4 * tg + s;
-      if (t < T) {
-        load4<FMT>(pA + t * row_stride * SB, ar[s], ai[s]);
-        load4<FMT>(pB + t * row_stride * SB, br[s], bi[s]);
-      } else {
-        ar[s] = ai[s] = br[s] = bi[s] = 0u;
+    for (int u = 0; u < QS; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t t = t0 + 4 * (tg + 8 * u) + s;
+        if (t < T) {
+          load4<FMT>(pA + t * row_stride * SB, ar[u][s], ai[u][s]);
+          load4<FMT>(pB + t * row_stride * SB, br[u][s], bi[u][s]);
+        } else {
+          ar[u][s] = ai[u][s] = br[u][s] = bi[u][s] = 0u;
+        }
       }
-    }
   };
 
   v16i cre[2][2], cip[2][2], cin[2][2];
@@ -143,33 +148,38 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   load(0);
   for (int64_t t0 = 0; t0 < T; t0 += KS) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int o = (4 * ag + j) * RS + 4 * tg;
-      *reinterpret_cast<uint32_t*>(&pl[0][o]) = column(ar, j);
-      *reinterpret_cast<uint32_t*>(&pl[1][o]) = column(ai, j);
-      *reinterpret_cast<uint32_t*>(&pl[2][o]) = column(br, j);
-      *reinterpret_cast<uint32_t*>(&pl[3][o]) = column(bi, j);
-    }
+    for (int u = 0; u < QS; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int o = (4 * ag + j) * RS + 4 * (tg + 8 * u);
+        *reinterpret_cast<uint32_t*>(&pl[0][o]) = column(ar[u], j);
+        *reinterpret_cast<uint32_t*>(&pl[1][o]) = column(ai[u], j);
+        *reinterpret_cast<uint32_t*>(&pl[2][o]) = column(br[u], j);
+        *reinterpret_cast<uint32_t*>(&pl[3][o]) = column(bi[u], j);
+      }
     __syncthreads();
     if (t0 + KS < T) load(t0 + KS);
-    v4i xr[2], xi[2], yr[2], yi[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int oa = (mw + 32 * i + orow) * RS + ok, ob = (nw + 32 * i + orow) * RS + ok;
-      xr[i] = *reinterpret_cast<const v4i*>(&pl[0][oa]);
-      xi[i] = *reinterpret_cast<const v4i*>(&pl[1][oa]);
-      yr[i] = *reinterpret_cast<const v4i*>(&pl[2][ob]);
-      yi[i] = *reinterpret_cast<const v4i*>(&pl[3][ob]);
-    }
+    for (int kk = 0; kk < KS / 32; ++kk) {
+      v4i xr[2], xi[2], yr[2], yi[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        cre[i][j] = mfma(xr[i], yr[j], cre[i][j]);
-        cre[i][j] = mfma(xi[i], yi[j], cre[i][j]);
-        cip[i][j] = mfma(xi[i], yr[j], cip[i][j]);
-        cin[i][j] = mfma(xr[i], yi[j], cin[i][j]);
+      for (int i = 0; i < 2; ++i) {
+        const int oa = (mw + 32 * i + orow) * RS + 32 * kk + ok, ob = (nw + 32 * i + orow) * RS + 32 * kk + ok;
+        xr[i] = *reinterpret_cast<const v4i*>(&pl[0][oa]);
+        xi[i] = *reinterpret_cast<const v4i*>(&pl[1][oa]);
+        yr[i] = *reinterpret_cast<const v4i*>(&pl[2][ob]);
+        yi[i] = *reinterpret_cast<const v4i*>(&pl[3][ob]);
       }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = mfma(xr[i], yr[j], cre[i][j]);
+          cre[i][j] = mfma(xi[i], yi[j], cre[i][j]);
+          cip[i][j] = mfma(xi[i], yr[j], cip[i][j]);
+          cin[i][j] = mfma(xr[i], yi[j], cin[i][j]);
+        }
+    }
     __syncthreads();
   }
 
