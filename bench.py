@@ -150,6 +150,9 @@ def run_form(omni, w, raw, form, steps, warmup):
     for k in ("forward", "reduce", "inverse"):
         v = plan.stage_times(k, steps)
         stages[k] = sum(v) / len(v)
+    calls = sorted(plan.stage_times("call", steps))  # per-call events around each whole call
+    stages["call_median"] = calls[len(calls) // 2] if len(calls) % 2 else 0.5 * (calls[len(calls) // 2 - 1] + calls[len(calls) // 2])
+    stages["call_min"] = calls[0]
     log(f"bench[{form}]: {ms:.3f} ms/step (wall {wall:.3f}); " + ", ".join(f"{k} {v:.3f} ms" for k, v in stages.items()))
     return {"ms": ms, "stages": stages, "kernel": desc["arrays"][0]["kernel"] + "_kernel", "vis": vis, "plan": plan}
 
@@ -396,6 +399,8 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_call_median": main_res["stages"]["call_median"],
+        "ms_per_call_min": main_res["stages"]["call_min"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

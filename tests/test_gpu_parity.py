@@ -620,3 +620,20 @@ def test_direct_correlator_agrees_with_fft_forms_full_size():
     power = (xf**2).sum(dim=(0, 2, 3)).cpu().numpy()
     dh = d.cpu().numpy().reshape(w.nchan, -1)
     assert np.array_equal(dh[:, dh.shape[1] // 2].real, power.astype(np.float32))
+
+
+@pytest.mark.parametrize("perm", [(1, 0, 3, 2), (2, 3, 0, 1)], ids=["swap_xy", "swap_levels"])
+def test_axis_permutation_equivariance(perm):
+    """Permuting the antenna axes (within or between levels) permutes the visibility axes (PIN13 on the GPU)."""
+    level_dims, T, F = [[4, 8], [2, 4]], 48, 2
+    dims = dims_of(level_dims)
+    gen = torch.Generator().manual_seed(5)
+    raw = random_raw("ci8", T, F, math.prod(dims), gen)
+    vis, _ = gpu_vis(level_dims, raw, "ci8")
+    pdims = [dims[k] for k in perm]
+    praw = raw.reshape(T, F, *dims, 2).permute(0, 1, *[2 + k for k in perm], 2 + len(dims)).contiguous()
+    praw = praw.reshape(T, F, -1, 2)
+    plevels = [[pdims[0], pdims[1]], [pdims[2], pdims[3]]]
+    pvis, _ = gpu_vis(plevels, praw, "ci8")
+    want = np.transpose(vis, (0,) + tuple(1 + k for k in perm))
+    assert rel_err(pvis, want) <= TOL["fp32"]

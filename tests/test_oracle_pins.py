@@ -124,6 +124,21 @@ def pin_separable(vis):
     assert np.array_equal(V, np.multiply.outer(Vu, Vv))
 
 
+def pin_axis_permutation_and_time_linearity(vis):
+    """Permuting the antenna axes permutes the visibility axes; the time sum splits (SURVEY PIN13)."""
+    dims = (3, 2, 4)
+    T = 3
+    x = np.stack([rand_cplx(dims) for _ in range(T)])  # [T, *dims]
+    V = vis(x.reshape(T, 1, -1), dims)[0]
+    perm = (2, 0, 1)
+    xp = np.transpose(x, (0,) + tuple(1 + k for k in perm))
+    Vp = vis(np.ascontiguousarray(xp).reshape(T, 1, -1), tuple(dims[k] for k in perm))[0]
+    assert np.array_equal(Vp, np.transpose(V, perm))
+    V1 = vis(x[:1].reshape(1, 1, -1), dims)[0]
+    V2 = vis(x[1:].reshape(T - 1, 1, -1), dims)[0]
+    assert np.array_equal(V, V1 + V2)
+
+
 def pin_library_correlate(vis):
     """numpy.correlate (1-D) and scipy.signal.correlate (N-D, direct) of a single sample."""
     a = rand_cplx(7)
@@ -216,6 +231,7 @@ PINS = [
     pin_hermitian,
     pin_two_deltas,
     pin_separable,
+    pin_axis_permutation_and_time_linearity,
     pin_library_correlate,
     pin_padded_fft,
     pin_brute_force,
