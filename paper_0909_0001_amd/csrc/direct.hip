@@ -32,7 +32,7 @@
 namespace omni {
 namespace dc {
 
-constexpr int NT = 256;     // 4 waves, each a 64 x 64 quarter of the 128 x 128 pair tile
+constexpr int NT = 512;     // 8 waves, each a 64 x 32 eighth of the 128 x 128 pair tile (two waves per SIMD)
 constexpr int KS = 32;      // time samples per step (the contracted length of one matrix-core product;
                             // 64- and 128-sample steps measured slower)
 constexpr int QS = KS / 32; // quads of 4 samples per thread and block per step
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   if (nb > kDirectMaxBins) return;  // the planner never launches such a pair
   // bin(a, b) = alpha[a - aI] + beta[b - aJ], alpha = sum_k (c_k(a) - minI_k) stride_k,
   // beta = sum_k (maxJ_k - c_k(b)) stride_k
-  {
+  if (tid < 2 * kDirectTile) {
     const bool isA = tid < kDirectTile;
     const int r = isA ? tid : tid - kDirectTile;
     int64_t a = (isA ? aI : aJ) + r;
@@ -113,13 +113,14 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   }
   for (int q = tid; q < nb; q += NT) bins[q][0] = bins[q][1] = 0ull;
 
-  // ---- staging items: samples 4 tq .. 4 tq + 3 of the step (tq = tid / 32 + 8 u, u < QS),
-  // antennas 4 ag .. 4 ag + 3 of each block
-  const int tg = tid >> 5, ag = tid & 31;
+  // ---- staging items: threads 0..255 stage block I, 256..511 block J; samples 4 tq .. 4 tq + 3 of the
+  // step (tq = (tid mod 256) / 32 + 8 u, u < QS), antennas 4 ag .. 4 ag + 3 of the block
+  const int half = tid >> 8, tg = (tid & 255) >> 5, ag = tid & 31;
   const int64_t row_stride = (int64_t)F * N;  // samples between consecutive times
-  const uint8_t* const pA = src + ((int64_t)f * N + aI + 4 * ag) * SB;
-  const uint8_t* const pB = src + ((int64_t)f * N + aJ + 4 * ag) * SB;
-  uint32_t ar[QS][4], ai[QS][4], br[QS][4], bi[QS][4];
+  const uint8_t* const pX = src + ((int64_t)f * N + (half ? aJ : aI) + 4 * ag) * SB;
+  uint8_t* const plr = pl[2 * half];
+  uint8_t* const pli = pl[2 * half + 1];
+  uint32_t xr4[QS][4], xi4[QS][4];
   auto load = [&](int64_t t0) {
 #pragma unroll
     for (int u = 0; u < QS; ++u)
@@ -127,23 +128,23 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
       for (int s = 0; s < 4; ++s) {
         const int64_t t = t0 + 4 * (tg + 8 * u) + s;
         if (t < T) {
-          load4<FMT>(pA + t * row_stride * SB, ar[u][s], ai[u][s]);
-          load4<FMT>(pB + t * row_stride * SB, br[u][s], bi[u][s]);
+          load4<FMT>(pX + t * row_stride * SB, xr4[u][s], xi4[u][s]);
         } else {
-          ar[u][s] = ai[u][s] = br[u][s] = bi[u][s] = 0u;
+          xr4[u][s] = xi4[u][s] = 0u;
         }
       }
   };
 
-  v16i cre[2][2], cip[2][2], cin[2][2];
+  constexpr int WJ = 1;  // 32-column blocks per wave
+  v16i cre[2][WJ], cip[2][WJ], cin[2][WJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) cre[i][j][r] = cip[i][j][r] = cin[i][j][r] = 0;
 
-  const int mw = (w >> 1) * 64, nw = (w & 1) * 64;
+  const int mw = (w & 1) * 64, nw = (w >> 1) * 32;
   const int orow = lane & 31, ok = 16 * (lane >> 5);
   load(0);
   for (int64_t t0 = 0; t0 < T; t0 += KS) {
@@ -152,28 +153,30 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int o = (4 * ag + j) * RS + 4 * (tg + 8 * u);
-        *reinterpret_cast<uint32_t*>(&pl[0][o]) = column(ar[u], j);
-        *reinterpret_cast<uint32_t*>(&pl[1][o]) = column(ai[u], j);
-        *reinterpret_cast<uint32_t*>(&pl[2][o]) = column(br[u], j);
-        *reinterpret_cast<uint32_t*>(&pl[3][o]) = column(bi[u], j);
+        *reinterpret_cast<uint32_t*>(&plr[o]) = column(xr4[u], j);
+        *reinterpret_cast<uint32_t*>(&pli[o]) = column(xi4[u], j);
       }
     __syncthreads();
     if (t0 + KS < T) load(t0 + KS);
 #pragma unroll
     for (int kk = 0; kk < KS / 32; ++kk) {
-      v4i xr[2], xi[2], yr[2], yi[2];
+      v4i xr[2], xi[2], yr[WJ], yi[WJ];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const int oa = (mw + 32 * i + orow) * RS + 32 * kk + ok, ob = (nw + 32 * i + orow) * RS + 32 * kk + ok;
+        const int oa = (mw + 32 * i + orow) * RS + 32 * kk + ok;
         xr[i] = *reinterpret_cast<const v4i*>(&pl[0][oa]);
         xi[i] = *reinterpret_cast<const v4i*>(&pl[1][oa]);
-        yr[i] = *reinterpret_cast<const v4i*>(&pl[2][ob]);
-        yi[i] = *reinterpret_cast<const v4i*>(&pl[3][ob]);
+      }
+#pragma unroll
+      for (int j = 0; j < WJ; ++j) {
+        const int ob = (nw + 32 * j + orow) * RS + 32 * kk + ok;
+        yr[j] = *reinterpret_cast<const v4i*>(&pl[2][ob]);
+        yi[j] = *reinterpret_cast<const v4i*>(&pl[3][ob]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < WJ; ++j) {
           cre[i][j] = mfma(xr[i], yr[j], cre[i][j]);
           cre[i][j] = mfma(xi[i], yi[j], cre[i][j]);
           cip[i][j] = mfma(xi[i], yr[j], cip[i][j]);
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < WJ; ++j) {
       const int n = nw + 32 * j + (lane & 31);
       const int bn = beta[n];
 #pragma unroll
