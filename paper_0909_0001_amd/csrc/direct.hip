@@ -16,7 +16,9 @@
 // Work-group = (block pair I <= J of 128 consecutive antennas, channel).  Each
 // step stages 32 time samples of both blocks in LDS, transposed to one row of
 // 32 bytes (padded to 48: conflict-free 16-byte row reads) per antenna and
-// plane; the next step's samples are loaded into registers meanwhile.  After the last step every pair (a in I, b in J, a <= b) adds its
+// plane, in two buffers: while one step's matrix products read one buffer,
+// the next step is written into the other and the step after is loaded into
+// registers (one barrier per step).  After the last step every pair (a in I, b in J, a <= b) adds its
 // sums into LDS bins covering the box of Delta values the two blocks can form
 // (64-bit integer LDS atomics), and the box is added into the channel's int64
 // half-sum G (global 64-bit atomics, one per nonzero bin).  Pairs a > b are
@@ -76,7 +78,9 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
                                                         const int32_t* __restrict__ blk, DirectGeom g,
                                                         unsigned long long* __restrict__ G) {
   constexpr int SB = FMT == 1 ? 2 : 1;  // bytes per sample
-  __shared__ __attribute__((aligned(16))) uint8_t pl[4][kDirectTile * RS];  // Ar, Ai, Br, Bi: [antenna][sample]
+  // two buffers of the staging planes Ar, Ai, Br, Bi ([antenna][sample]): step s is read from buffer s mod 2
+  // while step s + 1 is written into the other
+  __shared__ __attribute__((aligned(16))) uint8_t pl[2][4][kDirectTile * RS];
   __shared__ unsigned long long bins[kDirectMaxBins][2];
   __shared__ int alpha[kDirectTile], beta[kDirectTile];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -118,8 +122,6 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   const int half = tid >> 8, tg = (tid & 255) >> 5, ag = tid & 31;
   const int64_t row_stride = (int64_t)F * N;  // samples between consecutive times
   const uint8_t* const pX = src + ((int64_t)f * N + (half ? aJ : aI) + 4 * ag) * SB;
-  uint8_t* const plr = pl[2 * half];
-  uint8_t* const pli = pl[2 * half + 1];
   uint32_t xr4[QS][4], xi4[QS][4];
   auto load = [&](int64_t t0) {
 #pragma unroll
@@ -146,32 +148,42 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 
   const int mw = (w & 1) * 64, nw = (w >> 1) * 32;
   const int orow = lane & 31, ok = 16 * (lane >> 5);
-  load(0);
-  for (int64_t t0 = 0; t0 < T; t0 += KS) {
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < QS; ++u)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int o = (4 * ag + j) * RS + 4 * (tg + 8 * u);
-        *reinterpret_cast<uint32_t*>(&plr[o]) = column(xr4[u], j);
-        *reinterpret_cast<uint32_t*>(&pli[o]) = column(xi4[u], j);
+        *reinterpret_cast<uint32_t*>(&pl[buf][2 * half][o]) = column(xr4[u], j);
+        *reinterpret_cast<uint32_t*>(&pl[buf][2 * half + 1][o]) = column(xi4[u], j);
       }
-    __syncthreads();
-    if (t0 + KS < T) load(t0 + KS);
+  };
+  // one barrier per step: step s + 1 is staged (and step s + 2 loaded) while step s's products run
+  load(0);
+  stage(0);
+  if (KS < T) load(KS);
+  __syncthreads();
+  int cur = 0;
+  for (int64_t t0 = 0; t0 < T; t0 += KS) {
+    if (t0 + KS < T) {
+      stage(cur ^ 1);
+      if (t0 + 2 * KS < T) load(t0 + 2 * KS);
+    }
+    const uint8_t(*const P)[kDirectTile * RS] = pl[cur];
 #pragma unroll
     for (int kk = 0; kk < KS / 32; ++kk) {
       v4i xr[2], xi[2], yr[WJ], yi[WJ];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int oa = (mw + 32 * i + orow) * RS + 32 * kk + ok;
-        xr[i] = *reinterpret_cast<const v4i*>(&pl[0][oa]);
-        xi[i] = *reinterpret_cast<const v4i*>(&pl[1][oa]);
+        xr[i] = *reinterpret_cast<const v4i*>(&P[0][oa]);
+        xi[i] = *reinterpret_cast<const v4i*>(&P[1][oa]);
       }
 #pragma unroll
       for (int j = 0; j < WJ; ++j) {
         const int ob = (nw + 32 * j + orow) * RS + 32 * kk + ok;
-        yr[j] = *reinterpret_cast<const v4i*>(&pl[2][ob]);
-        yi[j] = *reinterpret_cast<const v4i*>(&pl[3][ob]);
+        yr[j] = *reinterpret_cast<const v4i*>(&P[2][ob]);
+        yi[j] = *reinterpret_cast<const v4i*>(&P[3][ob]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -184,6 +196,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
         }
     }
     __syncthreads();
+    cur ^= 1;
   }
 
   // ---- bin: accumulator r of lane l holds pair (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32)
