@@ -39,6 +39,11 @@ constexpr int KS = 32;      // time samples per step (the contracted length of o
                             // 64- and 128-sample steps measured slower)
 constexpr int QS = KS / 32; // quads of 4 samples per thread and block per step
 constexpr int RS = KS + 16; // LDS bytes per antenna row of one plane (padded: conflict-free 16-byte reads)
+// LDS row of antenna a of a block: (a mod 4) 36 + a / 4.  A staging store (antennas 4 ag + j of lanes
+// ag = 0..31) then covers consecutive rows (2-way bank conflicts instead of 8-way for rows 4 apart), and the
+// 16 rows an operand read serves at once stay on distinct banks (row mod 16 distinct).
+constexpr int NROWS = 3 * 36 + kDirectTile / 4;
+__device__ __forceinline__ int lds_row(int a) { return (a & 3) * 36 + (a >> 2); }
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
@@ -80,7 +85,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   constexpr int SB = FMT == 1 ? 2 : 1;  // bytes per sample
   // two buffers of the staging planes Ar, Ai, Br, Bi ([antenna][sample]): step s is read from buffer s mod 2
   // while step s + 1 is written into the other
-  __shared__ __attribute__((aligned(16))) uint8_t pl[2][4][kDirectTile * RS];
+  __shared__ __attribute__((aligned(16))) uint8_t pl[2][4][NROWS * RS];
   __shared__ unsigned long long bins[kDirectMaxBins][2];
   __shared__ int alpha[kDirectTile], beta[kDirectTile];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
     for (int u = 0; u < QS; ++u)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int o = (4 * ag + j) * RS + 4 * (tg + 8 * u);
+        const int o = lds_row(4 * ag + j) * RS + 4 * (tg + 8 * u);
         *reinterpret_cast<uint32_t*>(&pl[buf][2 * half][o]) = column(xr4[u], j);
         *reinterpret_cast<uint32_t*>(&pl[buf][2 * half + 1][o]) = column(xi4[u], j);
       }
@@ -169,19 +174,19 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
       stage(cur ^ 1);
       if (t0 + 2 * KS < T) load(t0 + 2 * KS);
     }
-    const uint8_t(*const P)[kDirectTile * RS] = pl[cur];
+    const uint8_t(*const P)[NROWS * RS] = pl[cur];
 #pragma unroll
     for (int kk = 0; kk < KS / 32; ++kk) {
       v4i xr[2], xi[2], yr[WJ], yi[WJ];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const int oa = (mw + 32 * i + orow) * RS + 32 * kk + ok;
+        const int oa = lds_row(mw + 32 * i + orow) * RS + 32 * kk + ok;
         xr[i] = *reinterpret_cast<const v4i*>(&P[0][oa]);
         xi[i] = *reinterpret_cast<const v4i*>(&P[1][oa]);
       }
 #pragma unroll
       for (int j = 0; j < WJ; ++j) {
-        const int ob = (nw + 32 * j + orow) * RS + 32 * kk + ok;
+        const int ob = lds_row(nw + 32 * j + orow) * RS + 32 * kk + ok;
         yr[j] = *reinterpret_cast<const v4i*>(&P[2][ob]);
         yi[j] = *reinterpret_cast<const v4i*>(&P[3][ob]);
       }
