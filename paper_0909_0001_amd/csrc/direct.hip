@@ -14,8 +14,8 @@
 // is negated (-128 has no int8 negation).
 //
 // Work-group = (block pair I <= J of 128 consecutive antennas, channel).  Each
-// step stages 32 time samples of both blocks in LDS, transposed to one row of
-// 32 bytes (padded to 48: conflict-free 16-byte row reads) per antenna and
+// step stages 64 time samples of both blocks in LDS, transposed to one row of
+// 64 bytes (padded to 80: conflict-free 16-byte row reads) per antenna and
 // plane, in two buffers: while one step's matrix products read one buffer,
 // the next step is written into the other and the step after is loaded into
 // registers (one barrier per step).  After the last step every pair (a in I, b in J, a <= b) adds its
@@ -34,9 +34,8 @@
 namespace omni {
 namespace dc {
 
-constexpr int NT = 512;     // 8 waves, each a 64 x 32 eighth of the 128 x 128 pair tile (two waves per SIMD)
-constexpr int KS = 32;      // time samples per step (the contracted length of one matrix-core product;
-                            // 64- and 128-sample steps measured slower)
+constexpr int NT = 1024;    // 16 waves, each a 32 x 32 block of the 128 x 128 pair tile (four waves per SIMD)
+constexpr int KS = 64;      // time samples per step (two matrix-core products of contracted length 32)
 constexpr int QS = KS / 32; // quads of 4 samples per thread and block per step
 constexpr int RS = KS + 16; // LDS bytes per antenna row of one plane (padded: conflict-free 16-byte reads)
 // LDS row of antenna a of a block: (a mod 4) 36 + a / 4.  A staging store (antennas 4 ag + j of lanes
@@ -124,11 +123,13 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 
   // ---- staging items: threads 0..255 stage block I, 256..511 block J; samples 4 tq .. 4 tq + 3 of the
   // step (tq = (tid mod 256) / 32 + 8 u, u < QS), antennas 4 ag .. 4 ag + 3 of the block
-  const int half = tid >> 8, tg = (tid & 255) >> 5, ag = tid & 31;
+  const bool stager = tid < 512;  // waves 0..7 stage, 8..15 only compute
+  const int half = (tid >> 8) & 1, tg = (tid & 255) >> 5, ag = tid & 31;
   const int64_t row_stride = (int64_t)F * N;  // samples between consecutive times
   const uint8_t* const pX = src + ((int64_t)f * N + (half ? aJ : aI) + 4 * ag) * SB;
   uint32_t xr4[QS][4], xi4[QS][4];
   auto load = [&](int64_t t0) {
+    if (!stager) return;
 #pragma unroll
     for (int u = 0; u < QS; ++u)
 #pragma unroll
@@ -143,17 +144,19 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   };
 
   constexpr int WJ = 1;  // 32-column blocks per wave
-  v16i cre[2][WJ], cip[2][WJ], cin[2][WJ];
+  constexpr int IW = 1;
+  v16i cre[IW][WJ], cip[IW][WJ], cin[IW][WJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IW; ++i)
 #pragma unroll
     for (int j = 0; j < WJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) cre[i][j][r] = cip[i][j][r] = cin[i][j][r] = 0;
 
-  const int mw = (w & 1) * 64, nw = (w >> 1) * 32;
+  const int mw = (w & 3) * 32, nw = (w >> 2) * 32;
   const int orow = lane & 31, ok = 16 * (lane >> 5);
   auto stage = [&](int buf) {
+    if (!stager) return;
 #pragma unroll
     for (int u = 0; u < QS; ++u)
 #pragma unroll
@@ -177,9 +180,9 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
     const uint8_t(*const P)[NROWS * RS] = pl[cur];
 #pragma unroll
     for (int kk = 0; kk < KS / 32; ++kk) {
-      v4i xr[2], xi[2], yr[WJ], yi[WJ];
+      v4i xr[IW], xi[IW], yr[WJ], yi[WJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < IW; ++i) {
         const int oa = lds_row(mw + 32 * i + orow) * RS + 32 * kk + ok;
         xr[i] = *reinterpret_cast<const v4i*>(&P[0][oa]);
         xi[i] = *reinterpret_cast<const v4i*>(&P[1][oa]);
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
         yi[j] = *reinterpret_cast<const v4i*>(&P[3][ob]);
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IW; ++i)
 #pragma unroll
         for (int j = 0; j < WJ; ++j) {
           cre[i][j] = mfma(xr[i], yr[j], cre[i][j]);
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 
   // ---- bin: accumulator r of lane l holds pair (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IW; ++i)
 #pragma unroll
     for (int j = 0; j < WJ; ++j) {
       const int n = nw + 32 * j + (lane & 31);
