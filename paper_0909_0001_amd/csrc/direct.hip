@@ -6,12 +6,11 @@
 // is exact (integer products and sums) until the final conversion to float.
 //
 // Integer samples only (ci8, ci4).  Per channel, C = sum_t x_t x_t^H is a
-// Hermitian N x N product with the time samples as the contracted axis; with
-// real and imaginary parts as separate int8 planes,
-//     Re C = Xr Xr^T + Xi Xi^T,   Im C = Xi Xr^T - Xr Xi^T,
-// four int8 matrix-core products (v_mfma_i32_32x32x32_i8, int32 sums), the
-// imaginary part's two terms in separate accumulators so that no int8 operand
-// is negated (-128 has no int8 negation).
+// Hermitian N x N product with the time samples as the contracted axis.  Each
+// antenna's samples stay interleaved, u_a = (xr_a(t), xi_a(t))_t, and with
+// w_b = (~xi_b(t), xr_b(t))_t (~x = -x - 1: no int8 negation, which -128 lacks)
+//     Re C[a,b] = u_a . u_b,    Im C[a,b] = u_a . w_b + sum_t xr_a(t),
+// two int8 matrix-core products (v_mfma_i32_32x32x32_i8, int32 sums).
 //
 // Work-group = (block pair I <= J of 128 consecutive antennas, channel).  Each
 // step stages 64 time samples of both blocks in LDS, transposed to one row of
@@ -37,7 +36,8 @@ namespace dc {
 constexpr int NT = 1024;    // 16 waves, each a 32 x 32 block of the 128 x 128 pair tile (four waves per SIMD)
 constexpr int KS = 64;      // time samples per step (two matrix-core products of contracted length 32)
 constexpr int QS = KS / 32; // quads of 4 samples per thread and block per step
-constexpr int RS = KS + 16; // LDS bytes per antenna row of one plane (padded: conflict-free 16-byte reads)
+constexpr int RS = 2 * KS + 16; // LDS bytes per antenna row (KS interleaved samples, padded: conflict-free
+                                // 16-byte reads)
 // LDS row of antenna a of a block: (a mod 4) 36 + a / 4.  A staging store (antennas 4 ag + j of lanes
 // ag = 0..31) then covers consecutive rows (2-way bank conflicts instead of 8-way for rows 4 apart), and the
 // 16 rows an operand read serves at once stay on distinct banks (row mod 16 distinct).
@@ -50,30 +50,28 @@ __device__ __forceinline__ v16i mfma(v4i a, v4i b, v16i c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
-// 4 consecutive antennas of one sample -> their real and imaginary int8 parts, antenna j in byte j.
+// 4 consecutive antennas of one sample, raw: ci8 (re, im) byte pairs in 8 bytes, ci4 one byte each in .x
 template <int FMT>
-__device__ __forceinline__ void load4(const uint8_t* p, uint32_t& re, uint32_t& im) {
-  if constexpr (FMT == 1) {  // ci8: (re, im) byte pairs
-    const uint2 u = *reinterpret_cast<const uint2*>(p);
-    re = (u.x & 0xffu) | ((u.x >> 8) & 0xff00u) | ((u.y << 16) & 0xff0000u) | ((u.y << 8) & 0xff000000u);
-    im = ((u.x >> 8) & 0xffu) | ((u.x >> 16) & 0xff00u) | ((u.y << 8) & 0xff0000u) | (u.y & 0xff000000u);
-  } else {  // ci4: one byte, re = high nibble, im = low nibble, two's complement
-    const uint32_t u = *reinterpret_cast<const uint32_t*>(p);
-    re = 0;
-    im = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int b = (int)(int8_t)(u >> (8 * j));
-      re |= (uint32_t)((b >> 4) & 0xff) << (8 * j);
-      im |= (uint32_t)(((int)(int8_t)(b << 4) >> 4) & 0xff) << (8 * j);
-    }
+__device__ __forceinline__ uint2 load_raw4(const uint8_t* p) {
+  if constexpr (FMT == 1) return *reinterpret_cast<const uint2*>(p);
+  return make_uint2(*reinterpret_cast<const uint32_t*>(p), 0u);
+}
+
+// antenna j of a raw word -> its (re, im) int8 pair in the low 16 bits (re in the low byte)
+template <int FMT>
+__device__ __forceinline__ uint32_t pair_of(uint2 raw, int j) {
+  if constexpr (FMT == 1) {
+    return ((j < 2 ? raw.x : raw.y) >> (16 * (j & 1))) & 0xffffu;
+  } else {  // ci4: re = high nibble, im = low nibble, two's complement
+    const int b = (int)(int8_t)(raw.x >> (8 * j));
+    return (uint32_t)((b >> 4) & 0xff) | ((uint32_t)(((int)(int8_t)(b << 4) >> 4) & 0xff) << 8);
   }
 }
 
-// byte j of w[s] -> byte s of the result (4 x 4 byte transpose, one output column)
-__device__ __forceinline__ uint32_t column(const uint32_t (&w)[4], int j) {
-  return ((w[0] >> (8 * j)) & 0xffu) | (((w[1] >> (8 * j)) & 0xffu) << 8) | (((w[2] >> (8 * j)) & 0xffu) << 16) |
-         (((w[3] >> (8 * j)) & 0xffu) << 24);
+// (re, im) byte pairs -> (~im, re) byte pairs, for each pair of a 32-bit word
+__device__ __forceinline__ int swap_not(int u) {
+  const uint32_t v = (uint32_t)u;
+  return (int)((((v >> 8) & 0x00ff00ffu) | ((v << 8) & 0xff00ff00u)) ^ 0x00ff00ffu);
 }
 
 template <int FMT>
@@ -82,11 +80,12 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
                                                         const int32_t* __restrict__ blk, DirectGeom g,
                                                         unsigned long long* __restrict__ G) {
   constexpr int SB = FMT == 1 ? 2 : 1;  // bytes per sample
-  // two buffers of the staging planes Ar, Ai, Br, Bi ([antenna][sample]): step s is read from buffer s mod 2
-  // while step s + 1 is written into the other
-  __shared__ __attribute__((aligned(16))) uint8_t pl[2][4][NROWS * RS];
+  // two buffers of the staging planes of blocks I and J ([antenna][interleaved samples]): step s is read from
+  // buffer s mod 2 while step s + 1 is written into the other
+  __shared__ __attribute__((aligned(16))) uint8_t pl[2][2][NROWS * RS];
   __shared__ unsigned long long bins[kDirectMaxBins][2];
   __shared__ int alpha[kDirectTile], beta[kDirectTile];
+  __shared__ int srow[kDirectTile];  // sum_t xr_a(t) over this launch, a in block I
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int f = blockIdx.y;
   const int I = pairs[2 * blockIdx.x], J = pairs[2 * blockIdx.x + 1];
@@ -120,6 +119,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
     (isA ? alpha : beta)[r] = acc;
   }
   for (int q = tid; q < nb; q += NT) bins[q][0] = bins[q][1] = 0ull;
+  if (tid < kDirectTile) srow[tid] = 0;
 
   // ---- staging items: threads 0..255 stage block I, 256..511 block J; samples 4 tq .. 4 tq + 3 of the
   // step (tq = (tid mod 256) / 32 + 8 u, u < QS), antennas 4 ag .. 4 ag + 3 of the block
@@ -127,7 +127,8 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   const int half = (tid >> 8) & 1, tg = (tid & 255) >> 5, ag = tid & 31;
   const int64_t row_stride = (int64_t)F * N;  // samples between consecutive times
   const uint8_t* const pX = src + ((int64_t)f * N + (half ? aJ : aI) + 4 * ag) * SB;
-  uint32_t xr4[QS][4], xi4[QS][4];
+  uint2 raw[QS][4];
+  int sre[4] = {0, 0, 0, 0};  // block I stagers: sum of the real parts of antennas 4 ag + j
   auto load = [&](int64_t t0) {
     if (!stager) return;
 #pragma unroll
@@ -135,23 +136,19 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int64_t t = t0 + 4 * (tg + 8 * u) + s;
-        if (t < T) {
-          load4<FMT>(pX + t * row_stride * SB, xr4[u][s], xi4[u][s]);
-        } else {
-          xr4[u][s] = xi4[u][s] = 0u;
-        }
+        raw[u][s] = t < T ? load_raw4<FMT>(pX + t * row_stride * SB) : make_uint2(0u, 0u);
       }
   };
 
   constexpr int WJ = 1;  // 32-column blocks per wave
   constexpr int IW = 1;
-  v16i cre[IW][WJ], cip[IW][WJ], cin[IW][WJ];
+  v16i cre[IW][WJ], cim[IW][WJ];
 #pragma unroll
   for (int i = 0; i < IW; ++i)
 #pragma unroll
     for (int j = 0; j < WJ; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) cre[i][j][r] = cip[i][j][r] = cin[i][j][r] = 0;
+      for (int r = 0; r < 16; ++r) cre[i][j][r] = cim[i][j][r] = 0;
 
   const int mw = (w & 3) * 32, nw = (w >> 2) * 32;
   const int orow = lane & 31, ok = 16 * (lane >> 5);
@@ -161,9 +158,14 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
     for (int u = 0; u < QS; ++u)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int o = lds_row(4 * ag + j) * RS + 4 * (tg + 8 * u);
-        *reinterpret_cast<uint32_t*>(&pl[buf][2 * half][o]) = column(xr4[u], j);
-        *reinterpret_cast<uint32_t*>(&pl[buf][2 * half + 1][o]) = column(xi4[u], j);
+        uint32_t p[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          p[s] = pair_of<FMT>(raw[u][s], j);
+          if (half == 0) sre[j] += (int)(int8_t)(p[s] & 0xffu);
+        }
+        const int o = lds_row(4 * ag + j) * RS + 8 * (tg + 8 * u);
+        *reinterpret_cast<uint2*>(&pl[buf][half][o]) = make_uint2(p[0] | (p[1] << 16), p[2] | (p[3] << 16));
       }
   };
   // one barrier per step: step s + 1 is staged (and step s + 2 loaded) while step s's products run
@@ -179,33 +181,33 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
     }
     const uint8_t(*const P)[NROWS * RS] = pl[cur];
 #pragma unroll
-    for (int kk = 0; kk < KS / 32; ++kk) {
-      v4i xr[IW], xi[IW], yr[WJ], yi[WJ];
+    for (int kk = 0; kk < 2 * KS / 32; ++kk) {
+      v4i ua[IW], ub[WJ], wb[WJ];
 #pragma unroll
-      for (int i = 0; i < IW; ++i) {
-        const int oa = lds_row(mw + 32 * i + orow) * RS + 32 * kk + ok;
-        xr[i] = *reinterpret_cast<const v4i*>(&P[0][oa]);
-        xi[i] = *reinterpret_cast<const v4i*>(&P[1][oa]);
-      }
+      for (int i = 0; i < IW; ++i)
+        ua[i] = *reinterpret_cast<const v4i*>(&P[0][lds_row(mw + 32 * i + orow) * RS + 32 * kk + ok]);
 #pragma unroll
       for (int j = 0; j < WJ; ++j) {
-        const int ob = lds_row(nw + 32 * j + orow) * RS + 32 * kk + ok;
-        yr[j] = *reinterpret_cast<const v4i*>(&P[2][ob]);
-        yi[j] = *reinterpret_cast<const v4i*>(&P[3][ob]);
+        ub[j] = *reinterpret_cast<const v4i*>(&P[1][lds_row(nw + 32 * j + orow) * RS + 32 * kk + ok]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) wb[j][e] = swap_not(ub[j][e]);
       }
 #pragma unroll
       for (int i = 0; i < IW; ++i)
 #pragma unroll
         for (int j = 0; j < WJ; ++j) {
-          cre[i][j] = mfma(xr[i], yr[j], cre[i][j]);
-          cre[i][j] = mfma(xi[i], yi[j], cre[i][j]);
-          cip[i][j] = mfma(xi[i], yr[j], cip[i][j]);
-          cin[i][j] = mfma(xr[i], yi[j], cin[i][j]);
+          cre[i][j] = mfma(ua[i], ub[j], cre[i][j]);
+          cim[i][j] = mfma(ua[i], wb[j], cim[i][j]);
         }
     }
     __syncthreads();
     cur ^= 1;
   }
+  if (stager && half == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) atomicAdd(&srow[4 * ag + j], sre[j]);
+  }
+  __syncthreads();
 
   // ---- bin: accumulator r of lane l holds pair (row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32)
 #pragma unroll
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
         if (I == J && m > n) continue;  // a > b: the conjugate of (b, a)
         const int q = alpha[m] + bn;
         const long long re = (long long)cre[i][j][r];
-        const long long im = (long long)cip[i][j][r] - (long long)cin[i][j][r];
+        const long long im = (long long)cim[i][j][r] + (long long)srow[m];
         if (re) atomicAdd(&bins[q][0], (unsigned long long)re);
         if (im) atomicAdd(&bins[q][1], (unsigned long long)im);
       }
