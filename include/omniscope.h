@@ -158,7 +158,7 @@ int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, v
  * Integer samples only (plan dtype OMNI_CI8 or OMNI_CI4); int8 matrix-core
  * products with int32 sums over at most 32768 samples per launch and int64
  * sums after that, so the result is exact up to its final rounding to float32.
- * Requires a single-array plan with N a multiple of 128, fewer than 2^22 pairs
+ * Requires a single-array plan with N a multiple of 128, fewer than 2^23 pairs
  * of blocks of 128 consecutive antennas, and at most 2048 index differences
  * per block pair (prod_k (2 e_k + 1) <= 2048, e_k the largest extent of a block
  * along axis k: 465 for a 16 x 16 grid, 675 for 8x8 tiles of 8x8).  The first

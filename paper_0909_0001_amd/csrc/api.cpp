@@ -1124,8 +1124,8 @@ int direct_setup(ArrayPlan& ap) {
   if (ap.N % kDirectTile != 0) return fail(OMNI_E_SHAPE, "direct correlator: N must be a multiple of 128");
   const int64_t nbk = ap.N / kDirectTile;
   const int64_t n_pairs = nbk * (nbk + 1) / 2;
-  // one work-group of 1024 threads per block pair: the grid's x extent in threads must stay below 2^32
-  if (n_pairs >= (int64_t(1) << 22)) return fail(OMNI_E_SHAPE, "direct correlator: N too large (2^22 block pairs or more)");
+  // one work-group of 512 threads per block pair: the grid's x extent in threads must stay below 2^32
+  if (n_pairs >= (int64_t(1) << 23)) return fail(OMNI_E_SHAPE, "direct correlator: N too large (2^23 block pairs or more)");
   omni::DirectGeom g;
   g.d = d;
   int64_t n_out = 1;

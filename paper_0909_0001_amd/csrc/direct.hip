@@ -12,16 +12,17 @@
 //     Re C[a,b] = u_a . u_b,    Im C[a,b] = u_a . w_b + sum_t xr_a(t),
 // two int8 matrix-core products (v_mfma_i32_32x32x32_i8, int32 sums).
 //
-// Work-group = (block pair I <= J of 128 consecutive antennas, channel).  Each
-// step stages 64 time samples of both blocks in LDS, transposed to one row of
-// 64 bytes (padded to 80: conflict-free 16-byte row reads) per antenna and
-// plane, in two buffers: while one step's matrix products read one buffer,
-// the next step is written into the other and the step after is loaded into
-// registers (one barrier per step).  After the last step every pair (a in I, b in J, a <= b) adds its
-// sums into LDS bins covering the box of Delta values the two blocks can form
-// (64-bit integer LDS atomics), and the box is added into the channel's int64
-// half-sum G (global 64-bit atomics, one per nonzero bin).  Pairs a > b are
-// the conjugates of pairs a < b at -Delta, so the finalize step forms
+// Work-group = (block pair I <= J of 128 consecutive antennas, channel), 8
+// waves of 64 x 32 pairs.  Each step stages 32 time samples of both blocks in
+// LDS, one row of 64 bytes (32 interleaved (re, im) pairs, padded to 80:
+// conflict-free 16-byte reads) per antenna, in two buffers: while one step's
+// matrix products read one buffer, the next step is written into the other and
+// the step after is loaded into registers (one barrier per step).  After the
+// last step every pair (a in I, b in J, a <= b) adds its sums into LDS bins
+// covering the box of Delta values the two blocks can form (64-bit integer LDS
+// atomics), and the box is added into the channel's int64 half-sum G (global
+// 64-bit atomics, one per nonzero bin).  Pairs a > b are the conjugates of
+// pairs a < b at -Delta, so the finalize step forms
 //     V[Delta] = G[Delta] + conj G[-Delta]  (Delta != 0),   V[0] = G[0].
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,8 +34,8 @@
 namespace omni {
 namespace dc {
 
-constexpr int NT = 1024;    // 16 waves, each a 32 x 32 block of the 128 x 128 pair tile (four waves per SIMD)
-constexpr int KS = 64;      // time samples per step (two matrix-core products of contracted length 32)
+constexpr int NT = 512;     // 8 waves, each a 64 x 32 block of the 128 x 128 pair tile; two work-groups per CU
+constexpr int KS = 32;      // time samples per step (two matrix-core products of contracted length 32 bytes)
 constexpr int QS = KS / 32; // quads of 4 samples per thread and block per step
 constexpr int RS = 2 * KS + 16; // LDS bytes per antenna row (KS interleaved samples, padded: conflict-free
                                 // 16-byte reads)
@@ -123,14 +124,12 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 
   // ---- staging items: threads 0..255 stage block I, 256..511 block J; samples 4 tq .. 4 tq + 3 of the
   // step (tq = (tid mod 256) / 32 + 8 u, u < QS), antennas 4 ag .. 4 ag + 3 of the block
-  const bool stager = tid < 512;  // waves 0..7 stage, 8..15 only compute
   const int half = (tid >> 8) & 1, tg = (tid & 255) >> 5, ag = tid & 31;
   const int64_t row_stride = (int64_t)F * N;  // samples between consecutive times
   const uint8_t* const pX = src + ((int64_t)f * N + (half ? aJ : aI) + 4 * ag) * SB;
   uint2 raw[QS][4];
   int sre[4] = {0, 0, 0, 0};  // block I stagers: sum of the real parts of antennas 4 ag + j
   auto load = [&](int64_t t0) {
-    if (!stager) return;
 #pragma unroll
     for (int u = 0; u < QS; ++u)
 #pragma unroll
@@ -141,7 +140,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
   };
 
   constexpr int WJ = 1;  // 32-column blocks per wave
-  constexpr int IW = 1;
+  constexpr int IW = 2;
   v16i cre[IW][WJ], cim[IW][WJ];
 #pragma unroll
   for (int i = 0; i < IW; ++i)
@@ -150,10 +149,9 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
 #pragma unroll
       for (int r = 0; r < 16; ++r) cre[i][j][r] = cim[i][j][r] = 0;
 
-  const int mw = (w & 3) * 32, nw = (w >> 2) * 32;
+  const int mw = (w & 1) * 64, nw = (w >> 1) * 32;
   const int orow = lane & 31, ok = 16 * (lane >> 5);
   auto stage = [&](int buf) {
-    if (!stager) return;
 #pragma unroll
     for (int u = 0; u < QS; ++u)
 #pragma unroll
@@ -203,7 +201,7 @@ __global__ __launch_bounds__(NT) void direct_tile_kernel(const uint8_t* __restri
     __syncthreads();
     cur ^= 1;
   }
-  if (stager && half == 0) {
+  if (half == 0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) atomicAdd(&srow[4 * ag + j], sre[j]);
   }
