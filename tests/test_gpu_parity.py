@@ -565,8 +565,9 @@ def assert_rounded_once(got, ref):
 @pytest.mark.parametrize("dtype", ["ci8", "ci4"])
 @pytest.mark.parametrize(
     "level_dims,T,F",
-    [([[16, 16]], 77, 3), ([[4, 4], [4, 4]], 40, 2), ([[2, 8], [4, 4]], 33, 1), ([[8, 16]], 1, 2)],
-    ids=["16x16", "4x4x4x4", "2x8x4x4", "8x16_T1"],
+    [([[16, 16]], 77, 3), ([[4, 4], [4, 4]], 40, 2), ([[2, 8], [4, 4]], 33, 1), ([[8, 16]], 1, 2),
+     ([[2, 2], [4, 4], [2, 4]], 35, 2)],
+    ids=["16x16", "4x4x4x4", "2x8x4x4", "8x16_T1", "2x2x4x4x2x4"],
 )
 def test_direct_correlator_matches_oracle(level_dims, T, F, dtype):
     gen = torch.Generator().manual_seed(11)
