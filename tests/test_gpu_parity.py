@@ -638,3 +638,29 @@ def test_axis_permutation_equivariance(perm):
     pvis, _ = gpu_vis(plevels, praw, "ci8")
     want = np.transpose(vis, (0,) + tuple(1 + k for k in perm))
     assert rel_err(pvis, want) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("name", ["hier16x16", "hier3"])
+def test_fft_forms_against_direct_full_size(name):
+    """Every cell at full size: both FFT forms against the exact direct correlator (integer sums, rounded once)."""
+    w = skysim.WORKLOADS[name]
+    say(name, "full size: generating")
+    raw = skysim.make_voltages(w, device="cuda")
+    say(name, "full size: direct correlator")
+    d = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, "fp32").direct_correlate(raw).reshape(w.nchan, -1)
+    torch.cuda.synchronize()
+    z = d[:, d.shape[1] // 2].real.double()
+    power = torch.zeros(w.nchan, dtype=torch.float64, device="cuda")
+    for f in range(w.nchan):  # exact total power per channel: sum |x|^2 of the ci4 samples
+        b = raw[:, f].to(torch.int16)
+        re, im = ((b << 8) >> 12).double(), ((b << 12) >> 12).double()  # signed high and low nibbles
+        power[f] = (re * re + im * im).sum()
+    assert torch.equal(z, power.float().double())
+    for form in ("fp32", "mixed"):
+        say(name, "full size:", form)
+        v = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form).correlate(raw).reshape(w.nchan, -1)
+        torch.cuda.synchronize()
+        e = float(((v - d).abs().amax(dim=1).double() / z).max())
+        say(name, form, "max |V - V_direct| / V[0]:", e)
+        assert e <= TOL[form]
+        del v
