@@ -131,6 +131,7 @@ constexpr int kStages = 4;  // forward, reduce, inverse, whole call
 // read-modified-written once per chunk, so fewer, larger chunks save that traffic), and a chunk at most
 // kChunkMax samples.
 constexpr int64_t kFrontBytes = int64_t(8) << 30;
+constexpr int64_t kFrontBytesMixed = int64_t(16) << 30;  // float16 front workspaces of the mixed form
 constexpr int64_t kChunkMax = 256;
 
 struct omni_plan_s {
@@ -396,7 +397,7 @@ void plan_mixed_behind_front(ArrayPlan& ap, int kernel) {
   fs.lds = kernel == 4 ? 99840 : 50176;
   // bytes per time sample of the last (float16) front output; earlier front outputs are float32
   const int64_t per_t = (int64_t)ap.F * ms * rest_n * 4;
-  ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kFrontBytes / per_t));
+  ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kFrontBytesMixed / per_t));
   ap.front_elems = (ap.chunk_T * per_t + 7) / 8;  // float2 units
   int64_t mm = 1, nn = ap.N;
   for (int k = 0; k + 1 < s; ++k) {
