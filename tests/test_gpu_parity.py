@@ -625,7 +625,7 @@ def test_direct_correlator_agrees_with_fft_forms_full_size():
 
 @pytest.mark.parametrize("perm", [(1, 0, 3, 2), (2, 3, 0, 1)], ids=["swap_xy", "swap_levels"])
 def test_axis_permutation_equivariance(perm):
-    """Permuting the antenna axes (within or between levels) permutes the visibility axes (PIN13 on the GPU)."""
+    """Permuting the antenna axes (within or between levels) permutes the visibility axes."""
     level_dims, T, F = [[4, 8], [2, 4]], 48, 2
     dims = dims_of(level_dims)
     gen = torch.Generator().manual_seed(5)

@@ -125,7 +125,7 @@ def pin_separable(vis):
 
 
 def pin_axis_permutation_and_time_linearity(vis):
-    """Permuting the antenna axes permutes the visibility axes; the time sum splits (SURVEY PIN13)."""
+    """Permuting the antenna axes permutes the visibility axes; the time sum splits into sub-sums."""
     dims = (3, 2, 4)
     T = 3
     x = np.stack([rand_cplx(dims) for _ in range(T)])  # [T, *dims]
