@@ -76,8 +76,6 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 /* omni_opts.flags */
 #define OMNI_PLAN_HOST_ONLY 0x1u /* geometry only: no device resources; correlate -> OMNI_E_STATE */
 #define OMNI_PLAN_TIMING 0x2u    /* record HIP events around each stage of every correlate call  */
-#define OMNI_PLAN_TUNE 0x4u      /* autotune the general kernel's schedule at plan time (timed on  \
-                                    an all-zero input; choice cached in the file OMNI_TUNE_CACHE) */
 #define OMNI_PLAN_GRAPH 0x8u     /* run every correlate call as one HIP graph whose arrays are     \
                                     parallel branches (first call captured, later calls replay)  */
 
@@ -85,16 +83,39 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 #define OMNI_NO_RESET 0x1u    /* add this call's samples to the running accumulator            */
 #define OMNI_NO_FINALIZE 0x2u /* skip the inverse transform (vis is not touched, may be NULL)  */
 
+/* omni_opts.tune: the plan-time autotuner times candidate schedules (short-DFT
+ * length cap x time slicing of the vector-ALU kernels; time slicing and the
+ * float32 block of the matrix-core kernels) on an all-zero input of a few
+ * samples with HIP events, and keeps the fastest.  The schedule changes only
+ * speed, never the result beyond rounding order. */
+typedef enum {
+  OMNI_TUNE_OFF = 0,    /* the planner's fixed schedule                                   */
+  OMNI_TUNE_CACHE = 1,  /* the schedule stored for this array in tune_cache, else search  */
+  OMNI_TUNE_SEARCH = 2  /* always search; the result is appended to tune_cache if named   */
+} omni_tune;
+
 typedef struct {
   omni_dtype dtype;   /* sample format of the voltages                        */
   omni_form form;     /* arithmetic form of the forward transform             */
   int32_t time_block; /* samples per float32 block before the float64 add; 0 = default (64, mixed 1024) */
   uint32_t flags;     /* OMNI_PLAN_* flags                                    */
+  int32_t tune;       /* omni_tune                                            */
+  const char* tune_cache; /* text file of tuned schedules (one line per array key), or NULL;
+                             read and appended at plan time only, never by correlate calls */
+  int32_t chunk_T;    /* grids transformed partly by front passes (one channel's Fourier grid too
+                         large for one work-group share): at most this many time samples per chunk
+                         of the front workspace; 0 = the planner's choice (<= 256 samples, <= 8 GiB
+                         per workspace, 16 GiB in the mixed form).  Smaller chunks use less memory. */
 } omni_opts;
 
 typedef struct omni_plan_s* omni_plan_t;
 
-/* Plan one array.
+/* Plan one array: the n-level hierarchy of rectangular grids of Sec. II.D
+ * (antenna positions r = sum_l A_l (i_lx, i_ly), Eq. GridEq) laid out as the
+ * 2L-dimensional hypercube whose zero-padded transform (Sec. II.A, II.C: every
+ * axis padded to m_k = 2 n_k, so that the circular correlation holds the whole
+ * linear one) the correlate calls take.  The plan fixes the axis order, the
+ * fold moduli of every axis' pruned DFT, the kernels and the workspaces.
  *   levels : L >= 1 levels of the hierarchy (d = 2L axes, d <= 8).
  *   dims   : [L][2] int32 (n_x, n_y) per level; each >= 1; N = prod n <= 2^22.
  *   A      : [L][2][2] float64 row-major; column c is the level's lattice vector
@@ -110,7 +131,7 @@ typedef struct omni_plan_s* omni_plan_t;
 int omni_plan(omni_plan_t* out, int32_t levels, const int32_t* dims, const double* A, int32_t nchan,
               const omni_opts* opts);
 
-/* One array of a batched plan. */
+/* One array of a batched plan (same fields as omni_plan's arguments). */
 typedef struct {
   int32_t levels;
   const int32_t* dims; /* [levels][2] */
@@ -119,11 +140,21 @@ typedef struct {
 } omni_array_desc;
 
 /* Plan several arrays (possibly of different shapes) that are always
- * correlated together, in one launch sequence, with a common T.  Sample format
- * and form are shared.  Errors as for omni_plan. */
+ * correlated together, in one launch sequence, with a common T: the same
+ * per-channel correlation of Sec. II.D, Eq. ProofEq2 repeated over arrays and
+ * frequency channels (Appendix A: the procedure is repeated for every
+ * frequency bin of interest).  Sample format and form are shared.  Array i of
+ * the plan is arrays[i].  Errors as for omni_plan. */
 int omni_plan_batch(omni_plan_t* out, int32_t n_arrays, const omni_array_desc* arrays, const omni_opts* opts);
 
-/* Correlate T time samples (T >= 0) of every channel.
+/* Correlate T time samples (T >= 0) of every channel: the visibility
+ * hypercube V_f[Delta] of Sec. II.D, Eq. ProofEq2 (every pair's product summed
+ * over the pairs sharing the index difference Delta), computed as in Sec. II.A
+ * and II.C: zero-padded d-dimensional DFT of each sample's hypercube, square
+ * modulus, sum over the samples (the time integration of Sec. II.A), one
+ * inverse DFT per channel.  Integer samples give Gaussian-integer visibilities
+ * which the float32 form reproduces to 1e-5 and the mixed form to 2e-3 of the
+ * channel's zero-lag power.
  *   volt   : device [T][F][N] samples in the plan's format (may be NULL iff T == 0).
  *   vis    : device complex64 [F][2n_1-1]...[2n_d-1]; may be NULL with OMNI_NO_FINALIZE.
  *   stream : hipStream_t, or NULL for the default stream.
@@ -136,7 +167,10 @@ int omni_plan_batch(omni_plan_t* out, int32_t n_arrays, const omni_array_desc* a
  * OMNI_E_HIP. */
 int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream, uint32_t flags);
 
-/* Batched form: volt[i] / vis[i] belong to array i of the batch plan.
+/* Batched form of omni_correlate (same computation per array, Sec. II.D,
+ * Eq. ProofEq2): volt[i] / vis[i] belong to array i of the batch plan, each in
+ * that array's layout; all arrays share T.  volt and vis are host arrays of
+ * n_arrays device pointers, read during the call only.
  * Without OMNI_PLAN_GRAPH the arrays run one after another on `stream`.  With
  * it, the plan captures its first call (all arrays, all stages) into one HIP
  * graph in which each array is an independent branch on a stream of its own,
@@ -172,32 +206,47 @@ int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, v
  * limits above), OMNI_E_NOMEM, OMNI_E_HIP. */
 int omni_direct_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream);
 
-/* Number of arrays in the plan (1 for omni_plan). */
+/* Number of arrays in the plan (1 for omni_plan).  Planning metadata, no
+ * passage of the paper.  Errors: OMNI_E_INVAL (NULL argument). */
 int omni_n_arrays(omni_plan_t plan, int32_t* n);
 
-/* Visibility shape of array `array`: *ndim = 1 + d, shape = [F, 2n_1-1, ...].
- * shape must hold 9 entries. */
+/* Visibility shape of array `array`: *ndim = 1 + d, shape = [F, 2n_1-1, ...],
+ * one cell per index difference Delta_k in [-(n_k-1), n_k-1] (the index range
+ * of Sec. II.D, Eq. ProofEq2; Sec. II.C's worked example has 2n-1 = 5 and 3
+ * cells for n = 3 and 2).  shape is host memory of at least 9 entries.
+ * Errors: OMNI_E_INVAL (NULL argument, array out of range). */
 int omni_vis_shape(omni_plan_t plan, int32_t array, int32_t* ndim, int64_t* shape);
 
 /* Physical baseline of every visibility cell of array `array`:
  * uv[cell][2] = sum_l A_l (Delta_lx, Delta_ly) in wavelengths at the reference
- * frequency (Sec. II.D, Eq. GridEq), cells in the visibility layout.  uv is
- * host memory of prod(2n_k-1)*2 doubles.  OMNI_E_STATE if planned without A. */
+ * frequency (Sec. II.D, Eq. GridEq applied to an index difference), cells in
+ * the visibility layout.  uv is host memory of prod(2n_k-1)*2 doubles, written.
+ * Errors: OMNI_E_INVAL (NULL argument, array out of range), OMNI_E_STATE
+ * (planned without A). */
 int omni_baselines(omni_plan_t plan, int32_t array, double* uv);
 
-/* Size in bytes of the plan's float64 accumulator (the integration state):
- * sum over arrays of F * prod(2 n_k) doubles, natural frequency order. */
+/* Size in bytes of the plan's float64 accumulator, the integration state
+ * sum_t |X_t[kappa]|^2 of Sec. II.A (squared transforms summed over the time
+ * samples before the single inverse transform): sum over arrays of
+ * F * prod(2 n_k) doubles, [array][F][kappa_1]...[kappa_d], natural frequency
+ * order.  Errors: OMNI_E_INVAL (NULL argument). */
 int omni_accumulator_bytes(omni_plan_t plan, size_t* bytes);
 
-/* Copy the accumulator to / from `buf` (host or device memory, `bytes` must
- * equal omni_accumulator_bytes).  Synchronous with respect to `stream`.
- * Together with OMNI_NO_RESET this checkpoints and resumes an integration. */
+/* Copy the accumulator (the time-summed power of Sec. II.A, layout as in
+ * omni_accumulator_bytes) to / from `buf` (host or device memory owned by the
+ * caller; `bytes` must equal omni_accumulator_bytes).  Synchronous with respect
+ * to `stream`.  Together with OMNI_NO_RESET this checkpoints and resumes an
+ * integration: the sum over time is linear, so a split integration equals the
+ * whole one up to rounding.  Errors: OMNI_E_INVAL (NULL, wrong size),
+ * OMNI_E_STATE (host-only plan), OMNI_E_HIP. */
 int omni_accumulator_get(omni_plan_t plan, void* buf, size_t bytes, void* stream);
 int omni_accumulator_set(omni_plan_t plan, const void* buf, size_t bytes, void* stream);
 
 /* A JSON description of the schedule the planner chose (axis order, fold
- * moduli, work-group split, kernel variants).  Writes at most len bytes
- * including the terminating NUL; *needed receives the full length. */
+ * moduli, work-group split, kernel variants, time chunk of the front passes).
+ * Planning metadata, no passage of the paper.  Writes at most len bytes of
+ * host memory including the terminating NUL (buf may be NULL when len is 0);
+ * *needed receives the full length.  Errors: OMNI_E_INVAL (NULL plan). */
 int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed);
 
 /* Stages timed by a plan made with OMNI_PLAN_TIMING. */
@@ -208,7 +257,8 @@ typedef enum {
   OMNI_STAGE_CALL = 3     /* the whole correlate call, on the caller's stream        */
 } omni_stage;
 
-/* Durations in milliseconds of `stage` over the most recent correlate calls
+/* Measurement support, no passage of the paper.
+ * Durations in milliseconds of `stage` over the most recent correlate calls
  * (oldest first; at most 256 calls are remembered; for a batch plan the
  * stage spans all arrays).  Waits for the recorded events.  Writes at most
  * `max` values to ms and the count to *n.  OMNI_E_STATE without
@@ -216,13 +266,15 @@ typedef enum {
  * arrays' stages overlap; only OMNI_STAGE_CALL is recorded). */
 int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n);
 
-/* Release the plan (waits for its last stream first).  NULL is a no-op. */
+/* Release the plan and everything it owns on the device (waits for the
+ * device first).  NULL is a no-op.  Always returns OMNI_OK. */
 int omni_destroy(omni_plan_t plan);
 
-/* Static text for a status code. */
+/* Static text for a status code (never NULL; "unknown status" otherwise). */
 const char* omni_strerror(int code);
 
-/* Detail of the last failure on the calling thread ("" if none). */
+/* Detail of the last failure on the calling thread ("" if none); the text is
+ * owned by the library and valid until the thread's next failing call. */
 const char* omni_last_error(void);
 
 #ifdef __cplusplus

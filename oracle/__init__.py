@@ -11,6 +11,8 @@ defines, written so it can be checked against the paper by eye:
 * ``visibilities``      -- the visibility hypercube G, i.e. the correlation of
   every antenna pair summed over pairs sharing the same index difference
   (Sec. II.A; Sec. II.C Eq. ConvolutionDefEq; Sec. II.D Eq. ProofEq2).
+* ``visibilities_by_outer_lag`` -- the same hypercube with the pair sum
+  grouped by the outer levels' index difference (large grids).
 * ``visibility_cells``  -- the same quantity for a list of individual index
   differences, one overlap sum per cell (for spot checks at full size).
 * ``fourier_power``     -- the time-summed square modulus of the padded
@@ -33,5 +35,6 @@ from .correlator import (  # noqa: F401
     fourier_power,
     lag_shape,
     visibilities,
+    visibilities_by_outer_lag,
     visibility_cells,
 )

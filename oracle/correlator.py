@@ -29,6 +29,7 @@ import numpy as np
 __all__ = [
     "lag_shape",
     "visibilities",
+    "visibilities_by_outer_lag",
     "visibility_cells",
     "fourier_power",
     "baselines",
@@ -94,6 +95,64 @@ def visibilities(x, dims: Sequence[int], panel: int = 2048) -> np.ndarray:
             V[f] += np.bincount(key, weights=C.real.ravel(), minlength=n_cells)
             V[f] += 1j * np.bincount(key, weights=C.imag.ravel(), minlength=n_cells)
     return V.reshape((F,) + out_shape)
+
+
+def visibilities_by_outer_lag(x, dims: Sequence[int], n_outer: int) -> np.ndarray:
+    """The visibility hypercube of ``visibilities``, with the pair sum grouped for large grids.
+
+    Each index tuple j = (p, i) is split into its first ``n_outer`` indices p (a "tile" of the outer
+    levels) and the remaining indices i.  The definition
+        V[Delta] = sum_t sum_{pairs (j, j') with j - j' = Delta} x_{t,j} conj(x_{t,j'})
+    then reads, for Delta = (dp, di),
+        V[(dp, di)] = sum_{i - i' = di}  S_dp[i, i'],
+        S_dp[i, i'] = sum_{tile pairs (p, q), p - q = dp}  sum_t x_{t,(p,i)} conj(x_{t,(q,i')}),
+    because the histogram over di is linear in the pair products: the products of all tile pairs sharing
+    one outer difference dp are added first (one matrix product over the tiles stacked along the time axis)
+    and binned once.  Only dp on the non-negative half of the outer lag grid (row-major position at or
+    after dp = 0) is summed; the rest follows from swapping the two antennas of every pair, which
+    conjugates the product and negates Delta:  V[-Delta] = conj V[Delta].  No other step differs from
+    ``visibilities``; for integer voltages the result is exact.  Returns complex128
+    [F, 2n_1-1, ..., 2n_d-1] like ``visibilities``.
+    """
+    x = np.asarray(x)
+    T, F, N = x.shape
+    dims = tuple(int(n) for n in dims)
+    if math.prod(dims) != N:
+        raise ValueError(f"prod(dims)={math.prod(dims)} != N={N}")
+    if not 0 < n_outer < len(dims):
+        raise ValueError("n_outer must leave at least one outer and one inner axis")
+    outer, inner = dims[:n_outer], dims[n_outer:]
+    P, I = math.prod(outer), math.prod(inner)
+    out_o, out_i = lag_shape(outer), lag_shape(inner)
+    n_o, n_i = math.prod(out_o), math.prod(out_i)
+    # inner histogram key of every (i, i') pair: position of i - i' in the inner lag grid
+    ci = _antenna_index_tuples(inner) @ _row_major_strides(out_i)
+    ci0 = int(np.sum((np.asarray(inner) - 1) * _row_major_strides(out_i)))
+    key = (ci[:, None] - ci[None, :] + ci0).ravel()
+    # tile pairs grouped by their outer difference dp (position in the outer lag grid)
+    po = _antenna_index_tuples(outer)
+    co = po @ _row_major_strides(out_o)
+    co0 = int(np.sum((np.asarray(outer) - 1) * _row_major_strides(out_o)))
+    dpos = (co[:, None] - co[None, :] + co0).ravel()
+    pp, qq = np.divmod(np.arange(P * P), P)
+    order = np.argsort(dpos, kind="stable")
+    bounds = np.searchsorted(dpos[order], np.arange(n_o + 1))
+    V = np.zeros((F, n_o, n_i), dtype=np.complex128)
+    for f in range(F):
+        X = np.asarray(x[:, f, :], dtype=np.complex128).reshape(T, P, I)
+        for g in range(co0, n_o):  # the non-negative half of the outer lags
+            sel = order[bounds[g] : bounds[g + 1]]
+            if sel.size == 0:
+                continue
+            A = X[:, pp[sel], :].reshape(-1, I)  # [T * pairs, I]: tile p of every pair, stacked
+            B = X[:, qq[sel], :].reshape(-1, I)  # tile q of the same pairs, same order
+            S = A.T @ B.conj()  # S[i, i'] = sum over pairs and samples of x_(p,i) conj(x_(q,i'))
+            V[f, g] = np.bincount(key, weights=S.real.ravel(), minlength=n_i) + 1j * np.bincount(
+                key, weights=S.imag.ravel(), minlength=n_i
+            )
+        # V[-Delta] = conj V[Delta]: in the row-major centred layout -Delta sits at the mirrored position
+        V[f, :co0] = np.conj(V[f, ::-1, ::-1][:co0])
+    return V.reshape((F,) + lag_shape(dims))
 
 
 def visibility_cells(x, dims: Sequence[int], deltas) -> np.ndarray:

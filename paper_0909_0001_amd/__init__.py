@@ -33,8 +33,8 @@ DTYPES = {"cf32": 0, "ci8": 1, "ci4": 2}
 FORMS = {"fp32": 0, "mixed": 1}
 PLAN_HOST_ONLY = 0x1
 PLAN_TIMING = 0x2
-PLAN_TUNE = 0x4
 PLAN_GRAPH = 0x8
+TUNE = {False: 0, None: 0, "off": 0, "cache": 1, True: 2, "search": 2}
 STAGES = {"forward": 0, "reduce": 1, "inverse": 2, "call": 3}
 NO_RESET = 0x1
 NO_FINALIZE = 0x2
@@ -72,6 +72,9 @@ class _Opts(ctypes.Structure):
         ("form", ctypes.c_int),
         ("time_block", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("tune", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
+        ("chunk_T", ctypes.c_int32),
     ]
 
 
@@ -144,7 +147,15 @@ class Plan:
     """A correlation plan for one array (or a batch of arrays) of a hierarchical grid.
 
     ``level_dims``: [[n_x, n_y], ...] per level (outer first);  ``A``: [levels, 2, 2]
-    lattice matrices (columns = lattice vectors), or None.
+    lattice matrices (columns = lattice vectors), or None.  ``tune``: False / "off",
+    "cache" (stored schedule, else search) or True / "search"; ``tune_cache``: file of
+    tuned schedules; ``chunk_T``: cap on the time samples per front-pass chunk (0: the
+    planner's choice).
+
+    Every device call checks its tensors against the plan before the library is
+    called (dtype for the plan's sample format, shape [T, F, N(, 2)], contiguity,
+    device; the output's shape and dtype): the C ABI receives raw pointers and
+    cannot.  A mismatch raises ValueError.
     """
 
     def __init__(
@@ -158,19 +169,24 @@ class Plan:
         host_only: bool = False,
         batch: Sequence[tuple] | None = None,
         timing: bool = False,
-        tune: bool = False,
+        tune=False,
         graph: bool = False,
+        tune_cache: str | None = None,
+        chunk_T: int = 0,
     ):
         self._h = ctypes.c_void_p()
-        flags = (
-            (PLAN_HOST_ONLY if host_only else 0)
-            | (PLAN_TIMING if timing else 0)
-            | (PLAN_TUNE if tune else 0)
-            | (PLAN_GRAPH if graph else 0)
-        )
-        opts = _Opts(DTYPES[dtype], FORMS[form], time_block, flags)
-        self.dtype, self.form = dtype, form
+        if dtype not in DTYPES:
+            raise ValueError(f"unknown sample format {dtype!r} (cf32, ci8, ci4)")
+        if form not in FORMS:
+            raise ValueError(f"unknown form {form!r} (fp32, mixed)")
+        if tune not in TUNE:
+            raise ValueError(f"unknown tune mode {tune!r} (off, cache, search)")
+        flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_TIMING if timing else 0) | (PLAN_GRAPH if graph else 0)
+        self._cache_path = tune_cache.encode() if tune_cache else None
+        opts = _Opts(DTYPES[dtype], FORMS[form], time_block, flags, TUNE[tune], self._cache_path, chunk_T)
+        self.dtype, self.form, self.graph = dtype, form, graph
         self._keep = []
+        self._graph_outs = None
         if batch is None:
             dims = np.ascontiguousarray(np.asarray(level_dims, dtype=np.int32).reshape(-1, 2))
             levels = dims.shape[0]
@@ -197,6 +213,11 @@ class Plan:
         n = ctypes.c_int32()
         _check(lib.omni_n_arrays(self._h, ctypes.byref(n)))
         self.n_arrays = n.value
+        # per array: (F, N) from the visibility shape [F, 2n_1 - 1, ...]
+        self._fn = []
+        for i in range(self.n_arrays):
+            shp = self.vis_shape(i)
+            self._fn.append((int(shp[0]), int(np.prod([(v + 1) // 2 for v in shp[1:]]))))
 
     # -- metadata ---------------------------------------------------------
     def vis_shape(self, array: int = 0) -> tuple:
@@ -230,59 +251,141 @@ class Plan:
         _check(lib.omni_accumulator_bytes(self._h, ctypes.byref(b)))
         return b.value
 
+    # -- argument checks (the C ABI sees raw pointers only) ---------------
+    def _check_volt(self, volt, array: int = 0) -> int:
+        """Validate one array's voltages [T, F, N(, 2)] against the plan (dtype, shape, contiguity); returns T."""
+        import torch
+
+        F, N = self._fn[array]
+        if not isinstance(volt, torch.Tensor):
+            raise ValueError(f"array {array}: voltages must be a torch tensor, got {type(volt).__name__}")
+        want = {
+            "cf32": {torch.float32: (F, N, 2), torch.complex64: (F, N)},
+            "ci8": {torch.int8: (F, N, 2)},
+            "ci4": {torch.uint8: (F, N), torch.int8: (F, N)},
+        }[self.dtype]
+        if volt.dtype not in want:
+            raise ValueError(f"array {array}: {self.dtype} samples must be "
+                             + " or ".join(str(d).replace("torch.", "") for d in want) + f", got {volt.dtype}")
+        shp = want[volt.dtype]
+        if volt.dim() != 1 + len(shp) or tuple(volt.shape[1:]) != shp:
+            raise ValueError(f"array {array}: voltages must have shape [T, {', '.join(map(str, shp))}] for this plan "
+                             f"({self.dtype}, F={F}, N={N}), got {list(volt.shape)}")
+        if not volt.is_contiguous():
+            raise ValueError(f"array {array}: voltages must be contiguous")
+        return int(volt.shape[0])
+
+    def _check_volt_device(self, volt, array: int = 0) -> None:
+        import torch
+
+        if volt.device.type != "cuda":
+            raise ValueError(f"array {array}: voltages must be on the GPU, got device {volt.device}")
+        if volt.device.index != torch.cuda.current_device():
+            raise ValueError(f"array {array}: voltages are on {volt.device}, the current device is "
+                             f"cuda:{torch.cuda.current_device()}")
+        if volt.shape[0] > 0 and volt.data_ptr() % 4:
+            raise ValueError(f"array {array}: voltage pointer must be 4-byte aligned")
+
+    def _check_out(self, out, array: int, like) -> None:
+        import torch
+
+        if not isinstance(out, torch.Tensor):
+            raise ValueError(f"array {array}: out must be a torch tensor, got {type(out).__name__}")
+        if out.dtype != torch.complex64:
+            raise ValueError(f"array {array}: out must be complex64, got {out.dtype}")
+        if tuple(out.shape) != self.vis_shape(array):
+            raise ValueError(f"array {array}: out must have shape {list(self.vis_shape(array))}, got {list(out.shape)}")
+        if not out.is_contiguous():
+            raise ValueError(f"array {array}: out must be contiguous")
+        if out.device.type != "cuda":
+            raise ValueError(f"array {array}: out must be on the GPU, got device {out.device}")
+        if like is not None and out.device != like.device:
+            raise ValueError(f"array {array}: out is on {out.device}, voltages on {like.device}")
+
     # -- device calls -----------------------------------------------------
     def correlate_into(self, volt, T: int, vis, stream=None, flags: int = 0) -> None:
-        """Raw call: ``volt`` / ``vis`` are device pointers (int) or tensors."""
+        """Raw call with device pointers (int).  Tensors are checked as in ``correlate``; plain integer pointers
+        cannot be checked and are the caller's responsibility."""
+        if hasattr(volt, "data_ptr"):
+            if self._check_volt(volt) != T:
+                raise ValueError(f"T={T} does not match the voltages' {volt.shape[0]} samples")
+            self._check_volt_device(volt)
+        if hasattr(vis, "data_ptr"):
+            self._check_out(vis, 0, volt if hasattr(volt, "data_ptr") else None)
         vp = volt.data_ptr() if hasattr(volt, "data_ptr") else volt
         op = vis.data_ptr() if hasattr(vis, "data_ptr") else vis
         _check(lib.omni_correlate(self._h, vp, T, op, _stream_handle(stream), flags))
 
     def correlate(self, volt, flags: int = 0, out=None, stream=None):
         """Correlate device voltages [T, F, N(, 2)] -> complex64 visibilities [F, 2n_1-1, ...]."""
-        import torch
-
-        T = int(volt.shape[0]) if volt is not None else 0
-        if volt is not None:
-            if not volt.is_cuda or not volt.is_contiguous():
-                raise ValueError("voltages must be a contiguous device tensor")
-        if out is None and not (flags & NO_FINALIZE):
-            dev = volt.device if volt is not None else torch.device("cuda")
-            out = torch.empty(self.vis_shape(0), dtype=torch.complex64, device=dev)
-        self.correlate_into(volt if volt is not None else 0, T, out if out is not None else 0, stream, flags)
-        return out
+        if self.n_arrays != 1:
+            raise ValueError("batch plan: use correlate_batch")
+        return self.correlate_batch([volt], flags=flags, outs=None if out is None else [out], stream=stream)[0]
 
     def direct_correlate(self, volt, out=None, stream=None):
         """Direct N^2 correlator (comparison baseline, integer samples): device [T, F, N(, 2)] -> complex64
         visibilities [F, 2n_1-1, ...], exact up to the final rounding to float32."""
         import torch
 
-        if not volt.is_cuda or not volt.is_contiguous():
-            raise ValueError("voltages must be a contiguous device tensor")
+        if self.n_arrays != 1:
+            raise ValueError("the direct correlator takes single-array plans")
+        T = self._check_volt(volt)
+        self._check_volt_device(volt)
         if out is None:
             out = torch.empty(self.vis_shape(0), dtype=torch.complex64, device=volt.device)
-        _check(lib.omni_direct_correlate(self._h, volt.data_ptr(), int(volt.shape[0]), out.data_ptr(),
-                                         _stream_handle(stream)))
+        self._check_out(out, 0, volt)
+        _check(lib.omni_direct_correlate(self._h, volt.data_ptr(), T, out.data_ptr(), _stream_handle(stream)))
         return out
 
     def correlate_batch(self, volts, flags: int = 0, outs=None, stream=None):
+        """Correlate every array of the plan: ``volts[i]`` is array i's [T, F_i, N_i(, 2)] (a common T).
+        Returns the list of visibility tensors (``outs`` if given).  A graph plan without ``outs`` reuses one set
+        of output tensors for every call (its captured graph writes fixed addresses)."""
         import torch
 
-        T = int(volts[0].shape[0])
+        if len(volts) != self.n_arrays:
+            raise ValueError(f"expected {self.n_arrays} voltage tensors, got {len(volts)}")
+        Ts = [self._check_volt(v, i) for i, v in enumerate(volts)]
+        if len(set(Ts)) != 1:
+            raise ValueError(f"every array of a batch takes the same number of samples, got T = {Ts}")
+        for i, v in enumerate(volts):
+            self._check_volt_device(v, i)
+        T = Ts[0]
         if outs is None and not (flags & NO_FINALIZE):
-            outs = [torch.empty(self.vis_shape(i), dtype=torch.complex64, device=volts[0].device)
-                    for i in range(self.n_arrays)]
-        vp = (ctypes.c_void_p * self.n_arrays)(*[v.data_ptr() for v in volts])
+            if self.graph:
+                if self._graph_outs is None:
+                    self._graph_outs = [torch.empty(self.vis_shape(i), dtype=torch.complex64, device=volts[0].device)
+                                        for i in range(self.n_arrays)]
+                outs = self._graph_outs
+            else:
+                outs = [torch.empty(self.vis_shape(i), dtype=torch.complex64, device=volts[0].device)
+                        for i in range(self.n_arrays)]
+        if outs is not None:
+            if len(outs) != self.n_arrays:
+                raise ValueError(f"expected {self.n_arrays} output tensors, got {len(outs)}")
+            for i, o in enumerate(outs):
+                self._check_out(o, i, volts[i])
+        vp = (ctypes.c_void_p * self.n_arrays)(*[v.data_ptr() if T > 0 else 0 for v in volts])
         op = (ctypes.c_void_p * self.n_arrays)(*([o.data_ptr() for o in outs] if outs else [0] * self.n_arrays))
         _check(lib.omni_correlate_batch(self._h, vp, T, op, _stream_handle(stream), flags))
         return outs
 
     def accumulator_get(self, buf, stream=None) -> None:
+        self._check_acc(buf)
         ptr = buf.data_ptr() if hasattr(buf, "data_ptr") else buf.ctypes.data
         _check(lib.omni_accumulator_get(self._h, ptr, self.accumulator_bytes(), _stream_handle(stream)))
 
     def accumulator_set(self, buf, stream=None) -> None:
+        self._check_acc(buf)
         ptr = buf.data_ptr() if hasattr(buf, "data_ptr") else buf.ctypes.data
         _check(lib.omni_accumulator_set(self._h, ptr, self.accumulator_bytes(), _stream_handle(stream)))
+
+    def _check_acc(self, buf) -> None:
+        nb = buf.numel() * buf.element_size() if hasattr(buf, "data_ptr") else buf.nbytes
+        contiguous = buf.is_contiguous() if hasattr(buf, "data_ptr") else buf.flags["C_CONTIGUOUS"]
+        if nb != self.accumulator_bytes() or not contiguous:
+            raise ValueError(f"accumulator buffer must be contiguous and hold {self.accumulator_bytes()} bytes, "
+                             f"got {nb}")
 
     def close(self) -> None:
         if self._h:

@@ -47,11 +47,24 @@ COMMON = [
 ]
 
 
+def _local_includes(path: str, seen: set) -> set:
+    """The project headers `path` includes, directly or through other project headers."""
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("#include") and '"' in line:
+            name = line.split('"')[1]
+            for d in (CSRC, os.path.join(ROOT, "include")):
+                h = os.path.join(d, name)
+                if os.path.exists(h) and h not in seen:
+                    seen.add(h)
+                    _local_includes(h, seen)
+    return seen
+
+
 def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if incremental and os.path.exists(obj):
-        deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
-        deps.append(os.path.join(ROOT, "include", "omniscope.h"))
+        deps = [src, *_local_includes(src, set())]
         if all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps):
             return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []

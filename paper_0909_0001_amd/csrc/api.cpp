@@ -99,7 +99,8 @@ struct ArrayPlan {
   std::vector<int> front_r;   // fold modulus of each front axis
   int front_tw_base = 0;      // offset of the remaining axes' twiddles
   int64_t chunk_T = 0;        // time samples per front chunk
-  int64_t front_elems = 0;    // complex elements of each front workspace
+  int64_t chunk_cap = 0;      // caller's cap on chunk_T (0: none)
+  int64_t y_bytes[2] = {0, 0};  // bytes of the two front workspaces (front pass k writes d_y[k % 2])
   std::vector<int32_t> tw_desc_fwd, tw_desc_inv;
   std::vector<int> inv_off;  // per axis offset into the twiddle tables
   int n_tw = 0;
@@ -159,6 +160,8 @@ struct omni_plan_s {
   int time_block = 64;
   bool host_only = false;
   int device = -1;
+  int tune = OMNI_TUNE_OFF;
+  std::string tune_cache;  // file of tuned schedules ("" = none)
 };
 
 namespace {
@@ -369,6 +372,22 @@ int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_s
   return OMNI_OK;
 }
 
+// Bytes of the two front workspaces for the plan's chunk: front pass k writes d_y[k % 2] (complex float32,
+// or float16 (re, im) where the pass feeds a matrix-core kernel: the last pass before kernel 4, every pass
+// before kernel 5); the fused 16 x 16 front pass of kernel 5 writes the last pass' output into d_y[1].
+void size_front_workspaces(ArrayPlan& ap) {
+  ap.y_bytes[0] = ap.y_bytes[1] = 0;
+  const int s = ap.n_front;
+  int64_t mm = 1, nn = ap.N;
+  for (int k = 0; k < s; ++k) {
+    mm *= 2 * ap.n[k];
+    nn /= ap.n[k];
+    const bool h16 = (ap.kernel == 4 && k == s - 1) || ap.kernel == 5;
+    const int64_t b = ap.chunk_T * ap.F * mm * nn * (h16 ? 4 : 8);
+    ap.y_bytes[k & 1] = std::max(ap.y_bytes[k & 1], b);
+  }
+}
+
 // Matrix-core kernels behind the front passes: kernel 4 for the (16,16,16)
 // grid behind one front pass, kernel 5 for (8,8,4,4) behind two.  Work-group
 // = (slice, front channel), all the channel's cells, cell order given by
@@ -395,16 +414,11 @@ void plan_mixed_behind_front(ArrayPlan& ap, int kernel) {
   // what `describe` reports for the matrix-core kernels (static LDS of the kernels)
   fs.cpt = 32;
   fs.lds = kernel == 4 ? 99840 : 50176;
-  // bytes per time sample of the last (float16) front output; earlier front outputs are float32
+  // bytes per time sample of the last (float16) front output
   const int64_t per_t = (int64_t)ap.F * ms * rest_n * 4;
   ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kFrontBytesMixed / per_t));
-  ap.front_elems = (ap.chunk_T * per_t + 7) / 8;  // float2 units
-  int64_t mm = 1, nn = ap.N;
-  for (int k = 0; k + 1 < s; ++k) {
-    mm *= 2 * ap.n[k];
-    nn /= ap.n[k];
-    ap.front_elems = std::max(ap.front_elems, ap.chunk_T * ap.F * mm * nn);
-  }
+  if (ap.chunk_cap > 0) ap.chunk_T = std::min(ap.chunk_T, ap.chunk_cap);
+  size_front_workspaces(ap);
 }
 
 // The 8x8x8x8 float32 kernel: work-group = (slice, channel, residue c of axis 0 mod 8);
@@ -483,13 +497,8 @@ int plan_front(ArrayPlan& ap, std::string* why) {
       // time chunk: the largest front output (after the last front pass) <= kFrontBytes
       const int64_t per_t = (int64_t)ap.F * MS * (ap.N / NS) * (int64_t)sizeof(float2);
       ap.chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kFrontBytes / per_t));
-      ap.front_elems = 0;
-      int64_t mm = 1, nn = ap.N;
-      for (int k = 0; k < s; ++k) {
-        mm *= 2 * ap.n[k];
-        nn /= ap.n[k];
-        ap.front_elems = std::max(ap.front_elems, ap.chunk_T * ap.F * mm * nn);
-      }
+      if (ap.chunk_cap > 0) ap.chunk_T = std::min(ap.chunk_T, ap.chunk_cap);
+      size_front_workspaces(ap);
       return OMNI_OK;
     }
   }
@@ -624,8 +633,8 @@ int alloc_array(ArrayPlan& ap) {
   HIP_TRY(hipMalloc(&ap.d_ws[0], ws));
   HIP_TRY(hipMalloc(&ap.d_ws[1], ws));
   if (ap.n_front > 0) {
-    HIP_TRY(hipMalloc(&ap.d_y[0], (size_t)ap.front_elems * sizeof(float2)));
-    HIP_TRY(hipMalloc(&ap.d_y[1], (size_t)ap.front_elems * sizeof(float2)));
+    for (int b = 0; b < 2; ++b)
+      if (ap.y_bytes[b] > 0) HIP_TRY(hipMalloc(&ap.d_y[b], (size_t)ap.y_bytes[b]));
   }
   HIP_TRY(hipMemcpy(ap.d_kmap, ap.fs.kmap.data(), ap.fs.kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   int32_t* d_desc = nullptr;
@@ -844,8 +853,8 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
 // Autotuner for the general fused kernel: times every candidate schedule
 // (longest short DFT lcap x work-group target of the time slicing) on an
 // all-zero input of a few samples with HIP events, keeps the fastest, and
-// remembers the choice in the file named by OMNI_TUNE_CACHE (one line per
-// array: key lcap wg_target ms), if set.
+// remembers the choice in the plan's tune_cache file (one line per array:
+// key lcap wg_target ms), if one is named.
 std::string tune_key(const ArrayPlan& ap, omni_dtype dtype) {
   std::string k = "gfx950:";
   for (int v : ap.n) k += std::to_string(v) + "x";
@@ -853,10 +862,9 @@ std::string tune_key(const ArrayPlan& ap, omni_dtype dtype) {
   return k;
 }
 
-bool tune_cache_lookup(const std::string& key, int* lcap, int* wgt) {
-  const char* path = std::getenv("OMNI_TUNE_CACHE");
-  if (!path) return false;
-  FILE* fp = std::fopen(path, "r");
+bool tune_cache_lookup(const std::string& path, const std::string& key, int* lcap, int* wgt) {
+  if (path.empty()) return false;
+  FILE* fp = std::fopen(path.c_str(), "r");
   if (!fp) return false;
   char k[256];
   int a, b;
@@ -872,10 +880,9 @@ bool tune_cache_lookup(const std::string& key, int* lcap, int* wgt) {
   return found;
 }
 
-void tune_cache_store(const std::string& key, int lcap, int wgt, double ms) {
-  const char* path = std::getenv("OMNI_TUNE_CACHE");
-  if (!path) return;
-  FILE* fp = std::fopen(path, "a");
+void tune_cache_store(const std::string& path, const std::string& key, int lcap, int wgt, double ms) {
+  if (path.empty()) return;
+  FILE* fp = std::fopen(path.c_str(), "a");
   if (!fp) return;
   std::fprintf(fp, "%s %d %d %.4f\n", key.c_str(), lcap, wgt, ms);
   std::fclose(fp);
@@ -890,7 +897,7 @@ int tune_array(omni_plan_s* p, ArrayPlan& ap) {
   const bool ct = ap.kernel == 3;
   const std::string key = tune_key(ap, p->dtype);
   int lc = 0, wg = 0;
-  const bool cached = tune_cache_lookup(key, &lc, &wg);
+  const bool cached = p->tune == OMNI_TUNE_CACHE && tune_cache_lookup(p->tune_cache, key, &lc, &wg);
   const bool front = ap.n_front > 0;
   const std::vector<int> axes = front ? std::vector<int>(ap.n.begin() + ap.n_front, ap.n.end()) : ap.n;
   const int Fk = ap.fs.F;
@@ -951,7 +958,7 @@ int tune_array(omni_plan_s* p, ArrayPlan& ap) {
     ap.wg_target = best_wg;
     ap.tuned_ms = best;
     HIP_TRY(hipMemcpy(ap.d_kmap, ap.fs.kmap.data(), ap.fs.kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (!cached) tune_cache_store(key, best_lc, best_wg, best);
+    if (!cached) tune_cache_store(p->tune_cache, key, best_lc, best_wg, best);
   }
   return OMNI_OK;
 }
@@ -1049,13 +1056,15 @@ bool same_call(const omni_plan_s* p, const void* const* volt, int64_t T, void* c
 int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, const omni_opts* opts) {
   if (!out) return fail(OMNI_E_INVAL, "out is NULL");
   *out = nullptr;
-  omni_opts o{OMNI_CF32, OMNI_FORM_FP32, 0, 0};
+  omni_opts o{OMNI_CF32, OMNI_FORM_FP32, 0, 0, OMNI_TUNE_OFF, nullptr, 0};
   if (opts) o = *opts;
   if (o.dtype < OMNI_CF32 || o.dtype > OMNI_CI4) return fail(OMNI_E_INVAL, "unknown dtype");
   if (o.form != OMNI_FORM_FP32 && o.form != OMNI_FORM_MIXED) return fail(OMNI_E_INVAL, "unknown form");
   if (o.time_block < 0) return fail(OMNI_E_INVAL, "time_block < 0");
-  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING | OMNI_PLAN_TUNE | OMNI_PLAN_GRAPH))
+  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING | OMNI_PLAN_GRAPH))
     return fail(OMNI_E_INVAL, "unknown plan flag");
+  if (o.tune < OMNI_TUNE_OFF || o.tune > OMNI_TUNE_SEARCH) return fail(OMNI_E_INVAL, "unknown tune mode");
+  if (o.chunk_T < 0) return fail(OMNI_E_INVAL, "chunk_T < 0");
   omni_plan_s* p = new (std::nothrow) omni_plan_s;
   if (!p) return fail(OMNI_E_NOMEM, "host allocation failed");
   p->dtype = o.dtype;
@@ -1066,8 +1075,11 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   p->time_block = o.time_block > 0 ? o.time_block : (o.form == OMNI_FORM_MIXED ? 1024 : 64);
   p->host_only = (o.flags & OMNI_PLAN_HOST_ONLY) != 0;
   p->timing = (o.flags & OMNI_PLAN_TIMING) != 0 && !p->host_only;
+  p->tune = o.tune;
+  if (o.tune_cache) p->tune_cache = o.tune_cache;
   p->arrays.resize(arrays.size());
   for (size_t i = 0; i < arrays.size(); ++i) {
+    p->arrays[i].chunk_cap = o.chunk_T;
     int rc = build_array(p->arrays[i], arrays[i].levels, arrays[i].dims, arrays[i].A, arrays[i].nchan, p->form,
                          p->dtype);
     if (rc) {
@@ -1102,7 +1114,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
     }
     for (auto& ap : p->arrays) {
       rc = alloc_array(ap);
-      if (rc == OMNI_OK && (o.flags & OMNI_PLAN_TUNE)) rc = tune_array(p, ap);
+      if (rc == OMNI_OK && p->tune != OMNI_TUNE_OFF) rc = tune_array(p, ap);
       if (rc) {
         destroy_plan_resources(p);
         delete p;

@@ -132,3 +132,89 @@ def test_stage_times_need_a_timing_plan():
     with pytest.raises(omni.OmniError) as ei:
         p.stage_times("call")
     assert omni.STATUS[ei.value.code] == "OMNI_E_STATE"
+
+
+def test_tune_and_chunk_options_are_validated():
+    """An unknown tune mode or a negative chunk cap is refused by the C ABI."""
+    dims = np.array([[4, 4]], dtype=np.int32)
+    h = ctypes.c_void_p()
+    for tune, chunk in ((3, 0), (-1, 0), (0, -5)):
+        opts = omni._Opts(omni.DTYPES["ci8"], omni.FORMS["fp32"], 0, omni.PLAN_HOST_ONLY, tune, None, chunk)
+        rc = omni.lib.omni_plan(ctypes.byref(h), 1, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 1,
+                                ctypes.byref(opts))
+        assert omni.STATUS[rc] == "OMNI_E_INVAL", (tune, chunk)
+    with pytest.raises(ValueError):
+        omni.Plan([[4, 4]], None, 1, "ci8", host_only=True, tune="sometimes")
+
+
+@pytest.mark.parametrize("form", ["fp32", "mixed"])
+def test_chunk_cap_sets_front_chunk(form):
+    """The chunk_T option caps the front passes' time chunk (a grid that needs front passes)."""
+    import json
+
+    ld = [[2, 16], [16, 16]]
+    free = json.loads(omni.Plan(ld, None, 2, "ci4", form, host_only=True).describe())["arrays"][0]
+    assert free["mode"] == "front" and free["chunk_T"] == 256
+    capped = json.loads(omni.Plan(ld, None, 2, "ci4", form, host_only=True, chunk_T=7).describe())["arrays"][0]
+    assert capped["chunk_T"] == 7
+
+
+def _host_plan(dtype, level_dims=((4, 4),), F=3, batch=None):
+    if batch is not None:
+        return omni.Plan(batch=batch, dtype=dtype, host_only=True)
+    return omni.Plan([list(ld) for ld in level_dims], None, F, dtype, host_only=True)
+
+
+@pytest.mark.parametrize(
+    "dtype, make, match",
+    [
+        ("ci8", lambda: np.zeros((2, 3, 16, 2), np.int8), "torch tensor"),
+        ("ci8", lambda: __import__("torch").zeros((2, 3, 16, 2), dtype=__import__("torch").int16), "int8"),
+        ("ci8", lambda: __import__("torch").zeros((2, 3, 16), dtype=__import__("torch").int8), "shape"),
+        ("ci8", lambda: __import__("torch").zeros((2, 3, 15, 2), dtype=__import__("torch").int8), "shape"),
+        ("ci8", lambda: __import__("torch").zeros((2, 2, 16, 2), dtype=__import__("torch").int8), "shape"),
+        ("ci4", lambda: __import__("torch").zeros((2, 3, 16, 2), dtype=__import__("torch").uint8), "shape"),
+        ("ci4", lambda: __import__("torch").zeros((2, 3, 16), dtype=__import__("torch").float32), "uint8"),
+        ("cf32", lambda: __import__("torch").zeros((2, 3, 16), dtype=__import__("torch").float32), "shape"),
+        ("cf32", lambda: __import__("torch").zeros((2, 3, 16, 2), dtype=__import__("torch").float64), "float32"),
+        ("ci8", lambda: __import__("torch").zeros((2, 3, 2, 16), dtype=__import__("torch").int8).transpose(2, 3),
+         "contiguous"),
+        ("ci8", lambda: __import__("torch").zeros((2, 3, 16, 2), dtype=__import__("torch").int8), "on the GPU"),
+    ],
+)
+def test_binding_rejects_bad_voltages_before_any_device_call(dtype, make, match):
+    """A mis-typed, mis-shaped, strided or host-resident voltage tensor raises ValueError in the binding; the
+    library is never reached (a host-only plan would answer OMNI_E_STATE)."""
+    p = _host_plan(dtype)
+    with pytest.raises(ValueError, match=match):
+        p.correlate(make())
+    if dtype != "cf32":
+        with pytest.raises(ValueError, match=match):
+            p.direct_correlate(make())
+
+
+def test_binding_rejects_bad_outputs_and_batches():
+    import torch
+
+    p = _host_plan("ci8")
+    good_shape = p.vis_shape()
+    volt = torch.zeros((2, 3, 16, 2), dtype=torch.int8)
+    for bad, match in (
+        (torch.zeros(good_shape, dtype=torch.complex128), "complex64"),
+        (torch.zeros((3, 7, 8), dtype=torch.complex64), "shape"),
+        (torch.zeros(good_shape[::-1], dtype=torch.complex64).permute(2, 1, 0), "contiguous"),
+        (torch.zeros(good_shape, dtype=torch.complex64), "on the GPU"),
+    ):
+        with pytest.raises(ValueError, match=match):
+            p._check_out(bad, 0, None)
+    with pytest.raises(ValueError, match="batch plan"):
+        _host_plan("ci8", batch=[([[4, 4]], None, 3), ([[2, 2]], None, 1)]).correlate(volt)
+    bp = _host_plan("ci8", batch=[([[4, 4]], None, 3), ([[2, 2]], None, 1)])
+    with pytest.raises(ValueError, match="expected 2 voltage tensors"):
+        bp.correlate_batch([volt])
+    with pytest.raises(ValueError, match="same number of samples"):
+        bp.correlate_batch([volt, torch.zeros((5, 1, 4, 2), dtype=torch.int8)])
+    with pytest.raises(ValueError, match="shape"):
+        bp.correlate_batch([volt, torch.zeros((2, 3, 16, 2), dtype=torch.int8)])
+    with pytest.raises(ValueError, match="accumulator buffer"):
+        p.accumulator_get(np.zeros(3))

@@ -65,6 +65,14 @@ def gpu_vis(level_dims, raw_cpu, dtype, form="fp32", F=None, **kw):
     return vis.cpu().numpy(), plan
 
 
+def chunk_count(plan, T, array=0):
+    """Time chunks the plan's front passes take for T samples (1 for a grid without front passes)."""
+    import json
+
+    a = json.loads(plan.describe())["arrays"][array]
+    return -(-T // a["chunk_T"]) if a["n_front"] else 1
+
+
 # ---------------------------------------------------------------------------
 
 
@@ -171,35 +179,43 @@ def test_empty_time_gives_zero():
 
 
 @pytest.mark.parametrize(
-    "level_dims,T,split",
+    "level_dims,T,split,form,chunk_T",
     [
-        ([[4, 4], [2, 4]], 50, 20),  # general kernel
-        ([[32, 32]], 50, 20),  # compile-time-shape kernel
-        ([[2, 2], [8, 8], [4, 4]], 150, 70),  # front passes, several time chunks, compile-time-shape kernel
-        ([[4, 4], [4, 4], [4, 4]], 150, 70),  # front passes, general kernel
+        ([[4, 4], [2, 4]], 50, 20, "fp32", 0),  # general kernel
+        ([[32, 32]], 50, 20, "fp32", 0),  # compile-time-shape kernel
+        ([[2, 2], [8, 8], [4, 4]], 150, 70, "fp32", 32),  # front passes, 3 + 3 chunks, compile-time-shape kernel
+        ([[4, 4], [4, 4], [4, 4]], 150, 70, "fp32", 32),  # front passes, 3 + 3 chunks, general kernel
+        ([[8, 8], [8, 8]], 50, 21, "mixed", 0),  # 8x8x8x8 matrix-core kernel
+        ([[2, 16], [16, 16]], 60, 25, "mixed", 8),  # front pass + (16,16,16) matrix-core kernel, 4 + 5 chunks
+        ([[2, 2], [8, 8], [4, 4]], 60, 25, "mixed", 8),  # front passes + (8,8,4,4) matrix-core kernel
     ],
 )
-def test_split_integration_and_resume(level_dims, T, split):
-    """T = T1 + T2 with OMNI_NO_RESET, and a checkpoint/resume of the accumulator, equal one call."""
+def test_split_integration_and_resume(level_dims, T, split, form, chunk_T):
+    """T = T1 + T2 with OMNI_NO_RESET, and a checkpoint/resume of the accumulator, equal one call (front paths
+    with several time chunks on both sides of the split)."""
     N = math.prod(dims_of(level_dims))
     gen = torch.Generator().manual_seed(5)
     raw = random_raw("ci8", T, 2, N, gen).cuda()
-    say("split/resume", level_dims, T, split)
-    plan = omni.Plan(level_dims, None, 2, "ci8")
+    say("split/resume", level_dims, form, T, split, "chunk_T", chunk_T)
+    plan = omni.Plan(level_dims, None, 2, "ci8", form, chunk_T=chunk_T)
+    if chunk_T:
+        assert chunk_count(plan, split) >= 3 and chunk_count(plan, T - split) >= 3
     full = plan.correlate(raw).clone()
     plan.correlate(raw[:split].contiguous(), flags=omni.NO_FINALIZE)
     part = plan.correlate(raw[split:].contiguous(), flags=omni.NO_RESET)
     torch.cuda.synchronize()
-    assert torch.allclose(full, part, rtol=0, atol=1e-6 * full.abs().max().item())
+    tol = 1e-6 if form == "fp32" else 1e-5  # the split changes the float32 blocks' rounding only
+    assert torch.allclose(full, part, rtol=0, atol=tol * full.abs().max().item())
     # checkpoint after `split` samples, resume in a fresh plan
     plan.correlate(raw[:split].contiguous(), flags=omni.NO_FINALIZE)
     ck = np.zeros(plan.accumulator_bytes() // 8)
     plan.accumulator_get(ck)
-    plan2 = omni.Plan(level_dims, None, 2, "ci8")
+    plan2 = omni.Plan(level_dims, None, 2, "ci8", form, chunk_T=chunk_T)
     plan2.accumulator_set(ck)
     resumed = plan2.correlate(raw[split:].contiguous(), flags=omni.NO_RESET)
     torch.cuda.synchronize()
-    assert torch.allclose(full, resumed, rtol=0, atol=1e-6 * full.abs().max().item())
+    assert torch.allclose(full, resumed, rtol=0, atol=tol * full.abs().max().item())
+    assert rel_err(resumed.cpu().numpy(), oracle_vis(raw.cpu(), "ci8", level_dims)) <= TOL[form]
 
 
 def test_bitwise_deterministic():
@@ -302,7 +318,7 @@ def test_mixed_other_shapes_fall_back_to_fp32_kernel():
     ],
 )
 def test_front_mode_full_oracle(level_dims, dtype, T):
-    """Shapes whose grid needs front passes; T=150 spans several time chunks of the front workspace."""
+    """Shapes whose grid needs front passes, at the planner's chunking (one chunk of up to 256 samples)."""
     N = math.prod(dims_of(level_dims))
     gen = torch.Generator().manual_seed(N + T)
     raw = random_raw(dtype, T, 3, N, gen)
@@ -310,6 +326,36 @@ def test_front_mode_full_oracle(level_dims, dtype, T):
     vis, plan = gpu_vis(level_dims, raw, dtype)
     assert '"mode":"front"' in plan.describe()
     assert rel_err(vis, oracle_vis(raw, dtype, level_dims)) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize(
+    "level_dims,dtype,form,T,chunk_T,kernel",
+    [
+        ([[4, 4], [4, 4], [4, 4]], "ci8", "fp32", 150, 40, "fused_fp32"),  # general kernel, 4 chunks
+        ([[4, 4], [4, 4], [4, 4]], "ci4", "fp32", 7, 2, "fused_fp32"),  # ragged last chunk of 1 sample
+        ([[2, 2], [8, 8], [4, 4]], "ci8", "fp32", 70, 20, "fused_ct_fp32"),  # compile-time-shape kernel
+        ([[2, 16], [16, 16]], "ci4", "mixed", 9, 3, "fused16x3_mixed"),  # (16,16,16) matrix-core kernel
+        ([[2, 16], [16, 16]], "ci8", "mixed", 70, 20, "fused16x3_mixed"),
+        ([[2, 2], [8, 8], [4, 4]], "ci4", "mixed", 9, 3, "fused8844_mixed"),  # (8,8,4,4) matrix-core kernel
+        ([[2, 2], [8, 8], [4, 4]], "ci8", "mixed", 70, 20, "fused8844_mixed"),
+    ],
+)
+def test_front_chunks_full_oracle(level_dims, dtype, form, T, chunk_T, kernel):
+    """Front passes over at least three time chunks (the later chunks add into the first chunk's partial sums,
+    or the general kernel reduces after every chunk): every lag against the oracle."""
+    N = math.prod(dims_of(level_dims))
+    gen = torch.Generator().manual_seed(N + T + chunk_T)
+    raw = random_raw(dtype, T, 2, N, gen)
+    plan = omni.Plan(level_dims, None, 2, dtype, form, time_block=4, chunk_T=chunk_T)
+    desc = plan.describe()
+    say("front chunks", level_dims, dtype, form, "T", T, "chunk_T", chunk_T, desc[:160])
+    assert f'"kernel":"{kernel}"' in desc
+    assert chunk_count(plan, T) >= 3
+    vis = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    err = rel_err(vis.cpu().numpy(), oracle_vis(raw, dtype, level_dims))
+    say("front chunks error", err)
+    assert err <= TOL[form]
 
 
 @pytest.mark.parametrize("shape", [[[64, 64]], [[128, 128]]])
@@ -322,21 +368,10 @@ def test_large_single_level_grids(shape):
     assert rel_err(vis, oracle_vis(raw, "ci4", shape)) <= TOL["fp32"]
 
 
-def sampled_cells_check(w, T, F, n_random=96, seed=0, form="fp32", kernel=None):
-    """Full-size geometry, few samples: the oracle one cell at a time (all |Delta_k| <= 1 plus random
-    cells), zero lag of every channel, and a few Fourier cells of the visibility grid against the
-    oracle's time-summed power (Wiener-Khinchin)."""
-    dims = w.dims
-    raw = skysim.make_voltages(w, T=T, nchan=F, device="cuda")
-    plan = omni.Plan(w.level_dims, w.A, F, w.dtype, form)
-    desc = plan.describe()
-    say(w.name, desc[:200])
-    if kernel:
-        assert f'"kernel":"{kernel}"' in desc
-    vis = plan.correlate(raw)
-    torch.cuda.synchronize()
-    V = vis.cpu().numpy()
-    x = oracle.decode(raw.cpu().numpy(), w.dtype, T, F, w.N)
+def check_cells(V, x, dims, form, n_random=256, seed=0, tag=""):
+    """The oracle one cell at a time (all |Delta_k| <= 1 plus ``n_random`` random cells), and a few Fourier cells
+    of the visibility grid against the oracle's time-summed power (Wiener-Khinchin).  V: [F, 2n_1-1, ...]."""
+    F = V.shape[0]
     rng = np.random.default_rng(seed)
     near = np.array(np.meshgrid(*[[-1, 0, 1]] * len(dims), indexing="ij")).reshape(len(dims), -1).T
     far = np.stack([rng.integers(-(n - 1), n, n_random) for n in dims], axis=1)
@@ -345,7 +380,7 @@ def sampled_cells_check(w, T, F, n_random=96, seed=0, form="fp32", kernel=None):
     got = np.stack([V[(slice(None),) + tuple(dl + np.array(dims) - 1)] for dl in deltas], axis=1)
     z = np.abs(ref[:, len(near) // 2])  # Delta = 0 is the centre of the near block
     err = float(np.max(np.abs(got - ref) / z[:, None]))
-    say(w.name, "sampled-cell error", err)
+    say(tag, "sampled-cell error", err, "over", len(deltas), "cells")
     assert err <= TOL[form]
     kap = rng.integers(0, 2 * np.array(dims), (3, len(dims)))
     P = oracle.fourier_power(x, dims, kap)
@@ -358,9 +393,26 @@ def sampled_cells_check(w, T, F, n_random=96, seed=0, form="fp32", kernel=None):
             assert abs(val - P[f, q]) <= (1e-4 if form == "fp32" else 2e-3) * np.sum(np.abs(x[:, f]) ** 2), (f, k)
 
 
+def sampled_cells_check(w, T, F, n_random=256, seed=0, form="fp32", kernel=None, chunk_T=0):
+    """Full-size geometry, few samples: the oracle one cell at a time, and Fourier cells (check_cells)."""
+    dims = w.dims
+    raw = skysim.make_voltages(w, T=T, nchan=F, device="cuda")
+    plan = omni.Plan(w.level_dims, w.A, F, w.dtype, form, chunk_T=chunk_T)
+    desc = plan.describe()
+    say(w.name, desc[:200])
+    if kernel:
+        assert f'"kernel":"{kernel}"' in desc
+    if chunk_T:
+        assert chunk_count(plan, T) >= 3
+    vis = plan.correlate(raw)
+    torch.cuda.synchronize()
+    x = oracle.decode(raw.cpu().numpy(), w.dtype, T, F, w.N)
+    check_cells(vis.cpu().numpy(), x, dims, form, n_random, seed, w.name)
+
+
 def test_hier3_sampled_cells():
-    """The three-level 16x16 / 8x8 / 4x4 hierarchy (N = 262144, M = 16.8M cells) at full N."""
-    sampled_cells_check(skysim.WORKLOADS["hier3"], T=12, F=2)
+    """The three-level 16x16 / 8x8 / 4x4 hierarchy (N = 262144, M = 16.8M cells) at full N, 3 time chunks."""
+    sampled_cells_check(skysim.WORKLOADS["hier3"], T=12, F=2, chunk_T=4)
 
 
 def test_hier16x16_sampled_cells():
@@ -370,7 +422,7 @@ def test_hier16x16_sampled_cells():
 
 def test_mixed_16x3_small_full_oracle():
     """Mixed form behind a front pass: (2, 16, 16, 16) grid (float16 front workspace, the (16,16,16) matrix-core
-    kernel), every lag against the oracle, several time blocks and chunks."""
+    kernel), every lag against the oracle, several float32 time blocks in one chunk."""
     level_dims = [[2, 16], [16, 16]]
     N = math.prod(dims_of(level_dims))
     for dtype, T in (("ci4", 7), ("ci8", 70)):
@@ -386,7 +438,7 @@ def test_mixed_16x3_small_full_oracle():
 
 def test_mixed_8844_small_full_oracle():
     """Mixed form behind two front passes: (2, 2, 8, 8, 4, 4) grid (float16 front workspace, the (8,8,4,4)
-    matrix-core kernel), every lag against the oracle, several time blocks and chunks."""
+    matrix-core kernel), every lag against the oracle, several float32 time blocks in one chunk."""
     level_dims = [[2, 2], [8, 8], [4, 4]]
     N = math.prod(dims_of(level_dims))
     for dtype, T in (("ci4", 9), ("ci8", 70)):
@@ -401,13 +453,14 @@ def test_mixed_8844_small_full_oracle():
 
 
 def test_mixed_hier3_sampled_cells():
-    """The three-level hierarchy in the mixed form at full N: sampled cells and Fourier cells."""
-    sampled_cells_check(skysim.WORKLOADS["hier3"], T=12, F=2, form="mixed", kernel="fused8844_mixed")
+    """The three-level hierarchy in the mixed form at full N (fused 16x16 front pass, 3 time chunks): sampled
+    cells and Fourier cells."""
+    sampled_cells_check(skysim.WORKLOADS["hier3"], T=12, F=2, form="mixed", kernel="fused8844_mixed", chunk_T=4)
 
 
 def test_mixed_hier16x16_sampled_cells():
-    """The 16x16-of-16x16 array in the mixed form at full N: sampled cells and Fourier cells."""
-    sampled_cells_check(skysim.WORKLOADS["hier16x16"], T=10, F=3, form="mixed", kernel="fused16x3_mixed")
+    """The 16x16-of-16x16 array in the mixed form at full N (4 time chunks): sampled cells and Fourier cells."""
+    sampled_cells_check(skysim.WORKLOADS["hier16x16"], T=10, F=3, form="mixed", kernel="fused16x3_mixed", chunk_T=3)
 
 
 @pytest.mark.parametrize("level_dims,kernel", [([[32, 32]], "fused_ct_fp32"), ([[16, 32]], "fused_fp32")])
@@ -664,3 +717,85 @@ def test_fft_forms_against_direct_full_size(name):
         say(name, form, "max |V - V_direct| / V[0]:", e)
         assert e <= TOL[form]
         del v
+
+
+# ---------------------------------------------------------------------------
+# Every cell of a full-size three-level grid against the oracle, on a subset of the input (2 channels x 16
+# samples of the three-level workload's bytes), and the batched workload's four shapes as one mixed graph plan.
+
+
+@pytest.fixture(scope="module")
+def hier3_subset():
+    w = skysim.WORKLOADS["hier3"]
+    T, F = 16, 2
+    raw = skysim.make_voltages(w, T=T, nchan=F, device="cuda")
+    x = oracle.decode(raw.cpu().numpy(), w.dtype, T, F, w.N)
+    say("hier3 subset: oracle on every cell (pair sum grouped by the outer level's lag)")
+    ref = oracle.visibilities_by_outer_lag(x, w.dims, 2)
+    say("hier3 subset: oracle done")
+    return w, raw, ref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("form,kernel", [("mixed", "fused8844_mixed"), ("fp32", "fused_ct_fp32")])
+def test_hier3_every_cell_on_input_subset(hier3_subset, form, kernel):
+    """N = 262144 at full size, 2 channels x T = 16 in 4 time chunks (5 + 5 + 5 + 1 samples): all 10.6M cells
+    per channel against the exact oracle."""
+    w, raw, ref = hier3_subset
+    plan = omni.Plan(w.level_dims, w.A, 2, w.dtype, form, chunk_T=5)
+    assert f'"kernel":"{kernel}"' in plan.describe()
+    assert chunk_count(plan, 16) == 4
+    say("hier3 subset:", form)
+    vis = plan.correlate(raw)
+    torch.cuda.synchronize()
+    err = rel_err(vis.cpu().numpy(), ref)
+    say("hier3 subset", form, "max error / zero lag over every cell", err)
+    assert err <= TOL[form]
+
+
+C5_SHAPES = [[[32, 32]], [[64, 64]], [[128, 128]], [[16, 16], [16, 16]]]
+
+
+@pytest.mark.timeout(600)
+def test_mixed_batch_graph_c5_shapes():
+    """The batched workload's four arrays (32x32, 64x64, 128x128, 16x16-of-16x16) as one mixed-form graph plan at
+    reduced T and F: every lag of 32x32 and 64x64 against the oracle, sampled and Fourier cells of 128x128 and of
+    16^4 (3 time chunks); replays equal; a split integration (NO_FINALIZE then NO_RESET) in a second graph plan."""
+    T, F = 40, 2
+    gen = torch.Generator().manual_seed(2048)
+    raws = [random_raw("ci4", T, F, math.prod(dims_of(ld)), gen) for ld in C5_SHAPES]
+    volts = [r.cuda() for r in raws]
+    batch = [(ld, None, F) for ld in C5_SHAPES]
+    gp = omni.Plan(batch=batch, dtype="ci4", form="mixed", graph=True, chunk_T=16)
+    say("c5 mixed graph", gp.describe()[:400])
+    assert chunk_count(gp, T, 3) >= 3
+    outs = gp.correlate_batch(volts)
+    torch.cuda.synchronize()
+    first = [o.clone() for o in outs]
+    for ld, r, o in zip(C5_SHAPES, raws, first):
+        dims = dims_of(ld)
+        x = oracle.decode(r.numpy(), "ci4", T, F, math.prod(dims))
+        if math.prod(dims) <= 4096:
+            err = rel_err(o.cpu().numpy(), oracle.visibilities(x, dims).reshape(o.shape))
+            say("c5 mixed graph", ld, "every lag", err)
+            assert err <= TOL["mixed"]
+        else:
+            check_cells(o.cpu().numpy(), x, dims, "mixed", 256, 7, f"c5 mixed graph {ld}")
+    # a replay without outputs reuses the plan's output tensors and gives the same bytes
+    again = gp.correlate_batch(volts)
+    torch.cuda.synchronize()
+    assert all(a.data_ptr() == b.data_ptr() for a, b in zip(again, outs))
+    assert all(torch.equal(a, b) for a, b in zip(again, first))
+    # split integration through two graph plans (one per call shape)
+    gp1 = omni.Plan(batch=batch, dtype="ci4", form="mixed", graph=True, chunk_T=16)
+    gp2 = omni.Plan(batch=batch, dtype="ci4", form="mixed", graph=True, chunk_T=16)
+    gp1.correlate_batch([v[:17].contiguous() for v in volts], flags=omni.NO_FINALIZE)
+    ck = torch.empty(gp1.accumulator_bytes() // 8, dtype=torch.float64, device="cuda")
+    gp1.accumulator_get(ck)
+    gp2.accumulator_set(ck)
+    split = gp2.correlate_batch([v[17:].contiguous() for v in volts], flags=omni.NO_RESET)
+    torch.cuda.synchronize()
+    for ld, a, b in zip(C5_SHAPES, split, first):
+        e = rel_err(a.cpu().numpy(), b.cpu().numpy().astype(np.complex128))
+        say("c5 mixed graph split vs whole", ld, e)
+        assert e <= 1e-5

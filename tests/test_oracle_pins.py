@@ -244,6 +244,27 @@ def test_oracle_pin(pin):
     pin(oracle.visibilities)
 
 
+def _grouped(x, dims):
+    """visibilities_by_outer_lag with the outer half of the axes as tiles (a 1-D grid gains a unit outer axis)."""
+    dims = tuple(int(n) for n in dims)
+    if len(dims) == 1:
+        v = oracle.visibilities_by_outer_lag(x, (1,) + dims, 1)
+        return v.reshape((v.shape[0],) + oracle.lag_shape(dims))
+    return oracle.visibilities_by_outer_lag(x, dims, max(1, len(dims) // 2))
+
+
+@pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
+def test_grouped_oracle_pin(pin):
+    """The pair sum grouped by outer-level lag (used at full three-level size) passes every pin itself."""
+    pin(_grouped)
+
+
+@pytest.mark.parametrize("dims,n_outer", [((3, 2, 4, 3), 1), ((3, 2, 4, 3), 3), ((2, 2, 3, 3, 2, 2), 2)])
+def test_grouped_oracle_every_split(dims, n_outer):
+    x = rand_cplx((3, 2, math.prod(dims)))
+    assert np.array_equal(oracle.visibilities_by_outer_lag(x, dims, n_outer), oracle.visibilities(x, dims))
+
+
 def test_panelled_equals_unpanelled():
     dims = (4, 4, 3)
     x = rand_cplx((3, 2, 48))
