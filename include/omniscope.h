@@ -206,6 +206,24 @@ int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, v
  * limits above), OMNI_E_NOMEM, OMNI_E_HIP. */
 int omni_direct_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream);
 
+/* omni_direct_correlate for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation, arguments, layouts and errors, and the
+ * same visibilities bit for bit, but every buffer the direct correlator needs
+ * beyond volt and vis (the int64 half-sums, the block pairs and block boxes,
+ * which omni_direct_correlate allocates on its first call) lives in a fixed
+ * 64 MiB device array of the library, one per device, held until the process
+ * ends.  The call makes no device allocation.  It needs
+ *   F x prod_k(2 n_k - 1) x 16 + (N/128)(N/128 + 1) x 4 + (N/128) x 64 bytes
+ * (rounded to 256-byte blocks) of that array and returns OMNI_E_NOMEM, with
+ * the sizes in the message, when they exceed 64 MiB (8 x 8 tiles of 8 x 8
+ * antennas: up to 82 channels).  Every call on a device shares that device's
+ * array and overwrites what the last call left there, so calls that overlap
+ * on one device (another stream, another thread, another plan) race: order
+ * them on one stream.  The array's address is looked up on the first call on
+ * each device. */
+int omni_direct_correlate_noalloc(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream);
+
 /* Number of arrays in the plan (1 for omni_plan).  Planning metadata, no
  * passage of the paper.  Errors: OMNI_E_INVAL (NULL argument). */
 int omni_n_arrays(omni_plan_t plan, int32_t* n);

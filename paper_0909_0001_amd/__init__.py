@@ -46,6 +46,7 @@ EXPORTS = [
     "omni_correlate",
     "omni_correlate_batch",
     "omni_direct_correlate",
+    "omni_direct_correlate_noalloc",
     "omni_n_arrays",
     "omni_vis_shape",
     "omni_baselines",
@@ -108,6 +109,7 @@ def _load():
         "omni_correlate": (ctypes.c_int, [P, P, i64, P, P, u32]),
         "omni_correlate_batch": (ctypes.c_int, [P, ctypes.POINTER(P), i64, ctypes.POINTER(P), P, u32]),
         "omni_direct_correlate": (ctypes.c_int, [P, P, i64, P, P]),
+        "omni_direct_correlate_noalloc": (ctypes.c_int, [P, P, i64, P, P]),
         "omni_n_arrays": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
         "omni_vis_shape": (ctypes.c_int, [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
         "omni_baselines": (ctypes.c_int, [P, i32, ctypes.POINTER(ctypes.c_double)]),
@@ -320,7 +322,8 @@ class Plan:
         """Correlate device voltages [T, F, N(, 2)] -> complex64 visibilities [F, 2n_1-1, ...]."""
         if self.n_arrays != 1:
             raise ValueError("batch plan: use correlate_batch")
-        return self.correlate_batch([volt], flags=flags, outs=None if out is None else [out], stream=stream)[0]
+        outs = self.correlate_batch([volt], flags=flags, outs=None if out is None else [out], stream=stream)
+        return outs[0] if outs else None
 
     def direct_correlate(self, volt, out=None, stream=None):
         """Direct N^2 correlator (comparison baseline, integer samples): device [T, F, N(, 2)] -> complex64
@@ -335,6 +338,17 @@ class Plan:
             out = torch.empty(self.vis_shape(0), dtype=torch.complex64, device=volt.device)
         self._check_out(out, 0, volt)
         _check(lib.omni_direct_correlate(self._h, volt.data_ptr(), T, out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def direct_correlate_noalloc(self, volt, out, stream=None):
+        """``direct_correlate`` through the entry point that allocates nothing (the library's fixed device
+        scratch): ``out`` must be given; the binding allocates nothing either."""
+        if self.n_arrays != 1:
+            raise ValueError("the direct correlator takes single-array plans")
+        T = self._check_volt(volt)
+        self._check_volt_device(volt)
+        self._check_out(out, 0, volt)
+        _check(lib.omni_direct_correlate_noalloc(self._h, volt.data_ptr(), T, out.data_ptr(), _stream_handle(stream)))
         return out
 
     def correlate_batch(self, volts, flags: int = 0, outs=None, stream=None):

@@ -120,6 +120,7 @@ struct ArrayPlan {
   int32_t* d_dc_pairs = nullptr;
   int32_t* d_dc_blk = nullptr;
   int64_t dc_pairs = 0;
+  bool dc_geom_ok = false;   // dc_geom / dc_pairs derived and within the kernel's limits
   omni::DirectGeom dc_geom;
 };
 
@@ -1126,12 +1127,13 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   return OMNI_OK;
 }
 
-// Direct correlator set-up: blocks of 128 consecutive antennas, the coordinate box of each block, the block
-// pairs I <= J, and the int64 half-sum buffer.  Every pair's Delta box must fit the kernel's LDS bins; the
-// bound used is prod_k (2 max_B ext_k(B) + 1) over the blocks' per-axis extents.
-int direct_setup(ArrayPlan& ap) {
+// Direct correlator geometry (host only, allocates nothing): blocks of 128 consecutive antennas, the
+// strides of the centred output, the number of block pairs I <= J, and the check that every pair's Delta box
+// fits the kernel's LDS bins (bound: prod_k (2 max_B ext_k(B) + 1) over the blocks' per-axis extents).
+int direct_geometry(ArrayPlan& ap) {
   using omni::kDirectMaxD;
   using omni::kDirectTile;
+  if (ap.dc_geom_ok) return OMNI_OK;
   const int d = (int)ap.dims.size();
   if (d < 1 || d > kDirectMaxD) return fail(OMNI_E_SHAPE, "direct correlator: 1 to 8 axes");
   if (ap.N % kDirectTile != 0) return fail(OMNI_E_SHAPE, "direct correlator: N must be a multiple of 128");
@@ -1148,8 +1150,42 @@ int direct_setup(ArrayPlan& ap) {
     n_out *= 2 * (int64_t)ap.dims[(size_t)k] - 1;
   }
   g.n_out = n_out;
+  int ext[kDirectMaxD] = {}, lo[kDirectMaxD] = {}, hi[kDirectMaxD] = {}, c[kDirectMaxD] = {};
+  for (int64_t B = 0; B < nbk; ++B) {
+    for (int64_t r = 0; r < kDirectTile; ++r) {
+      int64_t a = B * kDirectTile + r;
+      for (int k = d - 1; k >= 0; --k) {
+        c[k] = (int)(a % ap.dims[(size_t)k]);
+        a /= ap.dims[(size_t)k];
+      }
+      for (int k = 0; k < d; ++k) {
+        lo[k] = r == 0 ? c[k] : std::min(lo[k], c[k]);
+        hi[k] = r == 0 ? c[k] : std::max(hi[k], c[k]);
+      }
+    }
+    for (int k = 0; k < d; ++k) ext[k] = std::max(ext[k], hi[k] - lo[k]);
+  }
+  int64_t box = 1;
+  for (int k = 0; k < d; ++k) box *= 2 * (int64_t)ext[k] + 1;
+  if (box > omni::kDirectMaxBins)
+    return fail(OMNI_E_SHAPE, "direct correlator: a block pair spans " + std::to_string(box) +
+                                  " index differences (at most " + std::to_string(omni::kDirectMaxBins) + ")");
+  ap.dc_pairs = n_pairs;
+  ap.dc_geom = g;
+  ap.dc_geom_ok = true;
+  return OMNI_OK;
+}
+
+// Direct correlator buffers of omni_direct_correlate (allocated by its first call): the block boxes, the block
+// pairs I <= J (I-major), and the int64 half-sum buffer.
+int direct_setup(ArrayPlan& ap) {
+  using omni::kDirectMaxD;
+  using omni::kDirectTile;
+  int rc = direct_geometry(ap);
+  if (rc) return rc;
+  const int d = (int)ap.dims.size();
+  const int64_t nbk = ap.N / kDirectTile;
   std::vector<int32_t> blk((size_t)(nbk * kDirectMaxD * 2), 0);
-  std::vector<int> ext((size_t)d, 0);
   std::vector<int> c((size_t)d, 0);
   for (int64_t B = 0; B < nbk; ++B) {
     int32_t* b = &blk[(size_t)(B * kDirectMaxD * 2)];
@@ -1164,14 +1200,8 @@ int direct_setup(ArrayPlan& ap) {
         if (r == 0 || c[(size_t)k] > b[2 * k + 1]) b[2 * k + 1] = c[(size_t)k];
       }
     }
-    for (int k = 0; k < d; ++k) ext[(size_t)k] = std::max(ext[(size_t)k], b[2 * k + 1] - b[2 * k]);
   }
-  int64_t box = 1;
-  for (int k = 0; k < d; ++k) box *= 2 * (int64_t)ext[(size_t)k] + 1;
-  if (box > omni::kDirectMaxBins)
-    return fail(OMNI_E_SHAPE, "direct correlator: a block pair spans " + std::to_string(box) +
-                                  " index differences (at most " + std::to_string(omni::kDirectMaxBins) + ")");
-  std::vector<int32_t> pairs((size_t)(2 * n_pairs));
+  std::vector<int32_t> pairs((size_t)(2 * ap.dc_pairs));
   size_t q = 0;
   for (int64_t I = 0; I < nbk; ++I)
     for (int64_t J = I; J < nbk; ++J) {
@@ -1180,11 +1210,44 @@ int direct_setup(ArrayPlan& ap) {
     }
   HIP_TRY(hipMalloc(&ap.d_dc_blk, blk.size() * sizeof(int32_t)));
   HIP_TRY(hipMalloc(&ap.d_dc_pairs, pairs.size() * sizeof(int32_t)));
-  HIP_TRY(hipMalloc(&ap.d_dc_G, (size_t)ap.F * (size_t)n_out * 2 * sizeof(unsigned long long)));
+  HIP_TRY(hipMalloc(&ap.d_dc_G, (size_t)ap.F * (size_t)ap.dc_geom.n_out * 2 * sizeof(unsigned long long)));
   HIP_TRY(hipMemcpy(ap.d_dc_blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ap.d_dc_pairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  ap.dc_pairs = n_pairs;
-  ap.dc_geom = g;
+  return OMNI_OK;
+}
+
+// Argument checks shared by both direct-correlator entry points.
+int direct_check_args(omni_plan_t plan, const void* volt, int64_t T, const void* vis) {
+  if (!plan) return fail(OMNI_E_INVAL, "plan is NULL");
+  if (plan->host_only) return fail(OMNI_E_STATE, "plan was made with OMNI_PLAN_HOST_ONLY");
+  if (plan->arrays.size() != 1) return fail(OMNI_E_STATE, "direct correlator: single-array plans only");
+  if (plan->dtype != OMNI_CI8 && plan->dtype != OMNI_CI4)
+    return fail(OMNI_E_STATE, "direct correlator: integer samples (ci8, ci4) only");
+  if (T < 0) return fail(OMNI_E_INVAL, "T < 0");
+  if (T > 0 && !volt) return fail(OMNI_E_INVAL, "volt is NULL");
+  if (!vis) return fail(OMNI_E_INVAL, "vis is NULL");
+  const int sb = plan->dtype == OMNI_CI8 ? 2 : 1;
+  if (T > 0 && (reinterpret_cast<uintptr_t>(volt) & (uintptr_t)(4 * sb - 1)))
+    return fail(OMNI_E_INVAL, sb == 2 ? "voltage pointer not 8-byte aligned" : "voltage pointer not 4-byte aligned");
+  int cur = -1;
+  hipGetDevice(&cur);
+  if (cur != plan->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
+  return OMNI_OK;
+}
+
+// The launches of one direct-correlator call on buffers G (int64 half-sums), pairs and blk.
+int direct_run(omni_plan_t plan, ArrayPlan& ap, const void* volt, int64_t T, void* vis, hipStream_t st,
+               unsigned long long* G, const int32_t* pairs, const int32_t* blk) {
+  const omni::DirectGeom& g = ap.dc_geom;
+  const int sb = plan->dtype == OMNI_CI8 ? 2 : 1;
+  HIP_TRY(omni::launch_direct_zero(G, (int64_t)ap.F * g.n_out * 2, st));
+  const int64_t tstride = (int64_t)ap.F * ap.N * sb;  // bytes per time sample
+  for (int64_t t0 = 0; t0 < T; t0 += omni::kDirectMaxT) {
+    const int64_t tc = std::min<int64_t>(omni::kDirectMaxT, T - t0);
+    HIP_TRY(omni::launch_direct_tiles((int)plan->dtype, static_cast<const uint8_t*>(volt) + t0 * tstride, tc, ap.N,
+                                      ap.F, pairs, ap.dc_pairs, blk, g, G, st));
+  }
+  HIP_TRY(omni::launch_direct_finalize(G, vis, g.n_out, ap.F, st));
   return OMNI_OK;
 }
 
@@ -1272,36 +1335,47 @@ int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, voi
 
 int omni_direct_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream) {
   try {
-    if (!plan) return fail(OMNI_E_INVAL, "plan is NULL");
-    if (plan->host_only) return fail(OMNI_E_STATE, "plan was made with OMNI_PLAN_HOST_ONLY");
-    if (plan->arrays.size() != 1) return fail(OMNI_E_STATE, "direct correlator: single-array plans only");
-    if (plan->dtype != OMNI_CI8 && plan->dtype != OMNI_CI4)
-      return fail(OMNI_E_STATE, "direct correlator: integer samples (ci8, ci4) only");
-    if (T < 0) return fail(OMNI_E_INVAL, "T < 0");
-    if (T > 0 && !volt) return fail(OMNI_E_INVAL, "volt is NULL");
-    if (!vis) return fail(OMNI_E_INVAL, "vis is NULL");
-    const int sb = plan->dtype == OMNI_CI8 ? 2 : 1;
-    if (T > 0 && (reinterpret_cast<uintptr_t>(volt) & (uintptr_t)(4 * sb - 1)))
-      return fail(OMNI_E_INVAL, sb == 2 ? "voltage pointer not 8-byte aligned" : "voltage pointer not 4-byte aligned");
-    int cur = -1;
-    hipGetDevice(&cur);
-    if (cur != plan->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
+    int rc = direct_check_args(plan, volt, T, vis);
+    if (rc) return rc;
     ArrayPlan& ap = plan->arrays[0];
     if (!ap.d_dc_G) {
-      const int rc = direct_setup(ap);
+      rc = direct_setup(ap);
       if (rc) return rc;
     }
+    return direct_run(plan, ap, volt, T, vis, reinterpret_cast<hipStream_t>(stream), ap.d_dc_G, ap.d_dc_pairs,
+                      ap.d_dc_blk);
+  } catch (...) {
+    return fail(OMNI_E_NOMEM, "unexpected host exception");
+  }
+}
+
+int omni_direct_correlate_noalloc(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream) {
+  try {
+    int rc = direct_check_args(plan, volt, T, vis);
+    if (rc) return rc;
+    ArrayPlan& ap = plan->arrays[0];
+    rc = direct_geometry(ap);
+    if (rc) return rc;
+    // scratch layout: int64 half-sums G [F][cells][2], then the block pairs, then the block boxes
+    const int64_t nbk = ap.N / omni::kDirectTile;
+    const size_t g_bytes = (size_t)ap.F * (size_t)ap.dc_geom.n_out * 2 * sizeof(unsigned long long);
+    const size_t p_bytes = (size_t)(2 * ap.dc_pairs) * sizeof(int32_t);
+    const size_t b_bytes = (size_t)(nbk * omni::kDirectMaxD * 2) * sizeof(int32_t);
+    const size_t p_off = (g_bytes + 255) / 256 * 256, b_off = p_off + (p_bytes + 255) / 256 * 256;
+    const size_t need = b_off + b_bytes, cap = omni::direct_noalloc_capacity();
+    if (need > cap)
+      return fail(OMNI_E_NOMEM, "direct correlator without allocation: the call needs " + std::to_string(need) +
+                                    " bytes of scratch (F x cells x 16 + block lists), the fixed scratch holds " +
+                                    std::to_string(cap));
+    void* base = nullptr;
+    HIP_TRY(omni::direct_noalloc_scratch(&base));
+    char* sp = static_cast<char*>(base);
+    auto* G = reinterpret_cast<unsigned long long*>(sp);
+    auto* pairs = reinterpret_cast<int32_t*>(sp + p_off);
+    auto* blk = reinterpret_cast<int32_t*>(sp + b_off);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const omni::DirectGeom& g = ap.dc_geom;
-    HIP_TRY(omni::launch_direct_zero(ap.d_dc_G, (int64_t)ap.F * g.n_out * 2, st));
-    const int64_t tstride = (int64_t)ap.F * ap.N * sb;  // bytes per time sample
-    for (int64_t t0 = 0; t0 < T; t0 += omni::kDirectMaxT) {
-      const int64_t tc = std::min<int64_t>(omni::kDirectMaxT, T - t0);
-      HIP_TRY(omni::launch_direct_tiles((int)plan->dtype, static_cast<const uint8_t*>(volt) + t0 * tstride, tc, ap.N,
-                                        ap.F, ap.d_dc_pairs, ap.dc_pairs, ap.d_dc_blk, g, ap.d_dc_G, st));
-    }
-    HIP_TRY(omni::launch_direct_finalize(ap.d_dc_G, vis, g.n_out, ap.F, st));
-    return OMNI_OK;
+    HIP_TRY(omni::launch_direct_setup(ap.dc_geom, nbk, blk, pairs, st));
+    return direct_run(plan, ap, volt, T, vis, st, G, pairs, blk);
   } catch (...) {
     return fail(OMNI_E_NOMEM, "unexpected host exception");
   }

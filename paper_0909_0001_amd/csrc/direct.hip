@@ -268,7 +268,83 @@ __global__ void direct_zero_kernel(unsigned long long* __restrict__ p, int64_t n
     p[i] = 0ull;
 }
 
+// Block boxes and block pairs of the no-allocation entry point, built on the device: blk[B][k] = (min, max)
+// of axis k's index over the kDirectTile consecutive antennas of block B; pairs = every (I, J), I <= J, in the
+// order I-major (the same list the planner builds on the host).
+__global__ void direct_setup_kernel(DirectGeom g, int64_t nbk, int32_t* __restrict__ blk, int32_t* __restrict__ pairs) {
+  const int64_t n_pairs = nbk * (nbk + 1) / 2;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nbk + n_pairs;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nbk) {
+      int lo[kDirectMaxD], hi[kDirectMaxD];
+      for (int r = 0; r < kDirectTile; ++r) {
+        int64_t a = i * kDirectTile + r;
+        for (int k = g.d - 1; k >= 0; --k) {
+          const int c = (int)(a % g.n[k]);
+          a /= g.n[k];
+          lo[k] = r == 0 ? c : min(lo[k], c);
+          hi[k] = r == 0 ? c : max(hi[k], c);
+        }
+      }
+      for (int k = 0; k < kDirectMaxD; ++k) {
+        blk[(i * kDirectMaxD + k) * 2] = k < g.d ? lo[k] : 0;
+        blk[(i * kDirectMaxD + k) * 2 + 1] = k < g.d ? hi[k] : 0;
+      }
+    } else {
+      // pair q -> (I, J): the rows before row I hold S(I) = I nbk - I (I - 1) / 2 pairs, and
+      // q = S(I) + (J - I); I is the largest row with S(I) <= q (a float64 root, then corrected)
+      const int64_t q = i - nbk;
+      auto S = [&](int64_t r) { return r * nbk - r * (r - 1) / 2; };
+      const double b = 2.0 * (double)nbk + 1.0;
+      int64_t I = (int64_t)((b - sqrt(b * b - 8.0 * (double)q)) / 2.0);
+      I = max<int64_t>(0, min<int64_t>(I, nbk - 1));
+      while (I > 0 && S(I) > q) --I;
+      while (I + 1 < nbk && S(I + 1) <= q) ++I;
+      pairs[2 * q] = (int32_t)I;
+      pairs[2 * q + 1] = (int32_t)(I + (q - S(I)));
+    }
+  }
+}
+
 }  // namespace dc
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the no-allocation entry point (omni_direct_correlate_noalloc): the int64 half-sums,
+// the block pairs and the block boxes live in this array instead of buffers the library allocates.  Every
+// call on a device shares that device's copy, which keeps the last call's contents; calls that overlap on
+// one device race.  Host code uses the address resolved per device by direct_noalloc_scratch, never the
+// array's name.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+size_t direct_noalloc_capacity() { return kNoAllocScratchBytes; }
+
+// The device address of `scratch` on the current device, resolved once per device (the first call on a
+// device, with that device current).  Returns hipSuccess and sets *ptr, or the HIP error of the lookup.
+hipError_t direct_noalloc_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_direct_setup(const DirectGeom& g, int64_t nbk, int32_t* blk, int32_t* pairs, hipStream_t st) {
+  const int64_t items = nbk + nbk * (nbk + 1) / 2;
+  if (items <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((items + 255) / 256, 4096);
+  dc::direct_setup_kernel<<<(unsigned)blocks, 256, 0, st>>>(g, nbk, blk, pairs);
+  return hipGetLastError();
+}
 
 hipError_t launch_direct_zero(unsigned long long* G, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;

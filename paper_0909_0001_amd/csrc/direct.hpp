@@ -22,5 +22,10 @@ hipError_t launch_direct_tiles(int fmt, const void* src, int64_t T, int64_t N, i
                                int64_t n_pairs, const int32_t* blk, const DirectGeom& g, unsigned long long* G,
                                hipStream_t st);
 hipError_t launch_direct_finalize(const unsigned long long* G, void* vis, int64_t n_out, int F, hipStream_t st);
+// The no-allocation entry point's fixed device scratch (direct.hip): its size, its address on the current device
+// (resolved once per device), and the kernel that builds the block boxes and block pairs in it.
+size_t direct_noalloc_capacity();
+hipError_t direct_noalloc_scratch(void** ptr);
+hipError_t launch_direct_setup(const DirectGeom& g, int64_t nbk, int32_t* blk, int32_t* pairs, hipStream_t st);
 
 }  // namespace omni
