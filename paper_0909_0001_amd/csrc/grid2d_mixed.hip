@@ -109,10 +109,15 @@ __device__ __forceinline__ half4 to_half4(float a, float b, float c, float d) {
 __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __restrict__ src, int64_t T,
                                                             int64_t t_per_slice, const float2* __restrict__ tw,
                                                             double* __restrict__ partial, int F, int n_slices,
-                                                            int time_block, double out_scale) {
+                                                            int time_block, double out_scale, int aligned16) {
   using namespace g2m;
   __shared__ __attribute__((aligned(16))) _Float16 R1[32768];
   __shared__ __attribute__((aligned(16))) _Float16 R2[32768];
+  // the P0 and P2 fragments depend on the lane only (the same in every wave): one copy in LDS, entry j of
+  // lane l at j * 64 + l (16 lanes read 16 consecutive 16-byte slots)
+  __shared__ half8 WF[6 * 64];
+  // the P1 fragment of wave w at WF1[w * 64 + l]
+  __shared__ half8 WF1[16 * 64];
   const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   const int h = l >> 5, n32 = l & 31, n16 = l & 15, g16 = l >> 4;
   // work-group -> (slice, channel, s); with a multiple of 8 (slice, channel) groups the two halves of a
@@ -134,47 +139,59 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
   // ---- matrix fragments (fixed for the whole kernel) ----
   // P0: B = W1^T, W1[kappa_b1][j_h1] = w_32^{kappa_b1 j_h1} / 16, kappa_b1 = 16 s + (col & 15), output
   // component col / 16; K step ks, lane half h = input component, entry i = j_h1 8 ks + i.
-  half8 w0h[2], w0l[2];
+  // (held in WF: entries 0-1 hi, 2-3 lo by K step)
   // P1: B = W2^T (K = [hi comp 0 | hi comp 1 | lo comp 0 | lo comp 1] over the 8 j_l1), kappa_b1 = 16 s + w,
   // column n16 = (kappa_a1 = n16 & 7, output component n16 >> 3); entry i = j_l1 i ^ (4 (w >> 3)) (L1's units
   // are swapped for kappa_b1 local >= 8).  W2[kappa_a1][j_l1] = w_256^{(32 kappa_a1 + kappa_b1) j_l1} / 8.
-  half8 w1;
+  // (held in WF1)
   // P2: B = W1'^T, W1'[kappa_b0][j_h0] = w_16^{kappa_b0 j_h0} / 8, column n32 = (kappa_b0 = n32 & 15, output
   // component n32 >> 4); lane half h = input component, entry i = j_h0 i ^ 4h (L2's units swapped for comp 1).
-  half8 w2h, w2l;
+  // (held in WF: entry 4 hi, 5 lo)
   // P3: A = W2'(kappa_b0 = w), W2'[kappa_a0][j_l0] = w_256^{(16 kappa_a0 + w) j_l0} / 16, row n32 =
   // (kappa_a0 = n32 & 15, output component n32 >> 4); K step ks, lane half h = input component, entry i =
   // j_l0 8 ks + (i ^ 4 (w >> 3)).
   half8 w3h[2], w3l[2];
-  {
+  if (w == 0) {
     const int kb1 = 16 * s + (n32 & 15), co = n32 >> 4;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    for (int ks = 0; ks < 2; ++ks) {
+      half8 fh, fl;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int jh = 8 * ks + i;
         _Float16 hi, lo;
         split16(embed(tw[(8 * kb1 * jh) & 255], co, h) * 0.0625f, hi, lo);
-        w0h[ks][i] = hi;
-        w0l[ks][i] = lo;
+        fh[i] = hi;
+        fl[i] = lo;
       }
-    const int kb1w = 16 * s + w, ka1 = n16 & 7, co1 = n16 >> 3, ci1 = g16 & 1, lo1 = g16 >> 1;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int jl = i ^ (4 * (w >> 3));
-      _Float16 hi, lo;
-      split16(embed(tw[((32 * ka1 + kb1w) * jl) & 255], co1, ci1) * 0.125f, hi, lo);
-      w1[i] = lo1 ? lo : hi;
+      WF[ks * 64 + l] = fh;
+      WF[(2 + ks) * 64 + l] = fl;
     }
     const int kb0 = n32 & 15;
+    half8 fh, fl;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int jh0 = i ^ (4 * h);
       _Float16 hi, lo;
       split16(embed(tw[(16 * kb0 * jh0) & 255], co, h) * 0.125f, hi, lo);
-      w2h[i] = hi;
-      w2l[i] = lo;
+      fh[i] = hi;
+      fl[i] = lo;
     }
+    WF[4 * 64 + l] = fh;
+    WF[5 * 64 + l] = fl;
+  }
+  {
+    const int kb1w = 16 * s + w, ka1 = n16 & 7, co1 = n16 >> 3, ci1 = g16 & 1, lo1 = g16 >> 1;
+    half8 f1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int jl = i ^ (4 * (w >> 3));
+      _Float16 hi, lo;
+      split16(embed(tw[((32 * ka1 + kb1w) * jl) & 255], co1, ci1) * 0.125f, hi, lo);
+      f1[i] = lo1 ? lo : hi;
+    }
+    WF1[w * 64 + l] = f1;
+    const int co = n32 >> 4;
     const int ka0 = n32 & 15;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
@@ -191,12 +208,26 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
   // ---- D: thread tid decodes 16 bytes: i0 = tid / 8, i1 in [16 u, 16 u + 16) (u = tid % 8), i.e. j_h1 in
   // {2u, 2u + 1} and all 8 j_l1.  A 4-bit value v becomes the float16 1024 + (v + 8) by placing the biased
   // nibble under the exponent byte 0x64; subtracting 1032 is exact.
-  const int d_i0 = tid >> 3, d_u = tid & 7;
+  // (each pass starts from the lane index made opaque by an empty asm, so that its LDS addresses are formed
+  // inside the time loop instead of being held in registers across it)
+  auto lane_v = [&]() {
+    int v = l;
+    asm volatile("" : "+v"(v));
+    return v;
+  };
   uint4 raw;
+  // (a 4-byte aligned source takes four 4-byte loads)
   auto load_raw = [&](int64_t t) {
-    raw = *reinterpret_cast<const uint4*>(src + (t * F + ch) * 16384 + tid * 16);
+    const uint8_t* p = src + (t * F + ch) * 16384 + tid * 16;
+    if (aligned16) {
+      raw = *reinterpret_cast<const uint4*>(p);
+    } else {
+      const uint32_t* p4 = reinterpret_cast<const uint32_t*>(p);
+      raw = make_uint4(p4[0], p4[1], p4[2], p4[3]);
+    }
   };
   auto decode = [&]() {
+    const int tv = lane_v() + 64 * w, d_i0 = tv >> 3, d_u = tv & 7;
     const uint32_t b[4] = {raw.x ^ 0x88888888u, raw.y ^ 0x88888888u, raw.z ^ 0x88888888u, raw.w ^ 0x88888888u};
     const _Float16 bias = (_Float16)1032.f;
     const half2v bb = {bias, bias};
@@ -215,6 +246,7 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
 
   // ---- P0: tile tt of wave w (tiles 2w, 2w + 1): rows r = 8g + 4h' + e <-> (j_l1 = r & 7, i0 = 4 tile + r / 8)
   auto pass0 = [&]() {
+    const int lv = lane_v(), n32 = lv & 31, h = lv >> 5;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int tile = 2 * w + k;
@@ -223,8 +255,8 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         const half8 x = *reinterpret_cast<const half8*>(&R2[lx_at(h, jl, i0, 8 * ks)]);
-        d = mfma32(x, w0h[ks], d);
-        d = mfma32(x, w0l[ks], d);
+        d = mfma32(x, WF[ks * 64 + lv], d);
+        d = mfma32(x, WF[(2 + ks) * 64 + lv], d);
       }
       // column n32 = (kappa_b1 local = n32 & 15, comp n32 >> 4); rows 8g + 4h + e: j_l1 = 4h + e, i0 = 4 tile + g
       const int kb = n32 & 15, co = n32 >> 4;
@@ -240,6 +272,8 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
   // ---- P1: wave w, kappa_b1 local = w; 8 tiles of 16 lines: row rho <-> i0 = j_l0 + 16 j_h0 with
   // j_h0 = 4 ((rho / 4) & 1) + rho % 4, j_l0 = 2 tile + rho / 8
   auto pass1 = [&]() {
+    const int lv = lane_v(), n16 = lv & 15, g16 = lv >> 4;
+    const half8 w1 = WF1[w * 64 + lv];
 #pragma unroll 2
     for (int tile = 0; tile < 8; ++tile) {
       const int rho = n16;
@@ -258,12 +292,13 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
   // ---- P2 of chunk c (lambda in [32 c, 32 c + 32)): tile of wave w = lambda pair 32 c + 2w, +1; rows
   // r = 8g + 4h + e <-> (j_l0 = r & 15, lambda = 32 c + 2w + r / 16) -> L3 buffer c & 1
   auto pass2 = [&](int c) {
+    const int lv = lane_v(), n32 = lv & 31, h = lv >> 5;
     _Float16* L3 = R1 + (c & 1) * 16384;
     const int lam = 32 * c + 2 * w + (n32 >> 4), jl0 = n32 & 15;
     const half8 x = *reinterpret_cast<const half8*>(&R2[l2_row(h, lam, jl0)]);
     floatx16 d = {};
-    d = mfma32(x, w2h, d);
-    d = mfma32(x, w2l, d);
+    d = mfma32(x, WF[4 * 64 + lv], d);
+    d = mfma32(x, WF[5 * 64 + lv], d);
     // column n32 = (kappa_b0 = n32 & 15, comp n32 >> 4); rows 8g + 4h + e: j_l0 = 8 (g & 1) + 4h + e,
     // kappa_1 local = 2w + g / 2
     const int kb0 = n32 & 15, co = n32 >> 4;
@@ -282,6 +317,7 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
   // ---- P3 of chunk c: kappa_b0 = w, columns kappa_1 local n32; rows 8g + 4h + e (g < 2) hold Re and rows
   // 16 + 8g + 4h + e Im of kappa_a0 = 8g + 4h + e
   auto pass3 = [&](int c) {
+    const int lv = lane_v(), n32 = lv & 31, h = lv >> 5;
     const _Float16* L3 = R1 + (c & 1) * 16384;
     floatx16 d = {};
 #pragma unroll
@@ -337,16 +373,21 @@ __global__ __launch_bounds__(1024) void grid256_mixed_kernel(const uint8_t* __re
     __syncthreads();
     pass2(0);
     __syncthreads();
+    // (the scheduling barriers keep one pass' tile registers from overlapping the next pass')
     pass2(1);
+    __builtin_amdgcn_sched_barrier(0);
     pass3(0);
     __syncthreads();
     pass2(2);
+    __builtin_amdgcn_sched_barrier(0);
     pass3(1);
     __syncthreads();
     pass2(3);
+    __builtin_amdgcn_sched_barrier(0);
     pass3(2);
     __syncthreads();
     pass3(3);
+    __builtin_amdgcn_sched_barrier(0);
     if (t + 1 < t1) {
       decode();
       load_raw(min(t + 2, t1 - 1));
@@ -371,9 +412,11 @@ int grid256_cell(int s, int cell) {
 
 hipError_t launch_grid256_mixed(const void* src, int64_t T, int64_t tps, const float2* tw256, double* partial, int F,
                                 int n_slices, int time_block, double out_scale, hipStream_t st) {
-  if ((reinterpret_cast<uintptr_t>(src) & 15) != 0 || F < 1 || n_slices < 1) return hipErrorInvalidValue;
+  if ((reinterpret_cast<uintptr_t>(src) & 3) != 0 || F < 1 || n_slices < 1) return hipErrorInvalidValue;
+  const int aligned16 = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
   hipLaunchKernelGGL(grid256_mixed_kernel, dim3((unsigned)(n_slices * F * 2)), dim3(g2m::NT), 0, st,
-                     static_cast<const uint8_t*>(src), T, tps, tw256, partial, F, n_slices, time_block, out_scale);
+                     static_cast<const uint8_t*>(src), T, tps, tw256, partial, F, n_slices, time_block, out_scale,
+                     aligned16);
   return hipGetLastError();
 }
 

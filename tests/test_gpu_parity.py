@@ -799,3 +799,48 @@ def test_mixed_batch_graph_c5_shapes():
         e = rel_err(a.cpu().numpy(), b.cpu().numpy().astype(np.complex128))
         say("c5 mixed graph split vs whole", ld, e)
         assert e <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Matrix-core kernels of the single-level grids (mixed form).
+
+
+@pytest.mark.parametrize(
+    "level_dims,T,F,time_block,kernel",
+    [
+        ([[128, 128]], 21, 3, 4, "grid256_mixed"),  # 6 (slice, channel) groups: plain work-group order
+        ([[128, 128]], 16, 8, 0, "grid256_mixed"),  # 16 groups: the two halves of a channel on one XCD
+    ],
+)
+def test_single_level_mixed_full_oracle(level_dims, T, F, time_block, kernel):
+    """Every lag of a single-level grid in the mixed form against the oracle (ragged T, several float32
+    blocks)."""
+    N = math.prod(dims_of(level_dims))
+    gen = torch.Generator().manual_seed(N + T + F)
+    raw = random_raw("ci4", T, F, N, gen)
+    say("single level mixed", level_dims, "T", T, "F", F)
+    vis, plan = gpu_vis(level_dims, raw, "ci4", "mixed", time_block=time_block)
+    assert f'"kernel":"{kernel}"' in plan.describe()
+    err = rel_err(vis, oracle_vis(raw, "ci4", level_dims))
+    say("single level mixed", level_dims, "error", err)
+    assert err <= TOL["mixed"]
+
+
+def test_single_level_mixed_unaligned_and_sky():
+    """The 128x128 mixed kernel on a 4- but not 16-byte aligned source gives the aligned result; on the
+    sky-plus-noise workload bytes (64 channels, 24 samples) sampled cells agree with the oracle."""
+    w = skysim.WORKLOADS["grid128"]
+    raw = skysim.make_voltages(w, T=24, nchan=64, device="cuda")
+    plan = omni.Plan(w.level_dims, w.A, 64, "ci4", "mixed")
+    assert '"kernel":"grid256_mixed"' in plan.describe()
+    ref = plan.correlate(raw).clone()
+    flat = raw.reshape(-1)
+    big = torch.empty(flat.numel() + 4, dtype=raw.dtype, device="cuda")
+    big[4:].copy_(flat)
+    shifted = big[4:].view(raw.shape)
+    assert shifted.data_ptr() % 16 != 0
+    got = plan.correlate(shifted)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    x = oracle.decode(raw.cpu().numpy(), "ci4", 24, 64, w.N)
+    check_cells(ref.cpu().numpy()[:4], x[:, :4], w.dims, "mixed", 256, 3, "grid128 sky")
