@@ -46,9 +46,15 @@ hipError_t launch_fused8844_mixed(const void* src, int64_t T, int64_t tps, const
                                   double out_scale, hipStream_t st);
 hipError_t launch_fused16x3_mixed(const void* src, int64_t T, int64_t tps, const float2* tw, double* partial, int F,
                                   int n_slices, int time_block, int accumulate, double out_scale, hipStream_t st);
-int grid256_cell(int s, int cell);
-hipError_t launch_grid256_mixed(const void* src, int64_t T, int64_t tps, const float2* tw256, double* partial, int F,
+int grid128_cell(int s, int cell);
+int grid64_cell(int cell);
+int grid32_cell(int cell);
+hipError_t launch_grid128_mixed(const void* src, int64_t T, int64_t tps, const float2* tw256, double* partial, int F,
                                 int n_slices, int time_block, double out_scale, hipStream_t st);
+hipError_t launch_grid64_mixed(const void* src, int64_t T, int64_t tps, const float2* tw128, double* partial, int F,
+                               int n_slices, int time_block, double out_scale, hipStream_t st);
+hipError_t launch_grid32_mixed(const void* src, int64_t T, int64_t tps, const float2* tw64, double* partial, int F,
+                               int n_slices, int time_block, double out_scale, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -92,7 +98,7 @@ struct ArrayPlan {
   int kernel = 0;  // 0: general; 1: 8x8x8x8 float32; 2: 8x8x8x8 mixed (MFMA); 3: compile-time shape (float32);
                    // 4: (16,16,16) behind a front pass, mixed (MFMA), float16 front workspace;
                    // 5: (8,8,4,4) behind two front passes, mixed (MFMA), float16 front workspace;
-                   // 6: single-level 128 x 128, mixed (MFMA), 4-bit samples
+                   // 6, 7, 8: single-level 128 x 128, 64 x 64, 32 x 32, mixed (MFMA), 4-bit samples
   int ct_index = -1;         // entry of the compile-time shape table (kernel 3)
   int lcap = 32;             // longest short DFT the general kernel may use (autotuned)
   int wg_target = 1024;      // work-groups the general kernel's time slicing aims for (autotuned)
@@ -476,8 +482,9 @@ void plan_fused8x4_mixed(ArrayPlan& ap) {
 }
 
 // The single-level 128 x 128 grid in the mixed form: work-group = (slice, channel, half s of axis 1's
-// first-stage outputs), 1024 threads, 32768 cells each in the order given by grid256_cell.
-void plan_grid256(ArrayPlan& ap) {
+// first-stage outputs), 1024 threads, 32768 cells each in the order given by grid128_cell.
+// The 64 x 64 and 32 x 32 grids (kernels 7 and 8): one work-group per (slice, channel) owns all cells.
+void plan_grid128(ArrayPlan& ap) {
   ap.kernel = 6;
   FusedSetup& fs = ap.fs;
   fs.F = ap.F;
@@ -486,10 +493,25 @@ void plan_grid256(ArrayPlan& ap) {
   fs.fp.n_split = 2;
   fs.fp.cells_wg = 32768;
   fs.cpt = 32;
-  fs.lds = 131072;
+  fs.lds = 153600;
   fs.kmap.assign((size_t)ap.M, 0);
   for (int c = 0; c < 2; ++c)
-    for (int cell = 0; cell < 32768; ++cell) fs.kmap[(size_t)(c * 32768 + cell)] = omni::grid256_cell(c, cell);
+    for (int cell = 0; cell < 32768; ++cell) fs.kmap[(size_t)(c * 32768 + cell)] = omni::grid128_cell(c, cell);
+}
+
+void plan_grid_small(ArrayPlan& ap, int kernel) {
+  ap.kernel = kernel;
+  FusedSetup& fs = ap.fs;
+  fs.F = ap.F;
+  fs.N = ap.N;
+  fs.M = ap.M;
+  fs.fp.n_split = 1;
+  fs.fp.cells_wg = (int32_t)ap.M;
+  fs.cpt = 16;
+  fs.lds = kernel == 7 ? 98304 : 12288;
+  fs.kmap.assign((size_t)ap.M, 0);
+  for (int cell = 0; cell < (int)ap.M; ++cell)
+    fs.kmap[(size_t)cell] = kernel == 7 ? omni::grid64_cell(cell) : omni::grid32_cell(cell);
 }
 
 // Front mode: the first s axes are transformed by front passes over HBM, after
@@ -606,7 +628,11 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
       std::vector<int>(ap.n.begin() + 2, ap.n.end()) == std::vector<int>{8, 8, 4, 4})
     plan_mixed_behind_front(ap, 5);
   if (form == OMNI_FORM_MIXED && dtype == OMNI_CI4 && ap.n_front == 0 && ap.n == std::vector<int>{128, 128})
-    plan_grid256(ap);
+    plan_grid128(ap);
+  if (form == OMNI_FORM_MIXED && dtype == OMNI_CI4 && ap.n_front == 0 && ap.n == std::vector<int>{64, 64})
+    plan_grid_small(ap, 7);
+  if (form == OMNI_FORM_MIXED && dtype == OMNI_CI4 && ap.n_front == 0 && ap.n == std::vector<int>{32, 32})
+    plan_grid_small(ap, 8);
   const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
   ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
   // inverse in groups of channels whose complex float32 workspace fits 1 GiB per buffer
@@ -848,8 +874,25 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
     // the four stages scale by 1/16, 1/8, 1/8, 1/16: |X|^2 carries 2^-28
-    HIP_TRY(omni::launch_grid256_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
+    HIP_TRY(omni::launch_grid128_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
                                        268435456.0, st));
+  } else if (stage == 0 && T > 0 && (ap.kernel == 7 || ap.kernel == 8)) {
+    // 64 x 64: one 96 KiB work-group of 1024 threads per CU; 32 x 32: 256 threads and 12 KiB, about five
+    // work-groups per CU
+    const int64_t target = ap.kernel == 7 ? 1024 : 2560;
+    int64_t ns = std::max<int64_t>(1, (target + ap.F / 2) / ap.F);
+    ns = std::min<int64_t>(ns, ap.max_slices);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
+    const int64_t tps = (T + ns - 1) / ns;
+    ns = (T + tps - 1) / tps;
+    ap.last_slices = (int)ns;
+    // 64 x 64: four stages of 1/8, |X|^2 carries 2^-24; 32 x 32: two of 1/32, 2^-20
+    if (ap.kernel == 7)
+      HIP_TRY(omni::launch_grid64_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
+                                        16777216.0, st));
+    else
+      HIP_TRY(omni::launch_grid32_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
+                                        1048576.0, st));
   } else if (stage == 0 && T > 0 && ap.kernel == 3) {
     int rc = launch_ct(ap, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
     if (rc) return rc;
@@ -1515,7 +1558,9 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
                         : ap.kernel == 3 ? "fused_ct_fp32"
                         : ap.kernel == 4 ? "fused16x3_mixed"
                         : ap.kernel == 5 ? "fused8844_mixed"
-                        : ap.kernel == 6 ? "grid256_mixed"
+                        : ap.kernel == 6 ? "grid128_mixed"
+                        : ap.kernel == 7 ? "grid64_mixed"
+                        : ap.kernel == 8 ? "grid32_mixed"
                                          : "fused_fp32";
     s += std::string("{\"kernel\":\"") + kname + "\",\"mode\":\"" + (ap.n_front ? "front" : "direct") +
          "\",\"n_front\":" + std::to_string(ap.n_front) + ",\"chunk_T\":" + std::to_string(ap.chunk_T) +

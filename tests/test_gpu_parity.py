@@ -296,11 +296,16 @@ def test_mixed_sky_workload_full_size():
 
 
 def test_mixed_other_shapes_fall_back_to_fp32_kernel():
+    """Shapes (and sample formats) without a matrix-core kernel run the float32 kernels in a mixed plan."""
     gen = torch.Generator().manual_seed(23)
     raw = random_raw("ci8", 12, 2, 36, gen)
     vis, plan = gpu_vis([[6, 6]], raw, "ci8", "mixed")
     assert '"fused_fp32"' in plan.describe()
     assert rel_err(vis, oracle_vis(raw, "ci8", [[6, 6]])) <= TOL["fp32"]
+    raw = random_raw("ci8", 12, 2, 1024, gen)
+    vis, plan = gpu_vis([[32, 32]], raw, "ci8", "mixed")
+    assert '"fused_ct_fp32"' in plan.describe()
+    assert rel_err(vis, oracle_vis(raw, "ci8", [[32, 32]])) <= TOL["fp32"]
 
 
 # ---------------------------------------------------------------------------
@@ -808,8 +813,12 @@ def test_mixed_batch_graph_c5_shapes():
 @pytest.mark.parametrize(
     "level_dims,T,F,time_block,kernel",
     [
-        ([[128, 128]], 21, 3, 4, "grid256_mixed"),  # 6 (slice, channel) groups: plain work-group order
-        ([[128, 128]], 16, 8, 0, "grid256_mixed"),  # 16 groups: the two halves of a channel on one XCD
+        ([[128, 128]], 21, 3, 4, "grid128_mixed"),  # 6 (slice, channel) groups: plain work-group order
+        ([[128, 128]], 16, 8, 0, "grid128_mixed"),  # 16 groups: the two halves of a channel on one XCD
+        ([[64, 64]], 37, 3, 4, "grid64_mixed"),
+        ([[64, 64]], 9, 2, 0, "grid64_mixed"),
+        ([[32, 32]], 37, 3, 4, "grid32_mixed"),
+        ([[32, 32]], 1, 1, 0, "grid32_mixed"),  # a single sample
     ],
 )
 def test_single_level_mixed_full_oracle(level_dims, T, F, time_block, kernel):
@@ -832,7 +841,7 @@ def test_single_level_mixed_unaligned_and_sky():
     w = skysim.WORKLOADS["grid128"]
     raw = skysim.make_voltages(w, T=24, nchan=64, device="cuda")
     plan = omni.Plan(w.level_dims, w.A, 64, "ci4", "mixed")
-    assert '"kernel":"grid256_mixed"' in plan.describe()
+    assert '"kernel":"grid128_mixed"' in plan.describe()
     ref = plan.correlate(raw).clone()
     flat = raw.reshape(-1)
     big = torch.empty(flat.numel() + 4, dtype=raw.dtype, device="cuda")
