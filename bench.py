@@ -1,21 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the hierarchical-grid correlator on one MI355X.
 
-One step = one omni_correlate call over the whole workload: every time sample
-of every channel through the forward transform, |X|^2 and time integration,
-then the inverse transform to visibilities.  Inputs are synthetic (seeded
-sky-plus-noise voltages, quantised) and already resident in HBM.
+One step = one batched correlate call over the whole workload: every time
+sample of every channel of every array through the forward transform, |X|^2
+and time integration, then the inverse transform to visibilities.  Inputs are
+synthetic (seeded sky-plus-noise voltages, quantised) and already resident in
+HBM.
 
-The JSON line's `value` is the workload's own arithmetic form (the float32
-form for the 8x8-of-8x8 workload); the other form is timed on the same input
-bytes and reported under `other_form`.
+Default (`--workload batch4`): the four arrays 32x32, 64x64, 128x128 and
+16x16-of-16x16 (64 channels each, T = 2048, 4-bit samples) as one batched call
+in the mixed form, captured as one HIP graph with one branch per array.
+`value` is that call's antenna-samples/s; the float32 form on the same bytes
+and the sequential (non-graph) batch are timed beside it.  `roofline` is the
+main forward kernel of the dominant array (per-launch HIP events recorded by
+the library around that kernel, array alone, same bytes), `roofline_call` the
+whole call against the fixed work counts of all four arrays, `per_array` the
+same kernel rooflines for every array.
 
-`--workload batch4` times the four-array batch (32x32, 64x64, 128x128 and
-16x16-of-16x16, 64 channels each, T = 2048, 4-bit samples) as one batched call:
-the graph plan (one HIP graph, one branch per array) in the mixed form (the
-default there) is the headline; the same arrays run one after another, the
-other form, and the dominant array's kernel alone (roofline) are reported
-beside it.
+`--workload NAME` times one workload of skysim.WORKLOADS in its own form, the
+other form on the same bytes under `other_form`, and (integer samples, N <=
+16384) the GPU direct N^2 correlator.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -68,7 +72,8 @@ def mixed_form_flops_per_as(dims) -> float:
 
 
 def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is unchanged."""
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary (its
+    traffic_bytes_per_launch line), if the kernel's sources are unchanged since; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -85,7 +90,8 @@ def recorded_traffic(kernel: str, workload: str):
         src = os.path.join(ROOT, "paper_0909_0001_amd", "csrc", name)
         if not os.path.isfile(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != want:
             return None
-    return float(rec["traffic_bytes"])
+    v = rec.get("traffic_bytes_per_launch")
+    return float(v) if v is not None else None
 
 
 def copy_calibration() -> int:
@@ -103,24 +109,47 @@ def copy_calibration() -> int:
     return 0
 
 
-def roofline_of(w, res, work):
-    """Roofline entry of the forward stage of one plan: the fixed work count of the kernel's own form (a mixed plan
-    whose shape has no matrix-core kernel runs, and is priced as, the float32 form)."""
-    fwd_ms = res["stages"]["forward"]
-    if "mixed" not in res["kernel"]:
-        per_as, peak, bound = fp32_form_flops_per_as(w.dims), PEAK_FP32_VECTOR_TFLOPS, "alu"
-    else:
-        per_as, peak, bound = mixed_form_flops_per_as(w.dims), PEAK_FP16_MFMA_TFLOPS, "mfma"
-    achieved = per_as * work / (fwd_ms / 1e3) / 1e12
+def front_axes(desc_array) -> int:
+    return int(desc_array.get("n_front", 0))
+
+
+def kernel_flops_per_as(dims, n_front: int, form: str) -> float:
+    """Fixed work per antenna-sample of the main forward kernel alone: the form's count over the axes that
+    kernel transforms (a front pass transforms the first n_front axes on the vector units and over HBM; its
+    share is left out).  The front outputs are 2^n_front times the antennas, which the count carries."""
+    dims = [n for n in dims if n > 1]
+    front, rest = dims[:n_front], dims[n_front:]
+    scale = 2 ** len(front)
+    if form == "mixed":
+        return scale * mixed_form_flops_per_as(rest)
+    return scale * fp32_form_flops_per_as(rest)
+
+
+def kernel_roofline(w, res, form):
+    """Roofline entry of the main forward kernel of one plan, from the per-launch HIP events the library records
+    around it (OMNI_STAGE_KERNEL) on the stream it runs on: algorithmic flops per launch / mean launch time."""
+    arr = res["desc"]["arrays"][0]
+    n_front = front_axes(arr)
+    mixed_kernel = "mixed" in arr["kernel"]
+    kform = "mixed" if mixed_kernel else "fp32"
+    per_as = kernel_flops_per_as(w.dims, n_front, kform)
+    launches = res["launches"]
+    as_per_launch = w.antenna_samples() / launches
+    launch_ms = res["stages"]["kernel"]
+    achieved = per_as * as_per_launch / (launch_ms / 1e3) / 1e12
+    peak, bound = (PEAK_FP16_MFMA_TFLOPS, "mfma") if mixed_kernel else (PEAK_FP32_VECTOR_TFLOPS, "alu")
+    kname = arr["kernel"] + "_kernel"
     return {
         "bound": bound,
         "achieved": round(achieved, 3),
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": recorded_traffic(res["kernel"], w.name),
-        "kernel": res["kernel"],
-        "kernel_ms": round(fwd_ms, 4),
+        "traffic": recorded_traffic(kname, w.name),
+        "kernel": kname,
+        "launch_ms": round(launch_ms, 4),
+        "launches_per_call": launches,
+        "algorithmic_flops_per_launch": per_as * as_per_launch,
         "algorithmic_flops_per_antenna_sample": per_as,
     }
 
@@ -131,7 +160,7 @@ def run_form(omni, w, raw, form, steps, warmup):
 
     plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form, timing=True)
     desc = json.loads(plan.describe())
-    log(f"bench[{form}]: plan " + plan.describe())
+    log(f"bench[{w.name} {form}]: plan " + plan.describe())
     vis = torch.empty(plan.vis_shape(), dtype=torch.complex64, device=raw.device)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -147,14 +176,23 @@ def run_form(omni, w, raw, form, steps, warmup):
     wall = (time.perf_counter() - t0) / steps * 1e3
     ms = ev0.elapsed_time(ev1) / steps
     stages = {}
-    for k in ("forward", "reduce", "inverse"):
+    for k in ("forward", "reduce", "inverse", "kernel"):
         v = plan.stage_times(k, steps)
         stages[k] = sum(v) / len(v)
     calls = sorted(plan.stage_times("call", steps))  # per-call events around each whole call
     stages["call_median"] = calls[len(calls) // 2] if len(calls) % 2 else 0.5 * (calls[len(calls) // 2 - 1] + calls[len(calls) // 2])
     stages["call_min"] = calls[0]
-    log(f"bench[{form}]: {ms:.3f} ms/step (wall {wall:.3f}); " + ", ".join(f"{k} {v:.3f} ms" for k, v in stages.items()))
-    return {"ms": ms, "stages": stages, "kernel": desc["arrays"][0]["kernel"] + "_kernel", "vis": vis, "plan": plan}
+    arr = desc["arrays"][0]
+    launches = -(-w.T // arr["chunk_T"]) if arr["n_front"] else 1
+    log(f"bench[{w.name} {form}]: {ms:.3f} ms/step (wall {wall:.3f}); "
+        + ", ".join(f"{k} {v:.3f} ms" for k, v in stages.items()) + f"; {launches} kernel launch(es) per call")
+    return {"ms": ms, "stages": stages, "kernel": arr["kernel"] + "_kernel", "vis": vis, "plan": plan,
+            "desc": desc, "launches": launches}
+
+
+def roofline_of(w, res, work):
+    """Roofline entry of a single-workload line: the main forward kernel (per-launch events)."""
+    return kernel_roofline(w, res, res["desc"]["form"])
 
 
 def run_direct(omni, w, raw, steps, warmup):
@@ -199,11 +237,21 @@ def run_batch(omni, ws, raws, form, graph, steps, warmup):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
-    calls = plan.stage_times("call", steps)
+    calls = sorted(plan.stage_times("call", steps))
     kernels = [a["kernel"] for a in json.loads(plan.describe())["arrays"]]
     log(f"bench[batch4 {form} graph={graph}]: {ms:.3f} ms/call (call events: median "
-        f"{sorted(calls)[len(calls) // 2]:.3f}); kernels {kernels}")
+        f"{calls[len(calls) // 2]:.3f}); kernels {kernels}")
     return {"ms": ms, "call_ms": calls, "outs": outs, "kernels": kernels}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_batch4(args) -> int:
@@ -223,32 +271,60 @@ def bench_batch4(args) -> int:
         log(f"bench: generating {w.name} N={w.N} F={w.nchan} T={w.T} {w.dtype}")
         raws.append(skysim.make_voltages(w, device=dev))
     torch.cuda.synchronize()
+    # the timed line: one batched call of the four arrays as a HIP graph, `form` form
     g = run_batch(omni, ws, raws, form, True, args.steps, args.warmup)
     seq = run_batch(omni, ws, raws, form, False, args.steps, args.warmup)
     alt = run_batch(omni, ws, raws, other, True, args.steps, args.warmup) if not args.no_other_form else None
     same = all(torch.equal(a, b) for a, b in zip(g["outs"], seq["outs"]))
     work = sum(w.antenna_samples() for w in ws)
     ms = g["ms"]
-    # the dominant array (16x16-of-16x16, most of the call) alone, for its forward kernel's roofline
-    wd, rd = ws[-1], raws[-1]
-    dom = run_form(omni, wd, rd, form, args.steps, args.warmup)
-    cpu = None
+    # each array alone (same bytes, same form): its main kernel's per-launch events give the rooflines; the
+    # dominant array (the 16x16-of-16x16 one, most of the call) gives the line's `roofline`
+    alone = {w.name: run_form(omni, w, r, form, args.steps, args.warmup) for w, r in zip(ws, raws)}
+    per_array = {}
+    for w in ws:
+        res = alone[w.name]
+        per_array[w.name] = {
+            "N": w.N, "F": w.nchan, "T": w.T, "kernel": res["kernel"], "ms_alone": round(res["ms"], 4),
+            "value_alone": w.antenna_samples() / (res["ms"] / 1e3),
+            "roofline": kernel_roofline(w, res, form),
+        }
+    dom = max(ws, key=lambda w: alone[w.name]["ms"])
+    # the whole call against the fixed work counts of every array in the form's own roof
+    if form == "mixed":
+        flops = sum(mixed_form_flops_per_as(w.dims) * w.antenna_samples() for w in ws)
+        call_peak = PEAK_FP16_MFMA_TFLOPS
+    else:
+        flops = sum(fp32_form_flops_per_as(w.dims) * w.antenna_samples() for w in ws)
+        call_peak = PEAK_FP32_VECTOR_TFLOPS
+    call_achieved = flops / (ms / 1e3) / 1e12
     err = {"graph_equals_sequential_bytes": same}
-    if alt is not None and form == "mixed":
-        # float16 operands: compare the mixed batch with the float32 batch, per array, relative to zero lag
+    if alt is not None:
+        # the two forms on the same bytes, per array, relative to the zero lag of each channel
         for w, a, b in zip(ws, g["outs"], alt["outs"]):
             av, bv = a.reshape(w.nchan, -1), b.reshape(w.nchan, -1)
             c = av.shape[1] // 2
-            err[f"{w.name}_mixed_vs_fp32"] = float(((av - bv).abs().max(dim=1).values / bv[:, c].abs()).max())
+            err[f"{w.name}_{form}_vs_{other}"] = float(((av - bv).abs().max(dim=1).values / bv[:, c].abs()).max())
+    cpu = None
     if not args.no_cpu_baseline:
-        w0 = ws[0]
-        rate, nch, secs, ref = cpu_oracle_baseline(raws[0].cpu(), w0, budget_s=args.cpu_budget)
-        got = g["outs"][0].cpu().numpy().reshape(w0.nchan, -1)
-        c = got.shape[1] // 2
-        err[f"{w0.name}_max_over_lags_vs_oracle_{nch}ch"] = max(
-            float(np.max(np.abs(got[f] - ref[f])) / abs(ref[f][c])) for f in ref)
-        cpu = {"value": rate, "unit": "antenna-samples/s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
-               "sample": f"{nch} of {w0.nchan} channels of the {w0.name} array x all {w0.T} samples ({secs:.1f} s)"}
+        # whole channels of the smallest arrays, smallest first, until about cpu_budget seconds of oracle work
+        done_as, done_s, parts = 0, 0.0, []
+        for i, w0 in enumerate(ws[:2]):
+            if done_s >= args.cpu_budget:
+                break
+            rate, nch, secs, ref = cpu_oracle_baseline(raws[i].cpu(), w0, budget_s=args.cpu_budget - done_s)
+            done_as += w0.N * w0.T * nch
+            done_s += secs
+            parts.append(f"{nch} of {w0.nchan} channels of {w0.name} (N={w0.N}) x all {w0.T} samples, {secs:.1f} s")
+            got = g["outs"][i].cpu().numpy().reshape(w0.nchan, -1)
+            c = got.shape[1] // 2
+            err[f"{w0.name}_{form}_max_over_lags_vs_oracle_{nch}ch"] = max(
+                float(np.max(np.abs(got[f] - ref[f])) / abs(ref[f][c])) for f in ref)
+        cpu = {"value": done_as / done_s, "unit": "antenna-samples/s", "cores": len(os.sched_getaffinity(0)),
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": "; ".join(parts) + " (float64 pair products by BLAS matmul + histogram by index "
+               "difference); the rate is over those arrays only, not extrapolated to the larger arrays, whose "
+               "direct cost grows as N^2"}
     out = {
         "metric": METRIC,
         "value": work / (ms / 1e3),
@@ -257,21 +333,28 @@ def bench_batch4(args) -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_call_median": g["call_ms"][len(g["call_ms"]) // 2],
+        "ms_per_call_min": g["call_ms"][0],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f16-mfma/f32-acc" if form == "mixed" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"batch4: arrays 32x32, 64x64, 128x128, 16x16-of-16x16; 64 channels each, T=2048, ci4 "
-            f"voltages, {form} form, one batched call as a HIP graph with one branch per array",
+            "workload": "batch4: arrays 32x32, 64x64, 128x128 and 16x16-of-16x16 antennas, 64 channels each, "
+            f"T=2048, 4-bit complex voltages (sky + noise), {form} form, one batched call as a HIP graph with one "
+            "branch per array",
             "arrays": {w.name: {"N": w.N, "F": w.nchan, "T": w.T, "kernel": k} for w, k in zip(ws, g["kernels"])},
             "sample_format": "ci4",
             "form": form,
         },
-        "roofline": dict(roofline_of(wd, dom, wd.antenna_samples()),
-                         note=f"forward kernel of the dominant {wd.name} array, timed alone "
-                         f"({dom['ms']:.3f} ms a call there)"),
+        "roofline": dict(per_array[dom.name]["roofline"],
+                         note=f"main forward kernel of the dominant {dom.name} array, per-launch HIP events with the "
+                         f"array alone ({per_array[dom.name]['ms_alone']:.3f} ms a call there)"),
+        "roofline_call": {"bound": "mfma" if form == "mixed" else "alu", "achieved": round(call_achieved, 3),
+                          "peak": call_peak, "unit": "TFLOP/s", "frac": round(call_achieved / call_peak, 4),
+                          "algorithmic_flops_per_call": flops},
+        "per_array": per_array,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
         "tolerance": {"fp32": 1e-5, "mixed": 2e-3},
@@ -279,8 +362,8 @@ def bench_batch4(args) -> int:
                        "graph_speedup": seq["ms"] / ms},
     }
     if alt is not None:
-        out["other_form"] = {"form": other, "ms_per_step": alt["ms"], "value": work / (alt["ms"] / 1e3),
-                             "kernels": alt["kernels"], "speedup_vs_main_form": ms / alt["ms"]}
+        out[f"{other}_form"] = {"ms_per_step": alt["ms"], "value": work / (alt["ms"] / 1e3), "kernels": alt["kernels"]}
+        out[f"speedup_vs_{other}_form"] = alt["ms"] / ms
     print(json.dumps(out), flush=True)
     return 0
 
@@ -311,7 +394,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hier8x8", help="a workload name of skysim.WORKLOADS, or batch4")
+    ap.add_argument("--workload", default="batch4", help="batch4 (default) or a workload name of skysim.WORKLOADS")
     ap.add_argument("--form", default=None, help="fp32 | mixed (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -387,6 +470,7 @@ def main() -> int:
             "unit": "antenna-samples/s",
             "cores": len(os.sched_getaffinity(0)),
             "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{nch} of {w.nchan} channels x all {w.T} samples ({secs:.1f} s; float64 pair products "
             "by BLAS matmul + histogram by index difference)",
         }

@@ -272,7 +272,10 @@ typedef enum {
   OMNI_STAGE_FORWARD = 0, /* forward transform + |X|^2 + time integration kernel(s)  */
   OMNI_STAGE_REDUCE = 1,  /* partial-sum reduction into the float64 accumulator      */
   OMNI_STAGE_INVERSE = 2, /* inverse transform to visibilities                       */
-  OMNI_STAGE_CALL = 3     /* the whole correlate call, on the caller's stream        */
+  OMNI_STAGE_CALL = 3,    /* the whole correlate call, on the caller's stream        */
+  OMNI_STAGE_KERNEL = 4   /* per call, the mean duration of one launch of the main forward kernel (the
+                             fused or matrix-core kernel that squares and integrates; front passes,
+                             reduction and inverse excluded), over up to 16 launches per call */
 } omni_stage;
 
 /* Measurement support, no passage of the paper.
@@ -280,8 +283,9 @@ typedef enum {
  * (oldest first; at most 256 calls are remembered; for a batch plan the
  * stage spans all arrays).  Waits for the recorded events.  Writes at most
  * `max` values to ms and the count to *n.  OMNI_E_STATE without
- * OMNI_PLAN_TIMING, and for stages 0-2 of an OMNI_PLAN_GRAPH plan (its
- * arrays' stages overlap; only OMNI_STAGE_CALL is recorded). */
+ * OMNI_PLAN_TIMING, and for stages 0-2 and 4 of an OMNI_PLAN_GRAPH plan (its
+ * arrays' stages overlap; only OMNI_STAGE_CALL is recorded).  Stage 4 keeps the
+ * 32 most recent calls. */
 int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n);
 
 /* Release the plan and everything it owns on the device (waits for the

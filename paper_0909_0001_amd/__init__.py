@@ -35,7 +35,7 @@ PLAN_HOST_ONLY = 0x1
 PLAN_TIMING = 0x2
 PLAN_GRAPH = 0x8
 TUNE = {False: 0, None: 0, "off": 0, "cache": 1, True: 2, "search": 2}
-STAGES = {"forward": 0, "reduce": 1, "inverse": 2, "call": 3}
+STAGES = {"forward": 0, "reduce": 1, "inverse": 2, "call": 3, "kernel": 4}
 NO_RESET = 0x1
 NO_FINALIZE = 0x2
 

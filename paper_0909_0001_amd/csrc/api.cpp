@@ -139,6 +139,9 @@ struct ArrayPlan {
 constexpr int kTimingRing = 256;
 
 constexpr int kStages = 4;  // forward, reduce, inverse, whole call
+// Per-launch events of the main forward kernel (OMNI_STAGE_KERNEL): kKernRing calls x kKernMax launches.
+constexpr int kKernRing = 32;
+constexpr int kKernMax = 16;
 // Front mode: each of the two workspaces holds at most kFrontBytes (8 GiB: the partial sums are
 // read-modified-written once per chunk, so fewer, larger chunks save that traffic), and a chunk at most
 // kChunkMax samples.
@@ -151,6 +154,9 @@ struct omni_plan_s {
   bool timing = false;
   // [call % ring][stage][begin/end]
   std::vector<hipEvent_t> ev;
+  // [call % kKernRing][launch][begin/end] and the launches recorded per call
+  std::vector<hipEvent_t> kev;
+  std::vector<int> kev_n;
   // OMNI_PLAN_GRAPH: one branch stream per array, fork / join events, the
   // captured graph and the call it was captured for
   bool graph = false;
@@ -727,6 +733,17 @@ void mark(omni_plan_s* p, int stage, int end, bool edge, hipStream_t st) {
   if (p->timing && edge) hipEventRecord(stage_event(p, stage, end), st);
 }
 
+// Brackets one launch of the main forward kernel (begin: end = 0, end: end = 1) on `st` (timing plans that
+// are not graph plans; at most kKernMax launches per call).
+void kmark(omni_plan_s* p, int end, hipStream_t st) {
+  if (!p->timing || p->graph) return;
+  const int slot = (int)(p->n_calls % kKernRing);
+  const int k = p->kev_n[(size_t)slot];
+  if (k >= kKernMax) return;
+  hipEventRecord(p->kev[(size_t)((slot * kKernMax + k) * 2 + end)], st);
+  if (end) p->kev_n[(size_t)slot] = k + 1;
+}
+
 // General fused kernel over T samples of `src` (format fmt) with setup fs; float64
 // partial sums into ap.d_partial; returns the number of time slices used.
 int launch_general(ArrayPlan& ap, const FusedSetup& fs, int fmt, const void* src, int64_t T, int time_block,
@@ -812,8 +829,10 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         // all front channels of the chunk in one slice (2048 work-groups for 64 channels)
         // the front pass scaled by 1/n_0 and each of the three passes by 1/16: undo on |X|^2
         const double unscale = (double)ap.n[0] * 4096.0;
+        kmark(p, 0, st);
         HIP_TRY(omni::launch_fused16x3_mixed(cur, tc, tc, ap.d_tw32 + ap.front_tw_base, ap.d_partial, (int)ap.fs.F, 1,
                                              p->time_block, c0 > 0 ? 1 : 0, unscale * unscale, st));
+        kmark(p, 1, st);
         first_slices = 1;
         continue;
       }
@@ -821,19 +840,25 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
         // the front passes scaled by 1/n_0 and 1/n_1, the kernel's passes by 1/16, 1/8, 1/8: undo on |X|^2
         const double unscale = (double)ap.n[0] * (double)ap.n[1] * 1024.0;
         const float2* tw = ap.d_tw32 + ap.front_tw_base;  // tables of the rest axes: 16, 16, 8, 8 entries
+        kmark(p, 0, st);
         HIP_TRY(omni::launch_fused8844_mixed(cur, tc, tc, tw, tw + 32, ap.d_partial, (int)ap.fs.F, 1, p->time_block,
                                              c0 > 0 ? 1 : 0, unscale * unscale, st));
+        kmark(p, 1, st);
         first_slices = 1;
         continue;
       }
       if (ap.kernel == 3) {
+        kmark(p, 0, st);
         int rc = c0 == 0 ? launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &first_slices)
                          : launch_ct(ap, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices, 1,
                                      first_slices);
+        kmark(p, 1, st);
         if (rc) return rc;
         continue;
       }
+      kmark(p, 0, st);
       int rc = launch_general(ap, ap.fs, 0, cur, tc, p->time_block, ap.d_tw32 + ap.front_tw_base, st, &slices);
+      kmark(p, 1, st);
       if (rc) return rc;
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, (accumulate || c0 > 0) ? 1 : 0, st));
@@ -850,8 +875,10 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     const int64_t tps = (T + ns - 1) / ns;
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
+    kmark(p, 0, st);
     HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
                                        p->time_block, st));
+    kmark(p, 1, st);
   } else if (stage == 0 && T > 0 && ap.kernel == 2) {
     // one 112 KiB work-group of 1024 threads per CU: one round of 256 work-groups
     const int64_t per_slice_groups = (int64_t)ap.F * 2;
@@ -862,8 +889,10 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     const int64_t tps = (T + ns - 1) / ns;
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
+    kmark(p, 0, st);
     HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F,
                                         (int)ns, p->time_block, st));
+    kmark(p, 1, st);
   } else if (stage == 0 && T > 0 && ap.kernel == 6) {
     // one 128 KiB work-group of 1024 threads per CU: about four rounds of 256 work-groups
     const int64_t per_slice_groups = (int64_t)ap.F * 2;
@@ -874,8 +903,10 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
     // the four stages scale by 1/16, 1/8, 1/8, 1/16: |X|^2 carries 2^-28
+    kmark(p, 0, st);
     HIP_TRY(omni::launch_grid128_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
                                        268435456.0, st));
+    kmark(p, 1, st);
   } else if (stage == 0 && T > 0 && (ap.kernel == 7 || ap.kernel == 8)) {
     // 64 x 64: one 96 KiB work-group of 1024 threads per CU; 32 x 32: 256 threads and 12 KiB, about five
     // work-groups per CU
@@ -887,17 +918,23 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     ns = (T + tps - 1) / tps;
     ap.last_slices = (int)ns;
     // 64 x 64: four stages of 1/8, |X|^2 carries 2^-24; 32 x 32: two of 1/32, 2^-20
+    kmark(p, 0, st);
     if (ap.kernel == 7)
       HIP_TRY(omni::launch_grid64_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
                                         16777216.0, st));
     else
       HIP_TRY(omni::launch_grid32_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
                                         1048576.0, st));
+    kmark(p, 1, st);
   } else if (stage == 0 && T > 0 && ap.kernel == 3) {
+    kmark(p, 0, st);
     int rc = launch_ct(ap, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
+    kmark(p, 1, st);
     if (rc) return rc;
   } else if (stage == 0 && T > 0) {
+    kmark(p, 0, st);
     int rc = launch_general(ap, ap.fs, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
+    kmark(p, 1, st);
     if (rc) return rc;
   }
   if (stage == 1) {
@@ -1074,6 +1111,9 @@ void destroy_plan_resources(omni_plan_s* p) {
   for (auto& e : p->ev)
     if (e) hipEventDestroy(e);
   p->ev.clear();
+  for (auto& e : p->kev)
+    if (e) hipEventDestroy(e);
+  p->kev.clear();
   for (auto& e : p->join)
     if (e) hipEventDestroy(e);
   for (auto& s : p->branch)
@@ -1174,14 +1214,16 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
     }
     if (p->timing) {
       p->ev.assign((size_t)kTimingRing * kStages * 2, nullptr);
-      for (auto& e : p->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-          for (auto& e2 : p->ev)
-            if (e2) hipEventDestroy(e2);
-          delete p;
-          return fail(OMNI_E_HIP, "hipEventCreate failed");
+      p->kev.assign((size_t)kKernRing * kKernMax * 2, nullptr);
+      p->kev_n.assign((size_t)kKernRing, 0);
+      for (auto* v : {&p->ev, &p->kev})
+        for (auto& e : *v) {
+          if (hipEventCreate(&e) != hipSuccess) {
+            destroy_plan_resources(p);
+            delete p;
+            return fail(OMNI_E_HIP, "hipEventCreate failed");
+          }
         }
-      }
     }
     if (o.flags & OMNI_PLAN_GRAPH) {
       rc = make_graph_resources(p);
@@ -1372,6 +1414,7 @@ int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, v
     hipGetDevice(&cur);
     if (cur != plan->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (plan->timing) plan->kev_n[(size_t)(plan->n_calls % kKernRing)] = 0;
     mark(plan, OMNI_STAGE_CALL, 0, true, st);
     if (plan->graph) {
       if (!same_call(plan, volt, T, vis, flags)) {
@@ -1595,9 +1638,27 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
 int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n) {
   if (!plan || !n || (max > 0 && !ms)) return fail(OMNI_E_INVAL, "NULL argument");
   if (!plan->timing) return fail(OMNI_E_STATE, "plan was not made with OMNI_PLAN_TIMING");
-  if (stage < 0 || stage >= kStages) return fail(OMNI_E_INVAL, "unknown stage");
+  if (stage < 0 || stage > OMNI_STAGE_KERNEL) return fail(OMNI_E_INVAL, "unknown stage");
   if (plan->graph && stage != OMNI_STAGE_CALL)
     return fail(OMNI_E_STATE, "a graph plan records only the whole call (its arrays' stages overlap)");
+  if (stage == OMNI_STAGE_KERNEL) {
+    const int64_t cnt = std::min<int64_t>(std::min<int64_t>(plan->n_calls, kKernRing), max);
+    for (int64_t j = 0; j < cnt; ++j) {
+      const int slot = (int)((plan->n_calls - cnt + j) % kKernRing);
+      const int k = plan->kev_n[(size_t)slot];
+      float sum = 0.f;
+      for (int i = 0; i < k; ++i) {
+        hipEvent_t b = plan->kev[(size_t)((slot * kKernMax + i) * 2)], e = plan->kev[(size_t)((slot * kKernMax + i) * 2 + 1)];
+        HIP_TRY(hipEventSynchronize(e));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, b, e));
+        sum += t;
+      }
+      ms[j] = k ? sum / (float)k : 0.f;
+    }
+    *n = (int32_t)cnt;
+    return OMNI_OK;
+  }
   const int64_t avail = std::min<int64_t>(plan->n_calls, kTimingRing);
   const int64_t cnt = std::min<int64_t>(avail, max);
   for (int64_t j = 0; j < cnt; ++j) {
