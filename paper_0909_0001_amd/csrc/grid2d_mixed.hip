@@ -213,13 +213,48 @@ __global__ __launch_bounds__(1024) void grid128_mixed_kernel(const uint8_t* __re
   // ---- D: thread tid decodes 16 bytes: i0 = tid / 8, i1 in [16 u, 16 u + 16) (u = tid % 8), i.e. j_h1 in
   // {2u, 2u + 1} and all 8 j_l1.  A 4-bit value v becomes the float16 1024 + (v + 8) by placing the biased
   // nibble under the exponent byte 0x64; subtracting 1032 is exact.
-  // (each pass starts from the lane index made opaque by an empty asm, so that its LDS addresses are formed
-  // inside the time loop instead of being held in registers across it)
-  auto lane_v = [&]() {
-    int v = l;
-    asm volatile("" : "+v"(v));
-    return v;
-  };
+  // ---- LDS addresses.  Every access of a pass is a per-lane base combined with a compile-time constant (an
+  // XOR on bits the base leaves clear, or an add above them), worked out from the layouts above:
+  //   P0 read   lx_at(h, j_l1, i0, 8 ks), i0 = 8w + 4k + g'      = a0 ^ (64 k + 8 ks)
+  //   P0 store  l1_row(c, kb, 8w + 4k + g) + 4 (h ^ kb / 8)     = s0 + 256 k + 64 g
+  //   P1 read   l1_row(g16 & 1, w, i0(tile, n16))               = a1 + 128 tile
+  //   P1 store  l2_row(c, 16 ka + w, 2 tile + g16 / 2) + unit   = s1 ^ 16 tile
+  //   P2 read   l2_row(h, 32 c + 2w + n32 / 16, n32 & 15)       = (a2 ^ 16 c) + 4096 c
+  //   P2 store  l3_row(c, kb0, g & 1, 2w + g / 2) + unit        = (s2 ^ 8 (g / 2)) + 256 (g & 1) (+ 16384 buffer)
+  //   P3 read   l3_row(h, w, ks, n32)                           = a3 + 256 ks (+ 16384 buffer)
+  //   D  store  lx_at(comp, j_l1, i0, 2u)                       = (sd ^ 16 j_l1) + 2048 j_l1 + 16384 comp
+  // The bases are made opaque by an empty asm at the start of each pass, so that the compiler forms the
+  // pass' addresses there (one XOR or none each) instead of holding all of them across the time loop.
+  const int gq = n32 >> 3, jl_ = n32 & 7;
+  int a0 = (((h * 8 + jl_) * 128 + 8 * w) * 16) + (gq ^ jl_) * 16 + (gq & 1) * 8;
+  int s0;
+  {
+    const int kb = n32 & 15, co = n32 >> 4;
+    s0 = (co * 16 + kb) * 1024 + ((w >> 1) ^ (kb & 7)) * 8 + 512 * (w & 1) + 4 * (h ^ (kb >> 3));
+  }
+  int a1 = ((((g16 & 1) * 16 + w) * 128 + ((4 * ((n16 >> 2) & 1) + (n16 & 3)) ^ (w & 7)) + 8 * (n16 >> 3)) * 8);
+  int s1;
+  {
+    const int ka = n16 & 7, co = n16 >> 3, gb = g16 >> 1, u = (g16 & 1) ^ co;
+    s1 = (co * 128 + 16 * ka + w) * 128 + 16 * (ka >> 1) + 8 * (gb ^ (ka & 1)) + 4 * u;
+  }
+  int a2 = (h * 128 + 2 * w + (n32 >> 4)) * 128 + (((n32 & 15) ^ (w >> 3)) * 8);
+  int s2;
+  {
+    const int kb0 = n32 & 15, co = n32 >> 4;
+    s2 = (co * 16 + kb0) * 512 + ((2 * w) ^ (kb0 & 6)) * 8 + 8 * (kb0 & 1) + 4 * (h ^ (kb0 >> 3));
+  }
+  int a3 = (((h * 16 + w) * 2) * 32 + (n32 ^ (w & 7))) * 8;
+  int sd;
+  {
+    const int i0 = tid >> 3, u = tid & 7;
+    sd = ((i0 & ~7) + 0) * 16 + (i0 & 7) * 16 + (((u >> 2) ^ (i0 & 1)) << 3) + ((2 * u) & 7);
+  }
+  auto opaque = [](int& v) { asm volatile("" : "+v"(v)); };
+
+  // ---- D: thread tid decodes 16 bytes: i0 = tid / 8, i1 in [16 u, 16 u + 16) (u = tid % 8), i.e. j_h1 in
+  // {2u, 2u + 1} and all 8 j_l1.  A 4-bit value v becomes the float16 1024 + (v + 8) by placing the biased
+  // nibble under the exponent byte 0x64; subtracting 1032 is exact.
   uint4 raw;
   // (a 4-byte aligned source takes four 4-byte loads)
   auto load_raw = [&](int64_t t) {
@@ -232,7 +267,7 @@ __global__ __launch_bounds__(1024) void grid128_mixed_kernel(const uint8_t* __re
     }
   };
   auto decode = [&]() {
-    const int tv = lane_v() + 64 * w, d_i0 = tv >> 3, d_u = tv & 7;
+    opaque(sd);
     const uint32_t b[4] = {raw.x ^ 0x88888888u, raw.y ^ 0x88888888u, raw.z ^ 0x88888888u, raw.w ^ 0x88888888u};
     const _Float16 bias = (_Float16)1032.f;
     const half2v bb = {bias, bias};
@@ -244,75 +279,66 @@ __global__ __launch_bounds__(1024) void grid128_mixed_kernel(const uint8_t* __re
       const uint32_t pair = __builtin_amdgcn_perm(hi_w, lo_w, sel);  // [byte(lo_w), 0, byte(hi_w), 0]
       const uint32_t re = ((pair >> 4) & 0x000f000fu) | 0x64006400u, im = (pair & 0x000f000fu) | 0x64006400u;
       const half2v vr = __builtin_bit_cast(half2v, re) - bb, vi = __builtin_bit_cast(half2v, im) - bb;
-      *reinterpret_cast<half2v*>(&R2[lx_at(0, jl, d_i0, 2 * d_u)]) = vr;
-      *reinterpret_cast<half2v*>(&R2[lx_at(1, jl, d_i0, 2 * d_u)]) = vi;
+      const int at = (sd ^ (16 * jl)) + 2048 * jl;
+      *reinterpret_cast<half2v*>(&R2[at]) = vr;
+      *reinterpret_cast<half2v*>(&R2[at + 16384]) = vi;
     }
   };
 
   // ---- P0: tile tt of wave w (tiles 2w, 2w + 1): rows r = 8g + 4h' + e <-> (j_l1 = r & 7, i0 = 4 tile + r / 8)
   auto pass0 = [&]() {
-    const int lv = lane_v(), n32 = lv & 31, h = lv >> 5;
+    opaque(a0);
+    opaque(s0);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const int tile = 2 * w + k;
-      const int jl = n32 & 7, i0 = 4 * tile + (n32 >> 3);
       floatx16 d = {};
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        const half8 x = *reinterpret_cast<const half8*>(&R2[lx_at(h, jl, i0, 8 * ks)]);
-        d = mfma32(x, WF[ks * 64 + lv], d);
-        d = mfma32(x, WF[(2 + ks) * 64 + lv], d);
+        const half8 x = *reinterpret_cast<const half8*>(&R2[a0 ^ (64 * k + 8 * ks)]);
+        d = mfma32(x, WF[ks * 64 + l], d);
+        d = mfma32(x, WF[(2 + ks) * 64 + l], d);
       }
       // column n32 = (kappa_b1 local = n32 & 15, comp n32 >> 4); rows 8g + 4h + e: j_l1 = 4h + e, i0 = 4 tile + g
-      const int kb = n32 & 15, co = n32 >> 4;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int unit = h ^ (kb >> 3);
-        *reinterpret_cast<half4*>(&R1[l1_row(co, kb, 4 * tile + g) + 4 * unit]) =
+      for (int g = 0; g < 4; ++g)
+        *reinterpret_cast<half4*>(&R1[s0 + 256 * k + 64 * g]) =
             to_half4(d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]);
-      }
     }
   };
 
   // ---- P1: wave w, kappa_b1 local = w; 8 tiles of 16 lines: row rho <-> i0 = j_l0 + 16 j_h0 with
   // j_h0 = 4 ((rho / 4) & 1) + rho % 4, j_l0 = 2 tile + rho / 8
   auto pass1 = [&]() {
-    const int lv = lane_v(), n16 = lv & 15, g16 = lv >> 4;
-    const half8 w1 = WF1[w * 64 + lv];
+    opaque(a1);
+    opaque(s1);
+    const half8 w1 = WF1[w * 64 + l];
 #pragma unroll 2
     for (int tile = 0; tile < 8; ++tile) {
-      const int rho = n16;
-      const int i0 = (2 * tile + (rho >> 3)) + 16 * (4 * ((rho >> 2) & 1) + (rho & 3));
-      const half8 x = *reinterpret_cast<const half8*>(&R1[l1_row(g16 & 1, w, i0)]);
+      const half8 x = *reinterpret_cast<const half8*>(&R1[a1 + 128 * tile]);
       floatx4 d = {};
       d = mfma16(x, w1, d);
       // column n16 = (kappa_a1 = n16 & 7, comp n16 >> 3); rows 4 g16 + i: j_h0 = 4 (g16 & 1) + i,
       // j_l0 = 2 tile + g16 / 2
-      const int ka = n16 & 7, co = n16 >> 3, lam = 16 * ka + w, jl0 = 2 * tile + (g16 >> 1);
-      const int unit = (g16 & 1) ^ co;
-      *reinterpret_cast<half4*>(&R2[l2_row(co, lam, jl0) + 4 * unit]) = to_half4(d[0], d[1], d[2], d[3]);
+      *reinterpret_cast<half4*>(&R2[s1 ^ (16 * tile)]) = to_half4(d[0], d[1], d[2], d[3]);
     }
   };
 
   // ---- P2 of chunk c (lambda in [32 c, 32 c + 32)): tile of wave w = lambda pair 32 c + 2w, +1; rows
   // r = 8g + 4h + e <-> (j_l0 = r & 15, lambda = 32 c + 2w + r / 16) -> L3 buffer c & 1
   auto pass2 = [&](int c) {
-    const int lv = lane_v(), n32 = lv & 31, h = lv >> 5;
+    opaque(a2);
+    opaque(s2);
     _Float16* L3 = R1 + (c & 1) * 16384;
-    const int lam = 32 * c + 2 * w + (n32 >> 4), jl0 = n32 & 15;
-    const half8 x = *reinterpret_cast<const half8*>(&R2[l2_row(h, lam, jl0)]);
+    const half8 x = *reinterpret_cast<const half8*>(&R2[(a2 ^ (16 * c)) + 4096 * c]);
     floatx16 d = {};
-    d = mfma32(x, WF[4 * 64 + lv], d);
-    d = mfma32(x, WF[5 * 64 + lv], d);
+    d = mfma32(x, WF[4 * 64 + l], d);
+    d = mfma32(x, WF[5 * 64 + l], d);
     // column n32 = (kappa_b0 = n32 & 15, comp n32 >> 4); rows 8g + 4h + e: j_l0 = 8 (g & 1) + 4h + e,
     // kappa_1 local = 2w + g / 2
-    const int kb0 = n32 & 15, co = n32 >> 4;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int unit = h ^ (kb0 >> 3);
-      *reinterpret_cast<half4*>(&L3[l3_row(co, kb0, g & 1, 2 * w + (g >> 1)) + 4 * unit]) =
+    for (int g = 0; g < 4; ++g)
+      *reinterpret_cast<half4*>(&L3[(s2 ^ (8 * (g >> 1))) + 256 * (g & 1)]) =
           to_half4(d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]);
-    }
   };
 
   float acc[SLOTS];
@@ -322,12 +348,12 @@ __global__ __launch_bounds__(1024) void grid128_mixed_kernel(const uint8_t* __re
   // ---- P3 of chunk c: kappa_b0 = w, columns kappa_1 local n32; rows 8g + 4h + e (g < 2) hold Re and rows
   // 16 + 8g + 4h + e Im of kappa_a0 = 8g + 4h + e
   auto pass3 = [&](int c) {
-    const int lv = lane_v(), n32 = lv & 31, h = lv >> 5;
+    opaque(a3);
     const _Float16* L3 = R1 + (c & 1) * 16384;
     floatx16 d = {};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const half8 x = *reinterpret_cast<const half8*>(&L3[l3_row(h, w, ks, n32)]);
+      const half8 x = *reinterpret_cast<const half8*>(&L3[a3 + 256 * ks]);
       d = mfma32(w3h[ks], x, d);
       d = mfma32(w3l[ks], x, d);
     }
