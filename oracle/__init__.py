@@ -21,6 +21,9 @@ defines, written so it can be checked against the paper by eye:
 * ``baselines``         -- the physical separation of each index-difference
   cell, sum_k Delta_k a_k (Sec. II.D Eq. GridEq).
 * ``decode_*``          -- the voltage sample formats (independent decoders).
+* ``layout``            -- the physical-baseline fold of the hypercube and the
+  baseline-distribution experiment of Sec. III (d = l * l^- from antenna
+  positions, zeroed origin, asinh map, radial bins, boxcar smoothing).
 
 Every function is pinned by tests in ``tests/test_oracle_pins.py`` against
 values printed in the paper, closed forms, library routines and brute force.
@@ -37,4 +40,14 @@ from .correlator import (  # noqa: F401
     visibilities,
     visibilities_by_outer_lag,
     visibility_cells,
+)
+from .layout import (  # noqa: F401
+    asinh_map,
+    baseline_distribution,
+    boxcar,
+    fold,
+    image_centre,
+    layout_positions,
+    radial_profile,
+    zero_origin,
 )

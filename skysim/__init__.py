@@ -34,6 +34,7 @@ __all__ = [
     "make_voltages",
     "pack_ci4",
     "quantise",
+    "PAPER_LAYOUTS",
 ]
 
 
@@ -118,6 +119,18 @@ WORKLOADS = {
         "hier16x16", [[16, 16], [16, 16]], _stack(lattice(10.0), lattice(0.5)), 64, 2048, "ci4", 32, "mixed",
         seed=20090838,
     ),
+}
+
+#: The four hierarchical example layouts of Sec. III (Figs. ThreeLevelFig, BlocksFig, PlankFig,
+#: StripsFig), in metres (the minimum antenna spacing is 1 m): name -> (level_dims, A), outer level
+#: first, the columns of each A_l the level's two lattice vectors.  The 3-level layout is the one of
+#: Fig. 1 (a_1 = (1,0) with five positions and a_4 = (0,1); a_2 = (8,0), a_5 = (2,8); a_3 = (40,10),
+#: a_6 = (-10,40), three positions each).
+PAPER_LAYOUTS = {
+    "3-level": ([[3, 3], [3, 3], [5, 3]], _stack([[40, -10], [10, 40]], [[8, 2], [0, 8]], [[1, 0], [0, 1]])),
+    "Blocks": ([[2, 2], [16, 16]], _stack([[200, 0], [0, 200]], [[1, 0], [0, 1]])),
+    "Plank": ([[512, 32]], _stack([[1, 0], [0, 1]])),
+    "Strips": ([[32, 512]], _stack([[16, 0], [0, 1]])),
 }
 
 #: Target pre-clip RMS per real component for each integer format (clip at +-127 / +-7).
