@@ -288,6 +288,79 @@ typedef enum {
  * 32 most recent calls. */
 int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n);
 
+/* ---- Physical-baseline fold and baseline distributions -------------------
+ *
+ * Sec. II.D: hypercube cell Delta holds every antenna pair whose index tuples
+ * differ by Delta, at physical separation b(Delta) = sum_k Delta_k a_k
+ * (Eq. GridEq applied to an index difference).  Where several cells share one
+ * separation (the 3-level layout of Fig. 1), the physical correlation at b is
+ * their sum: the fold.  Sec. III draws each layout's two-dimensional baseline
+ * distribution d (the layout map correlated with its parity reversal, which is
+ * the fold of the visibilities of an all-ones input at one time sample) with
+ * the origin zeroed on an asinh(4 d / d_max) intensity scale, bins it radially
+ * and, for comparisons, smooths the radial distribution with a sliding boxcar.
+ *
+ * Pixels: cell Delta goes to pixel (rint(b_x / du), rint(b_y / dv)) relative to
+ * the image centre, rint rounding half to even (the exact fold for integer
+ * lattice vectors and du = dv = 1; nearest-pixel gridding otherwise).  The
+ * image is [ny][nx], row = y, ny = 2 cy + 1, nx = 2 cx + 1, the zero baseline
+ * at (cy, cx), cx = rint(X / du) with X = sum over lattice vectors of
+ * |a_x| (n - 1) (the largest |b_x|), cy likewise.  Radial bin of pixel
+ * (ix, iy) (offsets from the centre): floor(sqrt((ix du)^2 + (iy dv)^2) *
+ * radius_scale / dr).  Pixel and bin follow from correctly rounded float64
+ * operations in that order. */
+typedef struct omni_fold_s* omni_fold_t;
+
+typedef struct {
+  double du, dv;        /* pixel size along x and y, in the units of A (> 0)               */
+  double dr;            /* radial bin width, after radius_scale (> 0)                       */
+  double radius_scale;  /* factor on |b| before radial binning (> 0; 1: none).  Sec. III's
+                           comparison rescales every layout to the same largest baseline.    */
+  int32_t boxcar;       /* odd width, in radial bins, of the centred sliding mean (1: none)  */
+  int32_t zero_origin;  /* nonzero: omni_fold writes 0 to the zero-baseline pixel (Sec. III) */
+} omni_fold_opts;
+
+/* Plan the fold of array `array` of `plan` (which must carry lattice
+ * matrices): computes every cell's pixel and every pixel's radial bin on the
+ * device and keeps them grouped (cells sorted by pixel, pixels by bin), so
+ * that each fold call is a gather with a fixed summation order.  opts may be
+ * NULL (du = dv = dr = radius_scale = 1, no boxcar, origin kept).  Allocates
+ * about 8 bytes per cell and per pixel on the plan's device (which must be
+ * current) and synchronises it.  Errors: OMNI_E_INVAL (NULL, bad options,
+ * array out of range), OMNI_E_STATE (host-only plan, no A, other device),
+ * OMNI_E_SHAPE (image of 2^31 pixels or more), OMNI_E_NOMEM, OMNI_E_HIP. */
+int omni_fold_plan(omni_fold_t* out, omni_plan_t plan, int32_t array, const omni_fold_opts* opts);
+
+/* Image extent [ny][nx] and number of radial bins (host outputs). */
+int omni_fold_shape(omni_fold_t fold, int64_t* ny, int64_t* nx, int64_t* nbins);
+
+/* Fold visibilities: image[f][p] = sum of vis[f][cell] over the cells of
+ * pixel p, in float64 (ascending cell order), f < nchan.
+ *   vis   : device complex64 [nchan][prod(2 n_k - 1)] in the layout omni_correlate writes.
+ *   image : device complex128 [nchan][ny][nx], written.
+ *   nchan : 1 .. F of the array.
+ * Asynchronous on `stream`.  Errors: OMNI_E_INVAL, OMNI_E_SHAPE (nchan),
+ * OMNI_E_STATE (other device), OMNI_E_HIP. */
+int omni_fold(omni_fold_t fold, const void* vis, int32_t nchan, void* image, void* stream);
+
+/* Baseline-distribution products of Sec. III from the real part d of a
+ * folded image (device complex128 [nchan][ny][nx], e.g. omni_fold's output for
+ * an all-ones input, made with zero_origin):
+ *   map    : device float64 [nchan][ny][nx] = asinh(4 d / d_max), d_max the
+ *            channel's largest pixel (1 if that is not positive); may be NULL.
+ *   hist   : device float64 [nchan][nbins], the sum of d over each radial bin;
+ *            may be NULL.
+ *   smooth : device float64 [nchan][nbins], the centred boxcar mean of hist
+ *            over `boxcar` bins, bins beyond either end counting as zero; may be
+ *            NULL (needs hist).
+ * Asynchronous on `stream`; deterministic.  Errors: OMNI_E_INVAL (NULL image,
+ * smooth without hist), OMNI_E_SHAPE (nchan), OMNI_E_STATE, OMNI_E_HIP. */
+int omni_baseline_profile(omni_fold_t fold, const void* image, int32_t nchan, void* map, void* hist, void* smooth,
+                          void* stream);
+
+/* Release a fold (waits for the device first).  NULL is a no-op. */
+int omni_fold_destroy(omni_fold_t fold);
+
 /* Release the plan and everything it owns on the device (waits for the
  * device first).  NULL is a no-op.  Always returns OMNI_OK. */
 int omni_destroy(omni_plan_t plan);

@@ -58,6 +58,11 @@ EXPORTS = [
     "omni_destroy",
     "omni_strerror",
     "omni_last_error",
+    "omni_fold_plan",
+    "omni_fold_shape",
+    "omni_fold",
+    "omni_baseline_profile",
+    "omni_fold_destroy",
 ]
 
 
@@ -76,6 +81,17 @@ class _Opts(ctypes.Structure):
         ("tune", ctypes.c_int32),
         ("tune_cache", ctypes.c_char_p),
         ("chunk_T", ctypes.c_int32),
+    ]
+
+
+class _FoldOpts(ctypes.Structure):
+    _fields_ = [
+        ("du", ctypes.c_double),
+        ("dv", ctypes.c_double),
+        ("dr", ctypes.c_double),
+        ("radius_scale", ctypes.c_double),
+        ("boxcar", ctypes.c_int32),
+        ("zero_origin", ctypes.c_int32),
     ]
 
 
@@ -121,6 +137,11 @@ def _load():
         "omni_destroy": (ctypes.c_int, [P]),
         "omni_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "omni_last_error": (ctypes.c_char_p, []),
+        "omni_fold_plan": (ctypes.c_int, [ctypes.POINTER(P), P, i32, ctypes.POINTER(_FoldOpts)]),
+        "omni_fold_shape": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "omni_fold": (ctypes.c_int, [P, P, i32, P, P]),
+        "omni_baseline_profile": (ctypes.c_int, [P, P, i32, P, P, P, P]),
+        "omni_fold_destroy": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -417,6 +438,77 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Fold:
+    """Physical-baseline fold of one array's visibilities onto a (u, v) pixel grid, and the
+    baseline-distribution products (asinh map, radial distribution, boxcar) of Sec. III.
+
+    ``plan`` must carry lattice matrices.  Pixel size ``du`` x ``dv`` (units of A), radial bins of
+    width ``dr`` after multiplying |b| by ``radius_scale``, boxcar width ``boxcar`` (odd),
+    ``zero_origin`` zeroes the zero-baseline pixel.  The cell -> pixel grouping is built on the
+    device once, here.
+    """
+
+    def __init__(self, plan: Plan, array: int = 0, du: float = 1.0, dv: float = 1.0, dr: float = 1.0,
+                 radius_scale: float = 1.0, boxcar: int = 1, zero_origin: bool = False):
+        self._h = ctypes.c_void_p()
+        self._plan = plan
+        self.array = array
+        o = _FoldOpts(du, dv, dr, radius_scale, boxcar, 1 if zero_origin else 0)
+        _check(lib.omni_fold_plan(ctypes.byref(self._h), plan._h, array, ctypes.byref(o)))
+        ny, nx, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.omni_fold_shape(self._h, ctypes.byref(ny), ctypes.byref(nx), ctypes.byref(nb)))
+        self.shape = (ny.value, nx.value)
+        self.nbins = nb.value
+        self.F, _ = plan._fn[array]
+        self._cells = int(np.prod(plan.vis_shape(array)[1:]))
+
+    def fold(self, vis, out=None, stream=None):
+        """complex64 visibilities [C, 2n_1-1, ...] (C <= F channels) -> complex128 image [C, ny, nx]."""
+        import torch
+
+        if vis.dtype != torch.complex64 or not vis.is_contiguous() or vis.device.type != "cuda":
+            raise ValueError("vis must be a contiguous complex64 GPU tensor")
+        C = vis.shape[0]
+        if vis.numel() != C * self._cells or not 1 <= C <= self.F:
+            raise ValueError(f"vis must be [C <= {self.F}, ...] with {self._cells} cells per channel")
+        if out is None:
+            out = torch.empty((C,) + self.shape, dtype=torch.complex128, device=vis.device)
+        if out.dtype != torch.complex128 or tuple(out.shape) != (C,) + self.shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex128 tensor of shape {(C,) + self.shape}")
+        if out.device != vis.device:
+            raise ValueError("out and vis must be on one device")
+        _check(lib.omni_fold(self._h, vis.data_ptr(), C, out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def profile(self, image, stream=None):
+        """(asinh map [C, ny, nx], radial sums [C, nbins], boxcar-smoothed sums [C, nbins]) of Re image."""
+        import torch
+
+        if image.dtype != torch.complex128 or not image.is_contiguous() or image.device.type != "cuda":
+            raise ValueError("image must be a contiguous complex128 GPU tensor")
+        C = image.shape[0]
+        if tuple(image.shape) != (C,) + self.shape or not 1 <= C <= self.F:
+            raise ValueError(f"image must be [C <= {self.F}, {self.shape[0]}, {self.shape[1]}]")
+        dev = image.device
+        m = torch.empty((C,) + self.shape, dtype=torch.float64, device=dev)
+        h = torch.empty((C, self.nbins), dtype=torch.float64, device=dev)
+        sm = torch.empty((C, self.nbins), dtype=torch.float64, device=dev)
+        _check(lib.omni_baseline_profile(self._h, image.data_ptr(), C, m.data_ptr(), h.data_ptr(), sm.data_ptr(),
+                                         _stream_handle(stream)))
+        return m, h, sm
+
+    def close(self) -> None:
+        if self._h:
+            lib.omni_fold_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def strerror(code: int) -> str:

@@ -9,11 +9,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "direct.hpp"
+#include "fold.hpp"
 #include "plan.hpp"
 
 namespace omni {
@@ -1697,5 +1699,231 @@ const char* omni_strerror(int code) {
 }
 
 const char* omni_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Physical-baseline fold (Sec. II.D) and baseline distributions (Sec. III).
+// ---------------------------------------------------------------------------
+
+struct omni_fold_s {
+  int device = -1;
+  int F = 0;                 // channels of the array (capacity of dmax)
+  omni::FoldGeom g;
+  omni::RadialGeom rg;
+  int64_t npix = 0, nbins = 0, origin = -1;
+  int boxcar = 1;
+  uint32_t* d_cell = nullptr;  // cells sorted by pixel [cells]
+  uint32_t* d_off = nullptr;   // per-pixel offsets into d_cell [npix + 1]
+  uint32_t* d_pix = nullptr;   // pixels sorted by radial bin [npix]
+  uint32_t* d_boff = nullptr;  // per-bin offsets into d_pix [nbins + 1]
+  double* d_dmax = nullptr;    // per-channel largest pixel [F]
+};
+
+namespace {
+
+void fold_free(omni_fold_s* f) {
+  hipFree(f->d_cell);
+  hipFree(f->d_off);
+  hipFree(f->d_pix);
+  hipFree(f->d_boff);
+  hipFree(f->d_dmax);
+}
+
+int bits_for(int64_t v) {
+  int b = 1;
+  while (b < 32 && (int64_t(1) << b) <= v) ++b;
+  return b;
+}
+
+// Sort (key, value) pairs held in k0/v0 into k1/v1 and build the offsets of the groups 0..n_groups - 1;
+// checks that every element fell into a group.
+int sort_into_groups(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int64_t n_groups,
+                     uint32_t* off) {
+  size_t tmp_bytes = 0;
+  const int kb = bits_for(n_groups);
+  HIP_TRY(omni::sort_pairs(nullptr, &tmp_bytes, k0, k1, v0, v1, n, kb, nullptr));
+  void* tmp = nullptr;
+  HIP_TRY(hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16)));
+  hipError_t e = omni::sort_pairs(tmp, &tmp_bytes, k0, k1, v0, v1, n, kb, nullptr);
+  if (e == hipSuccess) e = omni::launch_group_offsets(k1, n, off, n_groups, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  hipFree(tmp);
+  if (e != hipSuccess) return fail(OMNI_E_HIP, std::string("fold plan sort: ") + hipGetErrorString(e));
+  uint32_t last = 0;
+  HIP_TRY(hipMemcpy(&last, off + n_groups, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if ((int64_t)last != n) return fail(OMNI_E_HIP, "fold plan: an element fell outside every group");
+  return OMNI_OK;
+}
+
+int fold_build(omni_fold_s* f) {
+  const int64_t cells = f->g.cells;
+  uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr;
+  const int64_t n_tmp = std::max(cells, f->npix);
+  auto release = [&]() {
+    hipFree(k0);
+    hipFree(v0);
+    hipFree(k1);
+  };
+  hipError_t e = hipMalloc(&k0, (size_t)n_tmp * 4);
+  if (e == hipSuccess) e = hipMalloc(&v0, (size_t)n_tmp * 4);
+  if (e == hipSuccess) e = hipMalloc(&k1, (size_t)n_tmp * 4);
+  if (e == hipSuccess) e = hipMalloc(&f->d_cell, (size_t)cells * 4);
+  if (e == hipSuccess) e = hipMalloc(&f->d_off, (size_t)(f->npix + 1) * 4);
+  if (e == hipSuccess) e = hipMalloc(&f->d_pix, (size_t)f->npix * 4);
+  if (e == hipSuccess) e = hipMalloc(&f->d_dmax, (size_t)f->F * sizeof(double));
+  if (e == hipSuccess) e = omni::launch_fold_keys(f->g, k0, v0, nullptr);
+  if (e != hipSuccess) {
+    release();
+    return fail(e == hipErrorOutOfMemory ? OMNI_E_NOMEM : OMNI_E_HIP, std::string("fold plan: ") + hipGetErrorString(e));
+  }
+  int rc = sort_into_groups(k0, v0, k1, f->d_cell, cells, f->npix, f->d_off);
+  if (rc) {
+    release();
+    return rc;
+  }
+  // radial bins of the pixels
+  uint32_t* d_max = nullptr;
+  e = hipMalloc(&d_max, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(d_max, 0, sizeof(uint32_t));
+  if (e == hipSuccess) e = omni::launch_radial_keys(f->rg, k0, v0, d_max, nullptr);
+  uint32_t max_bin = 0;
+  if (e == hipSuccess) e = hipMemcpy(&max_bin, d_max, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  hipFree(d_max);
+  if (e == hipSuccess && (int64_t)max_bin >= (int64_t(1) << 31)) e = hipErrorInvalidValue;
+  if (e == hipSuccess) {
+    f->nbins = (int64_t)max_bin + 1;
+    e = hipMalloc(&f->d_boff, (size_t)(f->nbins + 1) * 4);
+  }
+  if (e != hipSuccess) {
+    release();
+    return fail(e == hipErrorOutOfMemory ? OMNI_E_NOMEM : OMNI_E_HIP,
+                std::string("fold plan radial bins: ") + hipGetErrorString(e));
+  }
+  rc = sort_into_groups(k0, v0, k1, f->d_pix, f->npix, f->nbins, f->d_boff);
+  release();
+  return rc;
+}
+
+bool finite_positive(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+int omni_fold_plan(omni_fold_t* out, omni_plan_t plan, int32_t array, const omni_fold_opts* opts) {
+  if (!out || !plan) return fail(OMNI_E_INVAL, "NULL argument");
+  *out = nullptr;
+  if (array < 0 || (size_t)array >= plan->arrays.size()) return fail(OMNI_E_INVAL, "array index out of range");
+  const ArrayPlan& ap = plan->arrays[(size_t)array];
+  omni_fold_opts o = {1.0, 1.0, 1.0, 1.0, 1, 0};
+  if (opts) o = *opts;
+  if (!finite_positive(o.du) || !finite_positive(o.dv) || !finite_positive(o.dr) || !finite_positive(o.radius_scale))
+    return fail(OMNI_E_INVAL, "du, dv, dr and radius_scale must be finite and positive");
+  if (o.boxcar < 1 || o.boxcar % 2 == 0) return fail(OMNI_E_INVAL, "boxcar width must be odd and >= 1");
+  if (ap.A.empty()) return fail(OMNI_E_STATE, "plan has no lattice matrices");
+  if (plan->host_only) return fail(OMNI_E_STATE, "host-only plan");
+  if (ap.levels > omni::kFoldMaxLevels) return fail(OMNI_E_SHAPE, "too many levels for the fold");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != plan->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
+  auto f = std::make_unique<omni_fold_s>();
+  f->device = plan->device;
+  f->F = ap.F;
+  f->boxcar = o.boxcar;
+  omni::FoldGeom& g = f->g;
+  g.levels = ap.levels;
+  g.cells = 1;
+  for (int k = 0; k < 2 * ap.levels; ++k) {
+    g.n[k] = ap.dims[(size_t)k];
+    g.cells *= 2 * g.n[k] - 1;
+  }
+  // largest |b_x|, |b_y| over the cells: each lattice vector at its extreme lag
+  double X = 0.0, Y = 0.0;
+  for (int l = 0; l < ap.levels; ++l) {
+    for (int c = 0; c < 4; ++c) g.A[l][c] = ap.A[(size_t)(4 * l + c)];
+    const double nx1 = g.n[2 * l] - 1, ny1 = g.n[2 * l + 1] - 1;
+    X += std::fabs(g.A[l][0]) * nx1 + std::fabs(g.A[l][1]) * ny1;
+    Y += std::fabs(g.A[l][2]) * nx1 + std::fabs(g.A[l][3]) * ny1;
+  }
+  g.du = o.du;
+  g.dv = o.dv;
+  const double cxd = std::nearbyint(X / o.du), cyd = std::nearbyint(Y / o.dv);
+  if (!(cxd < 1e9 && cyd < 1e9)) return fail(OMNI_E_SHAPE, "fold image too large");
+  g.cx = (int64_t)cxd;
+  g.cy = (int64_t)cyd;
+  g.nx = 2 * g.cx + 1;
+  g.ny = 2 * g.cy + 1;
+  f->npix = g.nx * g.ny;
+  if (f->npix >= (int64_t(1) << 31)) return fail(OMNI_E_SHAPE, "fold image above 2^31 pixels (choose larger du, dv)");
+  if (g.cells >= (int64_t(1) << 32)) return fail(OMNI_E_SHAPE, "too many visibility cells for the fold");
+  f->origin = o.zero_origin ? g.cy * g.nx + g.cx : -1;
+  f->rg.cx = g.cx;
+  f->rg.cy = g.cy;
+  f->rg.nx = g.nx;
+  f->rg.ny = g.ny;
+  f->rg.du = o.du;
+  f->rg.dv = o.dv;
+  f->rg.dr = o.dr;
+  f->rg.scale = o.radius_scale;
+  const int rc = fold_build(f.get());
+  if (rc) {
+    fold_free(f.get());
+    return rc;
+  }
+  *out = f.release();
+  return OMNI_OK;
+}
+
+int omni_fold_shape(omni_fold_t fold, int64_t* ny, int64_t* nx, int64_t* nbins) {
+  if (!fold || !ny || !nx || !nbins) return fail(OMNI_E_INVAL, "NULL argument");
+  *ny = fold->g.ny;
+  *nx = fold->g.nx;
+  *nbins = fold->nbins;
+  return OMNI_OK;
+}
+
+int omni_fold(omni_fold_t fold, const void* vis, int32_t nchan, void* image, void* stream) {
+  if (!fold || !vis || !image) return fail(OMNI_E_INVAL, "NULL argument");
+  if (nchan < 1 || nchan > fold->F) return fail(OMNI_E_SHAPE, "nchan must be in [1, F] of the array");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != fold->device) return fail(OMNI_E_STATE, "current HIP device is not the fold's device");
+  HIP_TRY(omni::launch_fold_gather(static_cast<const float2*>(vis), fold->g.cells, fold->d_cell, fold->d_off,
+                                   fold->npix, nchan, fold->origin, static_cast<double2*>(image),
+                                   static_cast<hipStream_t>(stream)));
+  return OMNI_OK;
+}
+
+int omni_baseline_profile(omni_fold_t fold, const void* image, int32_t nchan, void* map, void* hist, void* smooth,
+                          void* stream) {
+  if (!fold || !image) return fail(OMNI_E_INVAL, "NULL argument");
+  if (smooth && !hist) return fail(OMNI_E_INVAL, "smooth needs hist");
+  if (nchan < 1 || nchan > fold->F) return fail(OMNI_E_SHAPE, "nchan must be in [1, F] of the array");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != fold->device) return fail(OMNI_E_STATE, "current HIP device is not the fold's device");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double2* im = static_cast<const double2*>(image);
+  if (map) {
+    HIP_TRY(omni::launch_channel_max(im, fold->npix, nchan, fold->d_dmax, st));
+    HIP_TRY(omni::launch_asinh_map(im, fold->npix, nchan, fold->d_dmax, static_cast<double*>(map), st));
+  }
+  if (hist)
+    HIP_TRY(omni::launch_radial_sum(im, fold->npix, nchan, fold->d_pix, fold->d_boff, fold->nbins,
+                                    static_cast<double*>(hist), st));
+  if (smooth)
+    HIP_TRY(omni::launch_boxcar(static_cast<const double*>(hist), fold->nbins, nchan, fold->boxcar,
+                                static_cast<double*>(smooth), st));
+  return OMNI_OK;
+}
+
+int omni_fold_destroy(omni_fold_t fold) {
+  if (!fold) return OMNI_OK;
+  hipDeviceSynchronize();
+  fold_free(fold);
+  delete fold;
+  return OMNI_OK;
+}
 
 }  // extern "C"

@@ -218,3 +218,28 @@ def test_binding_rejects_bad_outputs_and_batches():
         bp.correlate_batch([volt, torch.zeros((2, 3, 16, 2), dtype=torch.int8)])
     with pytest.raises(ValueError, match="accumulator buffer"):
         p.accumulator_get(np.zeros(3))
+
+
+def test_fold_plan_validates_before_any_device_call():
+    """The fold entry points refuse bad arguments, planless or A-less plans and host-only plans
+    without touching a device."""
+    ld, A = skysim.PAPER_LAYOUTS["Blocks"]
+    p = omni.Plan(ld, A, 1, "ci8", host_only=True)
+    h = ctypes.c_void_p()
+
+    def plan_fold(plan, opts):
+        return omni.lib.omni_fold_plan(ctypes.byref(h), plan, 0, ctypes.byref(opts) if opts is not None else None)
+
+    good = omni._FoldOpts(1.0, 1.0, 1.0, 1.0, 5, 1)
+    assert omni.STATUS[plan_fold(p._h, good)] == "OMNI_E_STATE"  # host-only plan
+    for bad in (omni._FoldOpts(0.0, 1.0, 1.0, 1.0, 1, 0), omni._FoldOpts(1.0, -1.0, 1.0, 1.0, 1, 0),
+                omni._FoldOpts(1.0, 1.0, float("nan"), 1.0, 1, 0), omni._FoldOpts(1.0, 1.0, 1.0, 0.0, 1, 0),
+                omni._FoldOpts(1.0, 1.0, 1.0, 1.0, 4, 0), omni._FoldOpts(1.0, 1.0, 1.0, 1.0, 0, 0)):
+        assert omni.STATUS[plan_fold(p._h, bad)] == "OMNI_E_INVAL"
+    assert omni.STATUS[omni.lib.omni_fold_plan(ctypes.byref(h), p._h, 3, None)] == "OMNI_E_INVAL"
+    assert omni.STATUS[omni.lib.omni_fold_plan(None, p._h, 0, None)] == "OMNI_E_INVAL"
+    no_a = omni.Plan(ld, None, 1, "ci8", host_only=True)
+    assert omni.STATUS[plan_fold(no_a._h, good)] == "OMNI_E_STATE"
+    assert omni.lib.omni_fold(None, None, 1, None, None) == -1
+    assert omni.lib.omni_baseline_profile(None, None, 1, None, None, None, None) == -1
+    assert omni.lib.omni_fold_destroy(None) == 0
