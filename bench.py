@@ -43,6 +43,7 @@ METRIC = "antenna-samples/s correlated (N·T·F/s) vs FP32 FFT form, at stated r
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP16_MFMA_TFLOPS = 2500.0
 PEAK_INT8_MFMA_TOPS = 5000.0  # dense int8 matrix-core peak (no sparsity)
+PEAK_HBM_GBS = 8000.0
 
 
 def log(*a):
@@ -154,11 +155,12 @@ def kernel_roofline(w, res, form):
     }
 
 
-def run_form(omni, w, raw, form, steps, warmup):
-    """Plan, warm up and time `steps` correlate calls; returns timings and the last visibilities."""
+def run_form(omni, w, raw, form, steps, warmup, tune="off", tune_cache=None):
+    """Plan (autotuned with tune="search"), warm up and time `steps` correlate calls; returns timings and the
+    last visibilities."""
     import torch
 
-    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form, timing=True)
+    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form, timing=True, tune=tune, tune_cache=tune_cache)
     desc = json.loads(plan.describe())
     log(f"bench[{w.name} {form}]: plan " + plan.describe())
     vis = torch.empty(plan.vis_shape(), dtype=torch.complex64, device=raw.device)
@@ -219,12 +221,13 @@ def run_direct(omni, w, raw, steps, warmup):
 BATCH4 = ["grid32", "grid64", "grid128", "hier16x16"]
 
 
-def run_batch(omni, ws, raws, form, graph, steps, warmup):
-    """Plan the arrays as one batch (optionally as a graph plan), warm up, time `steps` batched calls."""
+def run_batch(omni, ws, raws, form, graph, steps, warmup, tune="off", tune_cache=None):
+    """Plan the arrays as one batch (optionally as a graph plan; autotuned with tune="search"), warm up, time
+    `steps` batched calls."""
     import torch
 
     plan = omni.Plan(batch=[(w.level_dims, w.A, w.nchan) for w in ws], dtype=ws[0].dtype, form=form,
-                     timing=True, graph=graph)
+                     timing=True, graph=graph, tune=tune, tune_cache=tune_cache)
     outs = [torch.empty(plan.vis_shape(i), dtype=torch.complex64, device=raws[0].device) for i in range(len(ws))]
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -238,10 +241,81 @@ def run_batch(omni, ws, raws, form, graph, steps, warmup):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
     calls = sorted(plan.stage_times("call", steps))
-    kernels = [a["kernel"] for a in json.loads(plan.describe())["arrays"]]
-    log(f"bench[batch4 {form} graph={graph}]: {ms:.3f} ms/call (call events: median "
-        f"{calls[len(calls) // 2]:.3f}); kernels {kernels}")
-    return {"ms": ms, "call_ms": calls, "outs": outs, "kernels": kernels}
+    arrays = json.loads(plan.describe())["arrays"]
+    kernels = [a["kernel"] for a in arrays]
+    schedules = {w.name: {"wg_target": a["wg_target"], "block": a["block"], "tuned_ms": a["tuned_ms"]}
+                 for w, a in zip(ws, arrays)}
+    log(f"bench[batch4 {form} graph={graph} tune={tune}]: {ms:.3f} ms/call (call events: median "
+        f"{calls[len(calls) // 2]:.3f}); kernels {kernels}; schedules {schedules}")
+    return {"ms": ms, "call_ms": calls, "outs": outs, "kernels": kernels, "schedules": schedules}
+
+
+def bench_fold(omni, torch, skysim, steps, warmup, vis128=None):
+    """Sec. II.D fold and Sec. III baseline distributions on the GPU.
+
+    * experiment: per example layout, one all-ones sample through the correlator (float32 form), the fold
+      (origin zeroed) and the asinh map / radial sums / 5-bin boxcar, timed together per call;
+    * throughput: the fold gather alone on the 128x128 array's 64-channel visibilities of the batched call
+      (lattice 0.5, pixel 0.5: one cell per pixel), against HBM: algorithmic bytes = 8 B read per cell and
+      16 B written per pixel, per channel.
+    """
+    import numpy as np
+
+    out = {"experiment": {}}
+    for name, (ld, A) in skysim.PAPER_LAYOUTS.items():
+        N = int(np.prod([v for l in ld for v in l]))
+        plan = omni.Plan(ld, A, 1, "ci8", "fp32")
+        raw = torch.zeros((1, 1, N, 2), dtype=torch.int8, device="cuda")
+        raw[..., 0] = 1
+        fold = omni.Fold(plan, boxcar=5, zero_origin=True)
+        vis = torch.empty(plan.vis_shape(), dtype=torch.complex64, device="cuda")
+        img = torch.empty((1,) + fold.shape, dtype=torch.complex128, device="cuda")
+
+        def step():
+            plan.correlate(raw, out=vis)
+            fold.fold(vis, out=img)
+            return fold.profile(img)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(steps):
+            b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b.record()
+            step()
+            e.record()
+            e.synchronize()
+            times.append(b.elapsed_time(e))
+        times.sort()
+        out["experiment"][name] = {"N": N, "image": list(fold.shape), "radial_bins": fold.nbins,
+                                   "ms_median": round(times[len(times) // 2], 4)}
+        del fold, plan
+    if vis128 is not None:
+        F = vis128.shape[0]
+        plan = omni.Plan([[128, 128]], [skysim.lattice(0.5)], F, "ci4", "mixed", host_only=False)
+        fold = omni.Fold(plan, du=0.5, dv=0.5)
+        img = torch.empty((F,) + fold.shape, dtype=torch.complex128, device="cuda")
+        for _ in range(warmup):
+            fold.fold(vis128, out=img)
+        torch.cuda.synchronize()
+        b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = max(steps, 20)
+        b.record()
+        for _ in range(n):
+            fold.fold(vis128, out=img)
+        e.record()
+        e.synchronize()
+        ms = b.elapsed_time(e) / n
+        cells = int(np.prod(vis128.shape[1:]))
+        nbytes = F * (8 * cells + 16 * fold.shape[0] * fold.shape[1])
+        gbs = nbytes / (ms / 1e3) / 1e9
+        out["fold_grid128_64ch"] = {"ms_per_fold": round(ms, 5), "image": list(fold.shape),
+                                    "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                                 "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                                 "algorithmic_bytes": nbytes}}
+        del fold, plan
+    return out
 
 
 def cpu_model() -> str:
@@ -272,15 +346,24 @@ def bench_batch4(args) -> int:
         raws.append(skysim.make_voltages(w, device=dev))
     torch.cuda.synchronize()
     # the timed line: one batched call of the four arrays as a HIP graph, `form` form
-    g = run_batch(omni, ws, raws, form, True, args.steps, args.warmup)
-    seq = run_batch(omni, ws, raws, form, False, args.steps, args.warmup)
-    alt = run_batch(omni, ws, raws, other, True, args.steps, args.warmup) if not args.no_other_form else None
+    # with autotuning, the graph plan searches and stores its schedules in a scratch cache file; the sequential
+    # plan and the single-array runs take the same schedules from it (same launches, so the same bytes)
+    import tempfile
+
+    fd, cache = tempfile.mkstemp(prefix="omni_tune_", suffix=".txt")
+    os.close(fd)
+    again = "cache" if args.tune == "search" else "off"
+    g = run_batch(omni, ws, raws, form, True, args.steps, args.warmup, args.tune, cache)
+    seq = run_batch(omni, ws, raws, form, False, args.steps, args.warmup, again, cache)
+    alt = (run_batch(omni, ws, raws, other, True, args.steps, args.warmup, args.tune, cache)
+           if not args.no_other_form else None)
     same = all(torch.equal(a, b) for a, b in zip(g["outs"], seq["outs"]))
     work = sum(w.antenna_samples() for w in ws)
     ms = g["ms"]
     # each array alone (same bytes, same form): its main kernel's per-launch events give the rooflines; the
     # dominant array (the 16x16-of-16x16 one, most of the call) gives the line's `roofline`
-    alone = {w.name: run_form(omni, w, r, form, args.steps, args.warmup) for w, r in zip(ws, raws)}
+    alone = {w.name: run_form(omni, w, r, form, args.steps, args.warmup, again, cache) for w, r in zip(ws, raws)}
+    os.unlink(cache)
     per_array = {}
     for w in ws:
         res = alone[w.name]
@@ -347,6 +430,8 @@ def bench_batch4(args) -> int:
             "arrays": {w.name: {"N": w.N, "F": w.nchan, "T": w.T, "kernel": k} for w, k in zip(ws, g["kernels"])},
             "sample_format": "ci4",
             "form": form,
+            "tune": args.tune,
+            "schedules": g["schedules"],
         },
         "roofline": dict(per_array[dom.name]["roofline"],
                          note=f"main forward kernel of the dominant {dom.name} array, per-launch HIP events with the "
@@ -364,6 +449,10 @@ def bench_batch4(args) -> int:
     if alt is not None:
         out[f"{other}_form"] = {"ms_per_step": alt["ms"], "value": work / (alt["ms"] / 1e3), "kernels": alt["kernels"]}
         out[f"speedup_vs_{other}_form"] = alt["ms"] / ms
+    if not args.no_fold:
+        log("bench: baseline fold and distributions")
+        out["baseline_fold"] = bench_fold(omni, torch, skysim, args.steps, args.warmup,
+                                          g["outs"][BATCH4.index("grid128")])
     print(json.dumps(out), flush=True)
     return 0
 
@@ -401,6 +490,9 @@ def main() -> int:
     ap.add_argument("--no-other-form", action="store_true", help="time only the main form")
     ap.add_argument("--direct", action="store_true", help="also time the direct N^2 correlator at any N")
     ap.add_argument("--no-direct", action="store_true", help="never time the direct N^2 correlator")
+    ap.add_argument("--tune", default="search", choices=["off", "search"],
+                    help="plan-time autotuning of the schedules (default: search; planning is outside the timing)")
+    ap.add_argument("--no-fold", action="store_true", help="skip the baseline-fold measurements")
     ap.add_argument("--copy-calibration", action="store_true", help="only run 3 x 1 GiB device copies")
     args = ap.parse_args()
 
@@ -432,10 +524,10 @@ def main() -> int:
     raw = skysim.make_voltages(w, device=dev)
     torch.cuda.synchronize()
 
-    main_res = run_form(omni, w, raw, form, args.steps, args.warmup)
+    main_res = run_form(omni, w, raw, form, args.steps, args.warmup, args.tune)
     alt = None
     if not args.no_other_form and not (other == "mixed" and w.dtype == "cf32"):
-        alt = run_form(omni, w, raw, other, args.steps, args.warmup)
+        alt = run_form(omni, w, raw, other, args.steps, args.warmup, args.tune)
     direct = None
     if w.dtype != "cf32" and not args.no_direct and (args.direct or w.N <= 16384):
         direct = run_direct(omni, w, raw, args.steps, args.warmup)

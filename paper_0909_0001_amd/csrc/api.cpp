@@ -103,7 +103,8 @@ struct ArrayPlan {
                    // 6, 7, 8: single-level 128 x 128, 64 x 64, 32 x 32, mixed (MFMA), 4-bit samples
   int ct_index = -1;         // entry of the compile-time shape table (kernel 3)
   int lcap = 32;             // longest short DFT the general kernel may use (autotuned)
-  int wg_target = 1024;      // work-groups the general kernel's time slicing aims for (autotuned)
+  int wg_target = 1024;      // work-groups the time slicing aims for (general and sliced kernels; autotuned)
+  int tb = 0;                // float32 block of the sliced kernels (0: the plan's time_block; autotuned)
   double tuned_ms = 0.0;     // best candidate's time in the autotuner (0: not tuned)
   // front mode: the first n_front axes are transformed by front passes over HBM
   int n_front = 0;
@@ -177,6 +178,7 @@ struct omni_plan_s {
   omni_dtype dtype = OMNI_CF32;
   omni_form form = OMNI_FORM_FP32;
   int time_block = 64;
+  bool time_block_set = false;  // the caller chose time_block (the autotuner keeps it)
   bool host_only = false;
   int device = -1;
   int tune = OMNI_TUNE_OFF;
@@ -186,6 +188,24 @@ struct omni_plan_s {
 namespace {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Kernels with a fixed shape that split the time axis into slices (one partial-sum set each): 1 (8x8x8x8
+// float32), 2 (8x8x8x8 mixed) and 6-8 (single-level 128 x 128, 64 x 64, 32 x 32 mixed).
+bool sliced_kernel(int k) { return k == 1 || k == 2 || (k >= 6 && k <= 8); }
+
+// Default work-group target of the time slicing, per kernel: 8x8x8x8 float32: three 48 KiB work-groups a CU,
+// two rounds over 256 CUs; 8x8x8x8 mixed: one 112 KiB work-group a CU, one round; 128 x 128: one 128 KiB
+// work-group a CU, about four rounds; 64 x 64: one 96 KiB work-group a CU, four rounds; 32 x 32: 256 threads
+// and 12 KiB, about five work-groups a CU, two rounds.
+int default_wg_target(int k) {
+  switch (k) {
+    case 1: return 1536;
+    case 2: return 256;
+    case 8: return 2560;
+    default: return 1024;
+  }
+}
+
 
 int64_t prod(const std::vector<int>& v) {
   int64_t p = 1;
@@ -641,6 +661,7 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
     plan_grid_small(ap, 7);
   if (form == OMNI_FORM_MIXED && dtype == OMNI_CI4 && ap.n_front == 0 && ap.n == std::vector<int>{32, 32})
     plan_grid_small(ap, 8);
+  if (sliced_kernel(ap.kernel)) ap.wg_target = default_wg_target(ap.kernel);
   const size_t per_slice = (size_t)ap.F * (size_t)ap.M * sizeof(double);
   ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / per_slice));
   // inverse in groups of channels whose complex float32 workspace fits 1 GiB per buffer
@@ -786,6 +807,40 @@ int launch_ct(ArrayPlan& ap, int fmt, const void* src, int64_t T, int time_block
   return OMNI_OK;
 }
 
+// Launch a sliced kernel over T samples: about `target` work-groups (fewer when T is short or the partial
+// sums would not fit), float32 blocks of `tb` samples.  *slices receives the slice count.
+int launch_sliced(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, int64_t target, int tb,
+                  hipStream_t st, int* slices) {
+  const int64_t per_slice_groups = (int64_t)ap.F * (ap.kernel == 1 ? 8 : (ap.kernel == 2 || ap.kernel == 6) ? 2 : 1);
+  int64_t ns = std::max<int64_t>(1, (target + per_slice_groups / 2) / per_slice_groups);
+  ns = std::min<int64_t>(ns, ap.max_slices);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
+  const int64_t tps = (T + ns - 1) / ns;
+  ns = (T + tps - 1) / tps;
+  *slices = (int)ns;
+  const int fmt = fmt_of(p->dtype);
+  switch (ap.kernel) {
+    case 1:
+      HIP_TRY(omni::launch_fused8x4_fp32(fmt, volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, tb, st));
+      break;
+    case 2:
+      HIP_TRY(omni::launch_fused8x4_mixed(fmt, volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, tb, st));
+      break;
+    case 6:  // the four stages scale by 1/16, 1/8, 1/8, 1/16: |X|^2 carries 2^-28
+      HIP_TRY(omni::launch_grid128_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, tb, 268435456.0, st));
+      break;
+    case 7:  // four stages of 1/8: 2^-24
+      HIP_TRY(omni::launch_grid64_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, tb, 16777216.0, st));
+      break;
+    case 8:  // two stages of 1/32: 2^-20
+      HIP_TRY(omni::launch_grid32_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, tb, 1048576.0, st));
+      break;
+    default:
+      return fail(OMNI_E_STATE, "not a sliced kernel");
+  }
+  return OMNI_OK;
+}
+
 int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, void* vis, hipStream_t st,
                     uint32_t flags, int stage) {
   const bool accumulate = (flags & OMNI_NO_RESET) != 0;
@@ -868,66 +923,11 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     if (ap.kernel >= 3)
       HIP_TRY(omni::launch_reduce_scatter(ap.d_partial, ap.d_kmap, ap.d_A, first_slices, ap.fs.F, ap.fs.fp.n_split,
                                           ap.fs.fp.cells_wg, ap.fs.M, accumulate ? 1 : 0, st));
-  } else if (stage == 0 && T > 0 && ap.kernel == 1) {
-    // three 48 KiB work-groups fit one CU: aim for two full rounds over 256 CUs
-    const int64_t per_slice_groups = (int64_t)ap.F * 8;
-    int64_t ns = std::max<int64_t>(1, (1536 + per_slice_groups / 2) / per_slice_groups);
-    ns = std::min<int64_t>(ns, ap.max_slices);
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
-    const int64_t tps = (T + ns - 1) / ns;
-    ns = (T + tps - 1) / tps;
-    ap.last_slices = (int)ns;
+  } else if (stage == 0 && T > 0 && sliced_kernel(ap.kernel)) {
     kmark(p, 0, st);
-    HIP_TRY(omni::launch_fused8x4_fp32(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns,
-                                       p->time_block, st));
+    int rc = launch_sliced(p, ap, volt, T, ap.wg_target, ap.tb > 0 ? ap.tb : p->time_block, st, &ap.last_slices);
     kmark(p, 1, st);
-  } else if (stage == 0 && T > 0 && ap.kernel == 2) {
-    // one 112 KiB work-group of 1024 threads per CU: one round of 256 work-groups
-    const int64_t per_slice_groups = (int64_t)ap.F * 2;
-    const int64_t target = 256;
-    int64_t ns = std::max<int64_t>(1, (target + per_slice_groups / 2) / per_slice_groups);
-    ns = std::min<int64_t>(ns, ap.max_slices);
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
-    const int64_t tps = (T + ns - 1) / ns;
-    ns = (T + tps - 1) / tps;
-    ap.last_slices = (int)ns;
-    kmark(p, 0, st);
-    HIP_TRY(omni::launch_fused8x4_mixed(fmt_of(p->dtype), volt, T, tps, ap.d_tw32, ap.d_partial, ap.F,
-                                        (int)ns, p->time_block, st));
-    kmark(p, 1, st);
-  } else if (stage == 0 && T > 0 && ap.kernel == 6) {
-    // one 128 KiB work-group of 1024 threads per CU: about four rounds of 256 work-groups
-    const int64_t per_slice_groups = (int64_t)ap.F * 2;
-    int64_t ns = std::max<int64_t>(1, (1024 + per_slice_groups / 2) / per_slice_groups);
-    ns = std::min<int64_t>(ns, ap.max_slices);
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
-    const int64_t tps = (T + ns - 1) / ns;
-    ns = (T + tps - 1) / tps;
-    ap.last_slices = (int)ns;
-    // the four stages scale by 1/16, 1/8, 1/8, 1/16: |X|^2 carries 2^-28
-    kmark(p, 0, st);
-    HIP_TRY(omni::launch_grid128_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
-                                       268435456.0, st));
-    kmark(p, 1, st);
-  } else if (stage == 0 && T > 0 && (ap.kernel == 7 || ap.kernel == 8)) {
-    // 64 x 64: one 96 KiB work-group of 1024 threads per CU; 32 x 32: 256 threads and 12 KiB, about five
-    // work-groups per CU
-    const int64_t target = ap.kernel == 7 ? 1024 : 2560;
-    int64_t ns = std::max<int64_t>(1, (target + ap.F / 2) / ap.F);
-    ns = std::min<int64_t>(ns, ap.max_slices);
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, T / 8));
-    const int64_t tps = (T + ns - 1) / ns;
-    ns = (T + tps - 1) / tps;
-    ap.last_slices = (int)ns;
-    // 64 x 64: four stages of 1/8, |X|^2 carries 2^-24; 32 x 32: two of 1/32, 2^-20
-    kmark(p, 0, st);
-    if (ap.kernel == 7)
-      HIP_TRY(omni::launch_grid64_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
-                                        16777216.0, st));
-    else
-      HIP_TRY(omni::launch_grid32_mixed(volt, T, tps, ap.d_tw32, ap.d_partial, ap.F, (int)ns, p->time_block,
-                                        1048576.0, st));
-    kmark(p, 1, st);
+    if (rc) return rc;
   } else if (stage == 0 && T > 0 && ap.kernel == 3) {
     kmark(p, 0, st);
     int rc = launch_ct(ap, fmt_of(p->dtype), volt, T, p->time_block, ap.d_tw32, st, &ap.last_slices);
@@ -1008,9 +1008,72 @@ void tune_cache_store(const std::string& path, const std::string& key, int lcap,
 
 // Times the candidate schedules on zero input and keeps the fastest: for the
 // general kernel, short-DFT cap x time slicing; for the compile-time-shape
-// kernel (fixed fold moduli), time slicing only.  The 8x8x8x8 kernels have a
-// fixed schedule.
+// kernel (fixed fold moduli), time slicing only; for the sliced fixed-shape
+// kernels, time slicing x float32 block.  The kernels behind front passes take
+// all channels of a chunk in one launch and have no schedule to tune.
+// Sliced kernels (fixed shape): time slicing (work-group target) x float32 block.  The block is tuned only in
+// the mixed form and only when the caller left time_block at its default (longer float32 blocks stay far
+// inside the mixed form's error budget; the float32 form keeps its 64-sample block).  A cached schedule is
+// taken as stored (cache line: key block wg_target ms).
+int tune_sliced(omni_plan_s* p, ArrayPlan& ap) {
+  const std::string key = tune_key(ap, p->dtype);
+  int c_tb = 0, c_wg = 0;
+  if (p->tune == OMNI_TUNE_CACHE && tune_cache_lookup(p->tune_cache, key, &c_tb, &c_wg) && c_tb > 0 && c_wg > 0) {
+    ap.tb = c_tb;
+    ap.wg_target = c_wg;
+    return OMNI_OK;
+  }
+  const size_t bytes_t = (size_t)ap.F * (size_t)ap.N * sample_bytes(p->dtype);
+  const int64_t Tt = std::max<int64_t>(16, std::min<int64_t>(2048, (int64_t(1) << 30) / (int64_t)bytes_t));
+  std::vector<int> tbs;
+  if (p->form == OMNI_FORM_MIXED && !p->time_block_set)
+    tbs = {256, 1024};
+  else
+    tbs = {p->time_block};
+  std::vector<int> wgs = {256, 512, 1024, 2048, 4096};
+  if (std::find(wgs.begin(), wgs.end(), ap.wg_target) == wgs.end()) wgs.push_back(ap.wg_target);
+  void* zero = nullptr;
+  HIP_TRY(hipMalloc(&zero, bytes_t * (size_t)Tt));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipMemset(zero, 0, bytes_t * (size_t)Tt);
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  double best = 1e30;
+  int best_tb = ap.tb, best_wg = ap.wg_target;
+  int rc = OMNI_OK;
+  for (int tb : tbs) {
+    for (int wg : wgs) {
+      if (he != hipSuccess || rc != OMNI_OK) break;
+      float ms = 0.f;
+      int slices = 1;
+      for (int rep = 0; rep < 2 && rc == OMNI_OK && he == hipSuccess; ++rep) {
+        he = hipEventRecord(e0, 0);
+        if (he == hipSuccess) rc = launch_sliced(p, ap, zero, Tt, wg, tb, 0, &slices);
+        if (he == hipSuccess && rc == OMNI_OK) he = hipEventRecord(e1, 0);
+        if (he == hipSuccess && rc == OMNI_OK) he = hipEventSynchronize(e1);
+        if (he == hipSuccess && rc == OMNI_OK) he = hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (he == hipSuccess && rc == OMNI_OK && ms < best) {
+        best = ms;
+        best_tb = tb;
+        best_wg = wg;
+      }
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(zero);
+  if (rc) return rc;
+  if (he != hipSuccess) return fail(OMNI_E_HIP, std::string("autotuner: ") + hipGetErrorString(he));
+  ap.tb = best_tb;
+  ap.wg_target = best_wg;
+  ap.tuned_ms = best;
+  tune_cache_store(p->tune_cache, key, best_tb, best_wg, best);
+  return OMNI_OK;
+}
+
 int tune_array(omni_plan_s* p, ArrayPlan& ap) {
+  if (sliced_kernel(ap.kernel)) return tune_sliced(p, ap);
   if (ap.kernel != 0 && ap.kernel != 3) return OMNI_OK;
   const bool ct = ap.kernel == 3;
   const std::string key = tune_key(ap, p->dtype);
@@ -1194,6 +1257,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   // float64 partial sums in HBM (a float32 sum of 1024 non-negative terms stays within 2^-14 relative,
   // far inside the form's 2e-3)
   p->time_block = o.time_block > 0 ? o.time_block : (o.form == OMNI_FORM_MIXED ? 1024 : 64);
+  p->time_block_set = o.time_block > 0;
   p->host_only = (o.flags & OMNI_PLAN_HOST_ONLY) != 0;
   p->timing = (o.flags & OMNI_PLAN_TIMING) != 0 && !p->host_only;
   p->tune = o.tune;
@@ -1614,7 +1678,9 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
          ",\"cells_wg\":" + std::to_string(P.cells_wg) + ",\"cells_per_thread\":" + std::to_string(ap.fs.cpt) +
          ",\"lds_bytes\":" + std::to_string(ap.fs.lds) + ",\"max_slices\":" + std::to_string(ap.max_slices) +
          ",\"inverse_group\":" + std::to_string(ap.inv_group) + ",\"lcap\":" + std::to_string(ap.lcap) +
-         ",\"wg_target\":" + std::to_string(ap.wg_target) + ",\"tuned_ms\":" + std::to_string(ap.tuned_ms) +
+         ",\"wg_target\":" + std::to_string(ap.wg_target) +
+         ",\"block\":" + std::to_string(ap.tb > 0 ? ap.tb : plan->time_block) +
+         ",\"tuned_ms\":" + std::to_string(ap.tuned_ms) +
          ",\"axes\":[";
     for (int k = 0; k < P.d; ++k) {
       const AxisP& a = P.ax[k];

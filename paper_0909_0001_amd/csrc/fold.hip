@@ -14,8 +14,8 @@
 // the plan computes every cell's pixel on the device once, sorts the cells by
 // pixel (stable radix sort, so cells of one pixel stay in ascending order) and
 // keeps the sorted cell list with per-pixel offsets (CSR).  A fold call is then
-// a gather: one thread per (pixel, channel) sums its cells in that fixed order
-// in float64, so the result is deterministic.  The radial distribution uses
+// a gather: one thread per pixel and group of eight channels sums the pixel's
+// cells in that fixed order in float64, so the result is deterministic.  The radial distribution uses
 // the same scheme over pixels grouped by radial bin, one wave per (bin,
 // channel) with a fixed-order reduction.
 //
@@ -106,23 +106,37 @@ __global__ void group_offsets_kernel(const uint32_t* __restrict__ keys, int64_t 
   off[i] = (uint32_t)lo;
 }
 
+// One thread per pixel and group of kFoldCh channels: the pixel's cell list is read once and its channels'
+// loads are independent of each other.
+constexpr int kFoldCh = 8;
+
 __global__ void fold_gather_kernel(const float2* __restrict__ vis, int64_t cells, const uint32_t* __restrict__ cell,
-                                   const uint32_t* __restrict__ off, int64_t npix, int64_t origin,
+                                   const uint32_t* __restrict__ off, int64_t npix, int F, int64_t origin,
                                    double2* __restrict__ image) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int f = blockIdx.y;
+  const int f0 = blockIdx.y * kFoldCh;
   if (p >= npix) return;
-  const float2* v = vis + (int64_t)f * cells;
-  double re = 0.0, im = 0.0;
+  const int nf = min(kFoldCh, F - f0);
+  double re[kFoldCh], im[kFoldCh];
+#pragma unroll
+  for (int j = 0; j < kFoldCh; ++j) re[j] = im[j] = 0.0;
   if (p != origin) {
     const uint32_t e = off[p + 1];
     for (uint32_t i = off[p]; i < e; ++i) {
-      const float2 x = v[cell[i]];
-      re += (double)x.x;
-      im += (double)x.y;
+      const float2* v = vis + (int64_t)f0 * cells + cell[i];
+      float2 x[kFoldCh];
+#pragma unroll
+      for (int j = 0; j < kFoldCh; ++j) x[j] = j < nf ? v[(int64_t)j * cells] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < kFoldCh; ++j) {
+        re[j] += (double)x[j].x;
+        im[j] += (double)x[j].y;
+      }
     }
   }
-  image[(int64_t)f * npix + p] = make_double2(re, im);
+#pragma unroll
+  for (int j = 0; j < kFoldCh; ++j)
+    if (j < nf) image[(int64_t)(f0 + j) * npix + p] = make_double2(re[j], im[j]);
 }
 
 __global__ void channel_max_kernel(const double2* __restrict__ image, int64_t npix, double* __restrict__ dmax) {
@@ -216,8 +230,9 @@ hipError_t launch_fold_gather(const float2* vis, int64_t cells, const uint32_t* 
                               int64_t npix, int F, int64_t origin, double2* image, hipStream_t st) {
   const int64_t blocks = (npix + kThreads - 1) / kThreads;
   if (F < 1 || F > 65535 || blocks > INT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fold_gather_kernel, dim3((unsigned)blocks, (unsigned)F), dim3(kThreads), 0, st, vis, cells, cell,
-                     off, npix, origin, image);
+  const unsigned groups = (unsigned)((F + kFoldCh - 1) / kFoldCh);
+  hipLaunchKernelGGL(fold_gather_kernel, dim3((unsigned)blocks, groups), dim3(kThreads), 0, st, vis, cells, cell, off,
+                     npix, F, origin, image);
   return hipGetLastError();
 }
 

@@ -485,6 +485,51 @@ def test_autotuned_plan_matches_oracle(level_dims, kernel):
 
 
 @pytest.mark.parametrize(
+    "level_dims,dtype,form,kernel",
+    [
+        ([[32, 32]], "ci4", "mixed", "grid32_mixed"),
+        ([[64, 64]], "ci4", "mixed", "grid64_mixed"),
+        ([[128, 128]], "ci4", "mixed", "grid128_mixed"),
+        ([[8, 8], [8, 8]], "ci8", "mixed", "fused8x4_mixed"),
+        ([[8, 8], [8, 8]], "ci8", "fp32", "fused8x4_fp32"),
+    ],
+)
+def test_autotuned_sliced_kernels(level_dims, dtype, form, kernel, tmp_path):
+    """The autotuner's search over time slicing x float32 block of the fixed-shape kernels: the tuned plan
+    agrees with the oracle, its schedule is stored in the cache file, and a plan made from the cache takes the
+    same schedule without searching.  The float32 form keeps its 64-sample block."""
+    import json
+
+    gen = torch.Generator().manual_seed(41)
+    N = math.prod(dims_of(level_dims))
+    T = 40
+    raw = random_raw(dtype, T, 2, N, gen)
+    cache = str(tmp_path / "tune.txt")
+    plan = omni.Plan(level_dims, None, 2, dtype, form, tune="search", tune_cache=cache)
+    a = json.loads(plan.describe())["arrays"][0]
+    say("tuned", kernel, a["wg_target"], a["block"], a["tuned_ms"])
+    assert a["kernel"] == kernel and a["tuned_ms"] > 0
+    assert a["block"] in ((256, 1024) if form == "mixed" else (64,))
+    vis = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    N_full = 4096  # above this, the oracle one cell at a time
+    if N <= N_full:
+        ref_err = lambda v: rel_err(v, oracle_vis(raw, dtype, level_dims))  # noqa: E731
+    else:
+        x = oracle.decode(raw.numpy(), dtype, T, 2, N)
+        ref_err = lambda v: check_cells(v, x, dims_of(level_dims), form, 256, 5, kernel) or 0.0  # noqa: E731
+    assert ref_err(vis.cpu().numpy()) <= TOL[form]
+    line = open(cache).read().split()
+    assert int(line[1]) == a["block"] and int(line[2]) == a["wg_target"]
+    again = omni.Plan(level_dims, None, 2, dtype, form, tune="cache", tune_cache=cache)
+    b = json.loads(again.describe())["arrays"][0]
+    assert (b["wg_target"], b["block"], b["tuned_ms"]) == (a["wg_target"], a["block"], 0.0)
+    vis2 = again.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(vis2, vis)  # same schedule, same launch, same bytes
+
+
+@pytest.mark.parametrize(
     "level_dims,dtype,kernel",
     [
         ([[32, 32]], "ci4", "fused_ct_fp32"),
