@@ -318,6 +318,64 @@ def bench_fold(omni, torch, skysim, steps, warmup, vis128=None):
     return out
 
 
+def bench_fengine(omni, torch, steps, warmup, N=16384, F=64, T=2048):
+    """F-engine (Appendix A steps 2-3) on the 128x128 array's size: N antennas x T blocks of 2F int8 samples ->
+    ci4 voltages [T][F][N].  Algorithmic HBM bytes: 2F in + F out per antenna and block (gains: 8 F per antenna);
+    matrix-core work: the (2F outputs) x (2F samples) real product with hi + lo coefficients, 8 F^2 multiply-adds =
+    16 F^2 flops per antenna and block (8F flops per sample)."""
+    gen = torch.Generator(device="cuda").manual_seed(20090839)
+    raw = torch.randint(-40, 41, (N, 2 * F * T), generator=gen, device="cuda", dtype=torch.int8)
+    gains = torch.full((N, F), complex(2.5 / (23.0 * math.sqrt(F)), 0.0), dtype=torch.complex64, device="cuda")
+    out = torch.empty((T, F, N), dtype=torch.uint8, device="cuda")
+    for _ in range(max(1, warmup)):
+        omni.fengine(raw, F, gains, "ci4", out=out)
+    torch.cuda.synchronize()
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record()
+    for _ in range(steps):
+        omni.fengine(raw, F, gains, "ci4", out=out)
+    e.record()
+    e.synchronize()
+    ms = b.elapsed_time(e) / steps
+    nbytes = N * T * (2 * F + F) + N * F * 8
+    flops = 16.0 * F * F * N * T
+    gbs = nbytes / (ms / 1e3) / 1e9
+    tfs = flops / (ms / 1e3) / 1e12
+    hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": nbytes}
+    mfma = {"bound": "mfma", "achieved": round(tfs, 1), "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tfs / PEAK_FP16_MFMA_TFLOPS, 4), "algorithmic_flops": flops}
+    del raw, out
+    return {"N": N, "F": F, "T": T, "ms_per_call": round(ms, 4), "samples_per_s": N * T * 2 * F / (ms / 1e3),
+            "roofline": hbm if hbm["frac"] >= mfma["frac"] else mfma, "roofline_hbm": hbm, "roofline_mfma": mfma}
+
+
+def bench_aux(args) -> int:
+    """Lines of their own for the steps around the correlator: the F-engine (`--workload fengine`) and the baseline
+    fold with the Sec. III distributions (`--workload baselines`)."""
+    import torch
+
+    import paper_0909_0001_amd as omni
+    import skysim
+
+    torch.cuda.set_device(0)
+    if args.workload == "fengine":
+        r = bench_fengine(omni, torch, args.steps, args.warmup)
+        line = {"metric": "raw samples/s channelised (F-engine)", "value": r["samples_per_s"], "unit": "samples/s",
+                "ms_per_step": r["ms_per_call"], "config": {"workload": f"F-engine: N={r['N']} antennas, "
+                f"T={r['T']} blocks of {2 * r['F']} int8 samples -> {r['F']} channels, ci4 [T][F][N]"},
+                "roofline": r["roofline"], "detail": r}
+    else:
+        r = bench_fold(omni, torch, skysim, args.steps, args.warmup)
+        line = {"metric": "baseline distributions (Sec. III layouts)", "value": None, "unit": "ms",
+                "config": {"workload": "all-ones sample through the correlator, fold, asinh map, radial sums, boxcar"},
+                "detail": r}
+    line.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "cpu_baseline": None,
+                 "vs_baseline": None})
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -453,6 +511,9 @@ def bench_batch4(args) -> int:
         log("bench: baseline fold and distributions")
         out["baseline_fold"] = bench_fold(omni, torch, skysim, args.steps, args.warmup,
                                           g["outs"][BATCH4.index("grid128")])
+    if not args.no_fengine:
+        log("bench: F-engine")
+        out["fengine"] = bench_fengine(omni, torch, args.steps, args.warmup)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -483,7 +544,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch4", help="batch4 (default) or a workload name of skysim.WORKLOADS")
+    ap.add_argument("--workload", default="batch4",
+                    help="batch4 (default), a workload name of skysim.WORKLOADS, fengine or baselines")
     ap.add_argument("--form", default=None, help="fp32 | mixed (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -492,6 +554,7 @@ def main() -> int:
     ap.add_argument("--no-direct", action="store_true", help="never time the direct N^2 correlator")
     ap.add_argument("--tune", default="search", choices=["off", "search"],
                     help="plan-time autotuning of the schedules (default: search; planning is outside the timing)")
+    ap.add_argument("--no-fengine", action="store_true", help="skip the F-engine measurement")
     ap.add_argument("--no-fold", action="store_true", help="skip the baseline-fold measurements")
     ap.add_argument("--copy-calibration", action="store_true", help="only run 3 x 1 GiB device copies")
     args = ap.parse_args()
@@ -508,6 +571,8 @@ def main() -> int:
         return copy_calibration()
     if args.workload == "batch4":
         return bench_batch4(args)
+    if args.workload in ("fengine", "baselines"):
+        return bench_aux(args)
 
     import numpy as np
     import torch

@@ -288,6 +288,34 @@ typedef enum {
  * 32 most recent calls. */
 int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, int32_t* n);
 
+/* ---- F-engine ahead of the correlator ------------------------------------
+ *
+ * Appendix A, steps 2-3: each antenna's data are Fourier transformed in the
+ * time domain (and calibrated), then arranged per frequency bin as the
+ * hypercube the correlator takes.  Reading: raw real samples, one int8 per
+ * antenna and instant, antenna-major; blocks of 2F consecutive samples, one
+ * DFT per block, no window, bins k = 0 .. F-1 (the Nyquist bin dropped):
+ *   X[n][t][k] = sum_{j < 2F} raw[n][2F t + j] exp(-2 pi i j k / 2F);
+ * calibration and requantisation scale in one complex gain per antenna and
+ * channel, Y = gains[n][k] X[n][t][k]; real and imaginary parts rounded to
+ * the nearest integer (ties to even) and clipped to [-7, 7] (ci4) or
+ * [-127, 127] (ci8); written in the correlator's sample layout [t][k][n]
+ * (the corner turn).  The transform runs in float32 on the matrix cores
+ * (float16 operands, the DFT matrix split into float16 hi + lo parts): a
+ * code can differ from the exact value's by one only where the exact value
+ * lies within the float32 error (about 1e-5 of sum_j |raw| |gain|) of a
+ * rounding boundary.
+ *   raw   : device int8 [N][2 F T], 16-byte aligned.
+ *   N, T  : antennas (>= 1) and blocks (time samples of the output, >= 0).
+ *   F     : channels, 16, 32 or 64.
+ *   gains : device complex64 [N][F].
+ *   dtype : OMNI_CI4 (volt: uint8 [T][F][N]) or OMNI_CI8 (volt: int8 [T][F][N][2]).
+ *   volt  : device output, written.
+ * Asynchronous on `stream`.  Errors: OMNI_E_INVAL (NULL, alignment, dtype,
+ * N or T), OMNI_E_SHAPE (F, sizes), OMNI_E_HIP. */
+int omni_fengine(const void* raw, int64_t N, int64_t T, int32_t F, const void* gains, int32_t dtype, void* volt,
+                 void* stream);
+
 /* ---- Physical-baseline fold and baseline distributions -------------------
  *
  * Sec. II.D: hypercube cell Delta holds every antenna pair whose index tuples

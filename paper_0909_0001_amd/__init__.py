@@ -63,6 +63,7 @@ EXPORTS = [
     "omni_fold",
     "omni_baseline_profile",
     "omni_fold_destroy",
+    "omni_fengine",
 ]
 
 
@@ -142,6 +143,7 @@ def _load():
         "omni_fold": (ctypes.c_int, [P, P, i32, P, P]),
         "omni_baseline_profile": (ctypes.c_int, [P, P, i32, P, P, P, P]),
         "omni_fold_destroy": (ctypes.c_int, [P]),
+        "omni_fengine": (ctypes.c_int, [P, i64, i64, i32, P, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -438,6 +440,33 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def fengine(raw, F: int, gains, dtype: str = "ci4", out=None, stream=None):
+    """F-engine (Appendix A steps 2-3): raw int8 samples [N, 2 F T] (antenna-major, 16-byte aligned GPU tensor)
+    and complex64 gains [N, F] -> the correlator's voltages [T, F, N] (ci4, uint8) or [T, F, N, 2] (ci8, int8)."""
+    import torch
+
+    if dtype not in ("ci4", "ci8"):
+        raise ValueError("the F-engine writes ci4 or ci8 samples")
+    if raw.dtype != torch.int8 or raw.dim() != 2 or not raw.is_contiguous() or raw.device.type != "cuda":
+        raise ValueError("raw must be a contiguous int8 GPU tensor [N, 2 F T]")
+    N, S = raw.shape
+    if F not in (16, 32, 64) or S % (2 * F):
+        raise ValueError(f"F must be 16, 32 or 64 and divide the {S} samples per antenna into 2F-sample blocks")
+    T = S // (2 * F)
+    if gains.dtype != torch.complex64 or tuple(gains.shape) != (N, F) or not gains.is_contiguous() \
+            or gains.device != raw.device:
+        raise ValueError(f"gains must be a contiguous complex64 tensor [{N}, {F}] on the raw samples' device")
+    shape = (T, F, N) if dtype == "ci4" else (T, F, N, 2)
+    tdt = torch.uint8 if dtype == "ci4" else torch.int8
+    if out is None:
+        out = torch.empty(shape, dtype=tdt, device=raw.device)
+    if out.dtype != tdt or tuple(out.shape) != shape or not out.is_contiguous() or out.device != raw.device:
+        raise ValueError(f"out must be a contiguous {tdt} tensor of shape {shape} on the raw samples' device")
+    _check(lib.omni_fengine(raw.data_ptr(), N, T, F, gains.data_ptr(), DTYPES[dtype], out.data_ptr(),
+                            _stream_handle(stream)))
+    return out
 
 
 class Fold:

@@ -57,6 +57,8 @@ hipError_t launch_grid64_mixed(const void* src, int64_t T, int64_t tps, const fl
                                int n_slices, int time_block, double out_scale, hipStream_t st);
 hipError_t launch_grid32_mixed(const void* src, int64_t T, int64_t tps, const float2* tw64, double* partial, int F,
                                int n_slices, int time_block, double out_scale, hipStream_t st);
+hipError_t launch_fengine(const void* raw, int64_t N, int64_t T, int F, const void* gains, bool ci8, void* out,
+                          hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -1767,6 +1769,27 @@ const char* omni_strerror(int code) {
 const char* omni_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// F-engine (Appendix A, steps 2-3).
+// ---------------------------------------------------------------------------
+
+extern "C" int omni_fengine(const void* raw, int64_t N, int64_t T, int32_t F, const void* gains, int32_t dtype,
+                            void* volt, void* stream) {
+  if (N < 1 || T < 0) return fail(OMNI_E_INVAL, "N must be >= 1 and T >= 0");
+  if (F != 16 && F != 32 && F != 64) return fail(OMNI_E_SHAPE, "F-engine: F must be 16, 32 or 64 channels");
+  if (dtype != OMNI_CI4 && dtype != OMNI_CI8) return fail(OMNI_E_INVAL, "F-engine output must be ci4 or ci8");
+  if (T == 0) return OMNI_OK;
+  if (!raw || !gains || !volt) return fail(OMNI_E_INVAL, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(raw) & 15) != 0) return fail(OMNI_E_INVAL, "raw samples must be 16-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(gains) & 7) != 0) return fail(OMNI_E_INVAL, "gains must be 8-byte aligned");
+  if (dtype == OMNI_CI8 && (reinterpret_cast<uintptr_t>(volt) & 1) != 0)
+    return fail(OMNI_E_INVAL, "ci8 output must be 2-byte aligned");
+  if (N > (int64_t(1) << 31) || T > (int64_t(1) << 40) / (2 * F * N))
+    return fail(OMNI_E_SHAPE, "F-engine: N or T too large");
+  HIP_TRY(omni::launch_fengine(raw, N, T, F, gains, dtype == OMNI_CI8, volt, static_cast<hipStream_t>(stream)));
+  return OMNI_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Physical-baseline fold (Sec. II.D) and baseline distributions (Sec. III).

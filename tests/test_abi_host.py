@@ -243,3 +243,17 @@ def test_fold_plan_validates_before_any_device_call():
     assert omni.lib.omni_fold(None, None, 1, None, None) == -1
     assert omni.lib.omni_baseline_profile(None, None, 1, None, None, None, None) == -1
     assert omni.lib.omni_fold_destroy(None) == 0
+
+
+def test_fengine_validates_before_any_device_call():
+    f = omni.lib.omni_fengine
+    st = omni.STATUS
+    assert st[f(16, 0, 4, 64, 16, 2, 16, None)] == "OMNI_E_INVAL"  # N < 1
+    assert st[f(16, 8, -1, 64, 16, 2, 16, None)] == "OMNI_E_INVAL"  # T < 0
+    assert st[f(16, 8, 4, 48, 16, 2, 16, None)] == "OMNI_E_SHAPE"  # F not 16 / 32 / 64
+    assert st[f(16, 8, 4, 64, 16, 0, 16, None)] == "OMNI_E_INVAL"  # cf32 output
+    assert f(None, 8, 0, 64, None, 2, None, None) == 0  # T == 0: nothing to do
+    assert st[f(None, 8, 4, 64, 16, 2, 16, None)] == "OMNI_E_INVAL"  # NULL raw
+    assert st[f(24, 8, 4, 64, 16, 2, 16, None)] == "OMNI_E_INVAL"  # raw not 16-byte aligned
+    assert st[f(16, 8, 4, 64, 12, 2, 16, None)] == "OMNI_E_INVAL"  # gains not 8-byte aligned
+    assert st[f(16, 8, 4, 64, 16, 1, 17, None)] == "OMNI_E_INVAL"  # ci8 output not 2-byte aligned
