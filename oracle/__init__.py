@@ -24,6 +24,9 @@ defines, written so it can be checked against the paper by eye:
 * ``layout``            -- the physical-baseline fold of the hypercube and the
   baseline-distribution experiment of Sec. III (d = l * l^- from antenna
   positions, zeroed origin, asinh map, radial bins, boxcar smoothing).
+* ``beams``             -- the beam-space variant: unpadded 2-D transform of
+  every lowest-level block ("digital pointings"), then each pointing
+  correlated over the other levels (Appendix A, steps 4-5).
 * ``fengine``           -- the per-antenna time-domain Fourier transform,
   calibration, requantisation and corner turn ahead of the correlator
   (Appendix A, steps 2-3).
@@ -44,7 +47,7 @@ from .correlator import (  # noqa: F401
     visibilities_by_outer_lag,
     visibility_cells,
 )
-from . import fengine  # noqa: F401
+from . import beams, fengine  # noqa: F401
 from .layout import (  # noqa: F401
     asinh_map,
     baseline_distribution,
