@@ -78,6 +78,17 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
 #define OMNI_PLAN_TIMING 0x2u    /* record HIP events around each stage of every correlate call  */
 #define OMNI_PLAN_GRAPH 0x8u     /* run every correlate call as one HIP graph whose arrays are     \
                                     parallel branches (first call captured, later calls replay)  */
+/* Beam-space ("digital pointing") variant of Appendix A, steps 4-5: the lowest
+ * level (the last level, axes d-2 and d-1) consists of fully sampled n_x x n_y
+ * blocks; every block is Fourier transformed over those two axes without zero
+ * padding (pointing b = (b_x, b_y): B_b = sum_j x_j exp(-2 pi i (b_x j_x / n_x +
+ * b_y j_y / n_y))), and each pointing is correlated over the outer levels as in
+ * Sec. II (padded transforms, square modulus, time sum, inverse along the outer
+ * axes only).  Visibilities: complex64 [F][2n_1-1]...[2n_{d-2}-1][n_x][n_y]
+ * (pointings last).  Needs at least two levels and more than one block; runs
+ * on the general float32 kernel in either form; omni_baselines, the fold and
+ * the direct correlator refuse such plans (OMNI_E_STATE). */
+#define OMNI_PLAN_BEAMS 0x10u
 
 /* flags argument of omni_correlate* */
 #define OMNI_NO_RESET 0x1u    /* add this call's samples to the running accumulator            */
@@ -231,7 +242,8 @@ int omni_n_arrays(omni_plan_t plan, int32_t* n);
 /* Visibility shape of array `array`: *ndim = 1 + d, shape = [F, 2n_1-1, ...],
  * one cell per index difference Delta_k in [-(n_k-1), n_k-1] (the index range
  * of Sec. II.D, Eq. ProofEq2; Sec. II.C's worked example has 2n-1 = 5 and 3
- * cells for n = 3 and 2).  shape is host memory of at least 9 entries.
+ * cells for n = 3 and 2); an OMNI_PLAN_BEAMS plan ends in [n_x, n_y]
+ * pointings instead.  shape is host memory of at least 9 entries.
  * Errors: OMNI_E_INVAL (NULL argument, array out of range). */
 int omni_vis_shape(omni_plan_t plan, int32_t array, int32_t* ndim, int64_t* shape);
 

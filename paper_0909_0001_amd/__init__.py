@@ -34,6 +34,7 @@ FORMS = {"fp32": 0, "mixed": 1}
 PLAN_HOST_ONLY = 0x1
 PLAN_TIMING = 0x2
 PLAN_GRAPH = 0x8
+PLAN_BEAMS = 0x10
 TUNE = {False: 0, None: 0, "off": 0, "cache": 1, True: 2, "search": 2}
 STAGES = {"forward": 0, "reduce": 1, "inverse": 2, "call": 3, "kernel": 4}
 NO_RESET = 0x1
@@ -175,7 +176,9 @@ class Plan:
     lattice matrices (columns = lattice vectors), or None.  ``tune``: False / "off",
     "cache" (stored schedule, else search) or True / "search"; ``tune_cache``: file of
     tuned schedules; ``chunk_T``: cap on the time samples per front-pass chunk (0: the
-    planner's choice).
+    planner's choice); ``beams``: beam-space variant (the lowest level's blocks are
+    transformed into pointings, which are correlated over the outer levels; visibilities
+    [F, 2n_1-1, ..., n_x, n_y]).
 
     Every device call checks its tensors against the plan before the library is
     called (dtype for the plan's sample format, shape [T, F, N(, 2)], contiguity,
@@ -198,6 +201,7 @@ class Plan:
         graph: bool = False,
         tune_cache: str | None = None,
         chunk_T: int = 0,
+        beams: bool = False,
     ):
         self._h = ctypes.c_void_p()
         if dtype not in DTYPES:
@@ -207,6 +211,7 @@ class Plan:
         if tune not in TUNE:
             raise ValueError(f"unknown tune mode {tune!r} (off, cache, search)")
         flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_TIMING if timing else 0) | (PLAN_GRAPH if graph else 0)
+        flags |= PLAN_BEAMS if beams else 0
         self._cache_path = tune_cache.encode() if tune_cache else None
         opts = _Opts(DTYPES[dtype], FORMS[form], time_block, flags, TUNE[tune], self._cache_path, chunk_T)
         self.dtype, self.form, self.graph = dtype, form, graph
@@ -239,10 +244,12 @@ class Plan:
         _check(lib.omni_n_arrays(self._h, ctypes.byref(n)))
         self.n_arrays = n.value
         # per array: (F, N) from the visibility shape [F, 2n_1 - 1, ...]
+        # per array: (F, N)
+        level_sets = [level_dims] if batch is None else [ld for ld, _, _ in batch]
         self._fn = []
         for i in range(self.n_arrays):
-            shp = self.vis_shape(i)
-            self._fn.append((int(shp[0]), int(np.prod([(v + 1) // 2 for v in shp[1:]]))))
+            N = int(np.prod(np.asarray(level_sets[i], dtype=np.int64)))
+            self._fn.append((int(self.vis_shape(i)[0]), N))
 
     # -- metadata ---------------------------------------------------------
     def vis_shape(self, array: int = 0) -> tuple:

@@ -97,6 +97,9 @@ struct ArrayPlan {
   std::vector<double> A;    // [levels][2][2] or empty
   int F = 0;
   std::vector<int> n;       // axes with n > 1 (or a single axis when N == 1), in order
+  std::vector<int> m;       // transform length per axis of n: 2 n (zero-padded), or n for a beam axis
+  int nbeam = 0;            // beam-space plan: the last nbeam axes of n (the lowest level's) are pointings
+  bool beams = false;       // beam-space plan (the lowest level's two axes are pointing indices in the output)
   int64_t N = 0, M = 0, n_out = 0;
   FusedSetup fs;            // schedule of the fused kernel (all axes, or the axes after the front)
   int kernel = 0;  // 0: general; 1: 8x8x8x8 float32; 2: 8x8x8x8 mixed (MFMA); 3: compile-time shape (float32);
@@ -259,14 +262,14 @@ int check_geometry(const ArrayPlan& ap) {
 // first-processed axis (a split on a later axis repeats the earlier passes in
 // every work-group of the split).
 int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_split, int lcap, FusedSetup& fs,
-                    std::string* why, const int* r_force = nullptr, int s0_force = 0) {
+                    std::string* why, const int* r_force = nullptr, int s0_force = 0, const int* m_in = nullptr) {
   const int d = (int)n.size();
   FusedP& P = fs.fp;
   std::memset(&P, 0, sizeof(P));
   fs.F = F;
   fs.N = prod(n);
   fs.M = 1;
-  for (int v : n) fs.M *= 2 * v;
+  for (int k = 0; k < (int)n.size(); ++k) fs.M *= m_in ? m_in[k] : 2 * n[k];
   P.d = d;
   P.F = F;
   P.N = (int32_t)fs.N;
@@ -275,7 +278,7 @@ int plan_fused_axes(const std::vector<int>& n, int F, int tw_base, bool single_s
   in_str[d - 1] = 1;
   for (int k = d - 2; k >= 0; --k) in_str[k] = in_str[k + 1] * n[k + 1];
   for (int k = 0; k < d; ++k) {
-    m[k] = 2 * n[k];
+    m[k] = m_in ? m_in[k] : 2 * n[k];
     int rr = 1;
     while (m[k] / rr > lcap && (m[k] % (2 * rr)) == 0) rr *= 2;
     if (m[k] / rr > omni::kMaxL) {
@@ -553,7 +556,7 @@ int plan_front(ArrayPlan& ap, std::string* why) {
   const int d = (int)ap.n.size();
   int64_t MS = 1, NS = 1;
   for (int s = 1; s < d; ++s) {
-    if (!front_axis_ok(ap.n[s - 1])) break;
+    if (s - 1 >= d - ap.nbeam || !front_axis_ok(ap.n[s - 1])) break;
     MS *= 2 * ap.n[s - 1];
     NS *= ap.n[s - 1];
     std::vector<int> rest(ap.n.begin() + s, ap.n.end());
@@ -562,7 +565,8 @@ int plan_front(ArrayPlan& ap, std::string* why) {
     int tw_base = 0;
     for (int k = 0; k < s; ++k) tw_base += 2 * ap.n[k];
     FusedSetup fs;
-    if (plan_fused_axes(rest, (int)(ap.F * MS), tw_base, true, ap.lcap, fs, &w2) == OMNI_OK) {
+    if (plan_fused_axes(rest, (int)(ap.F * MS), tw_base, true, ap.lcap, fs, &w2, nullptr, 0, ap.m.data() + s) ==
+        OMNI_OK) {
       ap.fs = std::move(fs);
       ap.n_front = s;
       ap.front_tw_base = tw_base;
@@ -581,7 +585,7 @@ int plan_front(ArrayPlan& ap, std::string* why) {
 }
 
 int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form,
-                omni_dtype dtype) {
+                omni_dtype dtype, bool beams) {
   if (levels < 1 || levels > omni::kMaxD / 2) return fail(OMNI_E_SHAPE, "levels must be in [1, 4]");
   if (!dims) return fail(OMNI_E_INVAL, "dims is NULL");
   if (nchan < 1) return fail(OMNI_E_INVAL, "nchan must be >= 1");
@@ -601,11 +605,25 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   for (int v : ap.dims)
     if (v > 1) ap.n.push_back(v);
   if (ap.n.empty()) ap.n.push_back(1);
+  // beam-space plan: the lowest level's axes (the last two) are transformed without padding and never
+  // inverted; its axes of more than one antenna are the last nbeam entries of n
+  ap.nbeam = 0;
+  ap.beams = beams;
+  if (beams) {
+    if (levels < 2) return fail(OMNI_E_SHAPE, "a beam-space plan needs at least one level above the blocks");
+    ap.nbeam = (ap.dims[(size_t)(2 * levels - 2)] > 1) + (ap.dims[(size_t)(2 * levels - 1)] > 1);
+    int64_t outer = 1;
+    for (int k = 0; k < 2 * levels - 2; ++k) outer *= ap.dims[(size_t)k];
+    if (outer < 2) return fail(OMNI_E_SHAPE, "a beam-space plan needs more than one block");
+  }
+  ap.m.assign(ap.n.size(), 0);
   ap.M = 1;
   ap.n_out = 1;
-  for (int v : ap.n) {
-    ap.M *= 2 * v;
-    ap.n_out *= 2 * v - 1;
+  for (size_t k = 0; k < ap.n.size(); ++k) {
+    const bool beam = (int)k >= (int)ap.n.size() - ap.nbeam;
+    ap.m[k] = beam ? ap.n[k] : 2 * ap.n[k];
+    ap.M *= ap.m[k];
+    ap.n_out *= beam ? ap.n[k] : 2 * ap.n[k] - 1;
   }
   int rc = check_geometry(ap);
   if (rc) return rc;
@@ -616,21 +634,27 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   ap.inv_off.assign(d, 0);
   int off = 0;
   for (int k = 0; k < d; ++k) {
-    ap.tw_desc_fwd.insert(ap.tw_desc_fwd.end(), {2 * ap.n[k], -1, off});
-    ap.tw_desc_inv.insert(ap.tw_desc_inv.end(), {2 * ap.n[k], +1, off});
+    ap.tw_desc_fwd.insert(ap.tw_desc_fwd.end(), {ap.m[k], -1, off});
+    ap.tw_desc_inv.insert(ap.tw_desc_inv.end(), {ap.m[k], +1, off});
     ap.inv_off[k] = off;
-    off += 2 * ap.n[k];
+    off += ap.m[k];
   }
   ap.n_tw = off;
   std::string why, why2;
   ap.n_front = 0;
-  rc = plan_fused_axes(ap.n, ap.F, 0, true, ap.lcap, ap.fs, &why);
+  rc = plan_fused_axes(ap.n, ap.F, 0, true, ap.lcap, ap.fs, &why, nullptr, 0, ap.m.data());
   if (rc) rc = plan_front(ap, &why2);
   if (rc) {
     // last resort: residue splits along several axes (correct, repeats early passes)
-    rc = plan_fused_axes(ap.n, ap.F, 0, false, ap.lcap, ap.fs, &why);
+    rc = plan_fused_axes(ap.n, ap.F, 0, false, ap.lcap, ap.fs, &why, nullptr, 0, ap.m.data());
     if (rc) return fail(rc, why + "; " + why2);
     ap.single_split = false;
+  }
+  // the fixed-shape kernels all assume zero-padded axes: a beam-space plan keeps the general kernel
+  if (ap.nbeam > 0) {
+    ap.max_slices = (int)std::max<size_t>(1, std::min<size_t>(1024, kPartialBudget / ((size_t)ap.F * ap.M * 8)));
+    ap.inv_group = (int)std::max<int64_t>(1, std::min<int64_t>(ap.F, (int64_t(1) << 30) / (ap.M * 8)));
+    return OMNI_OK;
   }
   const bool eight4 = ap.n == std::vector<int>{8, 8, 8, 8};
   if (!eight4 && ap.single_split) {
@@ -950,18 +974,22 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     }
   }
   if (stage == 2 && !(flags & OMNI_NO_FINALIZE)) {
-    const int d = (int)ap.n.size();
+    // inverse along the zero-padded axes only (a beam-space plan keeps its pointing axes, the innermost, as
+    // they are: they ride along in `inner`), normalised by the product of their lengths
+    const int d = (int)ap.n.size() - ap.nbeam;
+    double m_inv = 1.0;
+    for (int k = 0; k < d; ++k) m_inv *= ap.m[k];
     for (int f0 = 0; f0 < ap.F; f0 += ap.inv_group) {
       const int g = std::min(ap.inv_group, ap.F - f0);
       const void* src = ap.d_A + (size_t)f0 * ap.M;
       int64_t outer = g;
       for (int k = 0; k < d; ++k) {
         int64_t inner = 1;
-        for (int j = k + 1; j < d; ++j) inner *= 2 * ap.n[j];
+        for (int j = k + 1; j < (int)ap.n.size(); ++j) inner *= ap.m[j];
         const bool last = (k == d - 1);
         void* dst = last ? (void*)(static_cast<float2*>(vis) + (size_t)f0 * ap.n_out) : (void*)ap.d_ws[k & 1];
-        HIP_TRY(omni::launch_inverse_axis(k == 0, last, src, dst, ap.d_tw64 + ap.inv_off[k], outer, 2 * ap.n[k],
-                                          ap.n[k], inner, 1.0 / (double)ap.M, st));
+        HIP_TRY(omni::launch_inverse_axis(k == 0, last, src, dst, ap.d_tw64 + ap.inv_off[k], outer, ap.m[k],
+                                          ap.n[k], inner, 1.0 / m_inv, st));
         src = dst;
         outer *= 2 * ap.n[k] - 1;
       }
@@ -1107,7 +1135,8 @@ int tune_array(omni_plan_s* p, ArrayPlan& ap) {
       std::string why;
       if (ct) {
         fs = ap.fs;
-      } else if (plan_fused_axes(axes, Fk, 0, front ? true : ap.single_split, lcaps[li], fs, &why)) {
+      } else if (plan_fused_axes(axes, Fk, 0, front ? true : ap.single_split, lcaps[li], fs, &why, nullptr, 0,
+                                 ap.m.data() + ap.n_front)) {
         continue;
       }
       const int keep_wg = ap.wg_target;
@@ -1247,7 +1276,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   if (o.dtype < OMNI_CF32 || o.dtype > OMNI_CI4) return fail(OMNI_E_INVAL, "unknown dtype");
   if (o.form != OMNI_FORM_FP32 && o.form != OMNI_FORM_MIXED) return fail(OMNI_E_INVAL, "unknown form");
   if (o.time_block < 0) return fail(OMNI_E_INVAL, "time_block < 0");
-  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING | OMNI_PLAN_GRAPH))
+  if (o.flags & ~(OMNI_PLAN_HOST_ONLY | OMNI_PLAN_TIMING | OMNI_PLAN_GRAPH | OMNI_PLAN_BEAMS))
     return fail(OMNI_E_INVAL, "unknown plan flag");
   if (o.tune < OMNI_TUNE_OFF || o.tune > OMNI_TUNE_SEARCH) return fail(OMNI_E_INVAL, "unknown tune mode");
   if (o.chunk_T < 0) return fail(OMNI_E_INVAL, "chunk_T < 0");
@@ -1268,7 +1297,7 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
   for (size_t i = 0; i < arrays.size(); ++i) {
     p->arrays[i].chunk_cap = o.chunk_T;
     int rc = build_array(p->arrays[i], arrays[i].levels, arrays[i].dims, arrays[i].A, arrays[i].nchan, p->form,
-                         p->dtype);
+                         p->dtype, (o.flags & OMNI_PLAN_BEAMS) != 0);
     if (rc) {
       delete p;
       return rc;
@@ -1409,6 +1438,7 @@ int direct_check_args(omni_plan_t plan, const void* volt, int64_t T, const void*
   if (!plan) return fail(OMNI_E_INVAL, "plan is NULL");
   if (plan->host_only) return fail(OMNI_E_STATE, "plan was made with OMNI_PLAN_HOST_ONLY");
   if (plan->arrays.size() != 1) return fail(OMNI_E_STATE, "direct correlator: single-array plans only");
+  if (plan->arrays[0].beams) return fail(OMNI_E_STATE, "direct correlator: not for beam-space plans");
   if (plan->dtype != OMNI_CI8 && plan->dtype != OMNI_CI4)
     return fail(OMNI_E_STATE, "direct correlator: integer samples (ci8, ci4) only");
   if (T < 0) return fail(OMNI_E_INVAL, "T < 0");
@@ -1582,7 +1612,8 @@ int omni_vis_shape(omni_plan_t plan, int32_t array, int32_t* ndim, int64_t* shap
   const ArrayPlan& ap = plan->arrays[(size_t)array];
   *ndim = 1 + (int32_t)ap.dims.size();
   shape[0] = ap.F;
-  for (size_t k = 0; k < ap.dims.size(); ++k) shape[k + 1] = 2 * ap.dims[k] - 1;
+  for (size_t k = 0; k < ap.dims.size(); ++k)
+    shape[k + 1] = ap.beams && k + 2 >= ap.dims.size() ? ap.dims[k] : 2 * ap.dims[k] - 1;
   return OMNI_OK;
 }
 
@@ -1591,6 +1622,7 @@ int omni_baselines(omni_plan_t plan, int32_t array, double* uv) {
   if (array < 0 || (size_t)array >= plan->arrays.size()) return fail(OMNI_E_INVAL, "array index out of range");
   const ArrayPlan& ap = plan->arrays[(size_t)array];
   if (ap.A.empty()) return fail(OMNI_E_STATE, "plan has no lattice matrices");
+  if (ap.beams) return fail(OMNI_E_STATE, "beam-space plan: its cells along the lowest level are pointings");
   const int d = (int)ap.dims.size();
   std::vector<int> out(d);
   int64_t cells = 1;
@@ -1905,6 +1937,7 @@ int omni_fold_plan(omni_fold_t* out, omni_plan_t plan, int32_t array, const omni
   *out = nullptr;
   if (array < 0 || (size_t)array >= plan->arrays.size()) return fail(OMNI_E_INVAL, "array index out of range");
   const ArrayPlan& ap = plan->arrays[(size_t)array];
+  if (ap.beams) return fail(OMNI_E_STATE, "beam-space plan: its cells along the lowest level are pointings");
   omni_fold_opts o = {1.0, 1.0, 1.0, 1.0, 1, 0};
   if (opts) o = *opts;
   if (!finite_positive(o.du) || !finite_positive(o.dv) || !finite_positive(o.dr) || !finite_positive(o.radius_scale))

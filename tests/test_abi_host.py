@@ -117,7 +117,7 @@ def test_unsupported_shapes_are_refused_not_crashed():
 
 def test_plan_flags_are_validated():
     """Unknown plan flags are refused; the graph flag is accepted on a host-only plan."""
-    opts = omni._Opts(omni.DTYPES["ci8"], omni.FORMS["fp32"], 0, omni.PLAN_HOST_ONLY | 0x10)
+    opts = omni._Opts(omni.DTYPES["ci8"], omni.FORMS["fp32"], 0, omni.PLAN_HOST_ONLY | 0x20)
     h = ctypes.c_void_p()
     dims = np.array([[4, 4]], dtype=np.int32)
     rc = omni.lib.omni_plan(ctypes.byref(h), 1, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, 1,
@@ -257,3 +257,27 @@ def test_fengine_validates_before_any_device_call():
     assert st[f(24, 8, 4, 64, 16, 2, 16, None)] == "OMNI_E_INVAL"  # raw not 16-byte aligned
     assert st[f(16, 8, 4, 64, 12, 2, 16, None)] == "OMNI_E_INVAL"  # gains not 8-byte aligned
     assert st[f(16, 8, 4, 64, 16, 1, 17, None)] == "OMNI_E_INVAL"  # ci8 output not 2-byte aligned
+
+
+def test_beam_space_plans_on_the_host():
+    """Beam-space plans: pointings last in the visibility shape, unpadded transforms on the lowest level's axes,
+    the general kernel; refusals for one level, one block, and for the baseline metadata."""
+    import json
+
+    p = omni.Plan([[4, 4], [8, 8]], np.stack([np.eye(2) * 8, np.eye(2)]), 2, "ci8", host_only=True, beams=True)
+    assert p.vis_shape() == (2, 7, 7, 8, 8)
+    a = json.loads(p.describe())["arrays"][0]
+    assert [(x["n"], x["m"]) for x in a["axes"]] == [(4, 8), (4, 8), (8, 8), (8, 8)]
+    assert a["kernel"] == "fused_fp32" and a["M"] == 8 * 8 * 8 * 8
+    with pytest.raises(omni.OmniError) as ei:
+        p.baselines()
+    assert omni.STATUS[ei.value.code] == "OMNI_E_STATE"
+    q = omni.Plan([[4, 1], [1, 8]], None, 1, "ci4", host_only=True, beams=True)
+    assert q.vis_shape() == (1, 7, 1, 1, 8)
+    for ld in ([[8, 8]], [[1, 1], [8, 8]]):
+        with pytest.raises(omni.OmniError) as ei:
+            omni.Plan(ld, None, 1, "ci8", host_only=True, beams=True)
+        assert omni.STATUS[ei.value.code] == "OMNI_E_SHAPE"
+    # the matrix-core kernels are not used for beam-space plans
+    r = omni.Plan([[8, 8], [8, 8]], None, 4, "ci8", "mixed", host_only=True, beams=True)
+    assert json.loads(r.describe())["arrays"][0]["kernel"] == "fused_fp32"

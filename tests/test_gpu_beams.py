@@ -1,0 +1,105 @@
+"""Parity of the beam-space variant (Appendix A steps 4-5; HIP, through the C ABI) with the
+oracle (oracle/beams.py).
+
+Bar: per channel and pointing, max over the outer lags of |V_gpu - V_oracle| relative to that
+pointing's zero-lag power, <= 1e-5 (float32 form) or 2e-3 (mixed form; a beam-space plan runs
+the float32 kernel in either form).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0909_0001_amd as omni
+from oracle import beams
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "mixed": 2e-3}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def random_raw(dtype, T, F, N, gen):
+    if dtype == "cf32":
+        return torch.randn((T, F, N, 2), generator=gen).float()
+    if dtype == "ci8":
+        return torch.randint(-127, 128, (T, F, N, 2), generator=gen, dtype=torch.int16).to(torch.int8)
+    re = torch.randint(-7, 8, (T, F, N), generator=gen, dtype=torch.int16)
+    im = torch.randint(-7, 8, (T, F, N), generator=gen, dtype=torch.int16)
+    return ((re & 0xF) << 4 | (im & 0xF)).to(torch.uint8)
+
+
+def beam_err(got, ref, level_dims):
+    """max over channels and pointings of (max over lags |got - ref|) / ref[zero lag]."""
+    F = ref.shape[0]
+    nb = level_dims[-1][0] * level_dims[-1][1]
+    g = np.moveaxis(got.reshape((F, -1, nb)), 2, 1)  # [F, nb, lags]
+    r = np.moveaxis(ref.reshape((F, -1, nb)), 2, 1)
+    c = r.shape[2] // 2
+    z = np.abs(r[:, :, c])
+    z[z == 0] = 1.0
+    return float(np.max(np.abs(g - r).max(axis=2) / z))
+
+
+CASES = [
+    ([[4, 4], [8, 8]], "ci8", "fp32", 20, 2),
+    ([[4, 4], [8, 8]], "ci4", "mixed", 20, 2),
+    ([[2, 3], [3, 3], [4, 4]], "ci4", "fp32", 9, 3),
+    ([[3, 3], [5, 5]], "cf32", "fp32", 7, 2),  # odd block sides: unpadded 5-point transforms
+    ([[4, 1], [1, 8]], "ci8", "fp32", 11, 2),  # one-dimensional blocks
+    ([[16, 16], [16, 16]], "ci4", "fp32", 12, 2),  # the 16 x 16-of-16 x 16 array: 256 pointings
+]
+
+
+@pytest.mark.parametrize("level_dims,dtype,form,T,F", CASES)
+def test_beam_space_matches_oracle(level_dims, dtype, form, T, F):
+    dims = [v for ld in level_dims for v in ld]
+    N = math.prod(dims)
+    gen = torch.Generator().manual_seed(N + T)
+    raw = random_raw(dtype, T, F, N, gen)
+    say(f"[beams] case {level_dims} {dtype} {form} T={T} F={F}")
+    plan = omni.Plan(level_dims, None, F, dtype, form, beams=True)
+    shape = plan.vis_shape()
+    assert shape == (F,) + tuple(2 * v - 1 for v in dims[:-2]) + tuple(dims[-2:])
+    vis = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    x = oracle.decode(raw.numpy(), dtype, T, F, N)
+    ref = beams.beam_visibilities(x, level_dims)
+    err = beam_err(vis.cpu().numpy(), ref, level_dims)
+    say(f"[beams] {level_dims}: err {err:.3g}")
+    assert err <= TOL[form]
+
+
+def test_beam_space_split_integration():
+    """Two calls (NO_RESET on the second) equal one call over all samples (linearity in time)."""
+    level_dims = [[4, 4], [8, 8]]
+    gen = torch.Generator().manual_seed(3)
+    raw = random_raw("ci8", 24, 2, 1024, gen).cuda()
+    plan = omni.Plan(level_dims, None, 2, "ci8", "fp32", beams=True)
+    whole = plan.correlate(raw).clone()
+    plan.correlate(raw[:10].contiguous(), flags=omni.NO_FINALIZE)
+    split = plan.correlate(raw[10:].contiguous(), flags=omni.NO_RESET)
+    torch.cuda.synchronize()
+    assert beam_err(split.cpu().numpy(), whole.cpu().numpy().astype(np.complex128), level_dims) <= 1e-6
+
+
+def test_beam_space_refusals():
+    level_dims = [[4, 4], [8, 8]]
+    A = np.stack([np.eye(2) * 8.0, np.eye(2)])
+    plan = omni.Plan(level_dims, A, 1, "ci8", "fp32", beams=True)
+    with pytest.raises(omni.OmniError):
+        plan.baselines()
+    with pytest.raises(omni.OmniError):
+        omni.Fold(plan)
+    raw = torch.zeros((2, 1, 1024, 2), dtype=torch.int8, device="cuda")
+    with pytest.raises(omni.OmniError):
+        plan.direct_correlate(raw)
+    with pytest.raises(omni.OmniError):
+        omni.Plan([[8, 8]], None, 1, "ci8", "fp32", beams=True)
