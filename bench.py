@@ -155,12 +155,13 @@ def kernel_roofline(w, res, form):
     }
 
 
-def run_form(omni, w, raw, form, steps, warmup, tune="off", tune_cache=None):
-    """Plan (autotuned with tune="search"), warm up and time `steps` correlate calls; returns timings and the
-    last visibilities."""
+def run_form(omni, w, raw, form, steps, warmup, tune="off", tune_cache=None, beams=False):
+    """Plan (autotuned with tune="search"; beam-space with beams=True), warm up and time `steps` correlate calls;
+    returns timings and the last visibilities."""
     import torch
 
-    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form, timing=True, tune=tune, tune_cache=tune_cache)
+    plan = omni.Plan(w.level_dims, w.A, w.nchan, w.dtype, form, timing=True, tune=tune, tune_cache=tune_cache,
+                     beams=beams)
     desc = json.loads(plan.describe())
     log(f"bench[{w.name} {form}]: plan " + plan.describe())
     vis = torch.empty(plan.vis_shape(), dtype=torch.complex64, device=raw.device)
@@ -315,6 +316,39 @@ def bench_fold(omni, torch, skysim, steps, warmup, vis128=None):
                                                  "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                                                  "algorithmic_bytes": nbytes}}
         del fold, plan
+    return out
+
+
+def beam_flops_per_as(dims) -> float:
+    """Float32 work per antenna-sample of a beam-space plan, counted like the FP32 plain form: a line-pruned
+    transform of n inputs to m outputs costs (m / n) 5 log2 m flops per input point, axes in the general
+    kernel's order (first axis, then innermost to outermost), the point count growing by m / n after each;
+    the lowest level's two axes are unpadded (m = n); plus 4 flops per Fourier cell for |X|^2 and the time sum."""
+    n = [v for v in dims]
+    m = [2 * v for v in n[:-2]] + n[-2:]
+    keep = [k for k in range(len(n)) if n[k] > 1]
+    order = keep[:1] + keep[1:][::-1]
+    total, factor = 0.0, 1.0
+    for k in order:
+        total += factor * (m[k] / n[k]) * 5 * math.log2(m[k])
+        factor *= m[k] / n[k]
+    return total + 4 * factor
+
+
+def bench_beams(omni, torch, w, raw, steps, warmup, main_ms):
+    """Beam-space variant (Appendix A steps 4-5) on the same bytes as the array's hot-path call: every lowest-level
+    16 x 16 block formed into 256 pointings, each correlated over the outer 16 x 16 level."""
+    res = run_form(omni, w, raw, "fp32", steps, warmup, beams=True)
+    per_as = beam_flops_per_as(w.dims)
+    launch_ms = res["stages"]["kernel"]
+    achieved = per_as * w.antenna_samples() / res["launches"] / (launch_ms / 1e3) / 1e12
+    out = {"workload": f"{w.name} beam-space: {w.level_dims[-1][0] * w.level_dims[-1][1]} pointings a block",
+           "kernel": res["kernel"], "ms_per_call": round(res["ms"], 4),
+           "value": w.antenna_samples() / (res["ms"] / 1e3), "vs_hot_path_same_bytes": round(main_ms / res["ms"], 4),
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                        "launch_ms": round(launch_ms, 4), "algorithmic_flops_per_antenna_sample": per_as}}
+    del res
     return out
 
 
@@ -514,6 +548,11 @@ def bench_batch4(args) -> int:
     if not args.no_fengine:
         log("bench: F-engine")
         out["fengine"] = bench_fengine(omni, torch, args.steps, args.warmup)
+    if not args.no_beams:
+        log("bench: beam-space variant")
+        i16 = BATCH4.index("hier16x16")
+        out["beam_space"] = bench_beams(omni, torch, ws[i16], raws[i16], args.steps, args.warmup,
+                                        alone["hier16x16"]["ms"])
     print(json.dumps(out), flush=True)
     return 0
 
@@ -554,6 +593,7 @@ def main() -> int:
     ap.add_argument("--no-direct", action="store_true", help="never time the direct N^2 correlator")
     ap.add_argument("--tune", default="search", choices=["off", "search"],
                     help="plan-time autotuning of the schedules (default: search; planning is outside the timing)")
+    ap.add_argument("--no-beams", action="store_true", help="skip the beam-space measurement")
     ap.add_argument("--no-fengine", action="store_true", help="skip the F-engine measurement")
     ap.add_argument("--no-fold", action="store_true", help="skip the baseline-fold measurements")
     ap.add_argument("--copy-calibration", action="store_true", help="only run 3 x 1 GiB device copies")

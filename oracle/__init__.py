@@ -27,6 +27,9 @@ defines, written so it can be checked against the paper by eye:
 * ``beams``             -- the beam-space variant: unpadded 2-D transform of
   every lowest-level block ("digital pointings"), then each pointing
   correlated over the other levels (Appendix A, steps 4-5).
+* ``hybrid``            -- hybrid tiles: every ordered pair of arbitrarily
+  translated rectangular tiles cross-correlated over index differences
+  (Sec. III, the hybrid-tile paragraph).
 * ``fengine``           -- the per-antenna time-domain Fourier transform,
   calibration, requantisation and corner turn ahead of the correlator
   (Appendix A, steps 2-3).
@@ -47,7 +50,7 @@ from .correlator import (  # noqa: F401
     visibilities_by_outer_lag,
     visibility_cells,
 )
-from . import beams, fengine  # noqa: F401
+from . import beams, fengine, hybrid  # noqa: F401
 from .layout import (  # noqa: F401
     asinh_map,
     baseline_distribution,
