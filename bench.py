@@ -338,7 +338,7 @@ def beam_flops_per_as(dims) -> float:
 def bench_beams(omni, torch, w, raw, steps, warmup, main_ms):
     """Beam-space variant (Appendix A steps 4-5) on the same bytes as the array's hot-path call: every lowest-level
     16 x 16 block formed into 256 pointings, each correlated over the outer 16 x 16 level."""
-    res = run_form(omni, w, raw, "fp32", steps, warmup, beams=True)
+    res = run_form(omni, w, raw, "fp32", steps, warmup, tune="search", beams=True)
     per_as = beam_flops_per_as(w.dims)
     launch_ms = res["stages"]["kernel"]
     achieved = per_as * w.antenna_samples() / res["launches"] / (launch_ms / 1e3) / 1e12
@@ -350,6 +350,39 @@ def bench_beams(omni, torch, w, raw, steps, warmup, main_ms):
                         "launch_ms": round(launch_ms, 4), "algorithmic_flops_per_antenna_sample": per_as}}
     del res
     return out
+
+
+def bench_hybrid(omni, torch, steps, warmup, P=16, nx=16, ny=16, F=64, T=2048):
+    """Hybrid tiles (Sec. III): P tiles of nx x ny antennas (the 16x16-of-16x16 array's antennas, N = 4096 x P/16)
+    at arbitrary offsets, 4-bit samples.  Work counted: the pair stage's P^2 complex multiply-adds (8 flops) per
+    Fourier cell (m = 2n per axis), channel and sample; it runs on the vector ALUs in float32."""
+    gen = torch.Generator(device="cuda").manual_seed(20090840)
+    N = P * nx * ny
+    re = torch.randint(-7, 8, (T, F, N), generator=gen, device="cuda", dtype=torch.int16)
+    im = torch.randint(-7, 8, (T, F, N), generator=gen, device="cuda", dtype=torch.int16)
+    raw = ((re & 0xF) << 4 | (im & 0xF)).to(torch.uint8)
+    del re, im
+    h = omni.Hybrid(P, nx, ny, F, "ci4")
+    out = torch.empty(h.vis_shape(), dtype=torch.complex64, device="cuda")
+    for _ in range(max(1, warmup)):
+        h.correlate(raw, out=out)
+    torch.cuda.synchronize()
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record()
+    for _ in range(steps):
+        h.correlate(raw, out=out)
+    e.record()
+    e.synchronize()
+    ms = b.elapsed_time(e) / steps
+    flops = 8.0 * P * P * (4 * nx * ny) * F * T
+    tfs = flops / (ms / 1e3) / 1e12
+    del raw, out, h
+    return {"P": P, "tile": [nx, ny], "N": N, "F": F, "T": T, "ms_per_call": round(ms, 4),
+            "value": N * T * F / (ms / 1e3), "unit": "antenna-samples/s",
+            "roofline": {"bound": "alu", "achieved": round(tfs, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tfs / PEAK_FP32_VECTOR_TFLOPS, 4), "algorithmic_flops_per_call": flops,
+                         "note": "pair-stage work over the whole call (tile transforms and the inverse included "
+                                 "in the time)"}}
 
 
 def bench_fengine(omni, torch, steps, warmup, N=16384, F=64, T=2048):
@@ -398,6 +431,19 @@ def bench_aux(args) -> int:
         line = {"metric": "raw samples/s channelised (F-engine)", "value": r["samples_per_s"], "unit": "samples/s",
                 "ms_per_step": r["ms_per_call"], "config": {"workload": f"F-engine: N={r['N']} antennas, "
                 f"T={r['T']} blocks of {2 * r['F']} int8 samples -> {r['F']} channels, ci4 [T][F][N]"},
+                "roofline": r["roofline"], "detail": r}
+    elif args.workload == "hybrid":
+        r = bench_hybrid(omni, torch, args.steps, args.warmup)
+        line = {"metric": "antenna-samples/s correlated (hybrid tiles, every tile pair)", "value": r["value"],
+                "unit": "antenna-samples/s", "ms_per_step": r["ms_per_call"],
+                "config": {"workload": f"hybrid tiles: {r['P']} tiles of {r['tile'][0]}x{r['tile'][1]}, "
+                           f"F={r['F']}, T={r['T']}, ci4"}, "roofline": r["roofline"], "detail": r}
+    elif args.workload == "beams":
+        w = skysim.WORKLOADS["hier16x16"]
+        raw = skysim.make_voltages(w, device=torch.device("cuda:0"))
+        r = bench_beams(omni, torch, w, raw, args.steps, args.warmup, float("nan"))
+        line = {"metric": "antenna-samples/s correlated (beam-space variant)", "value": r["value"],
+                "unit": "antenna-samples/s", "ms_per_step": r["ms_per_call"], "config": {"workload": r["workload"]},
                 "roofline": r["roofline"], "detail": r}
     else:
         r = bench_fold(omni, torch, skysim, args.steps, args.warmup)
@@ -548,6 +594,9 @@ def bench_batch4(args) -> int:
     if not args.no_fengine:
         log("bench: F-engine")
         out["fengine"] = bench_fengine(omni, torch, args.steps, args.warmup)
+    if not args.no_hybrid:
+        log("bench: hybrid tiles")
+        out["hybrid_tiles"] = bench_hybrid(omni, torch, args.steps, args.warmup)
     if not args.no_beams:
         log("bench: beam-space variant")
         i16 = BATCH4.index("hier16x16")
@@ -584,7 +633,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch4",
-                    help="batch4 (default), a workload name of skysim.WORKLOADS, fengine or baselines")
+                    help="batch4 (default), a workload name of skysim.WORKLOADS, fengine, baselines, hybrid or beams")
     ap.add_argument("--form", default=None, help="fp32 | mixed (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -593,6 +642,7 @@ def main() -> int:
     ap.add_argument("--no-direct", action="store_true", help="never time the direct N^2 correlator")
     ap.add_argument("--tune", default="search", choices=["off", "search"],
                     help="plan-time autotuning of the schedules (default: search; planning is outside the timing)")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the hybrid-tile measurement")
     ap.add_argument("--no-beams", action="store_true", help="skip the beam-space measurement")
     ap.add_argument("--no-fengine", action="store_true", help="skip the F-engine measurement")
     ap.add_argument("--no-fold", action="store_true", help="skip the baseline-fold measurements")
@@ -611,7 +661,7 @@ def main() -> int:
         return copy_calibration()
     if args.workload == "batch4":
         return bench_batch4(args)
-    if args.workload in ("fengine", "baselines"):
+    if args.workload in ("fengine", "baselines", "hybrid", "beams"):
         return bench_aux(args)
 
     import numpy as np

@@ -328,6 +328,49 @@ int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, in
 int omni_fengine(const void* raw, int64_t N, int64_t T, int32_t F, const void* gains, int32_t dtype, void* volt,
                  void* stream);
 
+/* ---- Hybrid tiles ---------------------------------------------------------
+ *
+ * Sec. III (the hybrid-tile paragraph): the array is P rectangular tiles of
+ * n_x x n_y antennas, translated relative to one another by arbitrary
+ * amounts.  Inside a tile the FFT method applies; the tiles' transforms
+ * (synthesized beams) are correlated between tiles by brute force.  The call
+ * computes, for every ordered pair of tiles (p, q) and index difference Delta
+ * inside the tile grid,
+ *   C_pq[Delta] = sum_t sum_{j, j-Delta in the tile} x_p[t][j] conj(x_q[t][j - Delta])
+ * (C_pp is tile p's own visibility hypercube of Sec. II.D, Eq. ProofEq2), as:
+ * zero-padded 2-D transform of every tile and sample (m = 2n per axis), the
+ * cross-power sums S_pq[kappa] = sum_t Y_p conj(Y_q) per Fourier cell (float32
+ * over a chunk of samples, then float64), one inverse transform per pair.
+ * Physical baseline of cell (p, q, Delta): o_p - o_q + A Delta. */
+typedef struct omni_hybrid_s* omni_hybrid_t;
+
+/* Plan P tiles (2, 4, 8, 16 or 32) of n_x x n_y antennas (each side 1, 2, 4,
+ * 8, 16 or 32), nchan channels, samples in format dtype (omni_dtype).
+ *   offsets : [P][2] float64 tile offsets o_p, or NULL (metadata only).
+ *   A       : [2][2] float64 row-major lattice matrix of a tile (columns =
+ *             lattice vectors), or NULL (metadata only).
+ * Allocates on the current device (gfx950).  Errors: OMNI_E_INVAL,
+ * OMNI_E_SHAPE, OMNI_E_NODEV, OMNI_E_NOMEM, OMNI_E_HIP. */
+int omni_hybrid_plan(omni_hybrid_t* out, int32_t P, int32_t nx, int32_t ny, int32_t nchan, int32_t dtype,
+                     const double* offsets, const double* A);
+
+/* Correlate T samples (T >= 0).
+ *   volt : device [T][F][P n_x n_y] samples, tile-major (antenna p n_x n_y +
+ *          i_x n_y + i_y), in the plan's format; may be NULL iff T == 0.
+ *   vis  : device complex64 [F][P][P][2 n_x - 1][2 n_y - 1] (written; may be
+ *          NULL with OMNI_NO_FINALIZE).
+ *   flags: OMNI_NO_RESET (add to the running sums), OMNI_NO_FINALIZE.
+ * Asynchronous on `stream`.  Errors: OMNI_E_INVAL, OMNI_E_STATE (other
+ * device), OMNI_E_HIP. */
+int omni_hybrid_correlate(omni_hybrid_t h, const void* volt, int64_t T, void* vis, void* stream, uint32_t flags);
+
+/* uv[p][q][Delta_x][Delta_y][2] = o_p - o_q + A (Delta_x, Delta_y) (host
+ * memory, written).  Errors: OMNI_E_INVAL, OMNI_E_STATE (no offsets or A). */
+int omni_hybrid_baselines(omni_hybrid_t h, double* uv);
+
+/* Release a hybrid plan (waits for the device first).  NULL is a no-op. */
+int omni_hybrid_destroy(omni_hybrid_t h);
+
 /* ---- Physical-baseline fold and baseline distributions -------------------
  *
  * Sec. II.D: hypercube cell Delta holds every antenna pair whose index tuples

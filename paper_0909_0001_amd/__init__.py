@@ -65,6 +65,10 @@ EXPORTS = [
     "omni_baseline_profile",
     "omni_fold_destroy",
     "omni_fengine",
+    "omni_hybrid_plan",
+    "omni_hybrid_correlate",
+    "omni_hybrid_baselines",
+    "omni_hybrid_destroy",
 ]
 
 
@@ -145,6 +149,11 @@ def _load():
         "omni_baseline_profile": (ctypes.c_int, [P, P, i32, P, P, P, P]),
         "omni_fold_destroy": (ctypes.c_int, [P]),
         "omni_fengine": (ctypes.c_int, [P, i64, i64, i32, P, i32, P, P]),
+        "omni_hybrid_plan": (ctypes.c_int, [ctypes.POINTER(P), i32, i32, i32, i32, i32,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "omni_hybrid_correlate": (ctypes.c_int, [P, P, i64, P, P, u32]),
+        "omni_hybrid_baselines": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double)]),
+        "omni_hybrid_destroy": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -474,6 +483,66 @@ def fengine(raw, F: int, gains, dtype: str = "ci4", out=None, stream=None):
     _check(lib.omni_fengine(raw.data_ptr(), N, T, F, gains.data_ptr(), DTYPES[dtype], out.data_ptr(),
                             _stream_handle(stream)))
     return out
+
+
+class Hybrid:
+    """Hybrid tiles (Sec. III): P tiles of nx x ny antennas at arbitrary offsets; ``correlate`` gives every ordered
+    pair's cross-correlation over index differences, complex64 [F, P, P, 2nx-1, 2ny-1].  ``offsets`` [P, 2] and
+    ``A`` [2, 2] (columns = a tile's lattice vectors) are metadata for ``baselines``."""
+
+    def __init__(self, P: int, nx: int, ny: int, nchan: int = 1, dtype: str = "cf32", offsets=None, A=None):
+        if dtype not in DTYPES:
+            raise ValueError(f"unknown sample format {dtype!r} (cf32, ci8, ci4)")
+        self._h = ctypes.c_void_p()
+        self.P, self.nx, self.ny, self.F, self.dtype = P, nx, ny, nchan, dtype
+        self.N = P * nx * ny
+        op = Ap = None
+        self._keep = []
+        if offsets is not None:
+            o = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(P, 2))
+            self._keep.append(o)
+            op = o.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if A is not None:
+            a = np.ascontiguousarray(np.asarray(A, dtype=np.float64).reshape(2, 2))
+            self._keep.append(a)
+            Ap = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(lib.omni_hybrid_plan(ctypes.byref(self._h), P, nx, ny, nchan, DTYPES[dtype], op, Ap))
+
+    def vis_shape(self) -> tuple:
+        return (self.F, self.P, self.P, 2 * self.nx - 1, 2 * self.ny - 1)
+
+    def correlate(self, volt, flags: int = 0, out=None, stream=None):
+        import torch
+
+        want = {"cf32": torch.float32, "ci8": torch.int8, "ci4": torch.uint8}[self.dtype]
+        tail = (self.F, self.N, 2) if self.dtype != "ci4" else (self.F, self.N)
+        if volt.dtype != want or tuple(volt.shape[1:]) != tail or not volt.is_contiguous() or volt.device.type != "cuda":
+            raise ValueError(f"voltages must be a contiguous {want} GPU tensor [T, {', '.join(map(str, tail))}]")
+        T = volt.shape[0]
+        if out is None and not (flags & NO_FINALIZE):
+            out = torch.empty(self.vis_shape(), dtype=torch.complex64, device=volt.device)
+        if out is not None and (out.dtype != torch.complex64 or tuple(out.shape) != self.vis_shape()
+                                or not out.is_contiguous() or out.device != volt.device):
+            raise ValueError(f"out must be a contiguous complex64 tensor {self.vis_shape()} on the voltages' device")
+        _check(lib.omni_hybrid_correlate(self._h, volt.data_ptr() if T > 0 else None, T,
+                                         out.data_ptr() if out is not None else None, _stream_handle(stream), flags))
+        return out
+
+    def baselines(self) -> np.ndarray:
+        uv = np.zeros(int(np.prod(self.vis_shape()[1:])) * 2, dtype=np.float64)
+        _check(lib.omni_hybrid_baselines(self._h, uv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return uv.reshape(self.vis_shape()[1:] + (2,))
+
+    def close(self) -> None:
+        if self._h:
+            lib.omni_hybrid_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Fold:

@@ -59,6 +59,9 @@ hipError_t launch_grid32_mixed(const void* src, int64_t T, int64_t tps, const fl
                                int n_slices, int time_block, double out_scale, hipStream_t st);
 hipError_t launch_fengine(const void* raw, int64_t N, int64_t T, int F, const void* gains, bool ci8, void* out,
                           hipStream_t st);
+hipError_t launch_xengine(const float2* Y, int64_t Tc, int F, int P, int64_t Mp, double2* S, int accumulate,
+                          hipStream_t st);
+hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -643,6 +646,13 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   std::string why, why2;
   ap.n_front = 0;
   rc = plan_fused_axes(ap.n, ap.F, 0, true, ap.lcap, ap.fs, &why, nullptr, 0, ap.m.data());
+  // a beam-space plan whose grid needs a split takes front passes over its outer axes where they apply: each
+  // work-group then owns whole pointing grids of one outer Fourier index instead of repeating the outer
+  // passes in every work-group of the split
+  if (rc == OMNI_OK && ap.nbeam > 0 && ap.fs.fp.n_split > 1) {
+    ArrayPlan trial = ap;
+    if (plan_front(trial, &why2) == OMNI_OK) ap = std::move(trial);
+  }
   if (rc) rc = plan_front(ap, &why2);
   if (rc) {
     // last resort: residue splits along several axes (correct, repeats early passes)
@@ -1822,6 +1832,164 @@ extern "C" int omni_fengine(const void* raw, int64_t N, int64_t T, int32_t F, co
   HIP_TRY(omni::launch_fengine(raw, N, T, F, gains, dtype == OMNI_CI8, volt, static_cast<hipStream_t>(stream)));
   return OMNI_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Hybrid tiles (Sec. III).
+// ---------------------------------------------------------------------------
+
+struct omni_hybrid_s {
+  int device = -1;
+  int P = 0, nx = 0, ny = 0, F = 0;
+  omni_dtype dtype = OMNI_CF32;
+  int64_t N = 0, mx = 0, my = 0, Mp = 0, chunk_T = 1;
+  std::vector<double> offsets, A;  // metadata for omni_hybrid_baselines (may be empty)
+  float2* d_tw32 = nullptr;        // forward tables: w_mx^q then w_my^q (float32)
+  double2* d_tw64 = nullptr;       // inverse tables (float64)
+  float2* d_y[2] = {nullptr, nullptr};  // the two front passes' outputs for one chunk
+  double2* d_S = nullptr;          // [F][P][P][mx][my] cross-power sums
+  float2* d_ws[2] = {nullptr, nullptr};  // inverse intermediates
+};
+
+namespace {
+
+constexpr int64_t kHybridChunkBytes = int64_t(4) << 30;
+
+void hybrid_free(omni_hybrid_s* h) {
+  hipFree(h->d_tw32);
+  hipFree(h->d_tw64);
+  hipFree(h->d_y[0]);
+  hipFree(h->d_y[1]);
+  hipFree(h->d_S);
+  hipFree(h->d_ws[0]);
+  hipFree(h->d_ws[1]);
+}
+
+int hybrid_alloc(omni_hybrid_s* h) {
+  const int64_t tiles = h->chunk_T * h->F;
+  const int64_t pairs = (int64_t)h->F * h->P * h->P;
+  HIP_TRY(hipMalloc(&h->d_tw32, (size_t)(h->mx + h->my) * sizeof(float2)));
+  HIP_TRY(hipMalloc(&h->d_tw64, (size_t)(h->mx + h->my) * sizeof(double2)));
+  HIP_TRY(hipMalloc(&h->d_y[0], (size_t)(tiles * h->P * h->mx * h->ny) * sizeof(float2)));
+  HIP_TRY(hipMalloc(&h->d_y[1], (size_t)(tiles * h->P * h->Mp) * sizeof(float2)));
+  HIP_TRY(hipMalloc(&h->d_S, (size_t)(pairs * h->Mp) * sizeof(double2)));
+  HIP_TRY(hipMalloc(&h->d_ws[0], (size_t)(pairs * h->Mp) * sizeof(float2)));
+  HIP_TRY(hipMalloc(&h->d_ws[1], (size_t)(pairs * (2 * h->nx - 1) * h->my) * sizeof(float2)));
+  const int32_t desc[12] = {(int32_t)h->mx, -1, 0, (int32_t)h->my, -1, (int32_t)h->mx,
+                            (int32_t)h->mx, +1, 0, (int32_t)h->my, +1, (int32_t)h->mx};
+  int32_t* d_desc = nullptr;
+  HIP_TRY(hipMalloc(&d_desc, sizeof(desc)));
+  hipError_t e = hipMemcpy(d_desc, desc, sizeof(desc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = omni::launch_twiddles(d_desc, 2, h->d_tw32, nullptr, 0);
+  if (e == hipSuccess) e = omni::launch_twiddles(d_desc + 6, 2, nullptr, h->d_tw64, 0);
+  if (e == hipSuccess) e = omni::launch_fill_f64(reinterpret_cast<double*>(h->d_S), 2 * pairs * h->Mp, 0.0, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipFree(d_desc);
+  if (e != hipSuccess) return fail(OMNI_E_HIP, std::string("hybrid plan setup: ") + hipGetErrorString(e));
+  return OMNI_OK;
+}
+
+bool hybrid_side_ok(int n) { return front_axis_ok(n); }
+
+}  // namespace
+
+extern "C" {
+
+int omni_hybrid_plan(omni_hybrid_t* out, int32_t P, int32_t nx, int32_t ny, int32_t nchan, int32_t dtype,
+                     const double* offsets, const double* A) {
+  if (!out) return fail(OMNI_E_INVAL, "NULL argument");
+  *out = nullptr;
+  if (P != 2 && P != 4 && P != 8 && P != 16 && P != 32) return fail(OMNI_E_SHAPE, "hybrid tiles: P must be 2, 4, 8, 16 or 32");
+  if (!hybrid_side_ok(nx) || !hybrid_side_ok(ny))
+    return fail(OMNI_E_SHAPE, "hybrid tiles: tile sides must be 1, 2, 4, 8, 16 or 32");
+  if (nchan < 1 || nchan > 65535) return fail(OMNI_E_INVAL, "nchan must be in [1, 65535]");
+  if (dtype != OMNI_CF32 && dtype != OMNI_CI8 && dtype != OMNI_CI4) return fail(OMNI_E_INVAL, "unknown sample format");
+  auto h = std::make_unique<omni_hybrid_s>();
+  h->P = P;
+  h->nx = nx;
+  h->ny = ny;
+  h->F = nchan;
+  h->dtype = (omni_dtype)dtype;
+  h->N = (int64_t)P * nx * ny;
+  h->mx = 2 * nx;
+  h->my = 2 * ny;
+  h->Mp = h->mx * h->my;
+  if (offsets) h->offsets.assign(offsets, offsets + 2 * P);
+  if (A) h->A.assign(A, A + 4);
+  const int64_t per_t = (int64_t)h->F * h->P * h->Mp * (int64_t)sizeof(float2);
+  h->chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kHybridChunkBytes / per_t));
+  int rc = check_device(&h->device);
+  if (rc) return rc;
+  rc = hybrid_alloc(h.get());
+  if (rc) {
+    hybrid_free(h.get());
+    return rc;
+  }
+  *out = h.release();
+  return OMNI_OK;
+}
+
+int omni_hybrid_correlate(omni_hybrid_t h, const void* volt, int64_t T, void* vis, void* stream, uint32_t flags) {
+  if (!h) return fail(OMNI_E_INVAL, "NULL hybrid plan");
+  if (T < 0) return fail(OMNI_E_INVAL, "T < 0");
+  if (T > 0 && !volt) return fail(OMNI_E_INVAL, "volt is NULL");
+  if (!(flags & OMNI_NO_FINALIZE) && !vis) return fail(OMNI_E_INVAL, "vis is NULL");
+  if (flags & ~(OMNI_NO_RESET | OMNI_NO_FINALIZE)) return fail(OMNI_E_INVAL, "unknown flag");
+  const size_t sb = sample_bytes(h->dtype);
+  if (T > 0 && (reinterpret_cast<uintptr_t>(volt) & (sb == 1 ? 0 : sb == 2 ? 1 : 3)) != 0)
+    return fail(OMNI_E_INVAL, "volt is not aligned to its sample size");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != h->device) return fail(OMNI_E_STATE, "current HIP device is not the plan's device");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool accumulate = (flags & OMNI_NO_RESET) != 0;
+  const int64_t pairs = (int64_t)h->F * h->P * h->P;
+  if (T == 0 && !accumulate)
+    HIP_TRY(omni::launch_fill_f64(reinterpret_cast<double*>(h->d_S), 2 * pairs * h->Mp, 0.0, st));
+  for (int64_t c0 = 0; c0 < T; c0 += h->chunk_T) {
+    const int64_t tc = std::min<int64_t>(h->chunk_T, T - c0);
+    const void* src = static_cast<const char*>(volt) + (size_t)(c0 * h->F * h->N) * sb;
+    // each tile's zero-padded 2-D transform: axis x, then axis y
+    HIP_TRY(omni::launch_front_axis(fmt_of(h->dtype), src, h->d_y[0], h->d_tw32, tc * h->F, h->P, h->nx, (int)h->mx,
+                                    std::max<int>(1, (int)h->mx / 16), h->ny, h->N, h->P * h->mx * h->ny, st, false,
+                                    1.f));
+    HIP_TRY(omni::launch_front_axis(0, h->d_y[0], h->d_y[1], h->d_tw32 + h->mx, tc * h->F, h->P * h->mx, h->ny,
+                                    (int)h->my, std::max<int>(1, (int)h->my / 16), 1, h->P * h->mx * h->ny,
+                                    h->P * h->Mp, st, false, 1.f));
+    HIP_TRY(omni::launch_xengine(h->d_y[1], tc, h->F, h->P, h->Mp, h->d_S, (accumulate || c0 > 0) ? 1 : 0, st));
+  }
+  if (!(flags & OMNI_NO_FINALIZE)) {
+    HIP_TRY(omni::launch_narrow(h->d_S, h->d_ws[0], pairs * h->Mp, st));
+    HIP_TRY(omni::launch_inverse_axis(false, false, h->d_ws[0], h->d_ws[1], h->d_tw64, pairs, (int)h->mx, h->nx,
+                                      h->my, 1.0, st));
+    HIP_TRY(omni::launch_inverse_axis(false, true, h->d_ws[1], vis, h->d_tw64 + h->mx, pairs * (2 * h->nx - 1),
+                                      (int)h->my, h->ny, 1, 1.0 / (double)h->Mp, st));
+  }
+  return OMNI_OK;
+}
+
+int omni_hybrid_baselines(omni_hybrid_t h, double* uv) {
+  if (!h || !uv) return fail(OMNI_E_INVAL, "NULL argument");
+  if (h->offsets.empty() || h->A.empty()) return fail(OMNI_E_STATE, "plan has no tile offsets or lattice matrix");
+  size_t i = 0;
+  for (int p = 0; p < h->P; ++p)
+    for (int q = 0; q < h->P; ++q)
+      for (int dx = -(h->nx - 1); dx < h->nx; ++dx)
+        for (int dy = -(h->ny - 1); dy < h->ny; ++dy) {
+          uv[i++] = h->offsets[2 * p] - h->offsets[2 * q] + (h->A[0] * dx + h->A[1] * dy);
+          uv[i++] = h->offsets[2 * p + 1] - h->offsets[2 * q + 1] + (h->A[2] * dx + h->A[3] * dy);
+        }
+  return OMNI_OK;
+}
+
+int omni_hybrid_destroy(omni_hybrid_t h) {
+  if (!h) return OMNI_OK;
+  hipDeviceSynchronize();
+  hybrid_free(h);
+  delete h;
+  return OMNI_OK;
+}
+
+}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // Physical-baseline fold (Sec. II.D) and baseline distributions (Sec. III).

@@ -281,3 +281,22 @@ def test_beam_space_plans_on_the_host():
     # the matrix-core kernels are not used for beam-space plans
     r = omni.Plan([[8, 8], [8, 8]], None, 4, "ci8", "mixed", host_only=True, beams=True)
     assert json.loads(r.describe())["arrays"][0]["kernel"] == "fused_fp32"
+
+
+def test_hybrid_plan_validates_before_any_device_call():
+    h = ctypes.c_void_p()
+    f = omni.lib.omni_hybrid_plan
+    st = omni.STATUS
+    assert st[f(None, 4, 8, 8, 1, 2, None, None)] == "OMNI_E_INVAL"
+    assert st[f(ctypes.byref(h), 3, 8, 8, 1, 2, None, None)] == "OMNI_E_SHAPE"  # P not a power of two
+    assert st[f(ctypes.byref(h), 4, 12, 8, 1, 2, None, None)] == "OMNI_E_SHAPE"  # side 12
+    assert st[f(ctypes.byref(h), 4, 8, 64, 1, 2, None, None)] == "OMNI_E_SHAPE"  # side 64 (m = 128)
+    assert st[f(ctypes.byref(h), 4, 8, 8, 0, 2, None, None)] == "OMNI_E_INVAL"
+    assert st[f(ctypes.byref(h), 4, 8, 8, 1, 7, None, None)] == "OMNI_E_INVAL"
+    assert omni.lib.omni_hybrid_correlate(None, None, 0, None, None, 0) == -1
+    assert omni.lib.omni_hybrid_destroy(None) == 0
+    # a valid geometry goes as far as the device check
+    rc = f(ctypes.byref(h), 4, 8, 8, 1, 2, None, None)
+    assert st[rc] in ("OMNI_E_NODEV", "OMNI_OK")
+    if rc == 0:
+        omni.lib.omni_hybrid_destroy(h)

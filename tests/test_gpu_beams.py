@@ -77,6 +77,25 @@ def test_beam_space_matches_oracle(level_dims, dtype, form, T, F):
     assert err <= TOL[form]
 
 
+def test_beam_space_front_chunks():
+    """The 16 x 16-of-16 x 16 beam-space plan takes a front pass over its outer axes; three time chunks."""
+    import json
+
+    level_dims = [[16, 16], [16, 16]]
+    T, F, N = 12, 2, 65536
+    gen = torch.Generator().manual_seed(77)
+    raw = random_raw("ci8", T, F, N, gen)
+    plan = omni.Plan(level_dims, None, F, "ci8", "fp32", beams=True, chunk_T=4)
+    a = json.loads(plan.describe())["arrays"][0]
+    assert a["mode"] == "front" and -(-T // a["chunk_T"]) == 3
+    vis = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    x = oracle.decode(raw.numpy(), "ci8", T, F, N)
+    err = beam_err(vis.cpu().numpy(), beams.beam_visibilities(x, level_dims), level_dims)
+    say(f"[beams] front chunks: err {err:.3g}")
+    assert err <= TOL["fp32"]
+
+
 def test_beam_space_split_integration():
     """Two calls (NO_RESET on the second) equal one call over all samples (linearity in time)."""
     level_dims = [[4, 4], [8, 8]]

@@ -1,0 +1,107 @@
+"""Parity of hybrid tiles (Sec. III; HIP, through the C ABI) with the oracle (oracle/hybrid.py).
+
+Bar: per channel and tile pair, max over index differences of |C_gpu - C_oracle| relative to
+sqrt(C_pp[0] C_qq[0]) (the Cauchy-Schwarz bound of |C_pq|), <= 1e-5: the transforms and the per-cell
+cross-power sums are float32 within a chunk of samples, float64 across chunks and in the inverse.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0909_0001_amd as omni
+from oracle import hybrid
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def random_raw(dtype, T, F, N, gen):
+    if dtype == "cf32":
+        return torch.randn((T, F, N, 2), generator=gen).float()
+    if dtype == "ci8":
+        return torch.randint(-127, 128, (T, F, N, 2), generator=gen, dtype=torch.int16).to(torch.int8)
+    re = torch.randint(-7, 8, (T, F, N), generator=gen, dtype=torch.int16)
+    im = torch.randint(-7, 8, (T, F, N), generator=gen, dtype=torch.int16)
+    return ((re & 0xF) << 4 | (im & 0xF)).to(torch.uint8)
+
+
+def pair_err(got, ref, nx, ny):
+    F, P = ref.shape[0], ref.shape[1]
+    c = (nx - 1, ny - 1)
+    zero = np.abs(ref[:, np.arange(P), np.arange(P), c[0], c[1]])  # [F, P]
+    scale = np.sqrt(zero[:, :, None] * zero[:, None, :])
+    scale[scale == 0] = 1.0
+    return float((np.abs(got - ref).reshape(F, P, P, -1).max(axis=-1) / scale).max())
+
+
+CASES = [
+    (4, 8, 8, "ci8", 20, 2),
+    (2, 4, 4, "ci4", 300, 1),  # two chunks of samples
+    (2, 1, 8, "cf32", 9, 3),  # one-antenna-wide tiles
+    (8, 4, 16, "ci4", 11, 2),
+    (16, 16, 16, "ci4", 8, 2),  # 16 tiles of 16 x 16
+    (32, 2, 4, "ci8", 6, 1),
+]
+
+
+@pytest.mark.parametrize("P,nx,ny,dtype,T,F", CASES)
+def test_hybrid_matches_oracle(P, nx, ny, dtype, T, F):
+    N = P * nx * ny
+    gen = torch.Generator().manual_seed(N + T)
+    raw = random_raw(dtype, T, F, N, gen)
+    say(f"[hybrid] case P={P} {nx}x{ny} {dtype} T={T} F={F}")
+    h = omni.Hybrid(P, nx, ny, F, dtype)
+    vis = h.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    x = oracle.decode(raw.numpy(), dtype, T, F, N)
+    ref = hybrid.tile_cross_correlations(x, P, nx, ny)
+    err = pair_err(vis.cpu().numpy(), ref, nx, ny)
+    say(f"[hybrid] P={P} {nx}x{ny}: err {err:.3g}")
+    assert err <= 1e-5
+
+
+def test_hybrid_split_integration_and_empty_call():
+    P, nx, ny, F = 4, 8, 4, 2
+    gen = torch.Generator().manual_seed(5)
+    raw = random_raw("ci8", 30, F, P * nx * ny, gen).cuda()
+    h = omni.Hybrid(P, nx, ny, F, "ci8")
+    whole = h.correlate(raw).clone()
+    h.correlate(raw[:13].contiguous(), flags=omni.NO_FINALIZE)
+    split = h.correlate(raw[13:].contiguous(), flags=omni.NO_RESET)
+    torch.cuda.synchronize()
+    assert pair_err(split.cpu().numpy(), whole.cpu().numpy().astype(np.complex128), nx, ny) <= 1e-6
+    empty = h.correlate(raw[:0].contiguous())
+    torch.cuda.synchronize()
+    assert float(empty.abs().max()) == 0.0
+
+
+def test_hybrid_baselines_metadata():
+    P, nx, ny = 2, 2, 4
+    off = np.array([[0.0, 0.0], [13.25, -4.5]])
+    A = np.array([[1.0, 0.2], [0.0, 0.9]])
+    h = omni.Hybrid(P, nx, ny, 1, "ci8", offsets=off, A=A)
+    uv = h.baselines()
+    for p in range(P):
+        for q in range(P):
+            for dx in range(-(nx - 1), nx):
+                for dy in range(-(ny - 1), ny):
+                    want = off[p] - off[q] + A @ np.array([dx, dy])
+                    assert np.allclose(uv[p, q, dx + nx - 1, dy + ny - 1], want)
+    with pytest.raises(omni.OmniError):
+        omni.Hybrid(P, nx, ny, 1, "ci8").baselines()
+
+
+def test_hybrid_argument_errors():
+    h = omni.Hybrid(2, 4, 4, 1, "ci8")
+    with pytest.raises(ValueError):
+        h.correlate(torch.zeros((3, 1, 31, 2), dtype=torch.int8, device="cuda"))
+    with pytest.raises(ValueError):
+        h.correlate(torch.zeros((3, 1, 32), dtype=torch.uint8, device="cuda"))
