@@ -319,38 +319,45 @@ def bench_fold(omni, torch, skysim, steps, warmup, vis128=None):
     return out
 
 
-def beam_flops_per_as(dims) -> float:
-    """Float32 work per antenna-sample of a beam-space plan, counted like the FP32 plain form: a line-pruned
-    transform of n inputs to m outputs costs (m / n) 5 log2 m flops per input point, axes in the general
-    kernel's order (first axis, then innermost to outermost), the point count growing by m / n after each;
-    the lowest level's two axes are unpadded (m = n); plus 4 flops per Fourier cell for |X|^2 and the time sum."""
+def beam_flops_per_as(dims, form) -> float:
+    """Algorithmic work per antenna-sample of the beam-space variant: the counts of the two forms with the lowest
+    level's two axes unpadded (m = n: a transform that adds no points).  Passes in decreasing m; the point count
+    grows by m / n after each pass.  Mixed form: 16 flops (hi + lo, real-embedded complex MAC) x the growth so far
+    x c(m) per pass (c(m) = m for m <= 32, as for the hot path); FP32 form: (m / n) 5 log2 m per point and pass,
+    plus 4 flops per Fourier cell for |X|^2 and the time sum."""
     n = [v for v in dims]
     m = [2 * v for v in n[:-2]] + n[-2:]
-    keep = [k for k in range(len(n)) if n[k] > 1]
-    order = keep[:1] + keep[1:][::-1]
-    total, factor = 0.0, 1.0
-    for k in order:
-        total += factor * (m[k] / n[k]) * 5 * math.log2(m[k])
-        factor *= m[k] / n[k]
-    return total + 4 * factor
+    axes = sorted((k for k in range(len(n)) if n[k] > 1), key=lambda k: -m[k])
+    total, growth = 0.0, 1.0
+    for k in axes:
+        if form == "mixed":
+            c = m[k] if m[k] <= 32 else min(r1 + 2 * (m[k] // r1) + 2 for r1 in range(2, m[k]) if m[k] % r1 == 0)
+            total += 16 * growth * c
+        else:
+            total += growth * (m[k] / n[k]) * 5 * math.log2(m[k])
+        growth *= m[k] / n[k]
+    return total if form == "mixed" else total + 4 * growth
 
 
-def bench_beams(omni, torch, w, raw, steps, warmup, main_ms):
+def bench_beams(omni, torch, w, raw, steps, warmup, main_ms, form="mixed"):
     """Beam-space variant (Appendix A steps 4-5) on the same bytes as the array's hot-path call: every lowest-level
-    16 x 16 block formed into 256 pointings, each correlated over the outer 16 x 16 level."""
-    res = run_form(omni, w, raw, "fp32", steps, warmup, tune="search", beams=True)
-    per_as = beam_flops_per_as(w.dims)
-    launch_ms = res["stages"]["kernel"]
-    achieved = per_as * w.antenna_samples() / res["launches"] / (launch_ms / 1e3) / 1e12
-    out = {"workload": f"{w.name} beam-space: {w.level_dims[-1][0] * w.level_dims[-1][1]} pointings a block",
-           "kernel": res["kernel"], "ms_per_call": round(res["ms"], 4),
-           "value": w.antenna_samples() / (res["ms"] / 1e3), "vs_hot_path_same_bytes": round(main_ms / res["ms"], 4),
-           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                        "launch_ms": round(launch_ms, 4), "algorithmic_flops_per_antenna_sample": per_as}}
+    16 x 16 block formed into 256 pointings, each correlated over the outer 16 x 16 level.  The plan runs the
+    ordinary kernel of the grid and keeps the even Fourier cells of the block axes (the unpadded transform's
+    cells), so the kernel does twice the variant's own work on the block axes; the roofline counts only the
+    variant's algorithmic work, over the whole call."""
+    res = run_form(omni, w, raw, form, steps, warmup, tune="search", beams=True)
+    per_as = beam_flops_per_as(w.dims, form)
+    achieved = per_as * w.antenna_samples() / (res["ms"] / 1e3) / 1e12
+    peak, bound = (PEAK_FP16_MFMA_TFLOPS, "mfma") if form == "mixed" else (PEAK_FP32_VECTOR_TFLOPS, "alu")
+    out = {"workload": f"{w.name} beam-space: {w.level_dims[-1][0] * w.level_dims[-1][1]} pointings a block, "
+           f"{form} form", "kernel": res["kernel"], "route": res["desc"]["arrays"][0]["beams"],
+           "ms_per_call": round(res["ms"], 4), "value": w.antenna_samples() / (res["ms"] / 1e3),
+           "vs_hot_path_same_bytes": round(main_ms / res["ms"], 4),
+           "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                        "frac": round(achieved / peak, 4), "algorithmic_flops_per_antenna_sample": per_as,
+                        "note": "variant's own work over the whole call time"}}
     del res
     return out
-
 
 def bench_hybrid(omni, torch, steps, warmup, P=16, nx=16, ny=16, F=64, T=2048):
     """Hybrid tiles (Sec. III): P tiles of nx x ny antennas (the 16x16-of-16x16 array's antennas, N = 4096 x P/16)

@@ -85,9 +85,14 @@ typedef enum { OMNI_FORM_FP32 = 0, OMNI_FORM_MIXED = 1 } omni_form;
  * b_y j_y / n_y))), and each pointing is correlated over the outer levels as in
  * Sec. II (padded transforms, square modulus, time sum, inverse along the outer
  * axes only).  Visibilities: complex64 [F][2n_1-1]...[2n_{d-2}-1][n_x][n_y]
- * (pointings last).  Needs at least two levels and more than one block; runs
- * on the general float32 kernel in either form; omni_baselines, the fold and
- * the direct correlator refuse such plans (OMNI_E_STATE). */
+ * (pointings last).  Since the unpadded transform of a block is the
+ * zero-padded one (m = 2n) at its even cells, B_b = X[2b], a grid whose
+ * ordinary plan has a fixed-shape kernel (matrix-core or compile-time shape)
+ * runs that kernel unchanged and keeps the even cells of the block axes
+ * before the inverse; other grids run the general kernel with the block axes
+ * unpadded.  Needs at least two levels and more than one block;
+ * omni_baselines, the fold and the direct correlator refuse such plans
+ * (OMNI_E_STATE). */
 #define OMNI_PLAN_BEAMS 0x10u
 
 /* flags argument of omni_correlate* */

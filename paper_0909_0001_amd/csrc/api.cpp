@@ -62,6 +62,7 @@ hipError_t launch_fengine(const void* raw, int64_t N, int64_t T, int F, const vo
 hipError_t launch_xengine(const float2* Y, int64_t Tc, int F, int P, int64_t Mp, double2* S, int accumulate,
                           hipStream_t st);
 hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t st);
+hipError_t launch_even_cells(const double* A, double* E, int64_t rows, int na, int nb, int axes, hipStream_t st);
 }  // namespace omni
 
 using omni::AxisP;
@@ -103,6 +104,9 @@ struct ArrayPlan {
   std::vector<int> m;       // transform length per axis of n: 2 n (zero-padded), or n for a beam axis
   int nbeam = 0;            // beam-space plan: the last nbeam axes of n (the lowest level's) are pointings
   bool beams = false;       // beam-space plan (the lowest level's two axes are pointing indices in the output)
+  bool beam_sub = false;    // beam-space plan run on the zero-padded transform: pointing b is its Fourier cell
+                            // 2b along the lowest level's axes (nbeam counts those axes; the forward pass is
+                            // the ordinary one)
   int64_t N = 0, M = 0, n_out = 0;
   FusedSetup fs;            // schedule of the fused kernel (all axes, or the axes after the front)
   int kernel = 0;  // 0: general; 1: 8x8x8x8 float32; 2: 8x8x8x8 mixed (MFMA); 3: compile-time shape (float32);
@@ -587,8 +591,8 @@ int plan_front(ArrayPlan& ap, std::string* why) {
   return OMNI_E_SHAPE;
 }
 
-int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form,
-                omni_dtype dtype, bool beams) {
+int build_array_core(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form,
+                     omni_dtype dtype, bool beams) {
   if (levels < 1 || levels > omni::kMaxD / 2) return fail(OMNI_E_SHAPE, "levels must be in [1, 4]");
   if (!dims) return fail(OMNI_E_INVAL, "dims is NULL");
   if (nchan < 1) return fail(OMNI_E_INVAL, "nchan must be >= 1");
@@ -611,7 +615,6 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   // beam-space plan: the lowest level's axes (the last two) are transformed without padding and never
   // inverted; its axes of more than one antenna are the last nbeam entries of n
   ap.nbeam = 0;
-  ap.beams = beams;
   if (beams) {
     if (levels < 2) return fail(OMNI_E_SHAPE, "a beam-space plan needs at least one level above the blocks");
     ap.nbeam = (ap.dims[(size_t)(2 * levels - 2)] > 1) + (ap.dims[(size_t)(2 * levels - 1)] > 1);
@@ -703,6 +706,39 @@ int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A,
   // inverse in groups of channels whose complex float32 workspace fits 1 GiB per buffer
   ap.inv_group = (int)std::max<int64_t>(1, std::min<int64_t>(ap.F, (int64_t(1) << 30) / (ap.M * 8)));
   return OMNI_OK;
+}
+
+// A beam-space plan (Appendix A steps 4-5).  The unpadded transform of a block, B_b = sum_j x_j
+// exp(-2 pi i b.j / n), is the zero-padded one at the even cells: B_b = X[2b] (m = 2n).  So where the ordinary
+// plan of the same grid has a fixed-shape kernel (matrix-core or compile-time shape), the beam-space plan runs
+// that kernel unchanged and keeps the even cells of the lowest level's axes before the inverse along the outer
+// axes; otherwise the general kernel transforms those axes without padding (a quarter of the cells).
+int build_array(ArrayPlan& ap, int levels, const int32_t* dims, const double* A, int32_t nchan, omni_form form,
+                omni_dtype dtype, bool beams) {
+  if (!beams) return build_array_core(ap, levels, dims, A, nchan, form, dtype, false);
+  if (levels < 2 || levels > omni::kMaxD / 2)
+    return fail(OMNI_E_SHAPE, "a beam-space plan needs at least one level above the blocks");
+  if (!dims) return fail(OMNI_E_INVAL, "dims is NULL");
+  int64_t outer = 1;
+  for (int k = 0; k < 2 * levels - 2; ++k) outer *= dims[k];
+  if (outer < 2) return fail(OMNI_E_SHAPE, "a beam-space plan needs more than one block");
+  const int64_t cap = ap.chunk_cap;
+  int rc = build_array_core(ap, levels, dims, A, nchan, form, dtype, false);
+  if (rc) return rc;
+  ap.beams = true;
+  if (ap.kernel != 0) {
+    ap.beam_sub = true;
+    ap.nbeam = (dims[2 * levels - 2] > 1) + (dims[2 * levels - 1] > 1);
+    ap.n_out = 1;
+    for (size_t k = 0; k < ap.n.size(); ++k)
+      ap.n_out *= (int)k >= (int)ap.n.size() - ap.nbeam ? ap.n[k] : 2 * ap.n[k] - 1;
+    return OMNI_OK;
+  }
+  ap = ArrayPlan();
+  ap.chunk_cap = cap;
+  rc = build_array_core(ap, levels, dims, A, nchan, form, dtype, true);
+  ap.beams = true;
+  return rc;
 }
 
 void free_array(ArrayPlan& ap) {
@@ -992,10 +1028,18 @@ int correlate_array(omni_plan_s* p, ArrayPlan& ap, const void* volt, int64_t T, 
     for (int f0 = 0; f0 < ap.F; f0 += ap.inv_group) {
       const int g = std::min(ap.inv_group, ap.F - f0);
       const void* src = ap.d_A + (size_t)f0 * ap.M;
+      if (ap.beam_sub && ap.nbeam > 0) {
+        // pointings = the even cells of the lowest level's (zero-padded) axes, gathered into d_ws[1]
+        const int na = ap.n[ap.n.size() - ap.nbeam], nb = ap.nbeam == 2 ? ap.n.back() : 1;
+        const int64_t rows = (int64_t)g * (ap.M / (ap.nbeam == 2 ? 4LL * na * nb : 2LL * na));
+        HIP_TRY(omni::launch_even_cells(static_cast<const double*>(src), reinterpret_cast<double*>(ap.d_ws[1]),
+                                        rows, na, nb, ap.nbeam, st));
+        src = ap.d_ws[1];
+      }
       int64_t outer = g;
       for (int k = 0; k < d; ++k) {
         int64_t inner = 1;
-        for (int j = k + 1; j < (int)ap.n.size(); ++j) inner *= ap.m[j];
+        for (int j = k + 1; j < (int)ap.n.size(); ++j) inner *= (ap.beam_sub && j >= d) ? ap.n[j] : ap.m[j];
         const bool last = (k == d - 1);
         void* dst = last ? (void*)(static_cast<float2*>(vis) + (size_t)f0 * ap.n_out) : (void*)ap.d_ws[k & 1];
         HIP_TRY(omni::launch_inverse_axis(k == 0, last, src, dst, ap.d_tw64 + ap.inv_off[k], outer, ap.m[k],
@@ -1715,7 +1759,9 @@ int omni_plan_describe(omni_plan_t plan, char* buf, size_t len, size_t* needed) 
                         : ap.kernel == 7 ? "grid64_mixed"
                         : ap.kernel == 8 ? "grid32_mixed"
                                          : "fused_fp32";
-    s += std::string("{\"kernel\":\"") + kname + "\",\"mode\":\"" + (ap.n_front ? "front" : "direct") +
+    s += std::string("{\"kernel\":\"") + kname + "\",\"beams\":\"" +
+         (ap.beams ? (ap.beam_sub ? "subset" : "unpadded") : "no") + "\",\"mode\":\"" +
+         (ap.n_front ? "front" : "direct") +
          "\",\"n_front\":" + std::to_string(ap.n_front) + ",\"chunk_T\":" + std::to_string(ap.chunk_T) +
          ",\"N\":" + std::to_string(ap.N) + ",\"M\":" + std::to_string(ap.M) + ",\"F\":" + std::to_string(ap.F) +
          ",\"kernel_channels\":" + std::to_string(ap.fs.F) + ",\"n_split\":" + std::to_string(P.n_split) +

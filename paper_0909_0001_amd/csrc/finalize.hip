@@ -315,4 +315,28 @@ hipError_t launch_twiddles(const int32_t* desc_dev, int n_tables, float2* tw32, 
   return hipGetLastError();
 }
 
+
+// The even Fourier cells of the last `axes` (1 or 2) axes of a real float64 array: rows of (2 na) x (2 nb)
+// values in, na x nb out (nb = 1 for one axis).  With m = 2n, the cell 2b of the zero-padded transform is
+// the unpadded transform's cell b.
+__global__ void even_cells_kernel(const double* __restrict__ A, double* __restrict__ E, int64_t rows, int na,
+                                  int nb, int axes) {
+  const int64_t per = (int64_t)na * nb;
+  const int64_t total = rows * per;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / per;
+    const int c = (int)(i - r * per);
+    const int bx = c / nb, by = c - bx * nb;
+    E[i] = axes == 2 ? A[(r * 2 * na + 2 * bx) * (2 * nb) + 2 * by] : A[r * 2 * na + 2 * bx];
+  }
+}
+
+hipError_t launch_even_cells(const double* A, double* E, int64_t rows, int na, int nb, int axes, hipStream_t st) {
+  if ((axes != 1 && axes != 2) || na < 1 || nb < 1 || (axes == 1 && nb != 1)) return hipErrorInvalidValue;
+  const int64_t total = rows * na * nb;
+  const int64_t g = std::max<int64_t>(1, std::min<int64_t>(65536, (total + 255) / 256));
+  hipLaunchKernelGGL(even_cells_kernel, dim3((unsigned)g), dim3(256), 0, st, A, E, rows, na, nb, axes);
+  return hipGetLastError();
+}
+
 }  // namespace omni

@@ -278,9 +278,13 @@ def test_beam_space_plans_on_the_host():
         with pytest.raises(omni.OmniError) as ei:
             omni.Plan(ld, None, 1, "ci8", host_only=True, beams=True)
         assert omni.STATUS[ei.value.code] == "OMNI_E_SHAPE"
-    # the matrix-core kernels are not used for beam-space plans
+    assert a["beams"] == "unpadded"
+    # where the ordinary plan has a fixed-shape kernel, the beam-space plan runs it and keeps the even cells
     r = omni.Plan([[8, 8], [8, 8]], None, 4, "ci8", "mixed", host_only=True, beams=True)
-    assert json.loads(r.describe())["arrays"][0]["kernel"] == "fused_fp32"
+    b = json.loads(r.describe())["arrays"][0]
+    assert (b["kernel"], b["beams"]) == ("fused8x4_mixed", "subset") and r.vis_shape() == (4, 15, 15, 8, 8)
+    c = omni.Plan([[1, 64], [64, 1]], None, 2, "ci4", "mixed", host_only=True, beams=True)
+    assert json.loads(c.describe())["arrays"][0]["beams"] == "subset" and c.vis_shape() == (2, 1, 127, 64, 1)
 
 
 def test_hybrid_plan_validates_before_any_device_call():

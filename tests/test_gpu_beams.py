@@ -2,8 +2,7 @@
 oracle (oracle/beams.py).
 
 Bar: per channel and pointing, max over the outer lags of |V_gpu - V_oracle| relative to that
-pointing's zero-lag power, <= 1e-5 (float32 form) or 2e-3 (mixed form; a beam-space plan runs
-the float32 kernel in either form).
+pointing's zero-lag power, <= 1e-5 (float32 form) or 2e-3 (mixed form).
 """
 
 import math
@@ -48,24 +47,32 @@ def beam_err(got, ref, level_dims):
     return float(np.max(np.abs(g - r).max(axis=2) / z))
 
 
+# (level_dims, dtype, form, T, F, route): "unpadded" = the general kernel with the blocks' axes unpadded;
+# "subset" = the ordinary plan's fixed-shape kernel, pointings taken as its even Fourier cells
 CASES = [
-    ([[4, 4], [8, 8]], "ci8", "fp32", 20, 2),
-    ([[4, 4], [8, 8]], "ci4", "mixed", 20, 2),
-    ([[2, 3], [3, 3], [4, 4]], "ci4", "fp32", 9, 3),
-    ([[3, 3], [5, 5]], "cf32", "fp32", 7, 2),  # odd block sides: unpadded 5-point transforms
-    ([[4, 1], [1, 8]], "ci8", "fp32", 11, 2),  # one-dimensional blocks
-    ([[16, 16], [16, 16]], "ci4", "fp32", 12, 2),  # the 16 x 16-of-16 x 16 array: 256 pointings
+    ([[4, 4], [8, 8]], "ci8", "fp32", 20, 2, "unpadded"),
+    ([[4, 4], [8, 8]], "ci4", "mixed", 20, 2, "unpadded"),
+    ([[2, 3], [3, 3], [4, 4]], "ci4", "fp32", 9, 3, "unpadded"),
+    ([[3, 3], [5, 5]], "cf32", "fp32", 7, 2, "unpadded"),  # odd block sides: unpadded 5-point transforms
+    ([[4, 1], [1, 8]], "ci8", "fp32", 11, 2, "unpadded"),  # one-dimensional blocks
+    ([[16, 16], [16, 16]], "ci4", "fp32", 12, 2, "subset"),  # 256 pointings, compile-time-shape kernel
+    ([[16, 16], [16, 16]], "ci4", "mixed", 12, 2, "subset"),  # the matrix-core kernel behind a front pass
+    ([[8, 8], [8, 8]], "ci8", "mixed", 16, 3, "subset"),  # 8x8x8x8 matrix-core kernel
+    ([[1, 64], [64, 1]], "ci4", "mixed", 10, 2, "subset"),  # one-dimensional blocks on the 64 x 64 kernel
 ]
 
 
-@pytest.mark.parametrize("level_dims,dtype,form,T,F", CASES)
-def test_beam_space_matches_oracle(level_dims, dtype, form, T, F):
+@pytest.mark.parametrize("level_dims,dtype,form,T,F,route", CASES)
+def test_beam_space_matches_oracle(level_dims, dtype, form, T, F, route):
+    import json
+
     dims = [v for ld in level_dims for v in ld]
     N = math.prod(dims)
     gen = torch.Generator().manual_seed(N + T)
     raw = random_raw(dtype, T, F, N, gen)
     say(f"[beams] case {level_dims} {dtype} {form} T={T} F={F}")
     plan = omni.Plan(level_dims, None, F, dtype, form, beams=True)
+    assert json.loads(plan.describe())["arrays"][0]["beams"] == route
     shape = plan.vis_shape()
     assert shape == (F,) + tuple(2 * v - 1 for v in dims[:-2]) + tuple(dims[-2:])
     vis = plan.correlate(raw.cuda())
