@@ -62,6 +62,9 @@ hipError_t launch_fengine(const void* raw, int64_t N, int64_t T, int F, const vo
 hipError_t launch_xengine(const float2* Y, int64_t Tc, int F, int P, int64_t Mp, double2* S, int accumulate,
                           hipStream_t st);
 hipError_t launch_narrow(const double2* src, float2* dst, int64_t n, hipStream_t st);
+bool xengine_fused_ok(int P, int ny);
+hipError_t launch_xengine_fused(const float2* Y1, int64_t Tc, int F, int P, int mx, int ny, const float2* twy,
+                                double2* S, int accumulate, hipStream_t st);
 hipError_t launch_even_cells(const double* A, double* E, int64_t rows, int na, int nb, int axes, hipStream_t st);
 }  // namespace omni
 
@@ -1888,6 +1891,7 @@ struct omni_hybrid_s {
   int P = 0, nx = 0, ny = 0, F = 0;
   omni_dtype dtype = OMNI_CF32;
   int64_t N = 0, mx = 0, my = 0, Mp = 0, chunk_T = 1;
+  bool fused = false;              // the y-axis transform runs inside the pair stage (P m_y <= 512)
   std::vector<double> offsets, A;  // metadata for omni_hybrid_baselines (may be empty)
   float2* d_tw32 = nullptr;        // forward tables: w_mx^q then w_my^q (float32)
   double2* d_tw64 = nullptr;       // inverse tables (float64)
@@ -1916,7 +1920,7 @@ int hybrid_alloc(omni_hybrid_s* h) {
   HIP_TRY(hipMalloc(&h->d_tw32, (size_t)(h->mx + h->my) * sizeof(float2)));
   HIP_TRY(hipMalloc(&h->d_tw64, (size_t)(h->mx + h->my) * sizeof(double2)));
   HIP_TRY(hipMalloc(&h->d_y[0], (size_t)(tiles * h->P * h->mx * h->ny) * sizeof(float2)));
-  HIP_TRY(hipMalloc(&h->d_y[1], (size_t)(tiles * h->P * h->Mp) * sizeof(float2)));
+  if (!h->fused) HIP_TRY(hipMalloc(&h->d_y[1], (size_t)(tiles * h->P * h->Mp) * sizeof(float2)));
   HIP_TRY(hipMalloc(&h->d_S, (size_t)(pairs * h->Mp) * sizeof(double2)));
   HIP_TRY(hipMalloc(&h->d_ws[0], (size_t)(pairs * h->Mp) * sizeof(float2)));
   HIP_TRY(hipMalloc(&h->d_ws[1], (size_t)(pairs * (2 * h->nx - 1) * h->my) * sizeof(float2)));
@@ -1963,6 +1967,11 @@ int omni_hybrid_plan(omni_hybrid_t* out, int32_t P, int32_t nx, int32_t ny, int3
   if (A) h->A.assign(A, A + 4);
   const int64_t per_t = (int64_t)h->F * h->P * h->Mp * (int64_t)sizeof(float2);
   h->chunk_T = std::max<int64_t>(1, std::min<int64_t>(kChunkMax, kHybridChunkBytes / per_t));
+  // the fused pair stage: a work-group owns 512 / (P m_y) rows kappa_x, which must divide m_x
+  if (omni::xengine_fused_ok(P, ny)) {
+    const int64_t rows = 512 / (P * h->my);
+    h->fused = rows >= 1 && h->mx % rows == 0;
+  }
   int rc = check_device(&h->device);
   if (rc) return rc;
   rc = hybrid_alloc(h.get());
@@ -1998,10 +2007,17 @@ int omni_hybrid_correlate(omni_hybrid_t h, const void* volt, int64_t T, void* vi
     HIP_TRY(omni::launch_front_axis(fmt_of(h->dtype), src, h->d_y[0], h->d_tw32, tc * h->F, h->P, h->nx, (int)h->mx,
                                     std::max<int>(1, (int)h->mx / 16), h->ny, h->N, h->P * h->mx * h->ny, st, false,
                                     1.f));
+    const int acc = (accumulate || c0 > 0) ? 1 : 0;
+    if (h->fused) {
+      // y-axis transform inside the pair stage
+      HIP_TRY(omni::launch_xengine_fused(h->d_y[0], tc, h->F, h->P, (int)h->mx, h->ny, h->d_tw32 + h->mx, h->d_S, acc,
+                                         st));
+      continue;
+    }
     HIP_TRY(omni::launch_front_axis(0, h->d_y[0], h->d_y[1], h->d_tw32 + h->mx, tc * h->F, h->P * h->mx, h->ny,
                                     (int)h->my, std::max<int>(1, (int)h->my / 16), 1, h->P * h->mx * h->ny,
                                     h->P * h->Mp, st, false, 1.f));
-    HIP_TRY(omni::launch_xengine(h->d_y[1], tc, h->F, h->P, h->Mp, h->d_S, (accumulate || c0 > 0) ? 1 : 0, st));
+    HIP_TRY(omni::launch_xengine(h->d_y[1], tc, h->F, h->P, h->Mp, h->d_S, acc, st));
   }
   if (!(flags & OMNI_NO_FINALIZE)) {
     HIP_TRY(omni::launch_narrow(h->d_S, h->d_ws[0], pairs * h->Mp, st));

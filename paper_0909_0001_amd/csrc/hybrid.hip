@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kXeThreads) void xengine_kernel(const float2* __res
     for (int q = 0; q < P; ++q) v[q] = y[(int64_t)q * Mp];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const float2 a = v[rb * RB + r];
+      const float2 a = y[(int64_t)(rb * RB + r) * Mp];  // (a register array indexed by rb would live in scratch)
 #pragma unroll
       for (int q = 0; q < P; ++q) {
         // a conj(v_q)
@@ -87,7 +87,157 @@ hipError_t launch_xe(const float2* Y, int64_t Tc, int F, int64_t Mp, double2* S,
   return hipGetLastError();
 }
 
+
+// Fused y-axis transform + X-engine, for P n_y <= 256 (m_y = 2 n_y, P m_y <= 512).  Input: the x-axis front
+// pass' output Y1[t][f][p][kappa_x][i_y] (complex float32).  A work-group owns R = 256 / (P n_y) rows kappa_x
+// of one channel, 256 threads.  Per sample:
+//   load   thread (row, p, i_y) brings one input value (eight samples ahead in registers) into LDS;
+//   y-DFT  the same thread forms outputs kappa_y = k and k + n_y (k = its i_y) of line (row, p) of the
+//          zero-padded m_y-point transform: with w = exp(-2 pi i / m_y), w^{(k + n_y) i} = (-1)^i w^{k i}, so
+//          the even- and odd-i partial sums E, O give E + O and E - O; the thread's n_y twiddles w^{k i} stay
+//          in registers (float32, from float64);
+//   pairs  thread (row, kappa_y, row block of 2 tiles) adds its 2 x P cross products.
+// Two barriers per two samples, LDS double-buffered.  Saves the y-axis front pass and the round trip of its
+// output through HBM.
+template <int P, int NY>
+__global__ __launch_bounds__(kXeThreads) void xengine_fused_kernel(const float2* __restrict__ Y1, int64_t Tc, int F,
+                                                                   int mx, const float2* __restrict__ twy,
+                                                                   double2* __restrict__ S, int accumulate) {
+  constexpr int MY = 2 * NY;
+  constexpr int UNITS = MY * (P / 2);  // pair-stage threads per row
+  constexpr int R = kXeThreads / UNITS;
+  static_assert(R * P * NY == kXeThreads, "one input value and one output pair per thread");
+  constexpr int kTb = 2;                              // samples per barrier pair
+  __shared__ float2 in_buf[2][kTb][kXeThreads];       // [row][p][i_y]
+  __shared__ float2 out_buf[2][kTb][2 * kXeThreads];  // [row][p][kappa_y]
+  const int tid = threadIdx.x;
+  const int f = blockIdx.y;
+  const int kx0 = blockIdx.x * R;
+  // (row, p, i_y) of this thread: its input value and its output pair (kappa_y = i_y, i_y + n_y)
+  const int er = tid / (P * NY), ep = (tid / NY) % P, ei = tid % NY;
+  const int64_t slab = (int64_t)P * mx * NY;
+  const int64_t in_off = ((int64_t)ep * mx + kx0 + er) * NY + ei;
+  float2 wk[NY];
+#pragma unroll
+  for (int i = 0; i < NY; ++i) wk[i] = twy[(ei * i) & (MY - 1)];
+  // pair-stage unit of this thread
+  const int ur = tid / UNITS, uk = (tid % UNITS) / (P / 2), rb = tid % (P / 2);
+  float2 acc[2][P];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[r][q] = make_float2(0.f, 0.f);
+  constexpr int kPf = 8;
+  float2 pf[kPf];
+#pragma unroll
+  for (int j = 0; j < kPf; ++j) pf[j] = j < Tc ? Y1[((int64_t)j * F + f) * slab + in_off] : make_float2(0.f, 0.f);
+  int b = 0;
+#pragma unroll 1
+  for (int64_t t = 0; t < Tc; t += kTb, b ^= 1) {
+    const int nt = (int)min<int64_t>(kTb, Tc - t);
+#pragma unroll
+    for (int s = 0; s < kTb; ++s) in_buf[b][s][tid] = pf[s];
+#pragma unroll
+    for (int j = 0; j < kPf - kTb; ++j) pf[j] = pf[j + kTb];
+#pragma unroll
+    for (int s = 0; s < kTb; ++s)
+      pf[kPf - kTb + s] = t + kPf + s < Tc ? Y1[((t + kPf + s) * F + f) * slab + in_off] : make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kTb; ++s) {
+      const float2* line = &in_buf[b][s][(er * P + ep) * NY];
+      float2 e = make_float2(0.f, 0.f), o = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int i = 0; i < NY; ++i) {
+        const float2 v = line[i];
+        float2& z = (i & 1) ? o : e;
+        z.x = fmaf(v.x, wk[i].x, fmaf(-v.y, wk[i].y, z.x));
+        z.y = fmaf(v.x, wk[i].y, fmaf(v.y, wk[i].x, z.y));
+      }
+      float2* dst = &out_buf[b][s][(er * P + ep) * MY + ei];
+      dst[0] = make_float2(e.x + o.x, e.y + o.y);
+      dst[NY] = make_float2(e.x - o.x, e.y - o.y);
+    }
+    __syncthreads();
+    for (int s = 0; s < nt; ++s) {
+      const float2* col = &out_buf[b][s][ur * P * MY + uk];
+      float2 v[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = col[q * MY];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const float2 a = col[(2 * rb + r) * MY];  // (a register array indexed by rb would live in scratch)
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          acc[r][q].x = fmaf(a.x, v[q].x, fmaf(a.y, v[q].y, acc[r][q].x));
+          acc[r][q].y = fmaf(a.y, v[q].x, fmaf(-a.x, v[q].y, acc[r][q].y));
+        }
+      }
+    }
+  }
+  const int64_t Mp = (int64_t)mx * MY;
+  const int64_t kappa = (int64_t)(kx0 + ur) * MY + uk;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int p = 2 * rb + r;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      double2* sp = S + (((int64_t)f * P + p) * P + q) * Mp + kappa;
+      double2 o = make_double2((double)acc[r][q].x, (double)acc[r][q].y);
+      if (accumulate) {
+        const double2 old = *sp;
+        o.x += old.x;
+        o.y += old.y;
+      }
+      *sp = o;
+    }
+  }
+}
+
+template <int P, int NY>
+hipError_t launch_xf(const float2* Y1, int64_t Tc, int F, int mx, const float2* twy, double2* S, int accumulate,
+                     hipStream_t st) {
+  if constexpr (P * NY > kXeThreads || NY < 1) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int R = kXeThreads / (2 * NY * (P / 2));
+    if (mx % R != 0 || F < 1 || F > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((xengine_fused_kernel<P, NY>), dim3((unsigned)(mx / R), (unsigned)F), dim3(kXeThreads), 0, st,
+                       Y1, Tc, F, mx, twy, S, accumulate);
+    return hipGetLastError();
+  }
+}
+
+template <int P>
+hipError_t launch_xf_ny(const float2* Y1, int64_t Tc, int F, int mx, int ny, const float2* twy, double2* S,
+                        int accumulate, hipStream_t st) {
+  switch (ny) {
+    case 1: return launch_xf<P, 1>(Y1, Tc, F, mx, twy, S, accumulate, st);
+    case 2: return launch_xf<P, 2>(Y1, Tc, F, mx, twy, S, accumulate, st);
+    case 4: return launch_xf<P, 4>(Y1, Tc, F, mx, twy, S, accumulate, st);
+    case 8: return launch_xf<P, 8>(Y1, Tc, F, mx, twy, S, accumulate, st);
+    case 16: return launch_xf<P, 16>(Y1, Tc, F, mx, twy, S, accumulate, st);
+    case 32: return launch_xf<P, 32>(Y1, Tc, F, mx, twy, S, accumulate, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
+
+// The fused form applies when P n_y <= 256 (n_y a power of two up to 32).
+bool xengine_fused_ok(int P, int ny) { return P >= 2 && ny >= 1 && ny <= 32 && (ny & (ny - 1)) == 0 && P * ny <= kXeThreads; }
+
+hipError_t launch_xengine_fused(const float2* Y1, int64_t Tc, int F, int P, int mx, int ny, const float2* twy,
+                                double2* S, int accumulate, hipStream_t st) {
+  switch (P) {
+    case 2: return launch_xf_ny<2>(Y1, Tc, F, mx, ny, twy, S, accumulate, st);
+    case 4: return launch_xf_ny<4>(Y1, Tc, F, mx, ny, twy, S, accumulate, st);
+    case 8: return launch_xf_ny<8>(Y1, Tc, F, mx, ny, twy, S, accumulate, st);
+    case 16: return launch_xf_ny<16>(Y1, Tc, F, mx, ny, twy, S, accumulate, st);
+    case 32: return launch_xf_ny<32>(Y1, Tc, F, mx, ny, twy, S, accumulate, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_xengine(const float2* Y, int64_t Tc, int F, int P, int64_t Mp, double2* S, int accumulate,
                           hipStream_t st) {

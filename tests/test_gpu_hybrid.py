@@ -1,5 +1,8 @@
 """Parity of hybrid tiles (Sec. III; HIP, through the C ABI) with the oracle (oracle/hybrid.py).
 
+Cases run both forms of the pair stage: with the y-axis transform fused in (P m_y <= 512 and m_x a
+multiple of its rows per work-group) and as a separate front pass.
+
 Bar: per channel and tile pair, max over index differences of |C_gpu - C_oracle| relative to
 sqrt(C_pp[0] C_qq[0]) (the Cauchy-Schwarz bound of |C_pq|), <= 1e-5: the transforms and the per-cell
 cross-power sums are float32 within a chunk of samples, float64 across chunks and in the inverse.
@@ -49,6 +52,7 @@ CASES = [
     (8, 4, 16, "ci4", 11, 2),
     (16, 16, 16, "ci4", 8, 2),  # 16 tiles of 16 x 16
     (32, 2, 4, "ci8", 6, 1),
+    (32, 2, 16, "ci4", 5, 1),  # P m_y above 512: separate y-axis pass and pair stage
 ]
 
 
