@@ -108,9 +108,10 @@ __device__ __forceinline__ void short_dft(float2 (&z)[LT], int L, int r, int m, 
 }
 
 // One pass over one axis.  SRC: 0 = LDS working array, 1 = global voltage tile.
-// SINK: 0 = LDS working array (in place), 1 = LDS power array (|X|^2).
+// SINK: 0 = LDS working array (in place), 1 = LDS power array (|X|^2).  Inlined: as calls, the schedule
+// structs they take by reference and their register arrays went through per-lane scratch memory.
 template <int LT, int SRC, int SINK, int FMT, int NT>
-__device__ void run_pass_t(const PassP& ps, const AxisP& a, int rho0, const void* __restrict__ src, int64_t tile,
+__device__ __forceinline__ void run_pass_t(const PassP& ps, const AxisP& a, int rho0, const void* __restrict__ src, int64_t tile,
                            float2* W, float* Pw, const float2* __restrict__ tw) {
   const float2* twm = tw + a.tw_off;
   const int m = a.m, mmask = (m & (m - 1)) == 0 ? m - 1 : -1;
@@ -169,7 +170,7 @@ __device__ void run_pass_t(const PassP& ps, const AxisP& a, int rho0, const void
 }
 
 template <int SRC, int SINK, int FMT, int NT>
-__device__ void run_pass(const PassP& ps, const AxisP& a, int rho0, const void* __restrict__ src, int64_t tile,
+__device__ __forceinline__ void run_pass(const PassP& ps, const AxisP& a, int rho0, const void* __restrict__ src, int64_t tile,
                          float2* W, float* Pw, const float2* __restrict__ tw) {
   const int L = a.L;
   if (L <= 1)
