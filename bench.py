@@ -352,7 +352,7 @@ def bench_beams(omni, torch, w, raw, steps, warmup, main_ms, form="mixed"):
     out = {"workload": f"{w.name} beam-space: {w.level_dims[-1][0] * w.level_dims[-1][1]} pointings a block, "
            f"{form} form", "kernel": res["kernel"], "route": res["desc"]["arrays"][0]["beams"],
            "ms_per_call": round(res["ms"], 4), "value": w.antenna_samples() / (res["ms"] / 1e3),
-           "vs_hot_path_same_bytes": round(main_ms / res["ms"], 4),
+           "vs_hot_path_same_bytes": round(main_ms / res["ms"], 4) if main_ms == main_ms else None,
            "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                         "frac": round(achieved / peak, 4), "algorithmic_flops_per_antenna_sample": per_as,
                         "note": "variant's own work over the whole call time"}}
