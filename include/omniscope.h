@@ -317,10 +317,11 @@ int omni_stage_times(omni_plan_t plan, int32_t stage, int32_t max, float* ms, in
  * channel, Y = gains[n][k] X[n][t][k]; real and imaginary parts rounded to
  * the nearest integer (ties to even) and clipped to [-7, 7] (ci4) or
  * [-127, 127] (ci8); written in the correlator's sample layout [t][k][n]
- * (the corner turn).  The transform runs in float32 on the matrix cores
- * (float16 operands, the DFT matrix split into float16 hi + lo parts): a
- * code can differ from the exact value's by one only where the exact value
- * lies within the float32 error (about 1e-5 of sum_j |raw| |gain|) of a
+ * (the corner turn).  The transform runs on the int8 matrix cores: the
+ * samples times a three-part int8 split of the DFT matrix (each coefficient
+ * within 6.1e-8), summed exactly in int32, combined and scaled in float32.
+ * A code can differ from the exact value's by one only where the exact value
+ * lies within that error (far below 1e-5 of sum_j |raw| |gain|) of a
  * rounding boundary.
  *   raw   : device int8 [N][2 F T], 16-byte aligned.
  *   N, T  : antennas (>= 1) and blocks (time samples of the output, >= 0).

@@ -47,6 +47,11 @@ COMMON = [
 ]
 
 
+# Per-source extra flags.  fengine.hip: keep matrix-core results in ordinary VGPRs (its int32 accumulators are
+# read by vector code right after each block; in accumulation registers every value costs one extra move).
+EXTRA = {"fengine.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _local_includes(path: str, seen: set) -> set:
     """The project headers `path` includes, directly or through other project headers."""
     for line in open(path):
@@ -68,7 +73,7 @@ def _compile(src: str, incremental: bool = False) -> str:
         if all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps):
             return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [hipcc(), *COMMON, *lang, "-c", src, "-o", obj]
+    cmd = [hipcc(), *COMMON, *EXTRA.get(os.path.basename(src), []), *lang, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -8,25 +8,39 @@
 //
 // The per-block transform is a dense contraction, X = W x with W[k][j] =
 // exp(-2 pi i j k / 2F), batched over antennas and blocks, so it runs on the
-// matrix cores: one real-embedded product per block on
-// v_mfma_f32_32x32x16_f16 with W on the A side (rows = Re and Im of 16 bins,
-// so an output's two parts land in one lane) and 32 antennas' samples on the
-// B side (columns), float16 operands (int8 samples are exact in float16; W is
-// split into float16 hi + lo parts) and float32 accumulation.  A vector-ALU FFT
-// of the same blocks would need about 20 ALU operations per sample and be
-// ALU-bound at well under the HBM rate; the product needs about
-// 4 x 2F flops a sample on the matrix cores, about level with the HBM time of
-// the 1 + 0.5 (or 1) bytes each sample moves.
+// matrix cores, and in integers: the samples are int8 already, so they are the
+// B operand of v_mfma_i32_32x32x32_i8 exactly as they sit in memory (no decode
+// at all), and W is split into three int8 parts,
+//   W ~= (h + (m + l / 254) / 254) / 127,  h = rint(127 W), m, l in [-127, 127],
+// each part's products summed exactly in int32 (|sum| <= 127 * 128 * 2F).  The
+// parts are combined once per output, X * 127 * 254^2 = 254^2 acc_h +
+// (254 acc_m + acc_l), with one float32 rounding; the split's own error is at
+// most 0.5 / (127 * 254^2) ~= 6e-8 per coefficient.  A wave's A fragments (W
+// rows = Re and Im of 16 bins, so an output's two parts land in one lane) stay
+// in registers for the whole time range.  An int8 product does the work of two
+// float16 ones per instruction, so the three parts cost 3/4 of the matrix-core
+// time of a float16 hi + lo split, and the samples skip the int8 -> float16
+// conversion that a float16 product needs (about 1.75 vector instructions a
+// sample, done once per wave, so four times per sample).
+//
+// Rounding and clipping use the float32 "magic number" form: adding
+// 1.5 * 2^23 rounds a value below 2^22 in magnitude to an integer, ties to
+// even, and leaves that integer in the low mantissa bits; the clip to
+// [-qmax, qmax] is a median of three in the same shifted domain (rounding is
+// monotone, so clipping after it is the same as clipping the rounded value).
+// The low 4 or 8 bits of the result are the code.
 //
 // Work-group: 256 threads, 4 waves; a wave owns 16 bins (output tile) of 64
-// antennas (two 32-column tiles) for every block of its time range.  Waves
-// split the F / 16 output tiles, the rest of the factor 4 goes to more antennas
-// (F = 64: 64 antennas a work-group; F = 16: 256).  The W fragments and the
-// lane's gains stay in registers and the W fragments in LDS for the whole time
-// range; samples go straight from HBM to registers (16-byte loads, the next
-// block's while the current one is transformed; each lane half reads alternate
-// 16-byte pieces of the block, and the W fragments follow the same sample
-// order).
+// antennas (two 32-column tiles, done one after the other) for every block of
+// its time range.  Waves split the F / 16 output tiles, the rest of the factor
+// 4 goes to more antennas (F = 64: 64 antennas a work-group; F = 16: 256).
+// Samples go straight from HBM to registers (16-byte loads, the next block's
+// while the current one is transformed); out-of-range antennas and the
+// prefetch past the last block read clamped, valid addresses, whose columns
+// are never stored.  Codes go through a per-wave LDS tile of 16 bins x 64
+// antennas so that each lane stores 16 contiguous bytes (rows of 64 antennas,
+// 64 or 128 bytes) when N is a multiple of 16 (ci4) or 8 (ci8) and the output
+// is 16-byte aligned; otherwise each lane stores its codes one by one.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -34,54 +48,40 @@
 namespace omni {
 namespace {
 
-typedef _Float16 fe_half8 __attribute__((ext_vector_type(8)));
-typedef _Float16 fe_half2 __attribute__((ext_vector_type(2)));
-typedef float fe_floatx16 __attribute__((ext_vector_type(16)));
+typedef int fe_int4 __attribute__((ext_vector_type(4)));
+typedef int fe_int16 __attribute__((ext_vector_type(16)));
 
 constexpr int kFeThreads = 256;
+constexpr float kFeMagic = 12582912.0f;          // 1.5 * 2^23
+constexpr float kFeScale = 1.0f / 8193532.0f;    // 1 / (127 * 254^2)
 
-// Sample order of the B operand: K-step s (16 samples), lane half h, element e -> sample j of the block.
-__device__ __forceinline__ int fe_sample(int s, int h, int e) { return 32 * (s >> 1) + 16 * h + 8 * (s & 1) + e; }
-
-// Two signed bytes of `w` (bytes b, b + 1) as exact float16: (1024 + (x + 128)) - 1152.
-__device__ __forceinline__ fe_half2 fe_bytes2(uint32_t x_flipped, uint32_t sel) {
-  const uint32_t p = __builtin_amdgcn_perm(0u, x_flipped, sel) | 0x64006400u;
-  const _Float16 b = (_Float16)1152.f;
-  const fe_half2 bias = {b, b};
-  return __builtin_bit_cast(fe_half2, p) - bias;
+// Ordering barrier for a wave reading LDS that other lanes of the same wave wrote (the LDS executes one
+// wave's accesses in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void fe_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void fe_unpack16(uint4 raw, fe_half8& a, fe_half8& b) {
-  const uint32_t w[4] = {raw.x ^ 0x80808080u, raw.y ^ 0x80808080u, raw.z ^ 0x80808080u, raw.w ^ 0x80808080u};
-  fe_half8 v[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const fe_half2 lo = fe_bytes2(w[2 * q + p], 0x0c010c00u);
-      const fe_half2 hi = fe_bytes2(w[2 * q + p], 0x0c030c02u);
-      v[q][4 * p + 0] = lo[0];
-      v[q][4 * p + 1] = lo[1];
-      v[q][4 * p + 2] = hi[0];
-      v[q][4 * p + 3] = hi[1];
-    }
-  }
-  a = v[0];
-  b = v[1];
+// Bit pattern of magic + rint(v) clipped to [-qmax, qmax]; its low bits are the two's-complement code.
+__device__ __forceinline__ uint32_t fe_code(float v, float qmax) {
+  const float y = v + kFeMagic;
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(y, kFeMagic - qmax, kFeMagic + qmax));
 }
 
-template <int F, bool CI8>
+template <int F, bool CI8, bool VEC>
 __global__ __launch_bounds__(kFeThreads) void fengine_kernel(const int8_t* __restrict__ raw, int64_t N, int64_t T,
                                                              int64_t t_per_chunk, const float2* __restrict__ gains,
                                                              uint8_t* __restrict__ out) {
-  constexpr int KS = F / 8;          // K-steps of 16 samples (2F samples a block)
+  constexpr int KS = F / 16;         // K-steps of 32 samples (2F samples a block)
   constexpr int TILES = F / 16;      // output tiles of 16 bins
   constexpr int CG = 4 / TILES;      // column groups of 64 antennas per work-group
   constexpr int ANT = 64 * CG;       // antennas per work-group
   constexpr int L = 2 * F;           // samples per block
-  __shared__ float2 tw[L];
-  // W fragments of every output tile: [tile][K-step][hi, lo][lane] (16 bytes each, conflict-free reads)
-  __shared__ fe_half8 wf[TILES * KS * 2 * 64];
+  constexpr int OB = CI8 ? 2 : 1;    // output bytes per code pair
+  __shared__ double tw[L][2];
+  // per wave: codes of 16 bins x 64 antennas, row-major (a row is 64 consecutive antennas of one bin)
+  __shared__ uint4 stage[4][64 * OB];
 
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int tile = w % TILES, cg = w / TILES;
@@ -89,123 +89,136 @@ __global__ __launch_bounds__(kFeThreads) void fengine_kernel(const int8_t* __res
   const int64_t t0 = (int64_t)blockIdx.y * t_per_chunk;
   const int64_t t1 = min(T, t0 + t_per_chunk);
 
-  // exp(-2 pi i q / 2F), q < 2F, from float64
-  for (int q = tid; q < L; q += kFeThreads) {
-    double s, c;
-    sincospi(-2.0 * (double)q / (double)L, &s, &c);
-    tw[q] = make_float2((float)c, (float)s);
-  }
+  // exp(-2 pi i q / 2F), q < 2F, in float64
+  for (int q = tid; q < L; q += kFeThreads) sincospi(-2.0 * (double)q / (double)L, &tw[q][1], &tw[q][0]);
   __syncthreads();
 
-  // W fragments (A operand): row col = 2 kk + comp (bin k = 16 tile + kk, comp 0 = Re, 1 = Im), samples of
-  // K-step s in the B operand's order; hi and lo parts.  Waves of column group 0 build their tile's.
-  if (cg == 0) {
+  // A fragments, three int8 parts: row col = 2 kk + comp (bin k = 16 tile + kk, comp 0 = Re, 1 = Im); within
+  // K-step s, lane half h, byte e -> sample 32 s + 16 h + e of the block (the B operand reads the same bytes).
+  fe_int4 wa[3][KS];
+  {
     const int kk = col >> 1, comp = col & 1, k = 16 * tile + kk;
-    for (int s = 0; s < KS; ++s) {
-      fe_half8 vh, vl;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = fe_sample(s, h, e);
-        const float2 z = tw[(j * k) % L];
-        const float v = comp ? z.y : z.x;
-        const _Float16 hi = (_Float16)v;
-        vh[e] = hi;
-        vl[e] = (_Float16)(v - (float)hi);
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        uint32_t ph = 0, pm = 0, pl = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = 32 * s + 16 * h + 4 * d + b;
+          const double a = 127.0 * tw[(j * k) % L][comp];
+          const double hv = rint(a);
+          const double r = (a - hv) * 254.0;
+          const double mv = rint(r);
+          const double lv = rint((r - mv) * 254.0);
+          ph |= (uint32_t)((int)hv & 0xFF) << (8 * b);
+          pm |= (uint32_t)((int)mv & 0xFF) << (8 * b);
+          pl |= (uint32_t)((int)lv & 0xFF) << (8 * b);
+        }
+        wa[0][s][d] = (int)ph;
+        wa[1][s][d] = (int)pm;
+        wa[2][s][d] = (int)pl;
       }
-      wf[((tile * KS + s) * 2 + 0) * 64 + l] = vh;
-      wf[((tile * KS + s) * 2 + 1) * 64 + l] = vl;
-    }
   }
-  __syncthreads();
-  const fe_half8* wt = wf + tile * KS * 2 * 64 + l;
 
-  // antennas of the lane's two column tiles, and their gains for the lane's 8 bins (j4, p):
-  // rows 8 j4 + 4 h + 2 p + {0, 1} -> bin kk = 4 j4 + 2 h + p
+  // antennas of the lane's two column tiles (loads clamped to a valid antenna), and their gains for the lane's
+  // 8 bins (j4, p), scaled by 1 / (127 * 254^2): rows 8 j4 + 4 h + 2 p + {0, 1} -> bin kk = 4 j4 + 2 h + p
   const int64_t n_base = (int64_t)blockIdx.x * ANT + 64 * cg;
   int64_t n[2];
   bool ok[2];
+  const int8_t* src[2];
   float2 g[2][8];
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     n[ct] = n_base + 32 * ct + col;
     ok[ct] = n[ct] < N;
+    src[ct] = raw + min(n[ct], N - 1) * (T * L) + 16 * h;
 #pragma unroll
     for (int j4 = 0; j4 < 4; ++j4)
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         const int k = 16 * tile + 4 * j4 + 2 * h + p;
-        g[ct][2 * j4 + p] = ok[ct] ? gains[n[ct] * F + k] : make_float2(0.f, 0.f);
+        const float2 gg = ok[ct] ? gains[n[ct] * F + k] : make_float2(0.f, 0.f);
+        g[ct][2 * j4 + p] = make_float2(gg.x * kFeScale, gg.y * kFeScale);
       }
   }
 
   const float qmax = CI8 ? 127.f : 7.f;
-  // raw samples of the lane for one block: KS / 2 16-byte pieces per column tile; the next block's pieces are
-  // loaded while the current block is transformed
-  uint4 cur[2][KS / 2], nxt[2][KS / 2];
-  auto load = [&](int64_t t, uint4 (&dst)[2][KS / 2]) {
+  uint8_t* const st_bytes = reinterpret_cast<uint8_t*>(stage[w]);
+
+  auto load = [&](int64_t t, fe_int4 (&dst)[2][KS]) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-      for (int sp = 0; sp < KS / 2; ++sp)
-        dst[ct][sp] = ok[ct] && t < t1
-                          ? *reinterpret_cast<const uint4*>(raw + n[ct] * (T * L) + t * L + 16 * h + 32 * sp)
-                          : make_uint4(0u, 0u, 0u, 0u);
+      for (int s = 0; s < KS; ++s) dst[ct][s] = *reinterpret_cast<const fe_int4*>(src[ct] + t * L + 32 * s);
   };
-  load(t0, cur);
-  for (int64_t t = t0; t < t1; ++t) {
-    load(t + 1, nxt);
-    // one accumulation chain per column tile (hi and lo parts of W in turn)
-    fe_floatx16 acc[2] = {};
-#pragma unroll
-    for (int sp = 0; sp < KS / 2; ++sp) {
-      const fe_half8 wh0 = wt[(4 * sp + 0) * 64], wl0 = wt[(4 * sp + 1) * 64];
-      const fe_half8 wh1 = wt[(4 * sp + 2) * 64], wl1 = wt[(4 * sp + 3) * 64];
-      fe_half8 a[2], b[2];
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) fe_unpack16(cur[ct][sp], a[ct], b[ct]);
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wh0, a[ct], acc[ct], 0, 0, 0);
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wl0, a[ct], acc[ct], 0, 0, 0);
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-        acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wh1, b[ct], acc[ct], 0, 0, 0);
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-        acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wl1, b[ct], acc[ct], 0, 0, 0);
-    }
+
+  auto block = [&](int64_t t, const fe_int4 (&b)[2][KS]) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
+      // one column tile's three accumulators live at a time (keeps the kernel at two waves a SIMD)
+      if (ct) __builtin_amdgcn_sched_barrier(0);
+      fe_int16 acc[3] = {};
 #pragma unroll
-      for (int sp = 0; sp < KS / 2; ++sp) cur[ct][sp] = nxt[ct][sp];
-      if (!ok[ct]) continue;
+      for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int j4 = 0; j4 < 4; ++j4) {
+        for (int q = 0; q < 3; ++q) acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa[q][s], b[ct][s], acc[q], 0, 0, 0);
+#pragma unroll
+      for (int j4 = 0; j4 < 4; ++j4)
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
           const int i = 4 * j4 + 2 * p;
-          const float xr = acc[ct][i], xi = acc[ct][i + 1];
+          const float xr = fmaf((float)acc[0][i], 64516.f, (float)(__mul24(acc[1][i], 254) + acc[2][i]));
+          const float xi = fmaf((float)acc[0][i + 1], 64516.f, (float)(__mul24(acc[1][i + 1], 254) + acc[2][i + 1]));
           const float2 gg = g[ct][2 * j4 + p];
-          const float yr = gg.x * xr - gg.y * xi;
-          const float yi = gg.x * xi + gg.y * xr;
-          const int cr = (int)fminf(qmax, fmaxf(-qmax, rintf(yr)));
-          const int ci = (int)fminf(qmax, fmaxf(-qmax, rintf(yi)));
-          const int k = 16 * tile + 4 * j4 + 2 * h + p;
-          const int64_t o = (t * F + k) * N + n[ct];
-          if (CI8) {
-            const uint16_t v = (uint16_t)((uint8_t)(int8_t)cr | ((uint16_t)(uint8_t)(int8_t)ci << 8));
-            *reinterpret_cast<uint16_t*>(out + 2 * o) = v;
-          } else {
-            out[o] = (uint8_t)(((cr & 0xF) << 4) | (ci & 0xF));
+          const uint32_t cr = fe_code(gg.x * xr - gg.y * xi, qmax);
+          const uint32_t ci = fe_code(gg.x * xi + gg.y * xr, qmax);
+          const int kk = 4 * j4 + 2 * h + p;
+          if (VEC) {
+            if (CI8)
+              reinterpret_cast<uint16_t*>(st_bytes)[kk * 64 + 32 * ct + col] = (uint16_t)((cr & 0xFFu) | (ci << 8));
+            else
+              st_bytes[kk * 64 + 32 * ct + col] = (uint8_t)((cr << 4) | (ci & 0xFu));
+          } else if (ok[ct]) {
+            const int64_t o = (t * F + 16 * tile + kk) * N + n[ct];
+            if (CI8)
+              *reinterpret_cast<uint16_t*>(out + 2 * o) = (uint16_t)((cr & 0xFFu) | (ci << 8));
+            else
+              out[o] = (uint8_t)((cr << 4) | (ci & 0xFu));
           }
         }
-      }
     }
+    if (VEC) {
+      fe_wave_sync();
+#pragma unroll
+      for (int c0 = 0; c0 < OB; ++c0) {
+        // 16-byte piece c of the tile: row c / (4 OB), antennas 16 / OB * (c % (4 OB)) ..
+        const int c = 64 * c0 + l;
+        const int row = c / (4 * OB), seg = c % (4 * OB);
+        const int64_t n0 = n_base + (16 / OB) * seg;
+        if (n0 < N)
+          *reinterpret_cast<uint4*>(out + OB * ((t * F + 16 * tile + row) * N + n0)) = stage[w][c];
+      }
+      fe_wave_sync();
+    }
+  };
+
+  fe_int4 bA[2][KS], bB[2][KS];
+  load(t0, bA);
+  int64_t t = t0;
+  for (; t + 1 < t1; t += 2) {
+    load(t + 1, bB);
+    block(t, bA);
+    load(min(t + 2, t1 - 1), bA);
+    block(t + 1, bB);
   }
+  if (t < t1) block(t, bA);
 }
 
 template <int F, bool CI8>
 hipError_t launch_fe(const int8_t* raw, int64_t N, int64_t T, const float2* gains, uint8_t* out, hipStream_t st) {
+  // 16-byte row pieces need rows that start on 16 bytes: N a multiple of 16 / (bytes a code pair), aligned output
+  const bool vec = N % (CI8 ? 8 : 16) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
   constexpr int ANT = 64 * (4 / (F / 16));
   const int64_t groups = (N + ANT - 1) / ANT;
   // about 2048 work-groups (8 a CU), at least 4 blocks each
@@ -213,8 +226,12 @@ hipError_t launch_fe(const int8_t* raw, int64_t N, int64_t T, const float2* gain
   const int64_t tpc = (T + chunks - 1) / chunks;
   chunks = (T + tpc - 1) / tpc;
   if (groups > INT32_MAX || chunks > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fengine_kernel<F, CI8>), dim3((unsigned)groups, (unsigned)chunks), dim3(kFeThreads), 0, st,
-                     raw, N, T, tpc, gains, out);
+  if (vec)
+    hipLaunchKernelGGL((fengine_kernel<F, CI8, true>), dim3((unsigned)groups, (unsigned)chunks), dim3(kFeThreads), 0,
+                       st, raw, N, T, tpc, gains, out);
+  else
+    hipLaunchKernelGGL((fengine_kernel<F, CI8, false>), dim3((unsigned)groups, (unsigned)chunks), dim3(kFeThreads), 0,
+                       st, raw, N, T, tpc, gains, out);
   return hipGetLastError();
 }
 

@@ -2,11 +2,12 @@
 Appendix A steps 2-3), and the F-engine feeding the correlator.
 
 Bar: the codes are integers decided by rounding float values, so they must equal the oracle's
-except where the exact (float64) value lies within the float32 transform's error of a rounding
-boundary; there either neighbouring code is a correct result.  The bound used per element is
-eps = |gain| * 1e-5 * sum_j |raw_j| + 1e-6 * |Y| (the float32 products and sums of a 2F-term
-DFT with float16 hi + lo coefficients stay far inside it).  Every other code is bit-exact, and
-near-boundary codes are rare (checked).
+except where the exact (float64) value lies within the kernel's error of a rounding boundary;
+there either neighbouring code is a correct result.  The bound used per element is
+eps = |gain| * 1e-5 * sum_j |raw_j| + 1e-6 * |Y|: the kernel's products and sums are exact int32
+ones of int8 samples and a three-part int8 split of the DFT coefficients (at most 6.1e-8 off
+each), followed by a few float32 roundings of the output, so its error stays far inside that.
+Every other code is bit-exact, and near-boundary codes are rare (checked).
 """
 
 import math
@@ -70,14 +71,16 @@ def check_codes(out_gpu, raw, F, gains, dtype):
     return got
 
 
+@pytest.mark.parametrize("N", [300, 336])
 @pytest.mark.parametrize("F", [16, 32, 64])
 @pytest.mark.parametrize("dtype", ["ci4", "ci8"])
-def test_fengine_matches_oracle(F, dtype):
-    """Ragged antenna count (masked lanes), several work-group time chunks."""
-    N, T = 300, 9
+def test_fengine_matches_oracle(F, dtype, N):
+    """Ragged antenna counts (masked lanes): 300 takes the code-by-code stores, 336 (a multiple of 16, not of
+    a work-group's antennas) the 16-byte row stores with a partly valid last group; several time chunks."""
+    T = 9
     raw = make_raw(N, F, T, seed=F)
     gains = make_gains(N, F, dtype, seed=F)
-    say(f"[fengine] case F={F} {dtype}")
+    say(f"[fengine] case F={F} {dtype} N={N}")
     out = omni.fengine(raw.cuda(), F, gains.cuda(), dtype)
     torch.cuda.synchronize()
     check_codes(out, raw, F, gains, dtype)
@@ -96,17 +99,19 @@ def test_fengine_clipping_and_extremes():
     assert (np.abs(got.real) == 7).any()
 
 
-def test_fengine_large_T_and_N():
+@pytest.mark.parametrize("dtype", ["ci4", "ci8"])
+def test_fengine_large_T_and_N(dtype):
     """A size with many work-groups and time chunks: 4096 antennas, 512 blocks of 128 samples (sampled check
     of 64 antennas against the oracle, since the layout and every code path are the same)."""
     F, N, T = 64, 4096, 512
     raw = make_raw(N, F, T, seed=5)
-    gains = make_gains(N, F, "ci4", seed=5)
-    out = omni.fengine(raw.cuda(), F, gains.cuda(), "ci4")
+    gains = make_gains(N, F, dtype, seed=5)
+    say(f"[fengine] large case {dtype}")
+    out = omni.fengine(raw.cuda(), F, gains.cuda(), dtype)
     torch.cuda.synchronize()
     idx = torch.arange(0, N, 64)
     sub_out = out[:, :, idx].contiguous()
-    check_codes(sub_out, raw[idx].contiguous(), F, gains[idx].contiguous(), "ci4")
+    check_codes(sub_out, raw[idx].contiguous(), F, gains[idx].contiguous(), dtype)
 
 
 def test_fengine_feeds_the_correlator():
