@@ -9,11 +9,23 @@
 // which the inverse transform (finalize.hip) turns into the cross-correlation
 // of tiles p and q over index differences (C_pp is tile p's own hypercube).
 //
-// xengine_kernel: a thread owns one cell kappa and a block of RB tiles p
-// (rows) against all P tiles q (columns), RB x P complex float32 sums over the
-// chunk's samples, then one float64 read-modify-write of S.  The row-block
-// threads of one cell are adjacent lanes, so the P loads of a cell and sample
-// are shared through the cache; consecutive cells are consecutive addresses.
+// Only the Hermitian half of the pairs is summed: S_qp[kappa] =
+// conj(S_pq[kappa]) at the same cell, so the other half is written as the
+// conjugate.  A thread with row block rb (rows p = 2 rb + r, r = 0, 1) takes
+// the pairs (p, (p + d) mod P) for d = 0 .. P/2: each unordered pair is then
+// one thread's exactly once (offset d and P - d name the same pair, and only
+// d <= P/2 is taken), except d = P/2, which rows p and p + P/2 would both take
+// and only p < P/2 keeps.  Every thread does P + 2 pair sums (one of them
+// dropped in half the threads) instead of 2 P, and touches the P/2 + 2 tiles
+// q = 2 rb + e mod P, e = 0 .. P/2 + 1, so every register index is a
+// compile-time constant.
+//
+// xengine_kernel: a thread owns one cell kappa and a row block, its P + 2
+// complex float32 sums over the chunk's samples, then float64
+// read-modify-writes of S (the pair and, off the diagonal, its conjugate).
+// The row-block threads of one cell are adjacent lanes, so the loads of a cell
+// and sample are shared through the cache; consecutive cells are consecutive
+// addresses.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,52 +35,75 @@ namespace {
 
 constexpr int kXeThreads = 256;
 
-template <int P, int RB>
+// The P/2 + 1 pair sums of row r of a row block: acc[r][d] += t_r conj(t_{r + d}), t_e = Y of tile 2 rb + e mod P.
+template <int P>
+__device__ __forceinline__ void half_pairs_add(float2 (&acc)[2][P / 2 + 1], const float2 (&v)[P / 2 + 2]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const float2 a = v[r];
+#pragma unroll
+    for (int d = 0; d <= P / 2; ++d) {
+      const float2 b = v[r + d];
+      acc[r][d].x = fmaf(a.x, b.x, fmaf(a.y, b.y, acc[r][d].x));
+      acc[r][d].y = fmaf(a.y, b.x, fmaf(-a.x, b.y, acc[r][d].y));
+    }
+  }
+}
+
+// Adds the row block's sums into S[f][p][q][kappa] (element stride Mp between (p, q) planes), and their conjugates
+// into S[f][q][p][kappa] off the diagonal; the duplicate d = P/2 of rows p >= P/2 is dropped.
+template <int P>
+__device__ __forceinline__ void half_pairs_store(const float2 (&acc)[2][P / 2 + 1], int rb, double2* Sf, int64_t Mp,
+                                                 int64_t kappa, int accumulate) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int p = 2 * rb + r;
+#pragma unroll
+    for (int d = 0; d <= P / 2; ++d) {
+      if (d == P / 2 && p >= P / 2) continue;
+      const int q = (p + d) & (P - 1);
+#pragma unroll
+      for (int c = 0; c < (d ? 2 : 1); ++c) {
+        double2* sp = Sf + ((int64_t)(c ? q : p) * P + (c ? p : q)) * Mp + kappa;
+        double2 o = make_double2((double)acc[r][d].x, c ? -(double)acc[r][d].y : (double)acc[r][d].y);
+        if (accumulate) {
+          const double2 old = *sp;
+          o.x += old.x;
+          o.y += old.y;
+        }
+        *sp = o;
+      }
+    }
+  }
+}
+
+template <int P>
 __global__ __launch_bounds__(kXeThreads) void xengine_kernel(const float2* __restrict__ Y, int64_t Tc, int F,
                                                              int64_t Mp, double2* __restrict__ S, int accumulate) {
-  constexpr int NRB = P / RB;           // row blocks per cell
+  constexpr int NRB = P / 2;               // row blocks per cell
   constexpr int CELLS = kXeThreads / NRB;  // cells per work-group
+  constexpr int E = P / 2 + 2;             // tiles a row block touches
   const int tid = threadIdx.x;
   const int rb = tid % NRB;
   const int64_t kappa = (int64_t)blockIdx.x * CELLS + tid / NRB;
   const int f = blockIdx.y;
   if (kappa >= Mp) return;
-  float2 acc[RB][P];
+  int64_t off[E];
 #pragma unroll
-  for (int r = 0; r < RB; ++r)
+  for (int e = 0; e < E; ++e) off[e] = (int64_t)((2 * rb + e) & (P - 1)) * Mp;
+  float2 acc[2][P / 2 + 1];
 #pragma unroll
-    for (int q = 0; q < P; ++q) acc[r][q] = make_float2(0.f, 0.f);
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int d = 0; d <= P / 2; ++d) acc[r][d] = make_float2(0.f, 0.f);
   for (int64_t t = 0; t < Tc; ++t) {
     const float2* y = Y + ((t * F + f) * (int64_t)P) * Mp + kappa;
-    float2 v[P];
+    float2 v[E];
 #pragma unroll
-    for (int q = 0; q < P; ++q) v[q] = y[(int64_t)q * Mp];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const float2 a = y[(int64_t)(rb * RB + r) * Mp];  // (a register array indexed by rb would live in scratch)
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        // a conj(v_q)
-        acc[r][q].x = fmaf(a.x, v[q].x, fmaf(a.y, v[q].y, acc[r][q].x));
-        acc[r][q].y = fmaf(a.y, v[q].x, fmaf(-a.x, v[q].y, acc[r][q].y));
-      }
-    }
+    for (int e = 0; e < E; ++e) v[e] = y[off[e]];
+    half_pairs_add<P>(acc, v);
   }
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    const int p = rb * RB + r;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      double2* s = S + (((int64_t)f * P + p) * P + q) * Mp + kappa;
-      double2 o = make_double2((double)acc[r][q].x, (double)acc[r][q].y);
-      if (accumulate) {
-        const double2 old = *s;
-        o.x += old.x;
-        o.y += old.y;
-      }
-      *s = o;
-    }
-  }
+  half_pairs_store<P>(acc, rb, S + (int64_t)f * P * P * Mp, Mp, kappa, accumulate);
 }
 
 __global__ void narrow_kernel(const double2* __restrict__ src, float2* __restrict__ dst, int64_t n) {
@@ -78,12 +113,11 @@ __global__ void narrow_kernel(const double2* __restrict__ src, float2* __restric
 
 template <int P>
 hipError_t launch_xe(const float2* Y, int64_t Tc, int F, int64_t Mp, double2* S, int accumulate, hipStream_t st) {
-  constexpr int RB = P >= 2 ? 2 : 1;
-  constexpr int CELLS = kXeThreads / (P / RB);
+  constexpr int CELLS = kXeThreads / (P / 2);
   const int64_t blocks = (Mp + CELLS - 1) / CELLS;
   if (blocks > INT32_MAX || F < 1 || F > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((xengine_kernel<P, RB>), dim3((unsigned)blocks, (unsigned)F), dim3(kXeThreads), 0, st, Y, Tc,
-                     F, Mp, S, accumulate);
+  hipLaunchKernelGGL((xengine_kernel<P>), dim3((unsigned)blocks, (unsigned)F), dim3(kXeThreads), 0, st, Y, Tc, F,
+                     Mp, S, accumulate);
   return hipGetLastError();
 }
 
@@ -96,7 +130,7 @@ hipError_t launch_xe(const float2* Y, int64_t Tc, int F, int64_t Mp, double2* S,
 //          zero-padded m_y-point transform: with w = exp(-2 pi i / m_y), w^{(k + n_y) i} = (-1)^i w^{k i}, so
 //          the even- and odd-i partial sums E, O give E + O and E - O; the thread's n_y twiddles w^{k i} stay
 //          in registers (float32, from float64);
-//   pairs  thread (row, kappa_y, row block of 2 tiles) adds its 2 x P cross products.
+//   pairs  thread (row, kappa_y, row block of 2 tiles) adds its P + 2 cross products (the Hermitian half).
 // Two barriers per two samples, LDS double-buffered.  Saves the y-axis front pass and the round trip of its
 // output through HBM.
 template <int P, int NY>
@@ -120,13 +154,17 @@ __global__ __launch_bounds__(kXeThreads) void xengine_fused_kernel(const float2*
   float2 wk[NY];
 #pragma unroll
   for (int i = 0; i < NY; ++i) wk[i] = twy[(ei * i) & (MY - 1)];
-  // pair-stage unit of this thread
+  // pair-stage unit of this thread: cell (row ur, kappa_y = uk), row block rb; LDS offsets of the tiles it touches
   const int ur = tid / UNITS, uk = (tid % UNITS) / (P / 2), rb = tid % (P / 2);
-  float2 acc[2][P];
+  constexpr int E = P / 2 + 2;
+  int off[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) off[e] = (ur * P + ((2 * rb + e) & (P - 1))) * MY + uk;
+  float2 acc[2][P / 2 + 1];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int q = 0; q < P; ++q) acc[r][q] = make_float2(0.f, 0.f);
+    for (int d = 0; d <= P / 2; ++d) acc[r][d] = make_float2(0.f, 0.f);
   constexpr int kPf = 8;
   float2 pf[kPf];
 #pragma unroll
@@ -160,38 +198,16 @@ __global__ __launch_bounds__(kXeThreads) void xengine_fused_kernel(const float2*
     }
     __syncthreads();
     for (int s = 0; s < nt; ++s) {
-      const float2* col = &out_buf[b][s][ur * P * MY + uk];
-      float2 v[P];
+      const float2* plane = out_buf[b][s];
+      float2 v[E];
 #pragma unroll
-      for (int q = 0; q < P; ++q) v[q] = col[q * MY];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const float2 a = col[(2 * rb + r) * MY];  // (a register array indexed by rb would live in scratch)
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-          acc[r][q].x = fmaf(a.x, v[q].x, fmaf(a.y, v[q].y, acc[r][q].x));
-          acc[r][q].y = fmaf(a.y, v[q].x, fmaf(-a.x, v[q].y, acc[r][q].y));
-        }
-      }
+      for (int e = 0; e < E; ++e) v[e] = plane[off[e]];
+      half_pairs_add<P>(acc, v);
     }
   }
   const int64_t Mp = (int64_t)mx * MY;
   const int64_t kappa = (int64_t)(kx0 + ur) * MY + uk;
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int p = 2 * rb + r;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      double2* sp = S + (((int64_t)f * P + p) * P + q) * Mp + kappa;
-      double2 o = make_double2((double)acc[r][q].x, (double)acc[r][q].y);
-      if (accumulate) {
-        const double2 old = *sp;
-        o.x += old.x;
-        o.y += old.y;
-      }
-      *sp = o;
-    }
-  }
+  half_pairs_store<P>(acc, rb, S + (int64_t)f * P * P * Mp, Mp, kappa, accumulate);
 }
 
 template <int P, int NY>
