@@ -154,8 +154,10 @@ __global__ __launch_bounds__(kXeThreads) void xengine_fused_kernel(const float2*
   float2 wk[NY];
 #pragma unroll
   for (int i = 0; i < NY; ++i) wk[i] = twy[(ei * i) & (MY - 1)];
-  // pair-stage unit of this thread: cell (row ur, kappa_y = uk), row block rb; LDS offsets of the tiles it touches
-  const int ur = tid / UNITS, uk = (tid % UNITS) / (P / 2), rb = tid % (P / 2);
+  // pair-stage unit of this thread: cell (row ur, kappa_y = uk), row block rb; LDS offsets of the tiles it touches.
+  // kappa_y runs fastest over the lanes, so a read of tile e by 32 lanes is 256 contiguous bytes (with the row
+  // block fastest, the lanes' tiles were 2 MY values apart: every lane of a read in the same banks).
+  const int ur = tid / UNITS, rb = (tid % UNITS) / MY, uk = tid % MY;
   constexpr int E = P / 2 + 2;
   int off[E];
 #pragma unroll
