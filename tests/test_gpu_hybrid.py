@@ -53,6 +53,9 @@ CASES = [
     (16, 16, 16, "ci4", 8, 2),  # 16 tiles of 16 x 16
     (32, 2, 4, "ci8", 6, 1),
     (32, 2, 16, "ci4", 5, 1),  # P m_y above 512: separate y-axis pass and pair stage
+    (4, 16, 2, "ci8", 12, 2),  # n_y = 2: the y-axis DFT on the vector units (n_y = 4 .. 16 use the matrix cores)
+    (8, 16, 1, "ci4", 10, 2),  # n_y = 1
+    (8, 2, 32, "ci4", 7, 1),  # n_y = 32, P n_y = 256: vector-unit y-axis DFT inside the pair stage
 ]
 
 
