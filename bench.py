@@ -361,8 +361,9 @@ def bench_beams(omni, torch, w, raw, steps, warmup, main_ms, form="mixed"):
 
 def bench_hybrid(omni, torch, steps, warmup, P=16, nx=16, ny=16, F=64, T=2048):
     """Hybrid tiles (Sec. III): P tiles of nx x ny antennas (the 16x16-of-16x16 array's antennas, N = 4096 x P/16)
-    at arbitrary offsets, 4-bit samples.  Work counted: the pair stage's P^2 complex multiply-adds (8 flops) per
-    Fourier cell (m = 2n per axis), channel and sample; it runs on the vector ALUs in float32."""
+    at arbitrary offsets, 4-bit samples.  Work counted: the pair stage's P (P + 1) / 2 distinct tile pairs (the
+    other half is their conjugate), one complex multiply-add (8 flops) each per Fourier cell (m = 2n per axis),
+    channel and sample; it runs on the vector ALUs in float32."""
     gen = torch.Generator(device="cuda").manual_seed(20090840)
     N = P * nx * ny
     re = torch.randint(-7, 8, (T, F, N), generator=gen, device="cuda", dtype=torch.int16)
@@ -381,7 +382,7 @@ def bench_hybrid(omni, torch, steps, warmup, P=16, nx=16, ny=16, F=64, T=2048):
     e.record()
     e.synchronize()
     ms = b.elapsed_time(e) / steps
-    flops = 8.0 * P * P * (4 * nx * ny) * F * T
+    flops = 8.0 * (P * (P + 1) // 2) * (4 * nx * ny) * F * T
     tfs = flops / (ms / 1e3) / 1e12
     del raw, out, h
     return {"P": P, "tile": [nx, ny], "N": N, "F": F, "T": T, "ms_per_call": round(ms, 4),
