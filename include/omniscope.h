@@ -21,6 +21,12 @@
  *   - Every call returns OMNI_OK (0) or a negative omni_status.  No C++
  *     exception crosses this boundary.  omni_last_error() gives a message for
  *     the most recent failure on the calling thread.
+ *   - Diagnostics: the environment variable OMNI_LOG_LEVEL (read once per
+ *     process) makes the library write to stderr: 1 = every failure as it is
+ *     returned, 2 = also each new plan's description and every autotuner
+ *     decision.  Unset or 0: silent.  The main entry points (plan, correlate,
+ *     direct, F-engine, hybrid, fold) push a roctx range named after the call
+ *     (rocprofv3 --marker-trace records them).
  *   - Axis order: axis 2l is level l's x index, axis 2l+1 its y index, levels
  *     in the caller's order (outermost first is the natural choice).  The
  *     antenna index a of a voltage sample is row-major over these axes.

@@ -3,8 +3,10 @@
 #include "omniscope.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <cstdarg>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -76,10 +78,39 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// OMNI_LOG_LEVEL (environment, read once): 0 or unset = silent, 1 = every error a call returns, 2 = also each
+// plan's description and every autotuner decision.  Lines go to stderr, prefixed "omniscope:".
+int log_level() {
+  static const int level = [] {
+    const char* e = std::getenv("OMNI_LOG_LEVEL");
+    return e ? std::atoi(e) : 0;
+  }();
+  return level;
+}
+
+void log_msg(int level, const char* fmt, ...) {
+  if (log_level() < level) return;
+  char line[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(line, sizeof line, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "omniscope: %s\n", line);
+}
+
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
+  log_msg(1, "error %d: %s", code, msg.c_str());
   return code;
 }
+
+// A roctx range (shown by rocprofv3 --marker-trace) around an entry point.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 constexpr int kNT = 256;              // threads per fused work-group
 constexpr int kMaxCPT = 32;           // Fourier cells per thread
@@ -1108,6 +1139,7 @@ int tune_sliced(omni_plan_s* p, ArrayPlan& ap) {
   if (p->tune == OMNI_TUNE_CACHE && tune_cache_lookup(p->tune_cache, key, &c_tb, &c_wg) && c_tb > 0 && c_wg > 0) {
     ap.tb = c_tb;
     ap.wg_target = c_wg;
+    log_msg(2, "autotuner: %s -> block %d, work-group target %d (from the cache)", key.c_str(), c_tb, c_wg);
     return OMNI_OK;
   }
   const size_t bytes_t = (size_t)ap.F * (size_t)ap.N * sample_bytes(p->dtype);
@@ -1156,6 +1188,8 @@ int tune_sliced(omni_plan_s* p, ArrayPlan& ap) {
   ap.wg_target = best_wg;
   ap.tuned_ms = best;
   tune_cache_store(p->tune_cache, key, best_tb, best_wg, best);
+  log_msg(2, "autotuner: %s -> block %d, work-group target %d (%.3f ms on %lld samples)", key.c_str(), best_tb,
+          best_wg, best, (long long)Tt);
   return OMNI_OK;
 }
 
@@ -1228,6 +1262,8 @@ int tune_array(omni_plan_s* p, ArrayPlan& ap) {
     ap.tuned_ms = best;
     HIP_TRY(hipMemcpy(ap.d_kmap, ap.fs.kmap.data(), ap.fs.kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (!cached) tune_cache_store(p->tune_cache, key, best_lc, best_wg, best);
+    log_msg(2, "autotuner: %s -> short-DFT cap %d, work-group target %d (%.3f ms)%s", key.c_str(), best_lc, best_wg,
+            best, cached ? " (cached schedule re-timed)" : "");
   }
   return OMNI_OK;
 }
@@ -1398,6 +1434,13 @@ int make_plan(omni_plan_t* out, const std::vector<omni_array_desc>& arrays, cons
     }
   }
   *out = p;
+  if (log_level() >= 2) {
+    size_t need = 0;
+    omni_plan_describe(p, nullptr, 0, &need);
+    std::string d(need, '\0');
+    omni_plan_describe(p, d.data(), need, nullptr);
+    log_msg(2, "plan %s", d.c_str());
+  }
   return OMNI_OK;
 }
 
@@ -1532,6 +1575,7 @@ extern "C" {
 
 int omni_plan(omni_plan_t* out, int32_t levels, const int32_t* dims, const double* A, int32_t nchan,
               const omni_opts* opts) {
+  TraceRange range("omni_plan");
   try {
     omni_array_desc a{levels, dims, A, nchan};
     return make_plan(out, {a}, opts);
@@ -1541,6 +1585,7 @@ int omni_plan(omni_plan_t* out, int32_t levels, const int32_t* dims, const doubl
 }
 
 int omni_plan_batch(omni_plan_t* out, int32_t n_arrays, const omni_array_desc* arrays, const omni_opts* opts) {
+  TraceRange range("omni_plan_batch");
   try {
     if (n_arrays < 1 || !arrays) return fail(OMNI_E_INVAL, "need at least one array");
     return make_plan(out, std::vector<omni_array_desc>(arrays, arrays + n_arrays), opts);
@@ -1551,6 +1596,7 @@ int omni_plan_batch(omni_plan_t* out, int32_t n_arrays, const omni_array_desc* a
 
 int omni_correlate_batch(omni_plan_t plan, const void* const* volt, int64_t T, void* const* vis, void* stream,
                          uint32_t flags) {
+  TraceRange range("omni_correlate");
   try {
     if (!plan) return fail(OMNI_E_INVAL, "plan is NULL");
     if (plan->host_only) return fail(OMNI_E_STATE, "plan was made with OMNI_PLAN_HOST_ONLY");
@@ -1610,6 +1656,7 @@ int omni_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, voi
 }
 
 int omni_direct_correlate(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream) {
+  TraceRange range("omni_direct_correlate");
   try {
     int rc = direct_check_args(plan, volt, T, vis);
     if (rc) return rc;
@@ -1626,6 +1673,7 @@ int omni_direct_correlate(omni_plan_t plan, const void* volt, int64_t T, void* v
 }
 
 int omni_direct_correlate_noalloc(omni_plan_t plan, const void* volt, int64_t T, void* vis, void* stream) {
+  TraceRange range("omni_direct_correlate_noalloc");
   try {
     int rc = direct_check_args(plan, volt, T, vis);
     if (rc) return rc;
@@ -1867,6 +1915,7 @@ const char* omni_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int omni_fengine(const void* raw, int64_t N, int64_t T, int32_t F, const void* gains, int32_t dtype,
                             void* volt, void* stream) {
+  TraceRange range("omni_fengine");
   if (N < 1 || T < 0) return fail(OMNI_E_INVAL, "N must be >= 1 and T >= 0");
   if (F != 16 && F != 32 && F != 64) return fail(OMNI_E_SHAPE, "F-engine: F must be 16, 32 or 64 channels");
   if (dtype != OMNI_CI4 && dtype != OMNI_CI8) return fail(OMNI_E_INVAL, "F-engine output must be ci4 or ci8");
@@ -1946,6 +1995,7 @@ extern "C" {
 
 int omni_hybrid_plan(omni_hybrid_t* out, int32_t P, int32_t nx, int32_t ny, int32_t nchan, int32_t dtype,
                      const double* offsets, const double* A) {
+  TraceRange range("omni_hybrid_plan");
   if (!out) return fail(OMNI_E_INVAL, "NULL argument");
   *out = nullptr;
   if (P != 2 && P != 4 && P != 8 && P != 16 && P != 32) return fail(OMNI_E_SHAPE, "hybrid tiles: P must be 2, 4, 8, 16 or 32");
@@ -1984,6 +2034,7 @@ int omni_hybrid_plan(omni_hybrid_t* out, int32_t P, int32_t nx, int32_t ny, int3
 }
 
 int omni_hybrid_correlate(omni_hybrid_t h, const void* volt, int64_t T, void* vis, void* stream, uint32_t flags) {
+  TraceRange range("omni_hybrid_correlate");
   if (!h) return fail(OMNI_E_INVAL, "NULL hybrid plan");
   if (T < 0) return fail(OMNI_E_INVAL, "T < 0");
   if (T > 0 && !volt) return fail(OMNI_E_INVAL, "volt is NULL");
@@ -2163,6 +2214,7 @@ bool finite_positive(double v) { return std::isfinite(v) && v > 0.0; }
 extern "C" {
 
 int omni_fold_plan(omni_fold_t* out, omni_plan_t plan, int32_t array, const omni_fold_opts* opts) {
+  TraceRange range("omni_fold_plan");
   if (!out || !plan) return fail(OMNI_E_INVAL, "NULL argument");
   *out = nullptr;
   if (array < 0 || (size_t)array >= plan->arrays.size()) return fail(OMNI_E_INVAL, "array index out of range");
@@ -2236,6 +2288,7 @@ int omni_fold_shape(omni_fold_t fold, int64_t* ny, int64_t* nx, int64_t* nbins) 
 }
 
 int omni_fold(omni_fold_t fold, const void* vis, int32_t nchan, void* image, void* stream) {
+  TraceRange range("omni_fold");
   if (!fold || !vis || !image) return fail(OMNI_E_INVAL, "NULL argument");
   if (nchan < 1 || nchan > fold->F) return fail(OMNI_E_SHAPE, "nchan must be in [1, F] of the array");
   int cur = -1;
@@ -2249,6 +2302,7 @@ int omni_fold(omni_fold_t fold, const void* vis, int32_t nchan, void* image, voi
 
 int omni_baseline_profile(omni_fold_t fold, const void* image, int32_t nchan, void* map, void* hist, void* smooth,
                           void* stream) {
+  TraceRange range("omni_baseline_profile");
   if (!fold || !image) return fail(OMNI_E_INVAL, "NULL argument");
   if (smooth && !hist) return fail(OMNI_E_INVAL, "smooth needs hist");
   if (nchan < 1 || nchan > fold->F) return fail(OMNI_E_SHAPE, "nchan must be in [1, F] of the array");

@@ -304,3 +304,41 @@ def test_hybrid_plan_validates_before_any_device_call():
     assert st[rc] in ("OMNI_E_NODEV", "OMNI_OK")
     if rc == 0:
         omni.lib.omni_hybrid_destroy(h)
+
+
+def _run_with_log_level(level, code):
+    import subprocess
+    import sys
+
+    env = dict(os.environ)
+    if level is None:
+        env.pop("OMNI_LOG_LEVEL", None)
+    else:
+        env["OMNI_LOG_LEVEL"] = str(level)
+    return subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                          timeout=120)
+
+
+_LOG_PROBE = """
+import paper_0909_0001_amd as omni
+try:
+    omni.Plan([[0, 4]], None, 1, host_only=True)
+except omni.OmniError:
+    pass
+omni.Plan([[4, 4]], None, 1, host_only=True)
+print("done")
+"""
+
+
+def test_log_level_controls_stderr():
+    """OMNI_LOG_LEVEL: unset or 0 silent; 1 reports the returned error; 2 also the plan's description."""
+    quiet = _run_with_log_level(None, _LOG_PROBE)
+    assert quiet.returncode == 0 and "done" in quiet.stdout
+    assert "omniscope:" not in quiet.stderr
+    errors = _run_with_log_level(1, _LOG_PROBE)
+    assert errors.returncode == 0
+    lines = [ln for ln in errors.stderr.splitlines() if ln.startswith("omniscope:")]
+    assert len(lines) == 1 and "error" in lines[0]
+    verbose = _run_with_log_level(2, _LOG_PROBE)
+    plans = [ln for ln in verbose.stderr.splitlines() if ln.startswith("omniscope: plan {")]
+    assert len(plans) == 1 and '"arrays"' in plans[0]
