@@ -148,3 +148,21 @@ def test_fengine_argument_errors():
     out = omni.fengine(raw, 64, gains, "ci8")
     torch.cuda.synchronize()
     assert out.shape == (2, 64, 8, 2) and int(out.abs().max()) == 0
+
+
+@pytest.mark.parametrize("dtype", ["ci4", "ci8"])
+def test_fengine_bench_size_sampled(dtype):
+    """The bench's configuration (16384 antennas, T = 2048 blocks of 128 samples -> 64 channels; 16-byte row
+    stores, every work-group and time chunk of the launch): 48 antennas spread over the array, all blocks and
+    channels, against the oracle on those antennas' samples (each antenna's codes depend on its own samples
+    and gains only)."""
+    F, N, T = 64, 16384, 2048
+    gen = torch.Generator(device="cuda").manual_seed(31 if dtype == "ci4" else 32)
+    raw = torch.randint(-128, 128, (N, 2 * F * T), generator=gen, device="cuda", dtype=torch.int16).to(torch.int8)
+    gains = make_gains(N, F, dtype, seed=7, sigma=74.0).cuda()
+    say(f"[fengine] bench size {dtype}")
+    out = omni.fengine(raw, F, gains, dtype)
+    torch.cuda.synchronize()
+    idx = torch.cat([torch.arange(0, N, 409)[:40], torch.tensor([63, 64, 8191, 8192, 16320, 16383, 1, 127])])
+    sub_out = out[:, :, idx.cuda()].contiguous()
+    check_codes(sub_out, raw[idx.cuda()].cpu(), F, gains[idx.cuda()].cpu(), dtype)

@@ -112,3 +112,33 @@ def test_hybrid_argument_errors():
         h.correlate(torch.zeros((3, 1, 31, 2), dtype=torch.int8, device="cuda"))
     with pytest.raises(ValueError):
         h.correlate(torch.zeros((3, 1, 32), dtype=torch.uint8, device="cuda"))
+
+
+def test_hybrid_bench_size_sampled():
+    """The bench's configuration (16 tiles of 16 x 16, F = 64, T = 2048, 4-bit, 8 chunks of samples): every tile
+    pair of two channels for three tile pairs against the oracle run on just those two tiles (a pair's
+    correlation depends on its two tiles' samples only), the diagonal blocks included."""
+    P, nx, ny, F, T = 16, 16, 16, 64, 2048
+    N = P * nx * ny
+    gen = torch.Generator(device="cuda").manual_seed(20260)
+    re = torch.randint(-7, 8, (T, F, N), generator=gen, device="cuda", dtype=torch.int16)
+    im = torch.randint(-7, 8, (T, F, N), generator=gen, device="cuda", dtype=torch.int16)
+    raw = ((re & 0xF) << 4 | (im & 0xF)).to(torch.uint8)
+    del re, im
+    say("[hybrid] bench size: 16 tiles of 16x16, F=64, T=2048")
+    h = omni.Hybrid(P, nx, ny, F, "ci4")
+    vis = h.correlate(raw)
+    torch.cuda.synchronize()
+    M = nx * ny
+    for f in (0, 37):
+        for p, q in ((0, 1), (5, 12), (15, 3)):
+            cols = torch.cat([torch.arange(p * M, (p + 1) * M), torch.arange(q * M, (q + 1) * M)]).cuda()
+            sub = raw[:, f:f + 1, :].index_select(2, cols).cpu().numpy()
+            x = oracle.decode(sub, "ci4", T, 1, 2 * M)
+            ref = hybrid.tile_cross_correlations(x, 2, nx, ny)  # [1, 2, 2, 31, 31]
+            idx = torch.tensor([p, q]).cuda()
+            got = vis[f:f + 1].index_select(1, idx).index_select(2, idx).cpu().numpy()
+            err = pair_err(got, ref, nx, ny)
+            say(f"[hybrid] bench size f={f} tiles ({p},{q}): err {err:.3g}")
+            assert err <= 1e-5
+    h.close()
