@@ -151,23 +151,27 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
       }
     };
     if constexpr (R == 2) {
-      // n = L: both residues use the same inputs, z_j = w_m^{rho j} x_j; one thread does both
-      float2 x[V][L], z[V][L];
+      // n = L: both residues use the same inputs, z_j = w_m^{rho j} x_j; one thread does both.  The inputs are
+      // loaded again for the second residue (from the cache) rather than kept: holding them cost 4 V L registers
+      // and a wave per SIMD of this memory-bound pass.
+      float2 z[V][L];
 #pragma unroll
       for (int j = 0; j < L; ++j) {
         float2 xv[V];
         ld(j, xv);
 #pragma unroll
-        for (int v = 0; v < V; ++v) x[v][j] = z[v][j] = xv[v];
+        for (int v = 0; v < V; ++v) z[v][j] = xv[v];
       }
 #pragma unroll
       for (int v = 0; v < V; ++v) sd::dft<L>(z[v]);
       store(z, 0);
 #pragma unroll
       for (int j = 0; j < L; ++j) {
+        float2 xv[V];
+        ld(j, xv);
         const float2 w = twm[j];  // w_m^j
 #pragma unroll
-        for (int v = 0; v < V; ++v) z[v][j] = j ? cmul(x[v][j], w) : x[v][j];
+        for (int v = 0; v < V; ++v) z[v][j] = j ? cmul(xv[v], w) : xv[v];
       }
 #pragma unroll
       for (int v = 0; v < V; ++v) sd::dft<L>(z[v]);
