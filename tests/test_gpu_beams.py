@@ -129,3 +129,38 @@ def test_beam_space_refusals():
         plan.direct_correlate(raw)
     with pytest.raises(omni.OmniError):
         omni.Plan([[8, 8]], None, 1, "ci8", "fp32", beams=True)
+
+
+def test_beam_space_bench_size_sampled():
+    """The bench's configuration (16 x 16-of-16 x 16, 4-bit, 64 channels, T = 2048, mixed form, subset route):
+    one channel's pointings against the oracle, for a handful of pointings (each pointing is the outer-grid
+    correlation of its own block beams, so it needs only those)."""
+    import json
+
+    level_dims = [[16, 16], [16, 16]]
+    T, F, N = 2048, 64, 65536
+    gen = torch.Generator(device="cuda").manual_seed(4242)
+    re = torch.randint(-7, 8, (T, F, N), generator=gen, device="cuda", dtype=torch.int16)
+    im = torch.randint(-7, 8, (T, F, N), generator=gen, device="cuda", dtype=torch.int16)
+    raw = ((re & 0xF) << 4 | (im & 0xF)).to(torch.uint8)
+    del re, im
+    say("[beams] bench size: 16x16-of-16x16, F=64, T=2048, mixed")
+    plan = omni.Plan(level_dims, None, F, "ci4", "mixed", beams=True)
+    assert json.loads(plan.describe())["arrays"][0]["beams"] == "subset"
+    vis = plan.correlate(raw)
+    torch.cuda.synchronize()
+    f = 29
+    x = oracle.decode(raw[:, f:f + 1].contiguous().cpu().numpy(), "ci4", T, 1, N)
+    del raw
+    B = beams.pointings(x, level_dims)[:, 0]  # [T, 256 blocks, 16, 16]
+    del x
+    picks = [(0, 0), (1, 0), (7, 13), (15, 15)]
+    xb = np.stack([B[:, :, bx, by] for bx, by in picks], axis=1)  # [T, 4, 256]
+    del B
+    ref = oracle.visibilities(xb, [16, 16])  # [4, 31, 31]
+    got = vis[f].cpu().numpy()  # [31, 31, 16, 16]
+    for k, (bx, by) in enumerate(picks):
+        g, r = got[:, :, bx, by], ref[k]
+        err = float(np.abs(g - r).max() / abs(r[15, 15]))
+        say(f"[beams] bench size pointing ({bx},{by}): err {err:.3g}")
+        assert err <= TOL["mixed"]
