@@ -99,19 +99,23 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
   const int64_t t0 = (int64_t)s * t_per_slice;
   const int64_t t1 = min(T, t0 + t_per_slice);
 
+  // Every contraction takes its 16 inputs in "even-odd" order: position p holds input sig(p) = 2 p for
+  // p < 8 and 2 (p - 8) + 1 for p >= 8, so K-step 0 carries the even inputs and K-step 1 the odd ones (the
+  // rows of LB and LC are stored in that order: pass A and pass B map their output rows to lines through sig).
   // DFT operand of this lane for K step ks: output (co = n32 / 16, kappa = n32 % 16), input (ci = h,
-  // j = 8 ks + (i ^ 4 sw)).  The outputs kappa + 16 use the same operand with the odd inputs negated
-  // (w_32^{(kappa + 16) j} = (-1)^j w_32^{kappa j}), applied to the data by flip_odd.  In waves with
-  // sw = 1 every operand row loaded in passes B and C has its two 4-half units swapped (bit 0 of the
-  // rows' unit permutation equals bit 1 of the wave index, see pass C's tiles), and pass A loads its
-  // operand swapped likewise, so the operand takes input 8 ks + (i ^ 4) at position i.
+  // j = sig(8 ks + (i ^ 4 sw))).  The outputs kappa + 16 use the same operand with the odd inputs negated
+  // (w_32^{(kappa + 16) j} = (-1)^j w_32^{kappa j}): the whole K-step-1 operand of the data, by flip_all.
+  // In waves with sw = 1 every operand row loaded in passes B and C has its two 4-half units swapped (bit 0
+  // of the rows' unit permutation equals bit 1 of the wave index, see pass C's tiles), and pass A builds its
+  // operand swapped likewise, so the operand takes position 8 ks + (i ^ 4) at element i.
   const int sw = (w >> 1) & 1;
+  auto sig = [](int p) { return p < 8 ? 2 * p : 2 * p - 15; };
   half8 Wh[2], Wl[2];
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int kap = n32 & 15, j = 8 * ks + (i ^ (4 * sw));
+      const int kap = n32 & 15, j = sig(8 * ks + (i ^ (4 * sw)));
       const float2 wv = tw[(kap * j) & 31];
       const bool co = n32 >= 16, ci = h != 0;
       const float v = (!co ? (!ci ? wv.x : -wv.y) : (!ci ? wv.y : wv.x)) * 0.0625f;
@@ -120,8 +124,8 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
       Wl[ks][i] = (_Float16)(v - (float)hi);
     }
   }
-  // negate the odd entries (the high half of each 32-bit word) when `mask` is 0x80000000
-  auto flip_odd = [](half8 v, uint32_t mask) {
+  // negate every entry (both halves of each 32-bit word) when `mask` is 0x80008000
+  auto flip_all = [](half8 v, uint32_t mask) {
     uint4 b = __builtin_bit_cast(uint4, v);
     b.x ^= mask;
     b.y ^= mask;
@@ -130,12 +134,12 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
     return __builtin_bit_cast(half8, b);
   };
 
-  // pass A tile of wave w: row tile rt = w % 8 (lines a = 2 rt + n32 / 16, b = n32 % 16), column tile
+  // pass A tile of wave w: row tile rt = w % 8 (lines a = 2 rt + n32 / 16, b = sig(n32 % 16)), column tile
   // ua = w / 8 (kappa_c in [16 ua, 16 ua + 16)).  The lane's operand: component h, the 16 values of c,
-  // read straight from HBM into registers, one sample ahead.
+  // read straight from HBM into registers, one sample ahead, and put in even-odd order by byte permutes.
   const int rt = w & 7, ua = w >> 3;
-  const int a_line = (2 * rt + (n32 >> 4)) * 16 + (n32 & 15);
-  // (in waves with sw = 1 the two 8-byte halves of each 16-byte operand are loaded in swapped order)
+  const int a_line = (2 * rt + (n32 >> 4)) * 16 + sig(n32 & 15);
+  // (in waves with sw = 1 the two 16-byte halves of the line, c < 8 and c >= 8, are loaded in swapped order)
   // (a wave-uniform tile address plus a 32-bit lane offset, added at each load: the empty asm keeps the
   // compiler from holding 64-bit lane addresses across the loop)
   const int xa_byte = (h * 4096 + a_line * 16) * 2;
@@ -144,10 +148,19 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
     asm volatile("" : "+v"(off));
     const uint2* g = reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(src + (t * F + ch) * 8192) + off);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const uint2 lo = g[2 * ks + sw], hi = g[2 * ks + 1 - sw];
-      xa[ks] = __builtin_bit_cast(half8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+    for (int q = 0; q < 2; ++q) {
+      const uint2 lo = g[2 * (q ^ sw)], hi = g[2 * (q ^ sw) + 1];
+      xa[q] = __builtin_bit_cast(half8, make_uint4(lo.x, lo.y, hi.x, hi.y));
     }
+  };
+  // even (ks = 0) or odd (ks = 1) entries of the loaded line: each 32-bit word of the result takes the low
+  // (even) or high (odd) halves of two consecutive words of the line
+  auto even_odd = [](const half8 (&x)[2], int ks) {
+    const uint32_t sel = ks ? 0x07060302u : 0x05040100u;
+    const uint4 a = __builtin_bit_cast(uint4, x[0]), b = __builtin_bit_cast(uint4, x[1]);
+    const uint4 r = make_uint4(__builtin_amdgcn_perm(a.y, a.x, sel), __builtin_amdgcn_perm(a.w, a.z, sel),
+                               __builtin_amdgcn_perm(b.y, b.x, sel), __builtin_amdgcn_perm(b.w, b.z, sel));
+    return __builtin_bit_cast(half8, r);
   };
 
   float acc[SLOTS];
@@ -181,31 +194,32 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
   // ---- A: axis c on this wave's tile (rt, ua); this lane's half h reads component h of c = 8 ks .. 8 ks + 7
   auto pass_a = [&]() {
     const int co = n32 >> 4;
-    const uint32_t mask = (uint32_t)ua << 31;
+    const uint32_t mask = ua ? 0x80008000u : 0u;
     floatx16 d = {};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const half8 x = flip_odd(xa[ks], mask);
+      const half8 x = ks ? flip_all(even_odd(xa, 1), mask) : even_odd(xa, 0);
       d = mfma(x, Wh[ks], d);
       d = mfma(x, Wl[ks], d);
     }
-    // column n32: (co, kappa_c = 16 ua + n32 % 16); rows 8g + 4h + e: b = 8 (g & 1) + 4h + e, a = 2 rt + g / 2
+    // column n32: (co, kappa_c = 16 ua + n32 % 16); rows 8g + 4h + e: position 8 (g & 1) + 4h + e of b,
+    // a = 2 rt + g / 2
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int a = 2 * rt + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
       *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * ua + (n32 & 15), b0)]) = to_half4(d, g);
     }
   };
-  // ---- B: axis b, row tile mt = w of lines (a = m % 16, kappa_c = 2 mt + m / 16), columns = one half of
-  // kappa_b
+  // ---- B: axis b, row tile mt = w of lines (a = sig(m % 16), kappa_c = 2 mt + m / 16), columns = one half
+  // of kappa_b
   auto pass_b = [&](int half) {
     const int mt = w;
-    const int a_in = n32 & 15, kc_in = 2 * mt + (n32 >> 4);
+    const int a_in = sig(n32 & 15), kc_in = 2 * mt + (n32 >> 4);
     floatx16 d = {};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const half8 x = flip_odd(load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, lb_x(kc_in)),
-                               (uint32_t)half << 31);
+      const half8 xl = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, lb_x(kc_in));
+      const half8 x = ks ? flip_all(xl, half ? 0x80008000u : 0u) : xl;
       d = mfma(x, Wh[ks], d);
       d = mfma(x, Wl[ks], d);
     }
@@ -230,7 +244,7 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
         floatx16 d = {};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          const half8 xu = u ? flip_odd(x[ks], 0x80000000u) : x[ks];
+          const half8 xu = (u && ks) ? flip_all(x[ks], 0x80008000u) : x[ks];
           d = mfma(Wh[ks], xu, d);
           d = mfma(Wl[ks], xu, d);
         }
