@@ -14,11 +14,17 @@
 //
 // Work-group = (time slice, channel), 1024 threads (16 waves, one work-group
 // per CU); it owns all 32768 cells of the channel, 32 float32 accumulators per
-// lane.  Per sample (one A tile, two B tiles and four C tiles per wave):
-//   A  axis c, lines (a, b): data x W^T, 8 row tiles x 2 column tiles -> LB
-//   B  axis b, lines (a, kappa_c): data x W^T, both halves of kappa_b -> LC
-//   C  axis a, lines (kappa_b, kappa_c): W x data, so that the real and the
-//      imaginary row of an output land in the same lane -> |X|^2 in registers.
+// lane.  Per sample:
+//   A  axis c, lines (a, b): data x W^T, 8 row tiles, each with both halves
+//      of kappa_c, in waves 0-7 -> LB
+//   B  axis b, lines (a, kappa_c): data x W^T, one row tile per wave, both
+//      halves of kappa_b -> LC
+//   C  axis a, lines (kappa_b, kappa_c): W x data, two column tiles per wave,
+//      both halves of kappa_a, so that the real and the imaginary row of an
+//      output land in the same lane -> |X|^2 in registers.
+// Inputs are taken in even-odd order, so each pair of output halves shares
+// the product of its even inputs (6 matrix-core instructions per pair
+// instead of 8).
 // In A and B the rows of a tile are lines ordered with the next pass'
 // contracted axis fastest, so a lane stores 4 consecutive values of it with
 // one 8-byte LDS write and the next pass reads an operand with one 16-byte
@@ -134,16 +140,19 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
     return __builtin_bit_cast(half8, b);
   };
 
-  // pass A tile of wave w: row tile rt = w % 8 (lines a = 2 rt + n32 / 16, b = sig(n32 % 16)), column tile
-  // ua = w / 8 (kappa_c in [16 ua, 16 ua + 16)).  The lane's operand: component h, the 16 values of c,
-  // read straight from HBM into registers, one sample ahead, and put in even-odd order by byte permutes.
-  const int rt = w & 7, ua = w >> 3;
+  // pass A: waves w < 8 take row tile rt = w (lines a = 2 rt + n32 / 16, b = sig(n32 % 16)) and both column
+  // halves ua (kappa_c in [16 ua, 16 ua + 16)), so the even-input product is formed once for both; waves
+  // w >= 8 have no pass-A work.  The lane's operand: component h, the 16 values of c, read straight from HBM
+  // into registers, one sample ahead, and put in even-odd order by byte permutes.
+  const bool a_wave = w < 8;
+  const int rt = w & 7;
   const int a_line = (2 * rt + (n32 >> 4)) * 16 + sig(n32 & 15);
   // (in waves with sw = 1 the two 16-byte halves of the line, c < 8 and c >= 8, are loaded in swapped order)
   // (a wave-uniform tile address plus a 32-bit lane offset, added at each load: the empty asm keeps the
   // compiler from holding 64-bit lane addresses across the loop)
   const int xa_byte = (h * 4096 + a_line * 16) * 2;
   auto load_xa = [&](int64_t t, half8* xa) {
+    if (!a_wave) return;
     int off = xa_byte;
     asm volatile("" : "+v"(off));
     const uint2* g = reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(src + (t * F + ch) * 8192) + off);
@@ -191,43 +200,54 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
   };
 
   half8 xa[2];
-  // ---- A: axis c on this wave's tile (rt, ua); this lane's half h reads component h of c = 8 ks .. 8 ks + 7
+  // ---- A: axis c on row tile rt, both halves of kappa_c; this lane's half h reads component h of c
   auto pass_a = [&]() {
+    if (!a_wave) return;
     const int co = n32 >> 4;
-    const uint32_t mask = ua ? 0x80008000u : 0u;
-    floatx16 d = {};
+    const half8 xe = even_odd(xa, 0), xo = even_odd(xa, 1);
+    floatx16 e = {};
+    e = mfma(xe, Wh[0], e);
+    e = mfma(xe, Wl[0], e);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const half8 x = ks ? flip_all(even_odd(xa, 1), mask) : even_odd(xa, 0);
-      d = mfma(x, Wh[ks], d);
-      d = mfma(x, Wl[ks], d);
-    }
-    // column n32: (co, kappa_c = 16 ua + n32 % 16); rows 8g + 4h + e: position 8 (g & 1) + 4h + e of b,
-    // a = 2 rt + g / 2
+    for (int ua = 0; ua < 2; ++ua) {
+      const half8 x = ua ? flip_all(xo, 0x80008000u) : xo;
+      floatx16 d = mfma(x, Wh[1], e);
+      d = mfma(x, Wl[1], d);
+      // column n32: (co, kappa_c = 16 ua + n32 % 16); rows 8g + 4h + e: position 8 (g & 1) + 4h + e of b,
+      // a = 2 rt + g / 2
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int a = 2 * rt + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
-      *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * ua + (n32 & 15), b0)]) = to_half4(d, g);
+      for (int g = 0; g < 4; ++g) {
+        const int a = 2 * rt + (g >> 1), b0 = 8 * (g & 1) + 4 * h;
+        *reinterpret_cast<half4*>(&LB[lb_at(co, a, 16 * ua + (n32 & 15), b0)]) = to_half4(d, g);
+      }
     }
   };
-  // ---- B: axis b, row tile mt = w of lines (a = sig(m % 16), kappa_c = 2 mt + m / 16), columns = one half
-  // of kappa_b
-  auto pass_b = [&](int half) {
+  // ---- B: axis b, row tile mt = w of lines (a = sig(m % 16), kappa_c = 2 mt + m / 16), both halves of
+  // kappa_b: the even-input product is formed once, the odd inputs added with and without their sign flip
+  auto pass_b = [&]() {
     const int mt = w;
     const int a_in = sig(n32 & 15), kc_in = 2 * mt + (n32 >> 4);
-    floatx16 d = {};
+    const _Float16* row = &LB[h * CMP + a_in * BLK + kc_in * 16];
+    const half8 xe = load8(row, 0, lb_x(kc_in)), xo = load8(row, 8, lb_x(kc_in));
+    floatx16 e = {};
+    e = mfma(xe, Wh[0], e);
+    e = mfma(xe, Wl[0], e);
+    floatx16 d[2];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const half8 xl = load8(&LB[h * CMP + a_in * BLK + kc_in * 16], 8 * ks, lb_x(kc_in));
-      const half8 x = ks ? flip_all(xl, half ? 0x80008000u : 0u) : xl;
-      d = mfma(x, Wh[ks], d);
-      d = mfma(x, Wl[ks], d);
+    for (int half = 0; half < 2; ++half) {
+      const half8 x = half ? flip_all(xo, 0x80008000u) : xo;
+      d[half] = mfma(x, Wh[1], e);
+      d[half] = mfma(x, Wl[1], d[half]);
     }
-    const int co = n32 >> 4, kb = 16 * half + (n32 & 15);
+    const int co = n32 >> 4;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int a0 = 8 * (g & 1) + 4 * h, kc = 2 * mt + (g >> 1);
-      *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d, g);
+    for (int half = 0; half < 2; ++half) {
+      const int kb = 16 * half + (n32 & 15);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int a0 = 8 * (g & 1) + 4 * h, kc = 2 * mt + (g >> 1);
+        *reinterpret_cast<half4*>(&LC[lc_at(co, kb, kc, a0)]) = to_half4(d[half], g);
+      }
     }
   };
   // ---- C: axis a, column tiles (lines kappa_b, kappa_c = n32), row tiles u; kappa_b takes the bits
@@ -239,15 +259,15 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
       half8 x[2];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) x[ks] = load8(&LC[h * CMPC + kb * BLK + n32 * 16], 8 * ks, lc_x(kb, n32));
+      // the even-input product once; row tile u adds the odd inputs, negated for u = 1 (kappa_a + 16)
+      floatx16 e = {};
+      e = mfma(Wh[0], x[0], e);
+      e = mfma(Wl[0], x[0], e);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        floatx16 d = {};
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-          const half8 xu = (u && ks) ? flip_all(x[ks], 0x80008000u) : x[ks];
-          d = mfma(Wh[ks], xu, d);
-          d = mfma(Wl[ks], xu, d);
-        }
+        const half8 xo = u ? flip_all(x[1], 0x80008000u) : x[1];
+        floatx16 d = mfma(Wh[1], xo, e);
+        d = mfma(Wl[1], xo, d);
         // rows r < 8 hold Re and rows r + 8 Im of the same kappa_a
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -267,8 +287,7 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
     pass_a();
     load_xa(min(t0 + 1, t1 - 1), xa);
     __syncthreads();
-    pass_b(0);
-    pass_b(1);
+    pass_b();
     __syncthreads();
   }
   int blk = 0;
@@ -277,8 +296,7 @@ __global__ __launch_bounds__(1024) void fused16x3_mixed_kernel(const _Float16* _
     load_xa(min(t + 2, t1 - 1), xa);
     pass_c();
     __syncthreads();
-    pass_b(0);
-    pass_b(1);
+    pass_b();
     __syncthreads();
     if (++blk == time_block) {
       blk = 0;
