@@ -13,6 +13,8 @@
 // remaining axes for the fused kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <stdint.h>
 
 #include "shortdft.hpp"
@@ -35,14 +37,13 @@ __device__ __forceinline__ float2 load(const void* __restrict__ base, int64_t i)
   return make_float2((float)(v >> 4), (float)((int8_t)(v << 4) >> 4));
 }
 
-// V samples at consecutive inner indices starting at element e
+// V samples at consecutive inner indices, the first at byte address q (ES bytes per sample)
 template <int FMT, int V>
-__device__ __forceinline__ void load_v(const void* __restrict__ src, int64_t e, float2 (&x)[V]) {
+__device__ __forceinline__ void load_v(const char* __restrict__ q, float2 (&x)[V]) {
   if constexpr (V == 1) {
-    x[0] = load<FMT>(src, e);
+    x[0] = load<FMT>(q, 0);
   } else if constexpr (FMT == 2) {  // V packed 4-bit samples in one 2- or 4-byte word
-    const uint32_t u = V == 4 ? *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(src) + e)
-                              : (uint32_t)*reinterpret_cast<const uint16_t*>(static_cast<const uint8_t*>(src) + e);
+    const uint32_t u = V == 4 ? *reinterpret_cast<const uint32_t*>(q) : (uint32_t)*reinterpret_cast<const uint16_t*>(q);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const int8_t b = (int8_t)(u >> (8 * v));
@@ -51,9 +52,9 @@ __device__ __forceinline__ void load_v(const void* __restrict__ src, int64_t e, 
   } else {  // FMT 1: V int8 pairs in 2 V bytes
     uint2 u;
     if constexpr (V == 4) {
-      u = *reinterpret_cast<const uint2*>(static_cast<const int8_t*>(src) + 2 * e);
+      u = *reinterpret_cast<const uint2*>(q);
     } else {
-      u.x = *reinterpret_cast<const uint32_t*>(static_cast<const int8_t*>(src) + 2 * e);
+      u.x = *reinterpret_cast<const uint32_t*>(q);
       u.y = 0;
     }
 #pragma unroll
@@ -63,6 +64,12 @@ __device__ __forceinline__ void load_v(const void* __restrict__ src, int64_t e, 
       x[v] = make_float2((float)(int8_t)(h >> s), (float)(int8_t)(h >> (s + 8)));
     }
   }
+}
+
+// bytes per sample of the formats load_v reads
+template <int FMT>
+constexpr int sample_bytes() {
+  return FMT == 0 ? 8 : FMT == 1 ? 2 : 1;
 }
 
 }  // namespace fr
@@ -79,44 +86,50 @@ __device__ __forceinline__ void load_v(const void* __restrict__ src, int64_t e, 
 // H16: the output is float16, scaled by `scale`, in planar blocks: for every
 // (tile, outer index, Fourier index) the inner run of real parts, then that of
 // imaginary parts (the operand layout of the float16 matrix-core kernel).
+//
+// A launch covers tiles tile0 .. tile0 + total / (outer * inner_v) - 1; its item
+// index is 32-bit (the launcher splits larger calls), and each item forms its
+// two 64-bit base addresses once: rows and Fourier indices are offsets that are
+// the same for every lane.
 template <int FMT, int L, int V, int R, bool H16>
 __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict__ src, void* __restrict__ dst_,
-                                                          const float2* __restrict__ twm, int64_t tiles,
-                                                          int64_t outer, int64_t inner, int64_t src_tile,
-                                                          int64_t dst_tile, float scale) {
+                                                          const float2* __restrict__ twm, uint32_t total,
+                                                          uint32_t outer, uint32_t inner_v, int64_t tile0,
+                                                          int64_t inner, int64_t src_tile, int64_t dst_tile,
+                                                          float scale) {
   using namespace fr;
   constexpr int M = L * R, N = M / 2;
   constexpr int NB = R >= 2 ? R / 2 : 1;
-  const int64_t inner_v = inner / V;
-  const int64_t per_tile = outer * inner_v;
-  const int64_t total = tiles * per_tile;
+  const uint32_t per_tile = outer * inner_v;
   const int rho = blockIdx.y;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t tile = idx / per_tile;
-    const int64_t rem = idx - tile * per_tile;
-    const int64_t o = rem / inner_v, in = (rem - o * inner_v) * V;
-    const int64_t sbase = tile * src_tile + o * N * inner + in;
-    const int64_t dbase = tile * dst_tile + o * M * inner + in;
+  for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const uint32_t tl = idx / per_tile;
+    const uint32_t rem = idx - tl * per_tile;
+    const uint32_t o = rem / inner_v, in = (rem - o * inner_v) * V;
+    const int64_t tile = tile0 + tl;
+    const int64_t sbase = tile * src_tile + (int64_t)o * N * inner + in;
     // V inputs of row p; FMT 3 reads float16 planar blocks of (tile, o): N * inner real parts, then as many
     // imaginary parts (the H16 output of a previous front pass)
+    const char* const sp = static_cast<const char*>(src) + (FMT == 3 ? 0 : sbase * sample_bytes<FMT>());
+    const _Float16* const hp = static_cast<const _Float16*>(src) + (FMT == 3 ? 2 * (sbase - in) + in : 0);
     auto ld = [&](int p, float2(&xv)[V]) {
       if constexpr (FMT == 3) {
-        const _Float16* h = static_cast<const _Float16*>(src);
-        const int64_t re = 2 * (sbase - in) + in + (int64_t)p * inner, plane = (int64_t)N * inner;
+        const _Float16* h = hp + (int64_t)p * inner;
+        const int64_t plane = (int64_t)N * inner;
 #pragma unroll
-        for (int v = 0; v < V; ++v) xv[v] = make_float2((float)h[re + v], (float)h[re + plane + v]);
+        for (int v = 0; v < V; ++v) xv[v] = make_float2((float)h[v], (float)h[plane + v]);
       } else {
-        load_v<FMT, V>(src, sbase + (int64_t)p * inner, xv);
+        load_v<FMT, V>(sp + (int64_t)p * inner * sample_bytes<FMT>(), xv);
       }
     };
+    _Float16* const dh = static_cast<_Float16*>(dst_) + ((tile * outer + o) * M) * 2 * inner + in;
+    float2* const dp = static_cast<float2*>(dst_) + tile * dst_tile + (int64_t)o * M * inner + in;
     auto store = [&](const float2(&zz)[V][L], int res) {
       if constexpr (H16) {
-        _Float16* const d16 = static_cast<_Float16*>(dst_);
 #pragma unroll
         for (int q = 0; q < L; ++q) {
           // planar block of (tile, o, kappa): 2 * inner halves
-          _Float16* d = d16 + ((tile * outer + o) * M + (R * q + res)) * 2 * inner + in;
+          _Float16* d = dh + (int64_t)(R * q + res) * 2 * inner;
           if constexpr (V == 2) {  // one 4-byte store per plane
             typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
             half2_t re, im;
@@ -136,10 +149,9 @@ __global__ __launch_bounds__(256) void front_axis_kernel(const void* __restrict_
         }
         return;
       }
-      float2* const dst = static_cast<float2*>(dst_);
 #pragma unroll
       for (int q = 0; q < L; ++q) {
-        float2* d = dst + dbase + (int64_t)(R * q + res) * inner;
+        float2* d = dp + (int64_t)(R * q + res) * inner;
         if constexpr (V == 4) {
           reinterpret_cast<float4*>(d)[0] = make_float4(zz[0][q].x, zz[0][q].y, zz[1][q].x, zz[1][q].y);
           reinterpret_cast<float4*>(d)[1] = make_float4(zz[2][q].x, zz[2][q].y, zz[3][q].x, zz[3][q].y);
@@ -323,19 +335,26 @@ hipError_t launch_front_axis(int fmt, const void* src, void* dst, const float2* 
                  (reinterpret_cast<uintptr_t>(src) & 3) == 0)
                     ? 2
                     : 1;  // fmt 3 (float16 planar) reads its halves one by one, two inner indices per thread
-  const int64_t total = tiles * outer * (inner / V);
-  int64_t g = (total + 255) / 256;
-  if (g > 65536) g = 65536;
+  // items of one tile; a launch takes as many whole tiles as keep its item index below 2^31
+  const int64_t per_tile = outer * (inner / V);
+  if (tiles < 0 || per_tile <= 0 || per_tile > INT32_MAX) return tiles == 0 ? hipSuccess : hipErrorInvalidValue;
+  const int64_t tiles_per_launch = INT32_MAX / per_tile;
   // r = 2: one thread computes both residue classes from the same inputs
-  const dim3 grid((unsigned)g, (unsigned)(r == 2 ? 1 : r)), block(256);
-#define OMNI_FRONT(F_, L_, V_, R_)                                                                             \
-  do {                                                                                                          \
-    if (half16)                                                                                                 \
-      hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_, true>), grid, block, 0, st, src, dst, twm, tiles,   \
-                         outer, inner, src_tile, dst_tile, scale);                                              \
-    else                                                                                                        \
-      hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_, false>), grid, block, 0, st, src, dst, twm, tiles,  \
-                         outer, inner, src_tile, dst_tile, scale);                                              \
+  const dim3 block(256);
+#define OMNI_FRONT(F_, L_, V_, R_)                                                                               \
+  do {                                                                                                            \
+    for (int64_t t0 = 0; t0 < tiles; t0 += tiles_per_launch) {                                                    \
+      const int64_t total = std::min(tiles_per_launch, tiles - t0) * per_tile;                                    \
+      const dim3 grid((unsigned)std::min<int64_t>((total + 255) / 256, 65536), (unsigned)(r == 2 ? 1 : r));      \
+      if (half16)                                                                                                 \
+        hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_, true>), grid, block, 0, st, src, dst, twm,          \
+                           (uint32_t)total, (uint32_t)outer, (uint32_t)(inner / V), t0, inner, src_tile,          \
+                           dst_tile, scale);                                                                      \
+      else                                                                                                        \
+        hipLaunchKernelGGL((front_axis_kernel<F_, L_, V_, R_, false>), grid, block, 0, st, src, dst, twm,         \
+                           (uint32_t)total, (uint32_t)outer, (uint32_t)(inner / V), t0, inner, src_tile,          \
+                           dst_tile, scale);                                                                      \
+    }                                                                                                             \
   } while (0)
   // the planner's fold moduli: L = 16 for m >= 16 (r = m / 16), else r = 1 and L = m
 #define OMNI_FRONT_LR(F_, V_)                              \
