@@ -363,6 +363,27 @@ def test_front_chunks_full_oracle(level_dims, dtype, form, T, chunk_T, kernel):
     assert err <= TOL[form]
 
 
+@pytest.mark.parametrize("dtype", ["ci4", "cf32"])
+def test_front_pass_fold_by_four(dtype):
+    """A front axis of 32 antennas (m = 64, folded into four residue classes of 16-point DFTs) on the
+    32x32-of-16x16 array (N = 262144, M = 4.2M cells), over three time chunks: sampled cells against the oracle."""
+    level_dims = [[32, 32], [16, 16]]
+    dims = dims_of(level_dims)
+    N = math.prod(dims)
+    T, F = 3, 1
+    gen = torch.Generator().manual_seed(N + len(dtype))
+    raw = random_raw(dtype, T, F, N, gen)
+    plan = omni.Plan(level_dims, None, F, dtype, "fp32", chunk_T=1)
+    desc = plan.describe()
+    say("fold by four", dtype, desc[:200])
+    assert '"mode":"front"' in desc and '"n_front":1' in desc  # the front pass takes the first axis (32 antennas)
+    assert chunk_count(plan, T) >= 3
+    vis = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    x = oracle.decode(raw.numpy(), dtype, T, F, N)
+    check_cells(vis.cpu().numpy(), x, dims, "fp32", n_random=64, seed=N, tag="fold by four " + dtype)
+
+
 @pytest.mark.parametrize("shape", [[[64, 64]], [[128, 128]]])
 def test_large_single_level_grids(shape):
     N = math.prod(dims_of(shape))
