@@ -363,6 +363,35 @@ def test_front_chunks_full_oracle(level_dims, dtype, form, T, chunk_T, kernel):
     assert err <= TOL[form]
 
 
+@pytest.mark.parametrize(
+    "level_dims,dtype,kernel",
+    [
+        ([[8, 8], [8, 8]], "ci8", "fused8x4_mixed"),
+        ([[2, 16], [16, 16]], "ci8", "fused16x3_mixed"),
+        ([[2, 16], [16, 16]], "ci4", "fused16x3_mixed"),
+        ([[32, 32]], "ci4", "grid32_mixed"),
+    ],
+)
+def test_mixed_quiet_and_loud_channels(level_dims, dtype, kernel):
+    """The mixed form applies no per-channel gain: a channel of unit-level samples (-1, 0, 1) beside one at the
+    format's full scale, each within the tolerance of its own zero-lag power (float16 keeps its relative precision
+    at any level, and the stage scales keep a unit sample out of its subnormal range)."""
+    dims = dims_of(level_dims)
+    N = math.prod(dims)
+    T, F = 9, 2
+    gen = torch.Generator().manual_seed(N + len(dtype))
+    full = 127 if dtype == "ci8" else 7
+    parts = [torch.randint(lo, hi + 1, (T, 1, N, 2), generator=gen, dtype=torch.int16) for lo, hi in ((-1, 1), (-full, full))]
+    x = torch.cat(parts, dim=1)
+    raw = x.to(torch.int8).contiguous() if dtype == "ci8" else skysim.pack_ci4(x[..., 0], x[..., 1])
+    say("quiet and loud channels", level_dims, dtype)
+    vis, plan = gpu_vis(level_dims, raw, dtype, form="mixed")
+    assert f'"kernel":"{kernel}"' in plan.describe()
+    err = rel_err(vis, oracle_vis(raw, dtype, level_dims))
+    say("quiet and loud channels error", err)
+    assert err <= TOL["mixed"]
+
+
 @pytest.mark.parametrize("dtype", ["ci4", "cf32"])
 def test_front_pass_fold_by_four(dtype):
     """A front axis of 32 antennas (m = 64, folded into four residue classes of 16-point DFTs) on the
