@@ -364,6 +364,37 @@ def test_front_chunks_full_oracle(level_dims, dtype, form, T, chunk_T, kernel):
 
 
 @pytest.mark.parametrize(
+    "level_dims,kernel",
+    [
+        ([[8, 8], [8, 8]], "fused8x4_mixed"),
+        ([[2, 16], [16, 16]], "fused16x3_mixed"),
+        ([[2, 2], [8, 8], [4, 4]], "fused8844_mixed"),
+        ([[32, 32]], "grid32_mixed"),
+        ([[64, 64]], "grid64_mixed"),
+        ([[128, 128]], "grid128_mixed"),
+    ],
+)
+def test_mixed_kernels_zero_and_one_sample(level_dims, kernel):
+    """Each matrix-core kernel with T = 0 (the output is cleared) and T = 1 (one sample: the prologue and the
+    software-pipelined loop run once, the loads that run ahead are clamped to that sample) against the oracle."""
+    N = math.prod(dims_of(level_dims))
+    plan = omni.Plan(level_dims, None, 2, "ci4", "mixed")
+    assert f'"kernel":"{kernel}"' in plan.describe()
+    out = torch.full(plan.vis_shape(), 7.0 + 1j, dtype=torch.complex64, device="cuda")
+    plan.correlate_into(0, 0, out)
+    torch.cuda.synchronize()
+    assert not out.abs().max().item()
+    gen = torch.Generator().manual_seed(N + 1)
+    raw = random_raw("ci4", 1, 2, N, gen)
+    say("one sample", level_dims, kernel)
+    vis = plan.correlate(raw.cuda())
+    torch.cuda.synchronize()
+    err = rel_err(vis.cpu().numpy(), oracle_vis(raw, "ci4", level_dims))
+    say("one sample error", err)
+    assert err <= TOL["mixed"]
+
+
+@pytest.mark.parametrize(
     "level_dims,dtype,kernel",
     [
         ([[8, 8], [8, 8]], "ci8", "fused8x4_mixed"),
